@@ -1,0 +1,248 @@
+"""Semi-implicit SDC / ISDC sweeps, the SDC residual and the time step.
+
+Test infrastructure only (see the package docstring).
+
+Paper basis:
+
+* Sweep: eq. (4).  For m = 0..M-1 (tau_0 = 0, dt_m = dt (tau_{m+1} - tau_m)):
+    u_{m+1}^{k+1} = u_m^{k+1} + dt_m [f^I(u_{m+1}^{k+1}) - f^I(u_{m+1}^k)]
+                    + dt_m [f^E(u_m^{k+1}) - f^E(u_m^k)] + S_m^{m+1} F(u^k),
+  i.e. (I - dt_m nu L_h) u_{m+1}^{k+1} = rhs with
+    rhs = u_m^{k+1} + dt_m [f^E(u_m^{k+1}) - f^E(u_m^k)] - dt_m f^I(u_{m+1}^k)
+          + S_m^{m+1} F(u^k).
+  u_0^k = u_0 for every k (the left end of the step).
+* Inner solve (Sec. 3): classical SDC solves each system fully (``exact``:
+  sine-transform direct solve; ``mg`` with ``vcycles = 0``: V-cycles until the
+  inner residual is at most ``inner_tol``); ISDC applies exactly L V-cycles
+  (``mg`` with ``vcycles = L``), optionally stopping early once ``inner_tol``
+  is met.  The initial guess is u_{m+1}^k (Sec. 4.3); the ablation of Sec. 4.3
+  replaces it by zero or by u_m^{k+1}.
+* Residual (Sec. 3): max over nodes m = 1..M and grid points of
+  |u_0 + dt sum_j q_{m,j} f(u_j^k) - u_m^k|; sweeps run until it is below the
+  tolerance.
+* Initial iterate: u_j^0 = u_0 at every node (the paper is silent; with this
+  choice sweep 1 is plain implicit / IMEX Euler).  At least one sweep is made.
+* Result: u_{n+1} = u_M (tau_M = 1 for Gauss-Lobatto and right Gauss-Radau).
+* Mixed precision: the inner V-cycles run in float32 on the correction
+  equation (I - c L_h) e = rhs - (I - c L_h) g for the guess g, with the
+  right-hand side rounded to float32 and u = g + e accumulated in float64.
+  The fixed point of the sweep is unchanged because that right-hand side
+  vanishes at the collocation solution.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .collocation import qmatrix, smatrix, nodes, NODES_LOBATTO
+from .multigrid import SMOOTH_RBGS, vcycle, residual_inf
+from .operators import FE_ZERO, f_explicit, f_implicit, apply_shifted, solve_shifted_exact
+
+GUESS_PREV_SWEEP = 0
+GUESS_ZERO = 1
+GUESS_PREV_NODE = 2
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+class Diverged(RuntimeError):
+    pass
+
+
+@dataclass
+class SDCConfig:
+    nu: float = 1.0
+    fe_kind: int = FE_ZERO
+    node_kind: int = NODES_LOBATTO
+    M: int = 3
+    inner: str = "mg"            # "exact" (direct solve) or "mg"
+    vcycles: int = 2             # L; 0 = classical: cycle until inner_tol
+    inner_tol: float = 1e-10
+    early_exit: bool = False
+    tol: float = 1e-10
+    max_sweeps: int = 100
+    smoother: int = SMOOTH_RBGS
+    nu1: int = 1
+    nu2: int = 1
+    omega: float | None = None
+    precision: int = PREC_FP64
+    guess: int = GUESS_PREV_SWEEP
+    max_classical_cycles: int = 100
+
+
+@dataclass
+class SDCStats:
+    sweeps: int = 0
+    vcycles: int = 0
+    residual: float = float("inf")
+    residual_hist: list = field(default_factory=list)
+    status: str = "ok"           # "ok" | "not_converged" | "diverged"
+
+
+@dataclass
+class SDCState:
+    u0: np.ndarray
+    U: list                      # U[j] = u_j^k, j = 1..M (index 0 unused: u_0)
+    F: list                      # F[j] = f(u_j^k)
+    dt: float
+    h: float
+    cfg: SDCConfig
+    tau: np.ndarray
+    Q: np.ndarray
+    S: np.ndarray
+    stats: SDCStats
+
+
+def _f(u, cfg, h):
+    return f_implicit(u, cfg.nu, h) + f_explicit(u, cfg.fe_kind)
+
+
+def sdc_residual(state: SDCState) -> float:
+    """Max-norm SDC residual of the current iterate (Sec. 3)."""
+    cfg = state.cfg
+    per_node = []
+    for m in range(1, cfg.M + 1):
+        quad = np.zeros_like(state.u0)
+        for j in range(1, cfg.M + 1):
+            quad = quad + state.Q[m - 1, j - 1] * state.F[j]
+        r = state.u0 + state.dt * quad - state.U[m]
+        per_node.append(np.max(np.abs(r)))
+    return float(np.max(per_node))  # np.max propagates NaN
+
+
+def sdc_begin(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig) -> SDCState:
+    """Spread u_0 to every node and evaluate f there (initial iterate k = 0)."""
+    u0 = np.asarray(u0, dtype=np.float64)
+    f0 = _f(u0, cfg, h)
+    M = cfg.M
+    U = [u0.copy() for _ in range(M + 1)]
+    F = [f0.copy() for _ in range(M + 1)]
+    return SDCState(u0=u0, U=U, F=F, dt=dt, h=h, cfg=cfg,
+                    tau=nodes(cfg.node_kind, M), Q=qmatrix(cfg.node_kind, M),
+                    S=smatrix(cfg.node_kind, M), stats=SDCStats())
+
+
+def _inner_solve(rhs, guess, c, h, cfg):
+    """Solve (I - c L_h) u = rhs; returns (u, number of V-cycles)."""
+    if cfg.inner == "exact":
+        return solve_shifted_exact(rhs, c, h), 0
+    if cfg.precision == PREC_FP64:
+        u = guess.copy()
+
+        def inner_res():
+            return residual_inf(u, rhs, c, h)
+    else:
+        r32 = (rhs - apply_shifted(guess, c, h)).astype(np.float32)
+        e = np.zeros_like(r32)
+
+        def inner_res():
+            return residual_inf(e, r32, c, h)
+
+    classical = cfg.vcycles == 0
+    limit = cfg.max_classical_cycles if classical else cfg.vcycles
+    check = classical or cfg.early_exit
+    ncyc = 0
+    while ncyc < limit:
+        if check and inner_res() <= cfg.inner_tol:
+            break
+        if cfg.precision == PREC_FP64:
+            u = vcycle(u, rhs, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
+        else:
+            e = vcycle(e, r32, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
+        ncyc += 1
+    if cfg.precision == PREC_FP64:
+        return u, ncyc
+    return guess + e.astype(np.float64), ncyc
+
+
+def sdc_sweep(state: SDCState) -> float:
+    """One sweep of eq. (4) over all substeps; returns the new SDC residual."""
+    cfg = state.cfg
+    dt, h, M = state.dt, state.h, cfg.M
+    tau_ext = np.concatenate([[0.0], state.tau])
+    # S_m^{m+1} F(u^k) for every substep, from the previous iterate
+    SF = []
+    for m in range(M):
+        acc = np.zeros_like(state.u0)
+        for j in range(1, M + 1):
+            acc = acc + state.S[m, j - 1] * state.F[j]
+        SF.append(dt * acc)
+    Uold = [u for u in state.U]
+    Unew = [None] * (M + 1)
+    Fnew = [None] * (M + 1)
+    Unew[0] = state.u0
+    Uold[0] = state.u0
+    for m in range(M):
+        dtm = dt * (tau_ext[m + 1] - tau_ext[m])
+        um_new, um_old, up_old = Unew[m], Uold[m], Uold[m + 1]
+        rhs = (um_new + dtm * (f_explicit(um_new, cfg.fe_kind) - f_explicit(um_old, cfg.fe_kind))
+               - dtm * f_implicit(up_old, cfg.nu, h) + SF[m])
+        c = dtm * cfg.nu
+        if dtm == 0.0:
+            u = rhs  # degenerate substep (tau_1 = 0 for Gauss-Lobatto): identity operator
+        else:
+            if cfg.guess == GUESS_PREV_SWEEP:
+                g = up_old
+            elif cfg.guess == GUESS_ZERO:
+                g = np.zeros_like(up_old)
+            elif cfg.guess == GUESS_PREV_NODE:
+                g = um_new
+            else:
+                raise ValueError("unknown guess mode")
+            u, ncyc = _inner_solve(rhs, g, c, h, cfg)
+            state.stats.vcycles += ncyc
+        Unew[m + 1] = u
+        Fnew[m + 1] = _f(u, cfg, h)
+    Fnew[0] = state.F[0]
+    state.U = Unew
+    state.F = Fnew
+    state.stats.sweeps += 1
+    res = sdc_residual(state)
+    state.stats.residual = res
+    state.stats.residual_hist.append(res)
+    return res
+
+
+def sdc_step(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig,
+             fixed_sweeps: int | None = None, raise_on_failure: bool = False):
+    """One ISDC / SDC time step: sweeps until residual < tol (Sec. 3, Sec. 4.2).
+
+    With ``fixed_sweeps`` set, exactly that many sweeps are made and no stopping
+    test is applied.  Returns (u_{n+1}, stats).
+    """
+    st = sdc_begin(u0, dt, h, cfg)
+    nmax = fixed_sweeps if fixed_sweeps is not None else cfg.max_sweeps
+    for _ in range(nmax):
+        res = sdc_sweep(st)
+        if not np.isfinite(res):
+            st.stats.status = "diverged"
+            if raise_on_failure:
+                raise Diverged(f"non-finite SDC residual after {st.stats.sweeps} sweeps")
+            break
+        if fixed_sweeps is None and res < cfg.tol:
+            break
+    else:
+        if fixed_sweeps is None:
+            st.stats.status = "not_converged"
+            if raise_on_failure:
+                raise NotConverged(f"residual {st.stats.residual:.3e} after {nmax} sweeps")
+    return st.U[cfg.M].copy(), st.stats
+
+
+def sdc_run(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig, nsteps: int):
+    """nsteps consecutive time steps; returns (u, list of per-step stats)."""
+    u = np.asarray(u0, dtype=np.float64)
+    all_stats = []
+    for _ in range(nsteps):
+        u, st = sdc_step(u, dt, h, cfg)
+        all_stats.append(st)
+        if st.status != "ok":
+            break
+    return u, all_stats

@@ -1,0 +1,277 @@
+"""Pins for the oracle's SDC / ISDC sweeps, residual and time step.
+
+Targets: the direct collocation solution (modal closed forms for the heat
+equation, Newton on the full system for the cubic reaction term), the
+continuum heat-equation decay of Sec. 4.1, counting identities of Sec. 3, the
+printed Table 1 arithmetic and the warm-start ablation of Sec. 4.3.
+"""
+
+import csv
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.sdc import (SDCConfig, sdc_step, sdc_begin, sdc_sweep, sdc_residual,
+                        GUESS_ZERO, GUESS_PREV_NODE, PREC_MIXED)
+
+LOB, RAD = O.NODES_LOBATTO, O.NODES_RADAU_RIGHT
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _grid(n):
+    h = 1.0 / (n + 1)
+    return (np.arange(n) + 1) * h, h
+
+
+def _smooth_u0(n, d, seed, K=6):
+    rng = np.random.default_rng(seed)
+    x, h = _grid(n)
+    u = np.zeros((n,) * d)
+    for _ in range(K):
+        a = rng.integers(1, 6, size=d)
+        t = rng.standard_normal() / float(np.sum(a * a))
+        for ax in range(d):
+            shape = [1] * d
+            shape[ax] = n
+            t = t * np.sin(a[ax] * np.pi * x).reshape(shape)
+        u = u + t
+    return u, h
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ---- exact-solve SDC converges to the collocation solution ----
+
+@pytest.mark.parametrize("d,n,kind,M,nu,dt", [(1, 127, LOB, 3, 1.0, 0.01), (2, 31, LOB, 5, 0.5, 0.01),
+                                             (2, 31, RAD, 3, 1.0, 0.005), (3, 15, RAD, 3, 1.0, 1e-3)])
+def test_exact_sdc_converges_to_collocation(d, n, kind, M, nu, dt):
+    u0, h = _smooth_u0(n, d, 21)
+    # the residual floor is ~1e-16 * dt * nu * 4d / h^2, so run a fixed count
+    cfg = SDCConfig(nu=nu, node_kind=kind, M=M, inner="exact")
+    u, st = sdc_step(u0, dt, h, cfg, fixed_sweeps=40)
+    assert st.residual < 1e-12
+    assert _rel(u, O.collocation_heat_modal(u0, dt, nu, h, kind, M)) < 1e-13
+
+
+def test_exact_sdc_converges_to_newton_collocation_cubic():
+    for kind, M in [(LOB, 3), (LOB, 5), (RAD, 3)]:
+        u0, h = _smooth_u0(7, 2, 22)
+        u0 = 3.0 * u0
+        cfg = SDCConfig(nu=0.2, fe_kind=O.FE_CUBIC, node_kind=kind, M=M, inner="exact")
+        u, st = sdc_step(u0, 0.05, h, cfg, fixed_sweeps=40)
+        assert st.residual < 1e-13
+        ref = O.collocation_dense(u0, 0.05, 0.2, h, O.FE_CUBIC, kind, M)
+        assert _rel(u, ref) < 1e-12
+
+
+def test_first_sweep_is_backward_euler():
+    # with the spread initial iterate, sweep 1 is implicit Euler across the
+    # substeps (Sec. 2, eq. (3)/(4) with u^0 = u_0 at every node)
+    u0, h = _smooth_u0(15, 2, 23)
+    dt, nu = 0.02, 1.0
+    cfg = SDCConfig(nu=nu, node_kind=RAD, M=3, inner="exact")
+    st = sdc_begin(u0, dt, h, cfg)
+    sdc_sweep(st)
+    tau = np.concatenate([[0.0], O.nodes(RAD, 3)])
+    v = u0.copy()
+    for m in range(3):
+        v = O.solve_shifted_exact(v, dt * (tau[m + 1] - tau[m]) * nu, h)
+        np.testing.assert_allclose(st.U[m + 1], v, atol=1e-13)
+
+
+def test_first_sweep_is_imex_euler():
+    # with f^E = u - u^3 and the spread initial iterate, sweep 1 of eq. (4) is
+    # IMEX Euler: (I - dt_m nu L_h) u_{m+1} = u_m + dt_m f^E(u_m)
+    u0, h = _smooth_u0(15, 2, 31)
+    u0 = 4.0 * u0
+    dt, nu = 0.05, 0.3
+    for kind, M in [(LOB, 5), (RAD, 3)]:
+        cfg = SDCConfig(nu=nu, fe_kind=O.FE_CUBIC, node_kind=kind, M=M, inner="exact")
+        st = sdc_begin(u0, dt, h, cfg)
+        sdc_sweep(st)
+        tau = np.concatenate([[0.0], O.nodes(kind, M)])
+        v = u0.copy()
+        for m in range(M):
+            dtm = dt * (tau[m + 1] - tau[m])
+            v = O.solve_shifted_exact(v + dtm * (v - v ** 3), dtm * nu, h)
+            np.testing.assert_allclose(st.U[m + 1], v, atol=1e-13)
+
+
+def test_heat_matches_continuum_decay():
+    # Sec. 4.1: u = exp(-2 pi^2 nu t) sin(pi x) sin(pi y); the discrete result
+    # differs by the O(h^2) space and O(dt^{2M-2}) time errors only
+    n, nu, dt = 63, 1.0, 1e-3
+    x, h = _grid(n)
+    u0 = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    cfg = SDCConfig(nu=nu, node_kind=LOB, M=3, vcycles=2, tol=5e-12)
+    u, st = sdc_step(u0, dt, h, cfg)
+    assert st.status == "ok"
+    exact = math.exp(-2 * math.pi ** 2 * nu * dt) * u0
+    # the discrete eigenvalue -(8/h^2) sin^2(pi h/2) differs from -2 pi^2 by a
+    # relative (pi h)^2 / 12, so the decay factor is off by ~2 pi^2 nu dt (pi h)^2 / 12;
+    # the time error of Lobatto M = 3 (order 4) at dt = 1e-3 is far below that
+    spatial = 2 * math.pi ** 2 * nu * dt * (math.pi * h) ** 2 / 12
+    err = np.max(np.abs(u - exact))
+    assert 0.95 * spatial < err < 1.05 * spatial
+
+
+# ---- ISDC (L V-cycles) and classical SDC (cycle to tolerance) ----
+
+@pytest.mark.parametrize("d,n,kind,M,nu,dt", [(1, 127, LOB, 3, 1.0, 0.01), (2, 63, LOB, 5, 0.1, 1e-3),
+                                             (3, 15, RAD, 3, 1.0, 1e-3)])
+def test_isdc_converges_to_collocation(d, n, kind, M, nu, dt):
+    u0, h = _smooth_u0(n, d, 24)
+    cfg = SDCConfig(nu=nu, node_kind=kind, M=M, vcycles=2, tol=1e-12)
+    u, st = sdc_step(u0, dt, h, cfg)
+    assert st.status == "ok"
+    assert _rel(u, O.collocation_heat_modal(u0, dt, nu, h, kind, M)) < 1e-9
+    # Sec. 3: exactly L cycles per implicit solve, (M-1) solves per sweep for
+    # Gauss-Lobatto (tau_1 = 0), M for right Gauss-Radau
+    nsolve = M - 1 if kind == LOB else M
+    assert st.vcycles == st.sweeps * nsolve * 2
+
+
+def test_classical_sdc_reproduces_exact_iterates():
+    u0, h = _smooth_u0(31, 2, 25)
+    base = dict(nu=1.0, node_kind=LOB, M=3, tol=1e-12)
+    ue, se = sdc_step(u0, 0.01, h, SDCConfig(inner="exact", **base), fixed_sweeps=4)
+    uc, sc = sdc_step(u0, 0.01, h, SDCConfig(inner="mg", vcycles=0, inner_tol=1e-15, **base),
+                      fixed_sweeps=4)
+    assert _rel(uc, ue) < 1e-13
+    assert sc.vcycles > 4 * 2 * 2  # needs more than two cycles per solve
+
+
+def test_early_exit_counts_fewer_cycles():
+    u0, h = _smooth_u0(31, 2, 26)
+    base = dict(nu=1.0, node_kind=LOB, M=3, vcycles=2, tol=1e-10)
+    _, full = sdc_step(u0, 1e-3, h, SDCConfig(**base))
+    _, early = sdc_step(u0, 1e-3, h, SDCConfig(early_exit=True, inner_tol=1e-10, **base))
+    assert early.vcycles < full.vcycles
+    assert early.vcycles <= early.sweeps * 2 * 2
+
+
+def test_mixed_precision_reaches_collocation():
+    # float32 V-cycles on the correction equation, float64 outer iteration
+    u0, h = _smooth_u0(63, 2, 27)
+    cfg = SDCConfig(nu=1.0, node_kind=LOB, M=3, vcycles=2, tol=1e-10, precision=PREC_MIXED)
+    u, st = sdc_step(u0, 1e-3, h, cfg)
+    assert st.status == "ok"
+    assert _rel(u, O.collocation_heat_modal(u0, 1e-3, 1.0, h, LOB, 3)) < 1e-8
+
+
+def test_mixed_precision_cubic_reaches_newton_collocation():
+    u0, h = _smooth_u0(15, 2, 28)
+    u0 = 3.0 * u0
+    cfg = SDCConfig(nu=0.3, fe_kind=O.FE_CUBIC, node_kind=LOB, M=5, vcycles=2, tol=1e-11,
+                    precision=PREC_MIXED)
+    u, st = sdc_step(u0, 0.01, h, cfg)
+    assert st.status == "ok"
+    ref = O.collocation_dense(u0, 0.01, 0.3, h, O.FE_CUBIC, LOB, 5)
+    assert _rel(u, ref) < 1e-8
+
+
+# ---- residual definition ----
+
+def test_residual_zero_at_collocation_and_sees_perturbation():
+    n = 7
+    u0, h = _smooth_u0(n, 2, 29)
+    dt, nu = 0.02, 0.5
+    cfg = SDCConfig(nu=nu, node_kind=LOB, M=3, inner="exact")
+    st = sdc_begin(u0, dt, h, cfg)
+    # put the collocation node values (modal solve per node) into the state
+    from scipy.fft import dstn, idstn
+    tau = O.nodes(LOB, 3)
+    Q = O.qmatrix(LOB, 3)
+    lam = O.laplacian_eigenvalues(n, 2, h)
+    c0 = dstn(u0, type=1, norm="ortho")
+    Z = (dt * nu * lam).reshape(-1)
+    A = np.eye(3)[None] - Z[:, None, None] * Q[None]
+    U = np.linalg.solve(A, np.ones((Z.size, 3, 1)))[:, :, 0]
+    for m in range(3):
+        st.U[m + 1] = idstn(c0 * U[:, m].reshape(n, n), type=1, norm="ortho")
+        st.F[m + 1] = nu * O.laplacian(st.U[m + 1], h)
+    assert sdc_residual(st) < 1e-14
+    st.U[3] = st.U[3].copy()
+    st.U[3][2, 5] += 3e-7
+    assert abs(sdc_residual(st) - 3e-7) < 1e-13
+
+
+def test_residual_nan_propagates():
+    u0, h = _smooth_u0(7, 1, 30)
+    u0[3] = np.nan
+    _, st = sdc_step(u0, 0.01, h, SDCConfig(nu=1.0, M=3, vcycles=2, tol=1e-10))
+    assert st.status == "diverged"
+
+
+# ---- Sec. 4.3 ablation: the warm start is what makes two cycles enough ----
+
+@pytest.mark.parametrize("guess", [GUESS_ZERO, GUESS_PREV_NODE])
+def test_ablation_bad_guess_isdc_stagnates(guess):
+    n = 63
+    x, h = _grid(n)
+    u0 = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    base = dict(nu=10.0, node_kind=LOB, M=3, tol=5e-8, max_sweeps=40)
+    _, good = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=2, **base))
+    assert good.status == "ok"
+    _, bad = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=2, guess=guess, **base))
+    assert bad.status == "not_converged"
+    # the residual stalls instead of decaying
+    assert min(bad.residual_hist[-10:]) > 0.3 * max(bad.residual_hist[-10:])
+    # classical SDC with the same bad guess still converges, with more cycles
+    _, sdc_good = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=0, inner_tol=5e-9, **base))
+    _, sdc_bad = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=0, inner_tol=5e-9, guess=guess, **base))
+    assert sdc_bad.status == "ok"
+    assert sdc_bad.vcycles > sdc_good.vcycles
+
+
+# ---- Table 1 (Sec. 4.2) and the setup of Sec. 4.1 ----
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return list(csv.DictReader(line for line in fh if not line.startswith("#")))
+
+
+def test_table1_arithmetic_and_count_reading():
+    rows = _rows("table1.csv")
+    assert len(rows) == 18
+    for r in rows:
+        sdc, isdc = int(r["sdc_cycles"]), int(r["isdc_cycles"])
+        M, ks = int(r["M"]), int(r["isdc_sweeps"])
+        # printed savings = 1 - ISDC/SDC, rounded half up (28/32 -> 12.5 -> 13)
+        assert math.floor(100 * (1 - isdc / sdc) + 0.5) == int(r["savings_pct"])
+        # L = 2 cycles per solve and M-1 solves per sweep bound the ISDC count
+        assert isdc <= ks * (M - 1) * 2
+        assert int(r["isdc_sweeps"]) >= int(r["sdc_sweeps"])
+    # the stiff rows use exactly K~ (M - 1) L cycles -- only possible if the
+    # number of implicit solves per sweep is M - 1 (Gauss-Lobatto, tau_1 = 0)
+    exact = [r for r in rows if int(r["isdc_cycles"]) == int(r["isdc_sweeps"]) * (int(r["M"]) - 1) * 2]
+    assert {(r["problem"], r["nu"], r["M"]) for r in exact} >= {
+        ("heat", "10", "3"), ("heat", "10", "5"), ("heat", "100", "3"), ("heat", "100", "5"),
+        ("burgers", "10", "3")}
+
+
+def test_cfl_reading_h_is_one_over_64():
+    for r in _rows("cfl.csv"):
+        cfl = float(r["nu"]) * 1e-3 / (1 / 64) ** 2
+        assert abs(cfl - float(r["cfl"])) / float(r["cfl"]) < 0.01
+
+
+@pytest.mark.slow
+def test_isdc_saves_cycles_on_stiff_heat():
+    # trend of Table 1(a): for a stiff heat problem ISDC needs at least as many
+    # sweeps as classical SDC but fewer V-cycles (absolute counts are not
+    # comparable: different stencil and multigrid components)
+    n = 63
+    x, h = _grid(n)
+    u0 = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    base = dict(nu=10.0, node_kind=LOB, M=3, tol=5e-8)
+    _, sdc = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=0, inner_tol=5e-9, **base))
+    _, isdc = sdc_step(u0, 1e-3, h, SDCConfig(vcycles=2, early_exit=True, inner_tol=5e-9, **base))
+    assert sdc.status == "ok" and isdc.status == "ok"
+    assert isdc.sweeps >= sdc.sweeps
+    assert isdc.vcycles < sdc.vcycles
