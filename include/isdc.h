@@ -1,0 +1,195 @@
+/*
+ * isdc.h -- C ABI of libisdc, an MI355X (gfx950) implementation of inexact
+ * spectral deferred corrections (ISDC; Speck, Ruprecht, Minion, Emmett and
+ * Krause, "Inexact spectral deferred corrections").
+ *
+ * Problem (Sec. 2, eq. (1)):  u' = f(u) = f^I(u) + f^E(u) on [0,1]^d,
+ *   f^I(u) = nu * L_h u  -- the (2d+1)-point second-order Laplacian on the
+ *                           n^d interior points x_i = (i+1) h, h = 1/(n+1),
+ *                           homogeneous Dirichlet boundary (Sec. 3: the
+ *                           linearly implicit case f^I = A u);
+ *   f^E(u) = 0 (heat equation, Sec. 4.1) or u - u^3 (reaction-diffusion).
+ * One time step of length dt runs semi-implicit SDC sweeps (eq. (4)) over M
+ * collocation nodes; every implicit Euler system (I - dt_m nu L_h) u = rhs is
+ * solved only approximately by L geometric-multigrid V-cycles warm-started
+ * from the previous sweep (Sec. 3, Sec. 4.3), and sweeps continue until the
+ * max-norm SDC residual (Sec. 3) is below a tolerance.
+ *
+ * Conventions shared by every entry point:
+ *  - Grid arrays are dense, row-major n^d arrays of the interior points with
+ *    the x index fastest (numpy C order of shape (n,)*d).  No ghost points.
+ *  - Device pointers (prefix d_) point to memory on the current HIP device,
+ *    allocated and owned by the caller; the library never allocates or frees
+ *    device memory.  Host pointers (prefix h_) are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it; entry points that must read a result back
+ *    say so and synchronise that stream.
+ *  - Every function returns an isdc_status (0 = success).  On failure a
+ *    message is available from isdc_last_error() (per thread).  Arguments are
+ *    validated before any device work is enqueued; an invalid argument leaves
+ *    device memory untouched.  No C++ exception crosses this interface.
+ *  - A plan is not thread safe: calls on one plan must not overlap.
+ */
+#ifndef ISDC_H
+#define ISDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ISDC_OK = 0,
+    ISDC_E_INVAL = -1,          /* invalid argument (nothing was enqueued)              */
+    ISDC_E_WORKSPACE = -2,      /* workspace too small or misaligned                    */
+    ISDC_E_HIP = -3,            /* a HIP runtime call failed                            */
+    ISDC_E_NOT_CONVERGED = -4,  /* max_sweeps reached; the last iterate was written     */
+    ISDC_E_DIVERGED = -5,       /* non-finite SDC residual; the last iterate was written */
+    ISDC_E_UNSUPPORTED = -6     /* valid request this build does not implement          */
+} isdc_status;
+
+/* Collocation node families (Sec. 1; Sec. 2 after eq. (2)). Both end on tau_M = 1. */
+enum { ISDC_NODES_LOBATTO = 0, ISDC_NODES_RADAU_RIGHT = 1 };
+/* Explicit part f^E of eq. (4). */
+enum { ISDC_FE_ZERO = 0, ISDC_FE_CUBIC = 1 };
+/* Multigrid smoother: red-black Gauss-Seidel (red = even index sum, first) or
+ * weighted Jacobi with omega = 2d/(2d+1). */
+enum { ISDC_SMOOTH_RBGS = 0, ISDC_SMOOTH_JACOBI = 1 };
+/* Arithmetic of the V-cycles.  The SDC residual, the S*F quadrature, the
+ * right-hand side and the node update are always float64. */
+enum { ISDC_PREC_FP64 = 0, ISDC_PREC_MIXED = 1 /* float32 V-cycles */ };
+/* Initial guess of each implicit solve (Sec. 4.3): u_{m+1}^k (the method),
+ * or the two ablations the paper reports as failing: zero, or u_m^{k+1}. */
+enum { ISDC_GUESS_PREV_SWEEP = 0, ISDC_GUESS_ZERO = 1, ISDC_GUESS_PREV_NODE = 2 };
+/* Component operators for isdc_mg_op (parity and roofline probes). */
+enum { ISDC_OP_SMOOTH = 0, ISDC_OP_RESTRICT = 1, ISDC_OP_PROLONG = 2, ISDC_OP_COARSE = 3,
+       ISDC_OP_RESIDUAL_NORM = 4 };
+
+#define ISDC_MAX_M 9
+#define ISDC_HIST 128
+
+typedef struct {
+    int32_t dim;      /* d = 1, 2 or 3                                                */
+    int32_t n;        /* interior points per axis, 2^k - 1 with 1 <= k <= 15 (d = 1),  */
+                      /* k <= 12 (d = 2), k <= 10 (d = 3)                             */
+    double nu;        /* diffusion coefficient, finite and >= 0                       */
+    int32_t fe_kind;  /* ISDC_FE_*                                                    */
+} isdc_problem;
+
+typedef struct {
+    int32_t node_kind;   /* ISDC_NODES_*                                                   */
+    int32_t M;           /* collocation nodes: 2..9 (Lobatto), 1..9 (right Radau)          */
+    int32_t vcycles;     /* L V-cycles per implicit solve (Sec. 3); 0 = classical SDC:     */
+                         /* cycle until the inner residual <= inner_tol (at most 100)      */
+    double inner_tol;    /* max-norm inner residual tolerance (classical / early exit)     */
+    int32_t early_exit;  /* 1: stop a solve before L cycles once inner_tol is met          */
+    double sdc_tol;      /* stop once the max-norm SDC residual < sdc_tol (Sec. 3)         */
+    int32_t max_sweeps;  /* 1..100000                                                      */
+    int32_t smoother;    /* ISDC_SMOOTH_*                                                  */
+    int32_t nu_pre;      /* pre-smoothing steps  (0..8)                                    */
+    int32_t nu_post;     /* post-smoothing steps (0..8), nu_pre + nu_post >= 1             */
+    int32_t precision;   /* ISDC_PREC_*                                                    */
+    int32_t guess;       /* ISDC_GUESS_*                                                   */
+} isdc_params;
+
+typedef struct {
+    int32_t sweeps;                    /* sweeps made in the last step (K~ of Sec. 3)     */
+    int32_t hist_len;                  /* entries of residual_hist in use                 */
+    int64_t vcycles;                   /* V-cycles over all implicit solves of the step   */
+    double residual;                   /* last SDC residual                               */
+    double residual_hist[ISDC_HIST];   /* residual after sweep 1, 2, ... (first 128)      */
+} isdc_stats;
+
+typedef struct isdc_plan isdc_plan;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int isdc_version(void);
+
+/* sizeof(isdc_problem), sizeof(isdc_params), sizeof(isdc_stats) as compiled
+ * into the library, so that bindings can check their mirrors of the structs.
+ * Host only; any pointer may be NULL. */
+int isdc_abi_sizes(size_t* problem, size_t* params, size_t* stats);
+
+/* Message of the last non-OK return on the calling thread ("" if none). */
+const char* isdc_last_error(void);
+
+/* Fill *p with the defaults: Lobatto, M = 3, L = 2, inner_tol = 1e-10,
+ * early_exit = 0, sdc_tol = 1e-10, max_sweeps = 100, RB-GS V(1,1), FP64,
+ * warm start from the previous sweep.  Host only. */
+int isdc_default_params(isdc_params* p);
+
+/* Collocation tables (Sec. 2, eq. (1)-(2)), host only, float64:
+ *   h_tau[j]      = tau_{j+1}, j = 0..M-1, nodes on [0, 1];
+ *   h_Q[m*M + j]  = q_{m+1,j+1} = integral over [0, tau_{m+1}] of the Lagrange
+ *                   polynomial l_{j+1} on tau_1..tau_M (may be NULL);
+ *   h_S[m*M + j]  = s_{m,j+1} = q_{m+1,j+1} - q_{m,j+1} with q_0 = 0: the
+ *                   node-to-node weights of eq. (2), m = 0..M-1 (may be NULL).
+ * Arrays are owned by the caller (M, M*M, M*M doubles). */
+int isdc_tables(int32_t node_kind, int32_t M, double* h_tau, double* h_Q, double* h_S);
+
+/* Bytes of device workspace a plan for (prob, par) needs (256-byte aligned
+ * start required).  Host only. */
+int isdc_workspace_bytes(const isdc_problem* prob, const isdc_params* par, size_t* out_bytes);
+
+/* Create a plan over caller-owned device workspace d_workspace of `bytes`
+ * bytes (at least isdc_workspace_bytes; 256-byte aligned).  The plan keeps
+ * pointers into the workspace, which must outlive it.  Host only: no device
+ * work is enqueued.  The plan binds to the HIP device current at its first
+ * device call. */
+int isdc_create(const isdc_problem* prob, const isdc_params* par, void* d_workspace,
+                size_t bytes, isdc_plan** out_plan);
+
+/* Destroy a plan (NULL is ignored).  Does not free the workspace. */
+void isdc_destroy(isdc_plan* plan);
+
+/* One ISDC time step (Sec. 2-3): d_u holds u_n (n^d float64) on entry and
+ * u_{n+1} = u_M on return.  Sweeps run until the SDC residual < sdc_tol or
+ * max_sweeps is reached.  Synchronises `stream` once per sweep to read the
+ * 8-byte residual.  Returns ISDC_E_NOT_CONVERGED or ISDC_E_DIVERGED with the
+ * last iterate in d_u and *out (may be NULL) filled. */
+int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats* out);
+
+/* The pieces of isdc_step, for callers that drive sweeps themselves:
+ * isdc_begin sets the initial iterate u_j^0 = u_0 at every node and computes
+ * S*F(u^0).  d_u0 must stay valid and unchanged until isdc_end.
+ * isdc_sweep makes one sweep of eq. (4) and writes the new SDC residual to
+ * *h_residual (synchronises `stream`).  isdc_end copies u_M to d_u_out (which
+ * may be d_u0). */
+int isdc_begin(isdc_plan* plan, const double* d_u0, double dt, void* stream);
+int isdc_sweep(isdc_plan* plan, void* stream, double* h_residual);
+int isdc_end(isdc_plan* plan, double* d_u_out, void* stream);
+
+/* Copy the current iterate at node j (1..M; 0 = u_0) to d_out (n^d float64). */
+int isdc_node_values(isdc_plan* plan, int32_t j, double* d_out, void* stream);
+
+/* Counters of the current / last step (sweeps, V-cycles, residual history). */
+int isdc_get_stats(const isdc_plan* plan, isdc_stats* out);
+
+/* `ncycles` V(nu_pre, nu_post)-cycles (the inner solver of Sec. 3) on
+ * (I - c L_h) u = rhs, starting from the iterate in d_u and overwriting it.
+ * precision selects float64 (ISDC_PREC_FP64: d_rhs, d_u are double*) or
+ * float32 (ISDC_PREC_MIXED: float*).  c >= 0 is dt_m * nu.  If h_res_inf is
+ * not NULL, max|rhs - (I - c L_h) u| after the cycles is written there and
+ * `stream` is synchronised. */
+int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs, void* d_u,
+                int32_t ncycles, void* stream, double* h_res_inf);
+
+/* One multigrid component on level `level` (0 = finest, n_l = 2^(k-l) - 1),
+ * for parity tests and kernel probes; precision as in isdc_vcycle.
+ *   ISDC_OP_SMOOTH:        d_out <- one smoothing step of d_b on (I - c L) x = d_a
+ *                          (d_out may equal d_b; d_a = rhs, d_b = iterate)
+ *   ISDC_OP_RESTRICT:      d_out (level+1) <- full weighting of d_a - (I - c L) d_b
+ *   ISDC_OP_PROLONG:       d_out (level)  += linear interpolation of d_a (level+1)
+ *   ISDC_OP_COARSE:        d_out <- one V-cycle from zero for rhs d_a on this level
+ *   ISDC_OP_RESIDUAL_NORM: *h_scalar <- max|d_a - (I - c L) d_b| (synchronises)
+ * Unused pointers may be NULL. */
+int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t precision,
+               const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISDC_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) implementation of inexact spectral deferred corrections.
+
+The HIP library libisdc.so (C ABI in include/isdc.h) does all the work; this
+package is a thin binding over it.  The library is loaded on first use and
+its absence is an error.
+"""
+from ._capi import (  # noqa: F401
+    ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, SMOOTH_RBGS, SMOOTH_JACOBI,
+    PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
+    OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, load,
+)
+
+
+def __getattr__(name):
+    # the torch-based binding is imported lazily so that the C-ABI checks and the
+    # input generators work without touching a GPU
+    if name in ("Plan", "StepStats", "tables", "make_params", "make_problem", "workspace_bytes"):
+        from . import isdc
+        return getattr(isdc, name)
+    raise AttributeError(name)

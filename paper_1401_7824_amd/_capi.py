@@ -1,0 +1,98 @@
+"""ctypes declarations of the libisdc C ABI (include/isdc.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libisdc.so")
+
+# status codes
+OK, E_INVAL, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {OK: "ok", E_INVAL: "invalid", E_WORKSPACE: "workspace", E_HIP: "hip",
+                E_NOT_CONVERGED: "not_converged", E_DIVERGED: "diverged", E_UNSUPPORTED: "unsupported"}
+NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
+FE_ZERO, FE_CUBIC = 0, 1
+SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
+OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM = 0, 1, 2, 3, 4
+MAX_M = 9
+HIST = 128
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("fe_kind", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("node_kind", C.c_int32), ("M", C.c_int32), ("vcycles", C.c_int32),
+                ("inner_tol", C.c_double), ("early_exit", C.c_int32), ("sdc_tol", C.c_double),
+                ("max_sweeps", C.c_int32), ("smoother", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("hist_len", C.c_int32), ("vcycles", C.c_int64),
+                ("residual", C.c_double), ("residual_hist", C.c_double * HIST)]
+
+
+# (name, restype, argtypes) for every function declared in include/isdc.h
+_VP, _DP, _SZP = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_size_t)
+SIGNATURES = [
+    ("isdc_version", C.c_int, []),
+    ("isdc_abi_sizes", C.c_int, [_SZP, _SZP, _SZP]),
+    ("isdc_last_error", C.c_char_p, []),
+    ("isdc_default_params", C.c_int, [C.POINTER(Params)]),
+    ("isdc_tables", C.c_int, [C.c_int32, C.c_int32, _DP, _DP, _DP]),
+    ("isdc_workspace_bytes", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _SZP]),
+    ("isdc_create", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)]),
+    ("isdc_destroy", None, [_VP]),
+    ("isdc_step", C.c_int, [_VP, _VP, C.c_double, _VP, C.POINTER(Stats)]),
+    ("isdc_begin", C.c_int, [_VP, _VP, C.c_double, _VP]),
+    ("isdc_sweep", C.c_int, [_VP, _VP, _DP]),
+    ("isdc_end", C.c_int, [_VP, _VP, _VP]),
+    ("isdc_node_values", C.c_int, [_VP, C.c_int32, _VP, _VP]),
+    ("isdc_get_stats", C.c_int, [_VP, C.POINTER(Stats)]),
+    ("isdc_vcycle", C.c_int, [_VP, C.c_double, C.c_int32, _VP, _VP, C.c_int32, _VP, _DP]),
+    ("isdc_mg_op", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _DP]),
+]
+
+_lib = None
+
+
+class ISDCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libisdc.so (cached).  Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1401_7824_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    sizes = [C.c_size_t() for _ in range(3)]
+    lib.isdc_abi_sizes(*[C.byref(s) for s in sizes])
+    mine = (C.sizeof(Problem), C.sizeof(Params), C.sizeof(Stats))
+    if tuple(s.value for s in sizes) != mine:
+        raise RuntimeError(f"struct layout mismatch: library {[s.value for s in sizes]}, binding {mine}")
+    _lib = lib
+    return lib
+
+
+def check(rc, allow=()):
+    """Raise ISDCError unless rc is OK or listed in `allow`; returns rc."""
+    if rc != OK and rc not in allow:
+        raise ISDCError(rc, load().isdc_last_error().decode())
+    return rc

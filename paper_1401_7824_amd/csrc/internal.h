@@ -1,0 +1,120 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/isdc.h"
+#include "tables.h"
+
+namespace isdc {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// ---------------------------------------------------------------- multigrid launchers
+// Coefficients of A_l = I - c L_{h_l} on one level: a = c / h_l^2,
+// diag = 1 + 2 d a, invdiag = 1 / diag, w = Jacobi weight.
+template <typename T>
+struct Coef {
+    T a, diag, invdiag, w;
+};
+
+struct MGConfig {
+    int d;
+    int smoother;  // ISDC_SMOOTH_*
+    int nu_pre, nu_post;
+    double omega;  // Jacobi weight
+};
+
+template <typename T>
+Coef<T> make_coef(double c, double h, int d, double omega);
+
+// One smoothing step.  RB-GS works in place on `u` (u_in is ignored unless
+// zero_guess is false and u_in != u, in which case it is copied first by the
+// caller); Jacobi writes u_out from u_in.  zero_guess: the current iterate is
+// identically zero and is not read.
+template <typename T>
+hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zero_guess,
+                         const T* rhs, const T* u_in, T* u_out, hipStream_t s);
+
+// rc = full weighting of (rhs - A u) on the fine level with n points per axis.
+template <typename T>
+hipError_t launch_restrict(int d, int n, const Coef<T>& co, const T* rhs, const T* u, T* rc,
+                           hipStream_t s);
+
+// u += linear interpolation of ec (fine level n points per axis).
+template <typename T>
+hipError_t launch_prolong(int d, int n, const T* ec, T* u, hipStream_t s);
+
+// One complete V-cycle on a small level (n <= tail_max_n(d)) and every level
+// below it, in a single workgroup.  zero_guess: start from e = 0, otherwise
+// from the iterate in e.
+template <typename T>
+hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero_guess, const T* rhs, T* e,
+                       hipStream_t s);
+int tail_max_n(int d);
+
+// partial[b] = max |rhs - A u| over the points of block b; returns the block
+// count in *nblocks (<= kReduceBlocks).
+constexpr int kReduceBlocks = 1024;
+template <typename T>
+hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T* u,
+                          double* partial, int* nblocks, hipStream_t s);
+
+// out[0] = NaN-propagating max of partial[0..nblocks).
+hipError_t launch_reduce_max(const double* partial, int nblocks, double* out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t count, T value, hipStream_t s);
+
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, size_t count, hipStream_t s);
+
+// ---------------------------------------------------------------- SDC launchers
+struct QuadArgs {
+    const double* u[ISDC_MAX_M + 1];    // u[0] = u_0, u[j] = node j (j = 1..M)
+    double* sf[ISDC_MAX_M];             // S*F for substep m (NULL: not written)
+    double dtS[ISDC_MAX_M * ISDC_MAX_M];  // dt * s_{m,j}
+    double dtQ[ISDC_MAX_M * ISDC_MAX_M];  // dt * q_{m,j}
+    double nu_h2;                       // nu / h^2
+    int M;
+    int n;
+    int fe;
+};
+
+// For every point: f_j = nu L_h u_j + f^E(u_j); sf[m] = sum_j dt s_{m,j} f_j;
+// partial[b] = max over the block of |u_0 + sum_j dt q_{m,j} f_j - u_m|.
+hipError_t launch_quad_residual(int d, const QuadArgs& qa, double* partial, int* nblocks,
+                                hipStream_t s);
+
+struct RhsArgs {
+    const double* um_new;  // u_m^{k+1}
+    const double* um_old;  // u_m^k
+    const double* up_old;  // u_{m+1}^k
+    const double* sf;      // S_m^{m+1} F(u^k)
+    double dtm;            // dt_m
+    double c;              // dt_m nu
+    double nu_h2;          // nu / h^2
+    int n;
+    int fe;
+    int guess;             // ISDC_GUESS_*
+};
+
+// r = rhs - (I - c L_h) g for the right-hand side of eq. (4) and the guess g.
+template <typename T>
+hipError_t launch_euler_rhs(int d, const RhsArgs& ra, T* r, hipStream_t s);
+
+// u_out = g + e with g = u_{m+1}^k (PREV_SWEEP), 0 (ZERO) or u_m^{k+1} (PREV_NODE).
+template <typename T>
+hipError_t launch_node_update(size_t N, int guess, const double* up_old, const double* um_new,
+                              const T* e, double* u_out, hipStream_t s);
+
+}  // namespace isdc

@@ -1,0 +1,521 @@
+// Geometric multigrid kernels for A_l = I - c L_{h_l} (Sec. 3: the implicit
+// Euler systems of eq. (4) are solved with spatial multigrid; ISDC uses a
+// fixed small number of V-cycles).
+//
+// Layout: dense n^d arrays of interior points, x fastest; ghosts are implicit
+// zeros (homogeneous Dirichlet).  Grid of a stencil launch: blockDim = 256
+// along x, gridDim = (ceil(points-per-row / 256), rows, planes).
+//
+// Components (the paper leaves them open; these are the textbook choices):
+//   smoothers  -- red-black Gauss-Seidel (red = even index sum, updated first)
+//                 or weighted Jacobi;
+//   restriction -- full weighting (1/4, 1/2, 1/4 per axis) of the residual;
+//   prolongation -- (bi/tri)linear interpolation added to the iterate;
+//   coarse tail  -- all levels below a size limit in one workgroup's LDS, down
+//                   to the exact one-point solve.
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+#include "internal.h"
+
+namespace isdc {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int D>
+__device__ __forceinline__ void coords(int n, int& x, int& y, int& z, int per_row_thread) {
+    x = per_row_thread;
+    y = (D >= 2) ? (int)blockIdx.y : 0;
+    z = (D == 3) ? (int)blockIdx.z : 0;
+}
+
+template <int D>
+__device__ __forceinline__ size_t lin(int n, int x, int y, int z) {
+    if (D == 1) return (size_t)x;
+    if (D == 2) return (size_t)y * n + x;
+    return ((size_t)z * n + y) * n + x;
+}
+
+// Sum of the 2d neighbours of point (x,y,z) with zero ghosts.
+template <typename T, int D>
+__device__ __forceinline__ T nbsum(const T* __restrict__ u, int n, int x, int y, int z, size_t i) {
+    T s = T(0);
+    if (x > 0) s += u[i - 1];
+    if (x < n - 1) s += u[i + 1];
+    if (D >= 2) {
+        if (y > 0) s += u[i - n];
+        if (y < n - 1) s += u[i + n];
+    }
+    if (D == 3) {
+        size_t nn = (size_t)n * n;
+        if (z > 0) s += u[i - nn];
+        if (z < n - 1) s += u[i + nn];
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------- smoothers
+
+template <typename T, int D, bool ZERO>
+__global__ void __launch_bounds__(kBlock)
+k_jacobi(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ out, int n, T a, T diag,
+         T invdiag, T w) {
+    int x, y, z;
+    coords<D>(n, x, y, z, blockIdx.x * kBlock + threadIdx.x);
+    if (x >= n) return;
+    size_t i = lin<D>(n, x, y, z);
+    T r = rhs[i];
+    if (ZERO) {
+        out[i] = w * (r * invdiag);
+        return;
+    }
+    T c = u[i];
+    T Au = diag * c - a * nbsum<T, D>(u, n, x, y, z, i);
+    out[i] = c + w * ((r - Au) * invdiag);
+}
+
+// Half of a red-black Gauss-Seidel step, in place: the points of `colour`
+// ((x+y+z) % 2 == colour) are set to (rhs + a * neighbour sum) / diag.
+// Thread j of a row owns x = 2j and 2j+1.  ZERO (red pass on a zero iterate):
+// red points get rhs / diag and black points are cleared.
+template <typename T, int D, bool ZERO>
+__global__ void __launch_bounds__(kBlock)
+k_rbgs_half(const T* __restrict__ rhs, T* __restrict__ u, int n, T a, T invdiag, int colour) {
+    int j, y, z;
+    coords<D>(n, j, y, z, blockIdx.x * kBlock + threadIdx.x);
+    int par = (colour + y + z) & 1;
+    int x = 2 * j + par;
+    if (ZERO) {
+        int xo = 2 * j + (par ^ 1);
+        if (xo < n) u[lin<D>(n, xo, y, z)] = T(0);
+        if (x < n) {
+            size_t i = lin<D>(n, x, y, z);
+            u[i] = rhs[i] * invdiag;
+        }
+        return;
+    }
+    if (x >= n) return;
+    size_t i = lin<D>(n, x, y, z);
+    u[i] = (rhs[i] + a * nbsum<T, D>(u, n, x, y, z, i)) * invdiag;
+}
+
+// ---------------------------------------------------------------- transfers
+
+template <typename T, int D>
+__device__ __forceinline__ T residual_at(const T* __restrict__ rhs, const T* __restrict__ u, int n,
+                                         int x, int y, int z, T a, T diag) {
+    size_t i = lin<D>(n, x, y, z);
+    return rhs[i] - (diag * u[i] - a * nbsum<T, D>(u, n, x, y, z, i));
+}
+
+// One thread per coarse point (X,Y,Z); the fine centre is (2X+1, 2Y+1, 2Z+1).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ rc, int n, T a, T diag) {
+    const int nc = (n - 1) / 2;
+    int X, Y, Z;
+    coords<D>(nc, X, Y, Z, blockIdx.x * kBlock + threadIdx.x);
+    if (X >= nc) return;
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+    const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+    const int ylo = (D >= 2) ? -1 : 0, yhi = (D >= 2) ? 1 : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+        for (int oy = ylo; oy <= yhi; ++oy) {
+            T row = T(0);
+            for (int ox = -1; ox <= 1; ++ox) {
+                int x = 2 * X + 1 + ox;
+                int y = (D >= 2) ? 2 * Y + 1 + oy : 0;
+                int z = (D == 3) ? 2 * Z + 1 + oz : 0;
+                row += wt[ox + 1] * residual_at<T, D>(rhs, u, n, x, y, z, a, diag);
+            }
+            T wyz = (D >= 2 ? wt[oy + 1] : T(1)) * (D == 3 ? wt[oz + 1] : T(1));
+            acc += wyz * row;
+        }
+    }
+    rc[lin<D>(nc, X, Y, Z)] = acc;
+}
+
+// Interpolation weights along one axis for fine index i: odd i -> coarse
+// (i-1)/2 with weight 1; even i -> coarse i/2-1 and i/2 with weight 1/2 each
+// (indices outside [0, nc) are boundary zeros).
+__device__ __forceinline__ int interp_taps(int i, int nc, int* idx, float* w) {
+    if (i & 1) {
+        idx[0] = (i - 1) >> 1;
+        w[0] = 1.0f;
+        return 1;
+    }
+    int k = 0;
+    int lo = (i >> 1) - 1, hi = i >> 1;
+    if (lo >= 0) { idx[k] = lo; w[k] = 0.5f; ++k; }
+    if (hi < nc) { idx[k] = hi; w[k] = 0.5f; ++k; }
+    return k;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(const T* __restrict__ ec, T* __restrict__ u, int n) {
+    const int nc = (n - 1) / 2;
+    int x, y, z;
+    coords<D>(n, x, y, z, blockIdx.x * kBlock + threadIdx.x);
+    if (x >= n) return;
+    int ix[2], iy[2] = {0, 0}, iz[2] = {0, 0};
+    float wx[2], wy[2] = {1.f, 1.f}, wz[2] = {1.f, 1.f};
+    int kx = interp_taps(x, nc, ix, wx);
+    int ky = (D >= 2) ? interp_taps(y, nc, iy, wy) : 1;
+    int kz = (D == 3) ? interp_taps(z, nc, iz, wz) : 1;
+    T acc = T(0);
+    for (int c = 0; c < kz; ++c)
+        for (int b = 0; b < ky; ++b)
+            for (int a = 0; a < kx; ++a)
+                acc += T(wx[a]) * T(wy[b]) * T(wz[c]) * ec[lin<D>(nc, ix[a], iy[b], iz[c])];
+    u[lin<D>(n, x, y, z)] += acc;
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+    if (a != a) return a;
+    if (b != b) return b;
+    return a > b ? a : b;
+}
+
+// Block-wide NaN-propagating max; result valid in thread 0.
+__device__ double block_max(double v) {
+    __shared__ double sh[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = nanmax(v, sh[i]);
+    }
+    return v;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_resnorm(const T* __restrict__ rhs, const T* __restrict__ u, int n, T a, T diag, double* partial) {
+    const size_t N = (D == 1) ? (size_t)n : (D == 2 ? (size_t)n * n : (size_t)n * n * n);
+    double m = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+        int x = (int)(i % n);
+        size_t t = i / n;
+        int y = (D >= 2) ? (int)(t % n) : 0;
+        int z = (D == 3) ? (int)(t / n) : 0;
+        T r = residual_at<T, D>(rhs, u, n, x, y, z, a, diag);
+        m = nanmax(m, fabs((double)r));
+    }
+    m = block_max(m);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reduce_max(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) m = nanmax(m, partial[i]);
+    m = block_max(m);
+    if (threadIdx.x == 0) out[0] = m;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, size_t count, T v) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy(const T* __restrict__ s, T* __restrict__ d, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+        d[i] = s[i];
+}
+
+// ---------------------------------------------------------------- coarse tail
+// The whole V-cycle on levels n_t, (n_t-1)/2, ..., 1 inside one workgroup,
+// with every level's iterate and right-hand side in LDS.
+
+constexpr int kTailThreads = 1024;
+template <int D> struct TailCap;
+template <> struct TailCap<1> { static constexpr int nmax = 2047, total = 4096, per_thread = 2; };
+template <> struct TailCap<2> { static constexpr int nmax = 63, total = 5216, per_thread = 4; };
+template <> struct TailCap<3> { static constexpr int nmax = 15, total = 3752, per_thread = 4; };
+
+template <int D>
+__device__ __forceinline__ int npts(int n) {
+    return D == 1 ? n : (D == 2 ? n * n : n * n * n);
+}
+
+template <int D>
+__device__ __forceinline__ void decomp(int i, int n, int& x, int& y, int& z) {
+    x = i % n;
+    int t = i / n;
+    y = (D >= 2) ? t % n : 0;
+    z = (D == 3) ? t / n : 0;
+}
+
+template <typename T, int D>
+__device__ void tail_smooth(T* e, const T* r, int n, T a, T diag, T invdiag, T w, int smoother) {
+    const int N = npts<D>(n);
+    if (smoother == ISDC_SMOOTH_RBGS) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int i = threadIdx.x; i < N; i += kTailThreads) {
+                int x, y, z;
+                decomp<D>(i, n, x, y, z);
+                if (((x + y + z) & 1) != colour) continue;
+                e[i] = (r[i] + a * nbsum<T, D>(e, n, x, y, z, (size_t)i)) * invdiag;
+            }
+            __syncthreads();
+        }
+    } else {
+        T buf[TailCap<D>::per_thread];
+        int k = 0;
+        for (int i = threadIdx.x; i < N; i += kTailThreads, ++k) {
+            int x, y, z;
+            decomp<D>(i, n, x, y, z);
+            T c = e[i];
+            T Au = diag * c - a * nbsum<T, D>(e, n, x, y, z, (size_t)i);
+            buf[k] = c + w * ((r[i] - Au) * invdiag);
+        }
+        __syncthreads();
+        k = 0;
+        for (int i = threadIdx.x; i < N; i += kTailThreads, ++k) e[i] = buf[k];
+        __syncthreads();
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kTailThreads)
+k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, double c, double h_t, int smoother,
+       int nu1, int nu2, double omega, int zero_guess) {
+    __shared__ T le[TailCap<D>::total];
+    __shared__ T lr[TailCap<D>::total];
+    int nlev = 0, off[16], nn[16];
+    {
+        int o = 0, n = n_t;
+        while (true) {
+            off[nlev] = o;
+            nn[nlev] = n;
+            o += npts<D>(n);
+            ++nlev;
+            if (n == 1) break;
+            n = (n - 1) / 2;
+        }
+    }
+    const int N0 = npts<D>(n_t);
+    for (int i = threadIdx.x; i < N0; i += kTailThreads) lr[i] = rhs_g[i];
+    __syncthreads();
+    double h = h_t;
+    // descend
+    for (int l = 0; l < nlev; ++l) {
+        const int n = nn[l];
+        const double ad = c / (h * h);
+        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
+        T* e = le + off[l];
+        T* r = lr + off[l];
+        const int N = npts<D>(n);
+        if (l == 0 && !zero_guess)
+            for (int i = threadIdx.x; i < N; i += kTailThreads) e[i] = e_g[i];
+        else
+            for (int i = threadIdx.x; i < N; i += kTailThreads) e[i] = T(0);
+        __syncthreads();
+        if (n == 1) {
+            if (threadIdx.x == 0) e[0] = r[0] / diag;
+            __syncthreads();
+            break;
+        }
+        for (int k = 0; k < nu1; ++k) tail_smooth<T, D>(e, r, n, a, diag, invdiag, T(omega), smoother);
+        // restrict the residual to level l+1
+        const int nc = (n - 1) / 2;
+        T* rc = lr + off[l + 1];
+        const int Nc = npts<D>(nc);
+        const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+        for (int I = threadIdx.x; I < Nc; I += kTailThreads) {
+            int X, Y, Z;
+            decomp<D>(I, nc, X, Y, Z);
+            T acc = T(0);
+            const int zl = (D == 3) ? -1 : 0, zh = (D == 3) ? 1 : 0;
+            const int yl = (D >= 2) ? -1 : 0, yh = (D >= 2) ? 1 : 0;
+            for (int oz = zl; oz <= zh; ++oz)
+                for (int oy = yl; oy <= yh; ++oy) {
+                    T row = T(0);
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        int x = 2 * X + 1 + ox;
+                        int y = (D >= 2) ? 2 * Y + 1 + oy : 0;
+                        int z = (D == 3) ? 2 * Z + 1 + oz : 0;
+                        int i = (D == 1) ? x : (D == 2 ? y * n + x : (z * n + y) * n + x);
+                        T res = r[i] - (diag * e[i] - a * nbsum<T, D>(e, n, x, y, z, (size_t)i));
+                        row += wt[ox + 1] * res;
+                    }
+                    T wyz = (D >= 2 ? wt[oy + 1] : T(1)) * (D == 3 ? wt[oz + 1] : T(1));
+                    acc += wyz * row;
+                }
+            rc[I] = acc;
+        }
+        __syncthreads();
+        h *= 2.0;
+    }
+    // ascend: levels nlev-2 .. 0
+    for (int l = nlev - 2; l >= 0; --l) {
+        h *= 0.5;
+        const int n = nn[l];
+        const int nc = nn[l + 1];
+        const double ad = c / (h * h);
+        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
+        T* e = le + off[l];
+        T* r = lr + off[l];
+        const T* ec = le + off[l + 1];
+        const int N = npts<D>(n);
+        for (int i = threadIdx.x; i < N; i += kTailThreads) {
+            int x, y, z;
+            decomp<D>(i, n, x, y, z);
+            int ix[2], iy[2] = {0, 0}, iz[2] = {0, 0};
+            float wx[2], wy[2] = {1.f, 1.f}, wz[2] = {1.f, 1.f};
+            int kx = interp_taps(x, nc, ix, wx);
+            int ky = (D >= 2) ? interp_taps(y, nc, iy, wy) : 1;
+            int kz = (D == 3) ? interp_taps(z, nc, iz, wz) : 1;
+            T acc = T(0);
+            for (int cc = 0; cc < kz; ++cc)
+                for (int b = 0; b < ky; ++b)
+                    for (int aa = 0; aa < kx; ++aa) {
+                        int j = (D == 1) ? ix[aa] : (D == 2 ? iy[b] * nc + ix[aa] : (iz[cc] * nc + iy[b]) * nc + ix[aa]);
+                        acc += T(wx[aa]) * T(wy[b]) * T(wz[cc]) * ec[j];
+                    }
+            e[i] += acc;
+        }
+        __syncthreads();
+        for (int k = 0; k < nu2; ++k) tail_smooth<T, D>(e, r, n, a, diag, invdiag, T(omega), smoother);
+    }
+    for (int i = threadIdx.x; i < N0; i += kTailThreads) e_g[i] = le[i];
+}
+
+inline dim3 stencil_grid(int d, int per_row, int n) {
+    return dim3((unsigned)((per_row + kBlock - 1) / kBlock), d >= 2 ? (unsigned)n : 1u, d == 3 ? (unsigned)n : 1u);
+}
+
+inline int reduce_blocks(size_t N) {
+    size_t b = (N + kBlock - 1) / kBlock;
+    return (int)(b < (size_t)kReduceBlocks ? b : (size_t)kReduceBlocks);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+Coef<T> make_coef(double c, double h, int d, double omega) {
+    double a = c / (h * h);
+    double diag = 1.0 + 2.0 * d * a;
+    return Coef<T>{T(a), T(diag), T(1.0 / diag), T(omega)};
+}
+
+#define ISDC_DISPATCH_D(d, ...)                      \
+    switch (d) {                                     \
+        case 1: { constexpr int D = 1; __VA_ARGS__; } break; \
+        case 2: { constexpr int D = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int D = 3; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;        \
+    }
+
+template <typename T>
+hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zero_guess, const T* rhs,
+                         const T* u_in, T* u_out, hipStream_t s) {
+    const int d = cfg.d;
+    if (cfg.smoother == ISDC_SMOOTH_JACOBI) {
+        dim3 g = stencil_grid(d, n, n);
+        ISDC_DISPATCH_D(d, {
+            if (zero_guess)
+                hipLaunchKernelGGL((k_jacobi<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+            else
+                hipLaunchKernelGGL((k_jacobi<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+        });
+        return hipGetLastError();
+    }
+    // RB-GS in place on u_out
+    dim3 g = stencil_grid(d, (n + 1) / 2, n);
+    ISDC_DISPATCH_D(d, {
+        if (zero_guess)
+            hipLaunchKernelGGL((k_rbgs_half<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+        else
+            hipLaunchKernelGGL((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+        hipLaunchKernelGGL((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 1);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(int d, int n, const Coef<T>& co, const T* rhs, const T* u, T* rc, hipStream_t s) {
+    int nc = (n - 1) / 2;
+    dim3 g = stencil_grid(d, nc, nc);
+    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_restrict<T, D>), g, dim3(kBlock), 0, s, rhs, u, rc, n, co.a, co.diag); });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(int d, int n, const T* ec, T* u, hipStream_t s) {
+    dim3 g = stencil_grid(d, n, n);
+    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_prolong<T, D>), g, dim3(kBlock), 0, s, ec, u, n); });
+    return hipGetLastError();
+}
+
+int tail_max_n(int d) {
+    return d == 1 ? TailCap<1>::nmax : (d == 2 ? TailCap<2>::nmax : TailCap<3>::nmax);
+}
+
+template <typename T>
+hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero_guess, const T* rhs, T* e,
+                       hipStream_t s) {
+    if (n > tail_max_n(cfg.d)) return hipErrorInvalidValue;
+    ISDC_DISPATCH_D(cfg.d, {
+        hipLaunchKernelGGL((k_tail<T, D>), dim3(1), dim3(kTailThreads), 0, s, rhs, e, n, c, h, cfg.smoother,
+                           cfg.nu_pre, cfg.nu_post, cfg.omega, zero_guess ? 1 : 0);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T* u, double* partial,
+                          int* nblocks, hipStream_t s) {
+    size_t N = d == 1 ? (size_t)n : (d == 2 ? (size_t)n * n : (size_t)n * n * n);
+    int nb = reduce_blocks(N);
+    *nblocks = nb;
+    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_resnorm<T, D>), dim3(nb), dim3(kBlock), 0, s, rhs, u, n, co.a, co.diag, partial); });
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_max(const double* partial, int nblocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t count, T value, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, size_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
+#define ISDC_INST(T)                                                                                      \
+    template Coef<T> make_coef<T>(double, double, int, double);                                          \
+    template hipError_t launch_smooth<T>(const MGConfig&, int, const Coef<T>&, bool, const T*, const T*, T*, \
+                                         hipStream_t);                                                    \
+    template hipError_t launch_restrict<T>(int, int, const Coef<T>&, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_prolong<T>(int, int, const T*, T*, hipStream_t);                          \
+    template hipError_t launch_tail<T>(const MGConfig&, int, double, double, bool, const T*, T*, hipStream_t); \
+    template hipError_t launch_resnorm<T>(int, int, const Coef<T>&, const T*, const T*, double*, int*,  \
+                                          hipStream_t);                                                   \
+    template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                      \
+    template hipError_t launch_copy<T>(const T*, T*, size_t, hipStream_t);
+
+ISDC_INST(float)
+ISDC_INST(double)
+
+}  // namespace isdc

@@ -1,0 +1,604 @@
+// Host runtime and C ABI of libisdc: plan layout over the caller's device
+// workspace, the V-cycle schedule, the SDC sweep of eq. (4) and the step loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace isdc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw Error{ISDC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
+    } while (0)
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline size_t pow_d(size_t n, int d) { return d == 1 ? n : (d == 2 ? n * n : n * n * n); }
+
+struct Level {
+    int n;
+    double h;
+    size_t N;
+    void* r;
+    void* e;
+    void* e2;  // Jacobi ping-pong partner
+};
+
+}  // namespace
+
+struct isdc_plan {
+    isdc_problem prob;
+    isdc_params par;
+    int d, n;
+    size_t N;
+    double h;
+    int M;
+    double tau[ISDC_MAX_M], Q[ISDC_MAX_M * ISDC_MAX_M], S[ISDC_MAX_M * ISDC_MAX_M];
+    double dtau[ISDC_MAX_M];  // tau_{m+1} - tau_m, tau_0 = 0
+    MGConfig mg;
+    std::vector<Level> lev;
+    int tail;  // index of the level run by the single-workgroup tail kernel
+
+    double* U[2][ISDC_MAX_M + 1];  // node arrays written by sweeps (index 0 unused)
+    double* SF[ISDC_MAX_M];        // S_m^{m+1} F for substep m (NULL if dt_m = 0)
+    double* partial;
+    double* scalars;
+
+    // step state
+    const double* u0 = nullptr;
+    double dt = 0.0;
+    const double* cur[ISDC_MAX_M + 1];  // current iterate per node (0 = u_0)
+    int wbuf = 0;                       // which U table the next sweep writes
+    bool begun = false;
+    isdc_stats stats;
+    double* h_pinned = nullptr;
+};
+
+namespace {
+
+bool valid_n(int d, int n) {
+    if (n < 1 || ((n + 1) & n) != 0) return false;
+    int k = 0;
+    while ((1 << k) - 1 < n) ++k;
+    int kmax = d == 1 ? 15 : (d == 2 ? 12 : 10);
+    return k <= kmax;
+}
+
+void validate(const isdc_problem* pb, const isdc_params* pr) {
+    if (!pb || !pr) fail(ISDC_E_INVAL, "NULL problem or params");
+    if (pb->dim < 1 || pb->dim > 3) fail(ISDC_E_INVAL, "dim must be 1, 2 or 3");
+    if (!valid_n(pb->dim, pb->n)) fail(ISDC_E_INVAL, "n must be 2^k - 1 within the size limit for dim");
+    if (!std::isfinite(pb->nu) || pb->nu < 0) fail(ISDC_E_INVAL, "nu must be finite and >= 0");
+    if (pb->fe_kind != ISDC_FE_ZERO && pb->fe_kind != ISDC_FE_CUBIC) fail(ISDC_E_INVAL, "unknown fe_kind");
+    if (pr->node_kind == ISDC_NODES_LOBATTO) {
+        if (pr->M < 2 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "Gauss-Lobatto needs 2 <= M <= 9");
+    } else if (pr->node_kind == ISDC_NODES_RADAU_RIGHT) {
+        if (pr->M < 1 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "right Gauss-Radau needs 1 <= M <= 9");
+    } else {
+        fail(ISDC_E_INVAL, "unknown node_kind");
+    }
+    if (pr->vcycles < 0 || pr->vcycles > 64) fail(ISDC_E_INVAL, "vcycles must be in 0..64");
+    if (!std::isfinite(pr->inner_tol) || pr->inner_tol < 0) fail(ISDC_E_INVAL, "inner_tol must be finite, >= 0");
+    if (pr->early_exit != 0 && pr->early_exit != 1) fail(ISDC_E_INVAL, "early_exit must be 0 or 1");
+    if (!std::isfinite(pr->sdc_tol) || pr->sdc_tol < 0) fail(ISDC_E_INVAL, "sdc_tol must be finite, >= 0");
+    if (pr->max_sweeps < 1 || pr->max_sweeps > 100000) fail(ISDC_E_INVAL, "max_sweeps must be in 1..100000");
+    if (pr->smoother != ISDC_SMOOTH_RBGS && pr->smoother != ISDC_SMOOTH_JACOBI) fail(ISDC_E_INVAL, "unknown smoother");
+    if (pr->nu_pre < 0 || pr->nu_pre > 8 || pr->nu_post < 0 || pr->nu_post > 8 || pr->nu_pre + pr->nu_post < 1)
+        fail(ISDC_E_INVAL, "nu_pre, nu_post must be in 0..8 with nu_pre + nu_post >= 1");
+    if (pr->precision != ISDC_PREC_FP64 && pr->precision != ISDC_PREC_MIXED) fail(ISDC_E_INVAL, "unknown precision");
+    if (pr->guess < ISDC_GUESS_PREV_SWEEP || pr->guess > ISDC_GUESS_PREV_NODE) fail(ISDC_E_INVAL, "unknown guess");
+}
+
+// Lay the plan's arrays out from `base` (nullptr: sizing only); returns the byte count.
+size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p) {
+    const int d = pb.dim, M = pr.M;
+    const size_t N = pow_d((size_t)pb.n, d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* ptr = base ? (void*)(base + off) : nullptr;
+        off = align_up(off + bytes);
+        return ptr;
+    };
+    double tau[ISDC_MAX_M];
+    tables(pr.node_kind, M, tau, nullptr, nullptr);
+    for (int w = 0; w < 2; ++w)
+        for (int j = 1; j <= M; ++j) {
+            bool alias_u0 = (j == 1 && pr.node_kind == ISDC_NODES_LOBATTO);  // tau_1 = 0: u_1 = u_0
+            void* ptr = alias_u0 ? nullptr : take(N * sizeof(double));
+            if (p) p->U[w][j] = (double*)ptr;
+        }
+    for (int m = 0; m < M; ++m) {
+        bool degenerate = (m == 0 && pr.node_kind == ISDC_NODES_LOBATTO);
+        void* ptr = degenerate ? nullptr : take(N * sizeof(double));
+        if (p) p->SF[m] = (double*)ptr;
+    }
+    // multigrid hierarchy: 8 bytes per entry so either precision fits
+    const int tmax = tail_max_n(d);
+    int n = pb.n;
+    double h = 1.0 / (pb.n + 1);
+    int l = 0;
+    if (p) p->lev.clear();
+    while (true) {
+        Level L{n, h, pow_d((size_t)n, d), nullptr, nullptr, nullptr};
+        bool is_tail = n <= tmax;
+        L.r = take(L.N * sizeof(double));
+        L.e = take(L.N * sizeof(double));
+        if (!is_tail || l == 0) L.e2 = take(L.N * sizeof(double));
+        if (p) {
+            p->lev.push_back(L);
+            if (is_tail) p->tail = l;
+        }
+        if (is_tail) break;
+        n = (n - 1) / 2;
+        h *= 2.0;
+        ++l;
+    }
+    void* part = take(kReduceBlocks * sizeof(double));
+    void* sc = take(16 * sizeof(double));
+    if (p) {
+        p->partial = (double*)part;
+        p->scalars = (double*)sc;
+    }
+    (void)tau;
+    return off;
+}
+
+void ensure_pinned(isdc_plan* p) {
+    if (!p->h_pinned) {
+        void* ptr = nullptr;
+        HIPCHK(hipHostMalloc(&ptr, 64, hipHostMallocDefault));
+        p->h_pinned = (double*)ptr;
+    }
+}
+
+double read_scalar(isdc_plan* p, const double* d_src, hipStream_t s) {
+    ensure_pinned(p);
+    HIPCHK(hipMemcpyAsync(p->h_pinned, d_src, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return p->h_pinned[0];
+}
+
+// ---------------------------------------------------------------- V-cycle schedule
+
+template <typename T>
+void smooth_steps(isdc_plan* p, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs, T*& cur, T*& other,
+                  hipStream_t s) {
+    for (int k = 0; k < nsteps; ++k) {
+        if (p->mg.smoother == ISDC_SMOOTH_RBGS) {
+            HIPCHK(launch_smooth<T>(p->mg, n, co, zero, rhs, cur, cur, s));
+        } else {
+            HIPCHK(launch_smooth<T>(p->mg, n, co, zero, rhs, cur, other, s));
+            std::swap(cur, other);
+        }
+        zero = false;
+    }
+}
+
+// One V-cycle on level l for (I - c L) e = rhs; the result ends in `e`.
+// tmp: scratch of the level's size (Jacobi only).
+template <typename T>
+void vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s) {
+    const Level& L = p->lev[l];
+    if (l == p->tail) {
+        HIPCHK(launch_tail<T>(p->mg, L.n, c, L.h, zero, rhs, e, s));
+        return;
+    }
+    Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
+    T* cur = e;
+    T* other = tmp;
+    smooth_steps<T>(p, p->mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
+    if (zero) {  // no pre-smoothing and a zero iterate
+        HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
+        zero = false;
+    }
+    const Level& C = p->lev[l + 1];
+    HIPCHK(launch_restrict<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
+    vcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
+    smooth_steps<T>(p, p->mg.nu_post, L.n, co, zero, rhs, cur, other, s);
+    if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
+}
+
+template <typename T>
+double resnorm(isdc_plan* p, int l, double c, const T* rhs, const T* u, hipStream_t s) {
+    const Level& L = p->lev[l];
+    Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
+    int nb = 0;
+    HIPCHK(launch_resnorm<T>(p->d, L.n, co, rhs, u, p->partial, &nb, s));
+    HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 1, s));
+    return read_scalar(p, p->scalars + 1, s);
+}
+
+// ---------------------------------------------------------------- SDC sweep
+
+void quad_residual(isdc_plan* p, const double* const* nodes, hipStream_t s) {
+    QuadArgs qa;
+    std::memset(&qa, 0, sizeof(qa));
+    for (int j = 0; j <= p->M; ++j) qa.u[j] = nodes[j];
+    for (int m = 0; m < p->M; ++m) {
+        qa.sf[m] = p->SF[m];
+        for (int j = 0; j < p->M; ++j) {
+            qa.dtS[m * ISDC_MAX_M + j] = p->dt * p->S[m * p->M + j];
+            qa.dtQ[m * ISDC_MAX_M + j] = p->dt * p->Q[m * p->M + j];
+        }
+    }
+    qa.nu_h2 = p->prob.nu / (p->h * p->h);
+    qa.M = p->M;
+    qa.n = p->n;
+    qa.fe = p->prob.fe_kind;
+    int nb = 0;
+    HIPCHK(launch_quad_residual(p->d, qa, p->partial, &nb, s));
+    HIPCHK(launch_reduce_max(p->partial, nb, p->scalars, s));
+}
+
+template <typename T>
+int inner_solve(isdc_plan* p, double c, hipStream_t s) {
+    const Level& L0 = p->lev[0];
+    T* r0 = (T*)L0.r;
+    T* e0 = (T*)L0.e;
+    T* t0 = (T*)L0.e2;
+    const isdc_params& pr = p->par;
+    const bool classical = pr.vcycles == 0;
+    const bool check = classical || pr.early_exit;
+    const int limit = classical ? 100 : pr.vcycles;
+    if (!check) {
+        for (int k = 0; k < limit; ++k) vcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s);
+        return limit;
+    }
+    HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
+    int k = 0;
+    for (; k < limit; ++k) {
+        double res = resnorm<T>(p, 0, c, r0, e0, s);
+        if (res <= pr.inner_tol) break;
+        vcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+    }
+    return k;
+}
+
+template <typename T>
+double sweep_impl(isdc_plan* p, hipStream_t s) {
+    const int M = p->M;
+    double* const* W = p->U[p->wbuf];
+    const double* nw[ISDC_MAX_M + 1];
+    nw[0] = p->u0;
+    for (int j = 1; j <= M; ++j) nw[j] = W[j] ? W[j] : p->u0;  // Lobatto node 1 is u_0
+    const double nu_h2 = p->prob.nu / (p->h * p->h);
+    for (int m = 0; m < M; ++m) {
+        if (p->dtau[m] == 0.0) continue;  // tau_1 = 0 (Lobatto): u_1 = u_0, no solve
+        const double dtm = p->dt * p->dtau[m];
+        RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
+                   p->prob.fe_kind, p->par.guess};
+        HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
+        p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, s);
+        HIPCHK(launch_node_update<T>(p->N, p->par.guess, p->cur[m + 1], nw[m], (const T*)p->lev[0].e,
+                                     (double*)nw[m + 1], s));
+    }
+    for (int j = 0; j <= M; ++j) p->cur[j] = nw[j];
+    p->wbuf ^= 1;
+    quad_residual(p, p->cur, s);
+    double res = read_scalar(p, p->scalars, s);
+    p->stats.sweeps += 1;
+    p->stats.residual = res;
+    if (p->stats.hist_len < ISDC_HIST) p->stats.residual_hist[p->stats.hist_len++] = res;
+    return res;
+}
+
+void begin_impl(isdc_plan* p, const double* d_u0, double dt, hipStream_t s) {
+    if (!d_u0) fail(ISDC_E_INVAL, "d_u0 is NULL");
+    if (!std::isfinite(dt) || dt <= 0) fail(ISDC_E_INVAL, "dt must be finite and > 0");
+    p->u0 = d_u0;
+    p->dt = dt;
+    for (int j = 0; j <= p->M; ++j) p->cur[j] = d_u0;  // spread u_0 to every node
+    p->wbuf = 0;
+    p->begun = true;
+    std::memset(&p->stats, 0, sizeof(p->stats));
+    quad_residual(p, p->cur, s);  // S*F(u^0) for sweep 1
+}
+
+double sweep_any(isdc_plan* p, hipStream_t s) {
+    if (!p->begun) fail(ISDC_E_INVAL, "isdc_sweep before isdc_begin");
+    return p->par.precision == ISDC_PREC_MIXED ? sweep_impl<float>(p, s) : sweep_impl<double>(p, s);
+}
+
+void end_impl(isdc_plan* p, double* d_out, hipStream_t s) {
+    if (!p->begun) fail(ISDC_E_INVAL, "isdc_end before isdc_begin");
+    if (!d_out) fail(ISDC_E_INVAL, "d_u_out is NULL");
+    const double* src = p->cur[p->M];
+    if (src != d_out) HIPCHK(hipMemcpyAsync(d_out, src, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    p->begun = false;
+}
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return ISDC_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return ISDC_E_HIP;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return ISDC_E_HIP;
+    }
+}
+
+void check_plan(const isdc_plan* p) {
+    if (!p) fail(ISDC_E_INVAL, "plan is NULL");
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+int isdc_version(void) { return 100; }
+
+int isdc_abi_sizes(size_t* problem, size_t* params, size_t* stats) {
+    if (problem) *problem = sizeof(isdc_problem);
+    if (params) *params = sizeof(isdc_params);
+    if (stats) *stats = sizeof(isdc_stats);
+    return ISDC_OK;
+}
+
+const char* isdc_last_error(void) { return g_last_error.c_str(); }
+
+int isdc_default_params(isdc_params* p) {
+    return guarded([&] {
+        if (!p) fail(ISDC_E_INVAL, "params is NULL");
+        p->node_kind = ISDC_NODES_LOBATTO;
+        p->M = 3;
+        p->vcycles = 2;
+        p->inner_tol = 1e-10;
+        p->early_exit = 0;
+        p->sdc_tol = 1e-10;
+        p->max_sweeps = 100;
+        p->smoother = ISDC_SMOOTH_RBGS;
+        p->nu_pre = 1;
+        p->nu_post = 1;
+        p->precision = ISDC_PREC_FP64;
+        p->guess = ISDC_GUESS_PREV_SWEEP;
+    });
+}
+
+int isdc_tables(int32_t node_kind, int32_t M, double* h_tau, double* h_Q, double* h_S) {
+    return guarded([&] {
+        if (!tables(node_kind, M, h_tau, h_Q, h_S)) fail(ISDC_E_INVAL, "invalid node_kind or M");
+    });
+}
+
+int isdc_workspace_bytes(const isdc_problem* prob, const isdc_params* par, size_t* out_bytes) {
+    return guarded([&] {
+        validate(prob, par);
+        if (!out_bytes) fail(ISDC_E_INVAL, "out_bytes is NULL");
+        *out_bytes = layout(*prob, *par, nullptr, nullptr);
+    });
+}
+
+int isdc_create(const isdc_problem* prob, const isdc_params* par, void* d_workspace, size_t bytes,
+                isdc_plan** out_plan) {
+    return guarded([&] {
+        validate(prob, par);
+        if (!out_plan) fail(ISDC_E_INVAL, "out_plan is NULL");
+        *out_plan = nullptr;
+        size_t need = layout(*prob, *par, nullptr, nullptr);
+        if (!d_workspace) fail(ISDC_E_WORKSPACE, "workspace is NULL");
+        if (((uintptr_t)d_workspace) % kAlign) fail(ISDC_E_WORKSPACE, "workspace must be 256-byte aligned");
+        if (bytes < need) fail(ISDC_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+        isdc_plan* p = new isdc_plan();
+        p->prob = *prob;
+        p->par = *par;
+        p->d = prob->dim;
+        p->n = prob->n;
+        p->N = pow_d((size_t)prob->n, prob->dim);
+        p->h = 1.0 / (prob->n + 1);
+        p->M = par->M;
+        tables(par->node_kind, par->M, p->tau, p->Q, p->S);
+        double prev = 0.0;
+        for (int m = 0; m < p->M; ++m) {
+            p->dtau[m] = p->tau[m] - prev;
+            prev = p->tau[m];
+        }
+        p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post, 2.0 * p->d / (2.0 * p->d + 1.0)};
+        std::memset(p->U, 0, sizeof(p->U));
+        std::memset(p->SF, 0, sizeof(p->SF));
+        layout(*prob, *par, (char*)d_workspace, p);
+        std::memset(&p->stats, 0, sizeof(p->stats));
+        *out_plan = p;
+    });
+}
+
+void isdc_destroy(isdc_plan* plan) {
+    if (!plan) return;
+    if (plan->h_pinned) (void)hipHostFree(plan->h_pinned);
+    delete plan;
+}
+
+int isdc_begin(isdc_plan* plan, const double* d_u0, double dt, void* stream) {
+    return guarded([&] {
+        check_plan(plan);
+        begin_impl(plan, d_u0, dt, (hipStream_t)stream);
+    });
+}
+
+int isdc_sweep(isdc_plan* plan, void* stream, double* h_residual) {
+    return guarded([&] {
+        check_plan(plan);
+        double r = sweep_any(plan, (hipStream_t)stream);
+        if (h_residual) *h_residual = r;
+    });
+}
+
+int isdc_end(isdc_plan* plan, double* d_u_out, void* stream) {
+    return guarded([&] {
+        check_plan(plan);
+        end_impl(plan, d_u_out, (hipStream_t)stream);
+    });
+}
+
+int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats* out) {
+    int status = ISDC_OK;
+    int rc = guarded([&] {
+        check_plan(plan);
+        if (!d_u) fail(ISDC_E_INVAL, "d_u is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        begin_impl(plan, d_u, dt, s);
+        status = ISDC_E_NOT_CONVERGED;
+        for (int k = 0; k < plan->par.max_sweeps; ++k) {
+            double res = sweep_any(plan, s);
+            if (!std::isfinite(res)) {
+                status = ISDC_E_DIVERGED;
+                break;
+            }
+            if (res < plan->par.sdc_tol) {
+                status = ISDC_OK;
+                break;
+            }
+        }
+        end_impl(plan, d_u, s);
+        if (out) *out = plan->stats;
+    });
+    if (rc != ISDC_OK) return rc;
+    if (status == ISDC_E_NOT_CONVERGED)
+        g_last_error = "SDC residual " + std::to_string(plan->stats.residual) + " not below sdc_tol after max_sweeps";
+    else if (status == ISDC_E_DIVERGED)
+        g_last_error = "non-finite SDC residual";
+    return status;
+}
+
+int isdc_node_values(isdc_plan* plan, int32_t j, double* d_out, void* stream) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!plan->begun) fail(ISDC_E_INVAL, "no step in progress (call isdc_begin first)");
+        if (j < 0 || j > plan->M) fail(ISDC_E_INVAL, "node index out of range");
+        if (!d_out) fail(ISDC_E_INVAL, "d_out is NULL");
+        HIPCHK(hipMemcpyAsync(d_out, plan->cur[j], plan->N * sizeof(double), hipMemcpyDeviceToDevice,
+                              (hipStream_t)stream));
+    });
+}
+
+int isdc_get_stats(const isdc_plan* plan, isdc_stats* out) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!out) fail(ISDC_E_INVAL, "out is NULL");
+        *out = plan->stats;
+    });
+}
+
+int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs, void* d_u, int32_t ncycles,
+                void* stream, double* h_res_inf) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!std::isfinite(c) || c < 0) fail(ISDC_E_INVAL, "c must be finite and >= 0");
+        if (precision != ISDC_PREC_FP64 && precision != ISDC_PREC_MIXED) fail(ISDC_E_INVAL, "unknown precision");
+        if (!d_rhs || !d_u) fail(ISDC_E_INVAL, "NULL rhs or u");
+        if (ncycles < 0) fail(ISDC_E_INVAL, "ncycles must be >= 0");
+        hipStream_t s = (hipStream_t)stream;
+        if (precision == ISDC_PREC_FP64) {
+            for (int k = 0; k < ncycles; ++k)
+                vcycle_rec<double>(plan, 0, c, false, (const double*)d_rhs, (double*)d_u, (double*)plan->lev[0].e2, s);
+            if (h_res_inf) *h_res_inf = resnorm<double>(plan, 0, c, (const double*)d_rhs, (const double*)d_u, s);
+        } else {
+            for (int k = 0; k < ncycles; ++k)
+                vcycle_rec<float>(plan, 0, c, false, (const float*)d_rhs, (float*)d_u, (float*)plan->lev[0].e2, s);
+            if (h_res_inf) *h_res_inf = resnorm<float>(plan, 0, c, (const float*)d_rhs, (const float*)d_u, s);
+        }
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+void mg_op_impl(isdc_plan* p, int op, int level, double c, const void* a, const void* b, void* out, hipStream_t s,
+                double* h_scalar) {
+    const int d = p->d;
+    int n = p->n;
+    double h = p->h;
+    for (int l = 0; l < level; ++l) {
+        n = (n - 1) / 2;
+        h *= 2.0;
+    }
+    const size_t N = pow_d((size_t)n, d);
+    Coef<T> co = make_coef<T>(c, h, d, p->mg.omega);
+    switch (op) {
+        case ISDC_OP_SMOOTH: {
+            if (!a || !b || !out) fail(ISDC_E_INVAL, "SMOOTH needs rhs, iterate and output");
+            if (p->mg.smoother == ISDC_SMOOTH_RBGS) {
+                if (out != b) HIPCHK(launch_copy<T>((const T*)b, (T*)out, N, s));
+                HIPCHK(launch_smooth<T>(p->mg, n, co, false, (const T*)a, (const T*)out, (T*)out, s));
+            } else {
+                if (out == b) fail(ISDC_E_INVAL, "Jacobi SMOOTH needs a separate output array");
+                HIPCHK(launch_smooth<T>(p->mg, n, co, false, (const T*)a, (const T*)b, (T*)out, s));
+            }
+            break;
+        }
+        case ISDC_OP_RESTRICT:
+            if (n < 3) fail(ISDC_E_INVAL, "RESTRICT needs a level with n >= 3");
+            if (!a || !b || !out) fail(ISDC_E_INVAL, "RESTRICT needs rhs, iterate and output");
+            HIPCHK(launch_restrict<T>(d, n, co, (const T*)a, (const T*)b, (T*)out, s));
+            break;
+        case ISDC_OP_PROLONG:
+            if (n < 3) fail(ISDC_E_INVAL, "PROLONG needs a level with n >= 3");
+            if (!a || !out) fail(ISDC_E_INVAL, "PROLONG needs coarse input and output");
+            HIPCHK(launch_prolong<T>(d, n, (const T*)a, (T*)out, s));
+            break;
+        case ISDC_OP_COARSE:
+            if (n > tail_max_n(d)) fail(ISDC_E_INVAL, "COARSE level too large for one workgroup");
+            if (!a || !out) fail(ISDC_E_INVAL, "COARSE needs rhs and output");
+            HIPCHK(launch_tail<T>(p->mg, n, c, h, true, (const T*)a, (T*)out, s));
+            break;
+        case ISDC_OP_RESIDUAL_NORM: {
+            if (!a || !b || !h_scalar) fail(ISDC_E_INVAL, "RESIDUAL_NORM needs rhs, iterate and h_scalar");
+            int nb = 0;
+            HIPCHK(launch_resnorm<T>(d, n, co, (const T*)a, (const T*)b, p->partial, &nb, s));
+            HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 2, s));
+            *h_scalar = read_scalar(p, p->scalars + 2, s);
+            break;
+        }
+        default:
+            fail(ISDC_E_INVAL, "unknown op");
+    }
+}
+
+}  // namespace
+
+extern "C" int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t precision, const void* d_a,
+                          const void* d_b, void* d_out, void* stream, double* h_scalar) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!std::isfinite(c) || c < 0) fail(ISDC_E_INVAL, "c must be finite and >= 0");
+        int nl = 0;
+        for (int n = plan->n; n >= 1; n = (n - 1) / 2) {
+            ++nl;
+            if (n == 1) break;
+        }
+        if (level < 0 || level >= nl) fail(ISDC_E_INVAL, "level out of range");
+        if (precision == ISDC_PREC_FP64)
+            mg_op_impl<double>(plan, op, level, c, d_a, d_b, d_out, (hipStream_t)stream, h_scalar);
+        else if (precision == ISDC_PREC_MIXED)
+            mg_op_impl<float>(plan, op, level, c, d_a, d_b, d_out, (hipStream_t)stream, h_scalar);
+        else
+            fail(ISDC_E_INVAL, "unknown precision");
+    });
+}

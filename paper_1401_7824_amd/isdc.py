@@ -1,0 +1,159 @@
+"""Python binding of libisdc: plans over torch-allocated device memory.
+
+PyTorch provides device memory (the workspace and the grid arrays) and the
+stream; every computation is a kernel of the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _capi as A
+
+
+@dataclass
+class StepStats:
+    status: str
+    sweeps: int
+    vcycles: int
+    residual: float
+    residual_hist: list = field(default_factory=list)
+
+    @classmethod
+    def from_c(cls, st: A.Stats, rc: int) -> "StepStats":
+        return cls(status=A.STATUS_NAMES.get(rc, str(rc)), sweeps=st.sweeps, vcycles=st.vcycles,
+                   residual=st.residual, residual_hist=[st.residual_hist[i] for i in range(st.hist_len)])
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype=None, numel=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"tensor must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"tensor must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_problem(dim, n, nu, fe_kind=A.FE_ZERO) -> A.Problem:
+    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind)
+
+
+def make_params(**kw) -> A.Params:
+    lib = A.load()
+    p = A.Params()
+    A.check(lib.isdc_default_params(C.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, int(v) if isinstance(v, bool) else v)
+    return p
+
+
+def tables(node_kind: int, M: int):
+    """(tau, Q, S) from the library's host-side table generator, as lists."""
+    lib = A.load()
+    tau = (C.c_double * M)()
+    Q = (C.c_double * (M * M))()
+    S = (C.c_double * (M * M))()
+    A.check(lib.isdc_tables(node_kind, M, tau, Q, S))
+    return list(tau), [list(Q[i * M:(i + 1) * M]) for i in range(M)], [list(S[i * M:(i + 1) * M]) for i in range(M)]
+
+
+def workspace_bytes(problem: A.Problem, params: A.Params) -> int:
+    lib = A.load()
+    out = C.c_size_t()
+    A.check(lib.isdc_workspace_bytes(C.byref(problem), C.byref(params), C.byref(out)))
+    return out.value
+
+
+class Plan:
+    """One ISDC problem instance: the C plan plus its torch-owned workspace."""
+
+    def __init__(self, dim: int, n: int, nu: float, fe_kind: int = A.FE_ZERO, device=None, **params):
+        self.lib = A.load()
+        self.problem = make_problem(dim, n, nu, fe_kind)
+        self.params = make_params(**params)
+        self.dim, self.n = dim, n
+        self.N = n ** dim
+        self.shape = (n,) * dim
+        nbytes = workspace_bytes(self.problem, self.params)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        A.check(self.lib.isdc_create(C.byref(self.problem), C.byref(self.params),
+                                     C.c_void_p(self.workspace.data_ptr()), nbytes, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.isdc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- the time step ----
+    def step(self, u: torch.Tensor, dt: float, stream=None) -> StepStats:
+        """One ISDC step in place on u (float64, shape (n,)*d)."""
+        st = A.Stats()
+        rc = self.lib.isdc_step(self._h, _dev_ptr(u, torch.float64, self.N), dt, _stream_handle(stream),
+                                C.byref(st))
+        A.check(rc, allow=(A.E_NOT_CONVERGED, A.E_DIVERGED))
+        return StepStats.from_c(st, rc)
+
+    def begin(self, u0: torch.Tensor, dt: float, stream=None):
+        self._u0 = u0  # must stay alive and unchanged until end()
+        A.check(self.lib.isdc_begin(self._h, _dev_ptr(u0, torch.float64, self.N), dt, _stream_handle(stream)))
+
+    def sweep(self, stream=None) -> float:
+        r = C.c_double()
+        A.check(self.lib.isdc_sweep(self._h, _stream_handle(stream), C.byref(r)))
+        return r.value
+
+    def end(self, out: torch.Tensor, stream=None):
+        A.check(self.lib.isdc_end(self._h, _dev_ptr(out, torch.float64, self.N), _stream_handle(stream)))
+        self._u0 = None
+
+    def node_values(self, j: int, stream=None) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        A.check(self.lib.isdc_node_values(self._h, j, _dev_ptr(out), _stream_handle(stream)))
+        return out
+
+    def stats(self) -> StepStats:
+        st = A.Stats()
+        A.check(self.lib.isdc_get_stats(self._h, C.byref(st)))
+        return StepStats.from_c(st, A.OK)
+
+    # ---- multigrid ----
+    def vcycle(self, c: float, rhs: torch.Tensor, u: torch.Tensor, ncycles: int = 1, want_residual=False,
+               stream=None):
+        prec = A.PREC_FP64 if u.dtype == torch.float64 else A.PREC_MIXED
+        dt = torch.float64 if prec == A.PREC_FP64 else torch.float32
+        res = C.c_double()
+        A.check(self.lib.isdc_vcycle(self._h, c, prec, _dev_ptr(rhs, dt, self.N), _dev_ptr(u, dt, self.N),
+                                     ncycles, _stream_handle(stream), C.byref(res) if want_residual else None))
+        return res.value if want_residual else None
+
+    def mg_op(self, op: int, level: int, c: float, a=None, b=None, out=None, stream=None):
+        t = next(x for x in (a, b, out) if x is not None)
+        prec = A.PREC_FP64 if t.dtype == torch.float64 else A.PREC_MIXED
+        res = C.c_double()
+        A.check(self.lib.isdc_mg_op(self._h, op, level, c, prec, _dev_ptr(a), _dev_ptr(b), _dev_ptr(out),
+                                    _stream_handle(stream), C.byref(res)))
+        return res.value

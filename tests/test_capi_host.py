@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI (no GPU): symbols, struct layout, tables,
+workspace sizing and argument validation."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1401_7824_amd import _capi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "isdc.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(isdc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = A.load()
+    declared = _declared_functions()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in include/isdc.h but not exported"
+    # the binding declares exactly the header's functions
+    assert sorted(n for n, _, _ in A.SIGNATURES) == declared
+
+
+def test_struct_sizes_match():
+    lib = A.load()
+    s = [C.c_size_t() for _ in range(3)]
+    assert lib.isdc_abi_sizes(*[C.byref(x) for x in s]) == 0
+    assert [x.value for x in s] == [C.sizeof(A.Problem), C.sizeof(A.Params), C.sizeof(A.Stats)]
+
+
+@pytest.mark.parametrize("kind,Ms", [(A.NODES_LOBATTO, range(2, 10)), (A.NODES_RADAU_RIGHT, range(1, 10))])
+def test_tables_match_oracle(kind, Ms):
+    from paper_1401_7824_amd.isdc import tables
+    for M in Ms:
+        tau, Q, S = (np.array(v) for v in tables(kind, M))
+        tol = 1e-15 if M <= 7 else 2e-15
+        np.testing.assert_allclose(tau, O.nodes(kind, M), atol=1e-16, rtol=0)
+        np.testing.assert_allclose(Q, O.qmatrix(kind, M), atol=tol, rtol=0)
+        np.testing.assert_allclose(S, O.smatrix(kind, M), atol=tol, rtol=0)
+
+
+def test_tables_reject_bad_arguments():
+    lib = A.load()
+    buf = (C.c_double * 100)()
+    assert lib.isdc_tables(A.NODES_LOBATTO, 1, buf, buf, buf) == A.E_INVAL
+    assert lib.isdc_tables(A.NODES_RADAU_RIGHT, 0, buf, buf, buf) == A.E_INVAL
+    assert lib.isdc_tables(A.NODES_LOBATTO, 10, buf, buf, buf) == A.E_INVAL
+    assert lib.isdc_tables(7, 3, buf, buf, buf) == A.E_INVAL
+    assert b"node_kind" in lib.isdc_last_error()
+
+
+def _params(**kw):
+    from paper_1401_7824_amd.isdc import make_params
+    return make_params(**kw)
+
+
+def _bytes(dim, n, nu=1.0, fe=A.FE_ZERO, **kw):
+    lib = A.load()
+    out = C.c_size_t()
+    rc = lib.isdc_workspace_bytes(C.byref(A.Problem(dim, n, nu, fe)), C.byref(_params(**kw)), C.byref(out))
+    return rc, out.value
+
+
+def test_default_params():
+    p = _params()
+    assert (p.node_kind, p.M, p.vcycles, p.smoother, p.nu_pre, p.nu_post, p.precision, p.guess) == \
+        (A.NODES_LOBATTO, 3, 2, A.SMOOTH_RBGS, 1, 1, A.PREC_FP64, A.GUESS_PREV_SWEEP)
+    assert p.sdc_tol == 1e-10 and p.max_sweeps == 100
+
+
+def test_workspace_bytes_scale_with_problem():
+    rc, b2 = _bytes(2, 1023, M=5)
+    assert rc == 0
+    N = 1023 ** 2
+    # 2(M-1) node arrays + (M-1) S*F arrays (Lobatto) + 3 fine MG arrays, float64
+    assert b2 >= (2 * 4 + 4 + 3) * N * 8
+    assert b2 < (2 * 4 + 4 + 3) * N * 8 * 1.4
+    rc, b3 = _bytes(3, 255, node_kind=A.NODES_RADAU_RIGHT, M=3)
+    assert rc == 0 and b3 > (2 * 3 + 3 + 3) * 255 ** 3 * 8
+    rc, b1 = _bytes(1, 127)
+    assert rc == 0 and b1 < 64 * 1024
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=0), dict(dim=4), dict(n=0), dict(n=10), dict(n=4096 * 2 - 1, dim=2), dict(nu=-1.0),
+    dict(nu=float("nan")), dict(fe=5), dict(M=1), dict(M=10), dict(node_kind=3), dict(vcycles=-1),
+    dict(sdc_tol=-1.0), dict(sdc_tol=float("inf")), dict(max_sweeps=0), dict(smoother=2), dict(nu_pre=0, nu_post=0),
+    dict(nu_pre=9), dict(precision=2), dict(guess=3), dict(early_exit=2), dict(inner_tol=float("nan")),
+])
+def test_validation_rejects(bad):
+    kw = dict(dim=2, n=63, nu=1.0, fe=A.FE_ZERO)
+    kw.update({k: v for k, v in bad.items() if k in kw})
+    par = {k: v for k, v in bad.items() if k not in ("dim", "n", "nu", "fe")}
+    rc, _ = _bytes(kw["dim"], kw["n"], kw["nu"], kw["fe"], **par)
+    assert rc == A.E_INVAL
+    assert A.load().isdc_last_error() != b""
+
+
+def test_create_checks_workspace_without_touching_it():
+    lib = A.load()
+    prob = A.Problem(2, 63, 1.0, A.FE_ZERO)
+    par = _params()
+    need = C.c_size_t()
+    assert lib.isdc_workspace_bytes(C.byref(prob), C.byref(par), C.byref(need)) == 0
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 40)  # never dereferenced: creation is host-only
+    assert lib.isdc_create(C.byref(prob), C.byref(par), fake, need.value - 1, C.byref(h)) == A.E_WORKSPACE
+    assert lib.isdc_create(C.byref(prob), C.byref(par), C.c_void_p((1 << 40) + 8), need.value, C.byref(h)) == A.E_WORKSPACE
+    assert lib.isdc_create(C.byref(prob), C.byref(par), None, need.value, C.byref(h)) == A.E_WORKSPACE
+    assert lib.isdc_create(C.byref(prob), C.byref(par), fake, need.value, C.byref(h)) == 0
+    assert h.value
+    st = A.Stats()
+    assert lib.isdc_get_stats(h, C.byref(st)) == 0 and st.sweeps == 0
+    # calls that would need a step in progress are rejected before any device work
+    r = C.c_double()
+    assert lib.isdc_sweep(h, None, C.byref(r)) == A.E_INVAL
+    assert lib.isdc_end(h, fake, None) == A.E_INVAL
+    assert lib.isdc_node_values(h, 1, fake, None) == A.E_INVAL
+    assert lib.isdc_begin(h, fake, -1.0, None) == A.E_INVAL
+    assert lib.isdc_begin(h, fake, float("nan"), None) == A.E_INVAL
+    assert lib.isdc_begin(h, None, 1e-3, None) == A.E_INVAL
+    assert lib.isdc_step(h, None, 1e-3, None, None) == A.E_INVAL
+    assert lib.isdc_vcycle(h, -1.0, A.PREC_FP64, fake, fake, 1, None, None) == A.E_INVAL
+    assert lib.isdc_vcycle(h, 1.0, 5, fake, fake, 1, None, None) == A.E_INVAL
+    assert lib.isdc_mg_op(h, 99, 0, 1.0, A.PREC_FP64, fake, fake, fake, None, None) == A.E_INVAL
+    assert lib.isdc_mg_op(h, A.OP_SMOOTH, 9, 1.0, A.PREC_FP64, fake, fake, fake, None, None) == A.E_INVAL
+    lib.isdc_destroy(h)
+    lib.isdc_destroy(None)
+
+
+def test_null_plan_rejected():
+    lib = A.load()
+    r = C.c_double()
+    assert lib.isdc_sweep(None, None, C.byref(r)) == A.E_INVAL
+    assert lib.isdc_get_stats(None, C.byref(A.Stats())) == A.E_INVAL
