@@ -67,35 +67,33 @@ def time_steps(plan, u, dt, steps, warmup, torch):
 
 
 def smoother_probe(plan, cfg, reps, torch):
-    """Average duration of the fine-level smoother half-sweep, timed with HIP
-    events on the stream it is launched on."""
+    """Average duration of the fine-level one-pass red-black smoother
+    (k_rbgs_tile), timed with HIP events on the stream it is launched on."""
     import paper_1401_7824_amd as P
     n, d = cfg["n"], cfg["dim"]
     dtype = torch.float64 if cfg["precision"] == 0 else torch.float32
     w = 8 if dtype == torch.float64 else 4
     g = torch.Generator(device="cuda").manual_seed(0)
     rhs = torch.randn((n,) * d, dtype=dtype, device="cuda", generator=g)
-    u = torch.randn((n,) * d, dtype=dtype, device="cuda", generator=g)
-    h = 1.0 / (n + 1)
+    u = [torch.randn((n,) * d, dtype=dtype, device="cuda", generator=g) for _ in range(2)]
     c = cfg["dt"] * cfg["nu"] * 0.3
-    for _ in range(3):
-        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u, out=u)
+    for k in range(4):
+        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u[k % 2], out=u[(k + 1) % 2])
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(reps):
-        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u, out=u)
+    for k in range(reps):
+        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u[k % 2], out=u[(k + 1) % 2])
     e1.record(stream)
     torch.cuda.synchronize()
-    per_launch = e0.elapsed_time(e1) / 1e3 / (2 * reps)  # RB-GS: two half-sweep kernels per step
+    per_launch = e0.elapsed_time(e1) / 1e3 / reps
     N = n ** d
-    alg_bytes = 2 * w * N  # per half-sweep: read neighbours + rhs of one colour, write that colour
+    alg_bytes = 3 * w * N  # read the iterate and the right-hand side, write the new iterate
     achieved = alg_bytes / per_launch / 1e9
-    del h
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"k_rbgs_half<{'double' if w == 8 else 'float'},{d}> fine level",
+                kernel=f"k_rbgs_tile<{'double' if w == 8 else 'float'},{d},false> (fine level, {n}^{d})",
                 avg_launch_us=round(per_launch * 1e6, 3), alg_bytes_per_launch=alg_bytes)
 
 

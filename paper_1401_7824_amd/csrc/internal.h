@@ -62,6 +62,21 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
                        hipStream_t s);
 int tail_max_n(int d);
 
+// Tiled kernels (mg_tiles.hip).  One complete red-black Gauss-Seidel step
+// from e_in to e_out (e_out != e_in; zero: e_in is identically zero and is
+// not read).
+template <typename T>
+hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
+                            hipStream_t s);
+// rc = full weighting of (r - A e); rc has (n-1)/2 points per axis.
+template <typename T>
+hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, const T* e, T* rc, hipStream_t s);
+// e_in + P ec followed by one red-black step.  mode 0: result to e_out;
+// mode 1: u_out = g + result (float64); mode 2: u_out = result.
+template <typename T>
+hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
+                                    T* e_out, const double* g, double* u_out, int mode, hipStream_t s);
+
 // partial[b] = max |rhs - A u| over the points of block b; returns the block
 // count in *nblocks (<= kReduceBlocks).
 constexpr int kReduceBlocks = 1024;

@@ -11,8 +11,9 @@
 //                 or weighted Jacobi;
 //   restriction -- full weighting (1/4, 1/2, 1/4 per axis) of the residual;
 //   prolongation -- (bi/tri)linear interpolation added to the iterate;
-//   coarse tail  -- all levels below a size limit in one workgroup's LDS, down
-//                   to the exact one-point solve.
+// These are the plain one-thread-per-point forms, used for the Jacobi
+// smoother, in-place red-black half steps and the residual norm; the tiled
+// kernels and the coarse tail live in mg_tiles.hip.
 #include <hip/hip_runtime.h>
 #include <cmath>
 
@@ -232,164 +233,6 @@ __global__ void __launch_bounds__(kBlock) k_copy(const T* __restrict__ s, T* __r
         d[i] = s[i];
 }
 
-// ---------------------------------------------------------------- coarse tail
-// The whole V-cycle on levels n_t, (n_t-1)/2, ..., 1 inside one workgroup,
-// with every level's iterate and right-hand side in LDS.
-
-constexpr int kTailThreads = 1024;
-template <int D> struct TailCap;
-template <> struct TailCap<1> { static constexpr int nmax = 2047, total = 4096, per_thread = 2; };
-template <> struct TailCap<2> { static constexpr int nmax = 63, total = 5216, per_thread = 4; };
-template <> struct TailCap<3> { static constexpr int nmax = 15, total = 3752, per_thread = 4; };
-
-template <int D>
-__device__ __forceinline__ int npts(int n) {
-    return D == 1 ? n : (D == 2 ? n * n : n * n * n);
-}
-
-template <int D>
-__device__ __forceinline__ void decomp(int i, int n, int& x, int& y, int& z) {
-    x = i % n;
-    int t = i / n;
-    y = (D >= 2) ? t % n : 0;
-    z = (D == 3) ? t / n : 0;
-}
-
-template <typename T, int D>
-__device__ void tail_smooth(T* e, const T* r, int n, T a, T diag, T invdiag, T w, int smoother) {
-    const int N = npts<D>(n);
-    if (smoother == ISDC_SMOOTH_RBGS) {
-        for (int colour = 0; colour < 2; ++colour) {
-            for (int i = threadIdx.x; i < N; i += kTailThreads) {
-                int x, y, z;
-                decomp<D>(i, n, x, y, z);
-                if (((x + y + z) & 1) != colour) continue;
-                e[i] = (r[i] + a * nbsum<T, D>(e, n, x, y, z, (size_t)i)) * invdiag;
-            }
-            __syncthreads();
-        }
-    } else {
-        T buf[TailCap<D>::per_thread];
-        int k = 0;
-        for (int i = threadIdx.x; i < N; i += kTailThreads, ++k) {
-            int x, y, z;
-            decomp<D>(i, n, x, y, z);
-            T c = e[i];
-            T Au = diag * c - a * nbsum<T, D>(e, n, x, y, z, (size_t)i);
-            buf[k] = c + w * ((r[i] - Au) * invdiag);
-        }
-        __syncthreads();
-        k = 0;
-        for (int i = threadIdx.x; i < N; i += kTailThreads, ++k) e[i] = buf[k];
-        __syncthreads();
-    }
-}
-
-template <typename T, int D>
-__global__ void __launch_bounds__(kTailThreads)
-k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, double c, double h_t, int smoother,
-       int nu1, int nu2, double omega, int zero_guess) {
-    __shared__ T le[TailCap<D>::total];
-    __shared__ T lr[TailCap<D>::total];
-    int nlev = 0, off[16], nn[16];
-    {
-        int o = 0, n = n_t;
-        while (true) {
-            off[nlev] = o;
-            nn[nlev] = n;
-            o += npts<D>(n);
-            ++nlev;
-            if (n == 1) break;
-            n = (n - 1) / 2;
-        }
-    }
-    const int N0 = npts<D>(n_t);
-    for (int i = threadIdx.x; i < N0; i += kTailThreads) lr[i] = rhs_g[i];
-    __syncthreads();
-    double h = h_t;
-    // descend
-    for (int l = 0; l < nlev; ++l) {
-        const int n = nn[l];
-        const double ad = c / (h * h);
-        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
-        T* e = le + off[l];
-        T* r = lr + off[l];
-        const int N = npts<D>(n);
-        if (l == 0 && !zero_guess)
-            for (int i = threadIdx.x; i < N; i += kTailThreads) e[i] = e_g[i];
-        else
-            for (int i = threadIdx.x; i < N; i += kTailThreads) e[i] = T(0);
-        __syncthreads();
-        if (n == 1) {
-            if (threadIdx.x == 0) e[0] = r[0] / diag;
-            __syncthreads();
-            break;
-        }
-        for (int k = 0; k < nu1; ++k) tail_smooth<T, D>(e, r, n, a, diag, invdiag, T(omega), smoother);
-        // restrict the residual to level l+1
-        const int nc = (n - 1) / 2;
-        T* rc = lr + off[l + 1];
-        const int Nc = npts<D>(nc);
-        const T wt[3] = {T(0.25), T(0.5), T(0.25)};
-        for (int I = threadIdx.x; I < Nc; I += kTailThreads) {
-            int X, Y, Z;
-            decomp<D>(I, nc, X, Y, Z);
-            T acc = T(0);
-            const int zl = (D == 3) ? -1 : 0, zh = (D == 3) ? 1 : 0;
-            const int yl = (D >= 2) ? -1 : 0, yh = (D >= 2) ? 1 : 0;
-            for (int oz = zl; oz <= zh; ++oz)
-                for (int oy = yl; oy <= yh; ++oy) {
-                    T row = T(0);
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        int x = 2 * X + 1 + ox;
-                        int y = (D >= 2) ? 2 * Y + 1 + oy : 0;
-                        int z = (D == 3) ? 2 * Z + 1 + oz : 0;
-                        int i = (D == 1) ? x : (D == 2 ? y * n + x : (z * n + y) * n + x);
-                        T res = r[i] - (diag * e[i] - a * nbsum<T, D>(e, n, x, y, z, (size_t)i));
-                        row += wt[ox + 1] * res;
-                    }
-                    T wyz = (D >= 2 ? wt[oy + 1] : T(1)) * (D == 3 ? wt[oz + 1] : T(1));
-                    acc += wyz * row;
-                }
-            rc[I] = acc;
-        }
-        __syncthreads();
-        h *= 2.0;
-    }
-    // ascend: levels nlev-2 .. 0
-    for (int l = nlev - 2; l >= 0; --l) {
-        h *= 0.5;
-        const int n = nn[l];
-        const int nc = nn[l + 1];
-        const double ad = c / (h * h);
-        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
-        T* e = le + off[l];
-        T* r = lr + off[l];
-        const T* ec = le + off[l + 1];
-        const int N = npts<D>(n);
-        for (int i = threadIdx.x; i < N; i += kTailThreads) {
-            int x, y, z;
-            decomp<D>(i, n, x, y, z);
-            int ix[2], iy[2] = {0, 0}, iz[2] = {0, 0};
-            float wx[2], wy[2] = {1.f, 1.f}, wz[2] = {1.f, 1.f};
-            int kx = interp_taps(x, nc, ix, wx);
-            int ky = (D >= 2) ? interp_taps(y, nc, iy, wy) : 1;
-            int kz = (D == 3) ? interp_taps(z, nc, iz, wz) : 1;
-            T acc = T(0);
-            for (int cc = 0; cc < kz; ++cc)
-                for (int b = 0; b < ky; ++b)
-                    for (int aa = 0; aa < kx; ++aa) {
-                        int j = (D == 1) ? ix[aa] : (D == 2 ? iy[b] * nc + ix[aa] : (iz[cc] * nc + iy[b]) * nc + ix[aa]);
-                        acc += T(wx[aa]) * T(wy[b]) * T(wz[cc]) * ec[j];
-                    }
-            e[i] += acc;
-        }
-        __syncthreads();
-        for (int k = 0; k < nu2; ++k) tail_smooth<T, D>(e, r, n, a, diag, invdiag, T(omega), smoother);
-    }
-    for (int i = threadIdx.x; i < N0; i += kTailThreads) e_g[i] = le[i];
-}
-
 inline dim3 stencil_grid(int d, int per_row, int n) {
     return dim3((unsigned)((per_row + kBlock - 1) / kBlock), d >= 2 ? (unsigned)n : 1u, d == 3 ? (unsigned)n : 1u);
 }
@@ -459,21 +302,6 @@ hipError_t launch_prolong(int d, int n, const T* ec, T* u, hipStream_t s) {
     return hipGetLastError();
 }
 
-int tail_max_n(int d) {
-    return d == 1 ? TailCap<1>::nmax : (d == 2 ? TailCap<2>::nmax : TailCap<3>::nmax);
-}
-
-template <typename T>
-hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero_guess, const T* rhs, T* e,
-                       hipStream_t s) {
-    if (n > tail_max_n(cfg.d)) return hipErrorInvalidValue;
-    ISDC_DISPATCH_D(cfg.d, {
-        hipLaunchKernelGGL((k_tail<T, D>), dim3(1), dim3(kTailThreads), 0, s, rhs, e, n, c, h, cfg.smoother,
-                           cfg.nu_pre, cfg.nu_post, cfg.omega, zero_guess ? 1 : 0);
-    });
-    return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T* u, double* partial,
                           int* nblocks, hipStream_t s) {
@@ -509,7 +337,6 @@ hipError_t launch_copy(const T* src, T* dst, size_t count, hipStream_t s) {
                                          hipStream_t);                                                    \
     template hipError_t launch_restrict<T>(int, int, const Coef<T>&, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_prolong<T>(int, int, const T*, T*, hipStream_t);                          \
-    template hipError_t launch_tail<T>(const MGConfig&, int, double, double, bool, const T*, T*, hipStream_t); \
     template hipError_t launch_resnorm<T>(int, int, const Coef<T>&, const T*, const T*, double*, int*,  \
                                           hipStream_t);                                                   \
     template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                      \

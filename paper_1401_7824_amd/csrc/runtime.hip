@@ -175,29 +175,40 @@ double read_scalar(isdc_plan* p, const double* d_src, hipStream_t s) {
 
 // ---------------------------------------------------------------- V-cycle schedule
 
+// Node update fused into the last kernel of a solve: u_out = g + e (mode 1)
+// or u_out = e (mode 2, zero guess).  mode 0: no fusion.
+struct Fuse {
+    int mode = 0;
+    const double* g = nullptr;
+    double* u_out = nullptr;
+};
+
 template <typename T>
 void smooth_steps(isdc_plan* p, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs, T*& cur, T*& other,
                   hipStream_t s) {
     for (int k = 0; k < nsteps; ++k) {
-        if (p->mg.smoother == ISDC_SMOOTH_RBGS) {
-            HIPCHK(launch_smooth<T>(p->mg, n, co, zero, rhs, cur, cur, s));
-        } else {
+        if (p->mg.smoother == ISDC_SMOOTH_RBGS)
+            HIPCHK(launch_rbgs_tile<T>(p->d, n, co, zero, rhs, cur, other, s));
+        else
             HIPCHK(launch_smooth<T>(p->mg, n, co, zero, rhs, cur, other, s));
-            std::swap(cur, other);
-        }
+        std::swap(cur, other);
         zero = false;
     }
 }
 
-// One V-cycle on level l for (I - c L) e = rhs; the result ends in `e`.
-// tmp: scratch of the level's size (Jacobi only).
+// One V-cycle on level l for (I - c L) e = rhs starting from e (or from zero);
+// the result ends in `e` (or, with fuse.mode != 0 on a fused path, goes to
+// fuse.u_out and `e` is left unspecified).  tmp: a scratch array of the
+// level's size.  Returns true if the fused update was done.
 template <typename T>
-void vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s) {
+bool vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s,
+                const Fuse& fuse = Fuse()) {
     const Level& L = p->lev[l];
     if (l == p->tail) {
         HIPCHK(launch_tail<T>(p->mg, L.n, c, L.h, zero, rhs, e, s));
-        return;
+        return false;
     }
+    const bool rbgs = p->mg.smoother == ISDC_SMOOTH_RBGS;
     Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
     T* cur = e;
     T* other = tmp;
@@ -207,11 +218,23 @@ void vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T*
         zero = false;
     }
     const Level& C = p->lev[l + 1];
-    HIPCHK(launch_restrict<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
+    HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
     vcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
-    HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
-    smooth_steps<T>(p, p->mg.nu_post, L.n, co, zero, rhs, cur, other, s);
+    bool fused = false;
+    if (rbgs && p->mg.nu_post >= 1) {
+        // prolongation + correction fused with the first post-smoothing step
+        const bool last = p->mg.nu_post == 1;
+        const int mode = (last && fuse.mode) ? fuse.mode : 0;
+        HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, mode, s));
+        if (mode) return true;
+        std::swap(cur, other);
+        smooth_steps<T>(p, p->mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s);
+    } else {
+        HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
+        smooth_steps<T>(p, p->mg.nu_post, L.n, co, zero, rhs, cur, other, s);
+    }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
+    return fused;
 }
 
 template <typename T>
@@ -246,8 +269,12 @@ void quad_residual(isdc_plan* p, const double* const* nodes, hipStream_t s) {
     HIPCHK(launch_reduce_max(p->partial, nb, p->scalars, s));
 }
 
+// The implicit solve of substep m in correction form: the right-hand side
+// r = rhs - A g is in lev[0].r; L V-cycles from e = 0 (or cycles until the
+// inner residual <= inner_tol), then u_out = g + e.  The update is fused into
+// the last V-cycle's final kernel when possible.
 template <typename T>
-int inner_solve(isdc_plan* p, double c, hipStream_t s) {
+int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
     const Level& L0 = p->lev[0];
     T* r0 = (T*)L0.r;
     T* e0 = (T*)L0.e;
@@ -256,16 +283,22 @@ int inner_solve(isdc_plan* p, double c, hipStream_t s) {
     const bool classical = pr.vcycles == 0;
     const bool check = classical || pr.early_exit;
     const int limit = classical ? 100 : pr.vcycles;
-    if (!check) {
-        for (int k = 0; k < limit; ++k) vcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s);
-        return limit;
-    }
-    HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
     int k = 0;
-    for (; k < limit; ++k) {
-        double res = resnorm<T>(p, 0, c, r0, e0, s);
-        if (res <= pr.inner_tol) break;
-        vcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+    bool fused = false;
+    if (!check) {
+        for (; k < limit; ++k) fused = vcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse());
+    } else {
+        HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
+        for (; k < limit; ++k) {
+            double res = resnorm<T>(p, 0, c, r0, e0, s);
+            if (res <= pr.inner_tol) break;
+            vcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+        }
+    }
+    if (!fused) {
+        if (k == 0 && !check) HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
+        const int guess = upd.mode == 2 ? ISDC_GUESS_ZERO : ISDC_GUESS_PREV_SWEEP;
+        HIPCHK(launch_node_update<T>(p->N, guess, upd.g, upd.g, e0, upd.u_out, s));
     }
     return k;
 }
@@ -284,9 +317,15 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
         RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
                    p->prob.fe_kind, p->par.guess};
         HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
-        p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, s);
-        HIPCHK(launch_node_update<T>(p->N, p->par.guess, p->cur[m + 1], nw[m], (const T*)p->lev[0].e,
-                                     (double*)nw[m + 1], s));
+        Fuse upd;
+        upd.u_out = (double*)nw[m + 1];
+        if (p->par.guess == ISDC_GUESS_ZERO) {
+            upd.mode = 2;
+        } else {
+            upd.mode = 1;
+            upd.g = p->par.guess == ISDC_GUESS_PREV_NODE ? nw[m] : p->cur[m + 1];
+        }
+        p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, upd, s);
     }
     for (int j = 0; j <= M; ++j) p->cur[j] = nw[j];
     p->wbuf ^= 1;
@@ -545,8 +584,10 @@ void mg_op_impl(isdc_plan* p, int op, int level, double c, const void* a, const 
         case ISDC_OP_SMOOTH: {
             if (!a || !b || !out) fail(ISDC_E_INVAL, "SMOOTH needs rhs, iterate and output");
             if (p->mg.smoother == ISDC_SMOOTH_RBGS) {
-                if (out != b) HIPCHK(launch_copy<T>((const T*)b, (T*)out, N, s));
-                HIPCHK(launch_smooth<T>(p->mg, n, co, false, (const T*)a, (const T*)out, (T*)out, s));
+                if (out != b)  // one-pass tiled red-black step
+                    HIPCHK(launch_rbgs_tile<T>(d, n, co, false, (const T*)a, (const T*)b, (T*)out, s));
+                else           // in place: red and black half steps
+                    HIPCHK(launch_smooth<T>(p->mg, n, co, false, (const T*)a, (const T*)out, (T*)out, s));
             } else {
                 if (out == b) fail(ISDC_E_INVAL, "Jacobi SMOOTH needs a separate output array");
                 HIPCHK(launch_smooth<T>(p->mg, n, co, false, (const T*)a, (const T*)b, (T*)out, s));
@@ -556,7 +597,7 @@ void mg_op_impl(isdc_plan* p, int op, int level, double c, const void* a, const 
         case ISDC_OP_RESTRICT:
             if (n < 3) fail(ISDC_E_INVAL, "RESTRICT needs a level with n >= 3");
             if (!a || !b || !out) fail(ISDC_E_INVAL, "RESTRICT needs rhs, iterate and output");
-            HIPCHK(launch_restrict<T>(d, n, co, (const T*)a, (const T*)b, (T*)out, s));
+            HIPCHK(launch_restrict_tile<T>(d, n, co, (const T*)a, (const T*)b, (T*)out, s));
             break;
         case ISDC_OP_PROLONG:
             if (n < 3) fail(ISDC_E_INVAL, "PROLONG needs a level with n >= 3");
