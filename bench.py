@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--probe-reps", type=int, default=50)
+    ap.add_argument("--probe-reps", type=int, default=100)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of 512 MiB (reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -66,35 +68,91 @@ def time_steps(plan, u, dt, steps, warmup, torch):
     return t0.elapsed_time(t1) / 1e3, wall, stats
 
 
-def smoother_probe(plan, cfg, reps, torch):
-    """Average duration of the fine-level one-pass red-black smoother
-    (k_rbgs_tile), timed with HIP events on the stream it is launched on."""
+KERNEL_NAMES = {
+    "smooth_restrict": "k_rbgs_restrict_tile<{T},{d},false>",
+    "prolong_smooth": "k_prolong_rbgs_tile<{T},{d},0>",
+    "tail": "k_tail<{T},{d}>",
+    "quad": "k_quad_residual_tile<{d},{M}>",
+}
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (profiles/traffic.json), or None if the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_1401_7824_amd/csrc/mg_tiles.hip", "paper_1401_7824_amd/csrc/tile_common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def kernel_probe(plan, cfg, reps, torch):
+    """Per-launch durations of the step's kernels, timed by the library with a
+    pair of HIP events around every launch on the stream it launches on, with
+    the workload's coefficient c = dt_m nu of the first non-degenerate substep."""
     import paper_1401_7824_amd as P
+    from paper_1401_7824_amd.isdc import tables
+    tau, _, _ = tables(cfg["node_kind"], cfg["M"])
+    taus = [0.0] + list(tau)
+    dtm = next(cfg["dt"] * (taus[m + 1] - taus[m]) for m in range(cfg["M"]) if taus[m + 1] > taus[m])
+    c = dtm * cfg["nu"]
+    prec = cfg["precision"]
+    T = "double" if prec == 0 else "float"
+    out = {}
+    kinds = [("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH),
+             ("tail", P.KERNEL_TAIL)]
+    for name, k in kinds:
+        if name == "smooth_restrict" and cfg["dim"] == 3:
+            continue
+        us, b = plan.time_kernel(k, 0, c, prec, reps)
+        out[name] = dict(kernel=KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"]), avg_us=round(us, 3),
+                         alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1))
+    return out
+
+
+def vcycle_probe(plan, cfg, reps, torch):
+    """Time of one whole fine-level V-cycle (isdc_vcycle, events on torch's
+    stream) and its algorithmic HBM bytes: every level's arrays read or
+    written once per kernel, summed over the levels the kernels touch."""
     n, d = cfg["n"], cfg["dim"]
     dtype = torch.float64 if cfg["precision"] == 0 else torch.float32
     w = 8 if dtype == torch.float64 else 4
     g = torch.Generator(device="cuda").manual_seed(0)
     rhs = torch.randn((n,) * d, dtype=dtype, device="cuda", generator=g)
-    u = [torch.randn((n,) * d, dtype=dtype, device="cuda", generator=g) for _ in range(2)]
+    u = torch.zeros_like(rhs)
     c = cfg["dt"] * cfg["nu"] * 0.3
-    for k in range(4):
-        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u[k % 2], out=u[(k + 1) % 2])
+    for _ in range(3):
+        plan.vcycle(c, rhs, u, 1)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for k in range(reps):
-        plan.mg_op(P.OP_SMOOTH, 0, c, a=rhs, b=u[k % 2], out=u[(k + 1) % 2])
+    for _ in range(reps):
+        plan.vcycle(c, rhs, u, 1)
     e1.record(stream)
     torch.cuda.synchronize()
-    per_launch = e0.elapsed_time(e1) / 1e3 / reps
-    N = n ** d
-    alg_bytes = 3 * w * N  # read the iterate and the right-hand side, write the new iterate
-    achieved = alg_bytes / per_launch / 1e9
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"k_rbgs_tile<{'double' if w == 8 else 'float'},{d},false> (fine level, {n}^{d})",
-                avg_launch_us=round(per_launch * 1e6, 3), alg_bytes_per_launch=alg_bytes)
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    # per multi-workgroup level: (3N + Nc) for smoothing+restriction and for
+    # prolongation+smoothing; the tail reads its rhs and writes its iterate
+    tail_n = {1: 2047, 2: 63, 3: 15}[d]
+    b, m = 0.0, n
+    while m > tail_n:
+        N, Nc = m ** d, ((m - 1) // 2) ** d
+        b += 2 * (3 * N + Nc) * w
+        m = (m - 1) // 2
+    b += 2 * m ** d * w
+    return dict(us_per_vcycle=round(us, 2), alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1),
+                frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
 
 
 def cpu_baseline(cfg, sweeps_per_step):
@@ -142,7 +200,13 @@ def main():
     elapsed, wall, stats = time_steps(plan, u, cfg["dt"], args.steps, args.warmup, torch)
     sweeps = sum(s.sweeps for s in stats) / len(stats)
     vcyc = sum(s.vcycles for s in stats) / len(stats)
-    roof = smoother_probe(plan, cfg, args.probe_reps, torch)
+    kp = kernel_probe(plan, cfg, args.probe_reps, torch)
+    vc = vcycle_probe(plan, cfg, 20, torch)
+    dom = kp.get("smooth_restrict") or kp["prolong_smooth"]
+    traffic = counter_traffic(dom["kernel"]) if args.workload == "rd2d" else None
+    roof = dict(bound="hbm", achieved=dom["gbps"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(dom["gbps"] / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["kernel"] + " (fine level)",
+                avg_launch_us=dom["avg_us"], alg_bytes_per_launch=dom["alg_bytes"])
     out = {
         "metric": METRIC,
         "value": round(args.steps / elapsed, 4),
@@ -163,7 +227,14 @@ def main():
                    "sweeps_per_step": sweeps, "vcycles_per_step": vcyc,
                    "host_wall_s": round(wall, 4)},
         "roofline": roof,
+        "vcycle": vc,
+        "kernels": kp,
     }
+    if args.calib_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, sweeps)
     print(json.dumps(out), flush=True)

@@ -67,6 +67,10 @@ enum { ISDC_GUESS_PREV_SWEEP = 0, ISDC_GUESS_ZERO = 1, ISDC_GUESS_PREV_NODE = 2 
 enum { ISDC_OP_SMOOTH = 0, ISDC_OP_RESTRICT = 1, ISDC_OP_PROLONG = 2, ISDC_OP_COARSE = 3,
        ISDC_OP_RESIDUAL_NORM = 4 };
 
+/* Kernels that isdc_time_kernel can time (see there). */
+enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KERNEL_SMOOTH = 2,
+       ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4 };
+
 #define ISDC_MAX_M 9
 #define ISDC_HIST 128
 
@@ -187,6 +191,26 @@ int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs,
  * Unused pointers may be NULL. */
 int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t precision,
                const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
+
+/* Time one of the plan's kernels as the step launches it: `reps` launches on
+ * `stream`, each bracketed by its own pair of HIP events, on the plan's own
+ * buffers at `level` (their contents are whatever the last solve left; the
+ * timing does not depend on the values).  Writes the average duration per
+ * launch in microseconds to *h_avg_us and the kernel's algorithmic bytes per
+ * launch (every array element read or written once) to *h_bytes, and
+ * synchronises `stream`.  For measurement; leaves the plan's workspace
+ * arrays with unspecified contents, so call it only between steps.
+ *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
+ *                                full-weighting restriction (levels above the
+ *                                coarse tail, d = 1 or 2)
+ *   ISDC_KERNEL_PROLONG_SMOOTH   prolongation + correction + one red-black step
+ *   ISDC_KERNEL_SMOOTH           one red-black step
+ *   ISDC_KERNEL_TAIL             the single-workgroup coarse tail (level ignored)
+ *   ISDC_KERNEL_QUAD             S*F quadrature + SDC residual of the current
+ *                                iterate (a step must be in progress; level ignored)
+ * precision selects the V-cycle arithmetic as in isdc_vcycle. */
+int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision, int32_t reps,
+                     void* stream, double* h_avg_us, double* h_bytes);
 
 #ifdef __cplusplus
 }

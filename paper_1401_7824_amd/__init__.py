@@ -8,6 +8,7 @@ from ._capi import (  # noqa: F401
     ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, SMOOTH_RBGS, SMOOTH_JACOBI,
     PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
     OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, load,
+    KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD,
 )
 
 

@@ -20,6 +20,7 @@ SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
 OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM = 0, 1, 2, 3, 4
+KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD = 0, 1, 2, 3, 4
 MAX_M = 9
 HIST = 128
 
@@ -59,6 +60,7 @@ SIGNATURES = [
     ("isdc_get_stats", C.c_int, [_VP, C.POINTER(Stats)]),
     ("isdc_vcycle", C.c_int, [_VP, C.c_double, C.c_int32, _VP, _VP, C.c_int32, _VP, _DP]),
     ("isdc_mg_op", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _DP]),
+    ("isdc_time_kernel", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, _VP, _DP, _DP]),
 ]
 
 _lib = None

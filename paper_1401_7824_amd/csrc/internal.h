@@ -27,6 +27,12 @@ struct Coef {
     T a, diag, invdiag, w;
 };
 
+// Level coefficients of the coarse tail (level 0 = the tail's finest level),
+// computed on the host exactly as make_coef does.
+struct TailCoefs {
+    double a[16], diag[16], invdiag[16];
+};
+
 struct MGConfig {
     int d;
     int smoother;  // ISDC_SMOOTH_*
@@ -71,6 +77,11 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
 // rc = full weighting of (r - A e); rc has (n-1)/2 points per axis.
 template <typename T>
 hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, const T* e, T* rc, hipStream_t s);
+// One red-black step from e_in to e_out fused with rc = full weighting of
+// (r - A e_out).  d = 1, 2 only.
+template <typename T>
+hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
+                                     T* rc, hipStream_t s);
 // e_in + P ec followed by one red-black step.  mode 0: result to e_out;
 // mode 1: u_out = g + result (float64); mode 2: u_out = result.
 template <typename T>
@@ -107,6 +118,8 @@ struct QuadArgs {
 
 // For every point: f_j = nu L_h u_j + f^E(u_j); sf[m] = sum_j dt s_{m,j} f_j;
 // partial[b] = max over the block of |u_0 + sum_j dt q_{m,j} f_j - u_m|.
+// partial must hold quad_partials(d, n) entries.
+int quad_partials(int d, int n);
 hipError_t launch_quad_residual(int d, const QuadArgs& qa, double* partial, int* nblocks,
                                 hipStream_t s);
 

@@ -18,99 +18,11 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "tile_common.h"
 
 namespace isdc {
 
 namespace {
-
-constexpr int kThreads = 256;
-
-template <int D> struct Tile;
-template <> struct Tile<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
-template <> struct Tile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
-template <> struct Tile<3> { static constexpr int X = 32, Y = 8, Z = 4; };
-
-// Coarse tile of the restriction kernel.
-template <int D> struct CTile;
-template <> struct CTile<1> { static constexpr int X = 512, Y = 1, Z = 1; };
-template <> struct CTile<2> { static constexpr int X = 32, Y = 8, Z = 1; };
-template <> struct CTile<3> { static constexpr int X = 8, Y = 4, Z = 4; };
-
-// A box of extents (X, Y, Z) in the used dimensions (unused ones are 1).
-template <int D, int EX, int EY, int EZ>
-struct Box {
-    static constexpr int X = EX;
-    static constexpr int Y = D >= 2 ? EY : 1;
-    static constexpr int Z = D == 3 ? EZ : 1;
-    static constexpr int N = X * Y * Z;
-    static constexpr int SY = X;      // stride of y
-    static constexpr int SZ = X * Y;  // stride of z
-    __device__ static __forceinline__ void split(int k, int& lx, int& ly, int& lz) {
-        lx = k % X;
-        int t = k / X;
-        ly = t % Y;
-        lz = t / Y;
-    }
-};
-
-template <int D, int H>
-using HaloBox = Box<D, Tile<D>::X + 2 * H, Tile<D>::Y + 2 * H, Tile<D>::Z + 2 * H>;
-
-template <int D>
-__device__ __forceinline__ bool inside(int x, int y, int z, int n) {
-    bool ok = (unsigned)x < (unsigned)n;
-    if (D >= 2) ok = ok && (unsigned)y < (unsigned)n;
-    if (D == 3) ok = ok && (unsigned)z < (unsigned)n;
-    return ok;
-}
-
-template <int D>
-__device__ __forceinline__ size_t gidx(int x, int y, int z, int n) {
-    if (D == 1) return (size_t)x;
-    if (D == 2) return (size_t)y * n + x;
-    return ((size_t)z * n + y) * n + x;
-}
-
-// Logical tile of this workgroup: XCD k gets a contiguous range of tiles.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int q = nb >> 3, rem = nb & 7;
-    const int xcd = b & 7, slot = b >> 3;
-    return xcd * q + (xcd < rem ? xcd : rem) + slot;
-}
-
-__device__ __forceinline__ void tile_origin(int ntx, int nty, int TX, int TY, int TZ, int& x0, int& y0, int& z0) {
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    int tx = t % ntx;
-    int r = t / ntx;
-    int ty = r % nty;
-    int tz = r / nty;
-    x0 = tx * TX;
-    y0 = ty * TY;
-    z0 = tz * TZ;
-}
-
-// Sum of the 2d neighbours of LDS point i in box B (ghosts already zero).
-template <typename T, int D, typename B>
-__device__ __forceinline__ T lds_nbsum(const T* s, int i) {
-    T v = s[i - 1] + s[i + 1];
-    if (D >= 2) v += s[i - B::SY] + s[i + B::SY];
-    if (D == 3) v += s[i - B::SZ] + s[i + B::SZ];
-    return v;
-}
-
-// Stage a box of a global array whose origin is (ox, oy, oz); outside the
-// domain the box holds zeros (homogeneous Dirichlet ghosts).
-template <typename T, int D, typename B>
-__device__ __forceinline__ void stage(T* s, const T* __restrict__ g, int n, int ox, int oy, int oz, bool zero) {
-    for (int k = threadIdx.x; k < B::N; k += kThreads) {
-        int lx, ly, lz;
-        B::split(k, lx, ly, lz);
-        int x = ox + lx, y = oy + ly, z = oz + lz;
-        T v = T(0);
-        if (!zero && inside<D>(x, y, z, n)) v = g[gidx<D>(x, y, z, n)];
-        s[k] = v;
-    }
-}
 
 // Red update on the tile plus a halo of 1, then black on the tile, in LDS.
 // se: box with halo 2 (origin tile - 2), sr: box with halo 1 (origin tile - 1).
@@ -214,6 +126,90 @@ k_restrict_tile(const T* __restrict__ r, const T* __restrict__ e, T* __restrict_
     }
 }
 
+// One red-black step from e_in to e_out fused with the residual of the new
+// iterate and its full-weighting restriction to rc.  The tile's new iterate
+// is computed on the tile plus a halo of 1 (red on a halo of 2), so the
+// residual is available on every fine point under the tile's coarse points.
+template <typename T, int D, bool ZERO>
+__global__ void __launch_bounds__(kThreads)
+k_rbgs_restrict_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
+                     int n, int ntx, int nty, T a, T diag, T invdiag) {
+    using TL = Tile<D>;
+    using EB = Box<D, TL::X + 7, TL::Y + 7, TL::Z + 7>;  // old iterate, origin tile - 3
+    using RB = Box<D, TL::X + 5, TL::Y + 5, TL::Z + 5>;  // rhs (later residual), origin tile - 2
+    using BB = Box<D, TL::X + 3, TL::Y + 3, TL::Z + 3>;  // black region, origin tile - 1
+    using RP = Box<D, TL::X + 1, TL::Y + 1, TL::Z + 1>;  // residual region, origin tile
+    using B0 = Box<D, TL::X, TL::Y, TL::Z>;
+    __shared__ T se[EB::N];
+    __shared__ T sr[RB::N];
+    const int nc = (n - 1) / 2;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
+    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
+    stage<T, D, EB>(se, e_in, n, x0 - 3, y0 - 3 * hy, z0 - 3 * hz, ZERO);
+    stage<T, D, RB>(sr, r, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
+    __syncthreads();
+    auto eidx = [&](int lx, int ly, int lz, int off) {  // EB index of a point given in a box with origin tile - off
+        return ((lz + (3 - off) * hz) * EB::Y + (ly + (3 - off) * hy)) * EB::X + (lx + 3 - off);
+    };
+    for (int k = threadIdx.x; k < RB::N; k += kThreads) {  // red on the halo-2 region
+        int lx, ly, lz;
+        RB::split(k, lx, ly, lz);
+        int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
+        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) continue;
+        int i = eidx(lx, ly, lz, 2);
+        se[i] = (sr[k] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < BB::N; k += kThreads) {  // black on the halo-1 region
+        int lx, ly, lz;
+        BB::split(k, lx, ly, lz);
+        int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
+        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) continue;
+        int i = eidx(lx, ly, lz, 1);
+        int kr = ((lz + hz) * RB::Y + (ly + hy)) * RB::X + (lx + 1);
+        se[i] = (sr[kr] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
+        int lx, ly, lz;
+        B0::split(k, lx, ly, lz);
+        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (inside<D>(x, y, z, n)) e_out[gidx<D>(x, y, z, n)] = se[eidx(lx, ly, lz, 0)];
+    }
+    for (int k = threadIdx.x; k < RP::N; k += kThreads) {  // residual, in place of the rhs
+        int lx, ly, lz;
+        RP::split(k, lx, ly, lz);
+        if (!inside<D>(x0 + lx, y0 + ly, z0 + lz, n)) continue;
+        int i = eidx(lx, ly, lz, 0);
+        int kr = ((lz + 2 * hz) * RB::Y + (ly + 2 * hy)) * RB::X + (lx + 2);
+        sr[kr] = sr[kr] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
+    }
+    __syncthreads();
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    constexpr int CX = TL::X / 2, CY = D >= 2 ? TL::Y / 2 : 1, CZ = D == 3 ? TL::Z / 2 : 1;
+    for (int k = threadIdx.x; k < CX * CY * CZ; k += kThreads) {
+        int cx = k % CX;
+        int t = k / CX;
+        int cy = t % CY;
+        int cz = t / CY;
+        int X = x0 / 2 + cx, Y = (y0 / 2 + cy) * hy, Z = (z0 / 2 + cz) * hz;
+        if (!inside<D>(X, Y, Z, nc)) continue;
+        T acc = T(0);
+#pragma unroll
+        for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz) {
+#pragma unroll
+            for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
+                const int base = ((2 * cz + oz + 2 * hz) * RB::Y + (2 * cy + oy + 2 * hy)) * RB::X + 2 * cx + 2;
+                T row = w[0] * sr[base] + w[1] * sr[base + 1] + w[2] * sr[base + 2];
+                T wyz = (D >= 2 ? w[oy] : T(1)) * (D == 3 ? w[oz] : T(1));
+                acc += wyz * row;
+            }
+        }
+        rc[gidx<D>(X, Y, Z, nc)] = acc;
+    }
+}
+
 template <typename T, int D, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
@@ -282,30 +278,69 @@ k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T
 
 // ---------------------------------------------------------------- coarse tail
 // All levels n_t, (n_t-1)/2, ..., 1 in one workgroup with every level's
-// iterate, right-hand side and a residual scratch in LDS.  Threads are laid
-// out as a fixed (x, y, z) block so that no index needs a division.
+// iterate, right-hand side and a residual scratch in LDS.  Threads form a
+// fixed (X, Y, Z) block; thread (tx, ty, tz) owns at most P points of a level
+// (its "slots", strided along the last used axis), so no index needs a
+// division.  Each phase first computes all of a thread's values and only then
+// stores them, letting the LDS reads of all slots overlap.
 
 constexpr int kTail = 1024;
+// X * Y * Z = kTail; slots run along the last used axis, so a slot beyond the
+// level is skipped by whole waves (the slot coordinate is uniform per wave).
 template <int D> struct TailLayout;
-template <> struct TailLayout<1> { static constexpr int X = 1024, Y = 1, Z = 1, nmax = 2047, total = 4096; };
-template <> struct TailLayout<2> { static constexpr int X = 64, Y = 16, Z = 1, nmax = 63, total = 5216; };
-template <> struct TailLayout<3> { static constexpr int X = 16, Y = 16, Z = 4, nmax = 15, total = 3752; };
+template <> struct TailLayout<1> { static constexpr int X = 1024, Y = 1, Z = 1, P = 2, nmax = 2047, total = 4096, big = 2047; };
+template <> struct TailLayout<2> { static constexpr int X = 64, Y = 16, Z = 1, P = 4, nmax = 63, total = 5216, big = 3969; };
+template <> struct TailLayout<3> { static constexpr int X = 16, Y = 16, Z = 4, P = 4, nmax = 15, total = 3752, big = 3375; };
 
 template <int D>
 __device__ __forceinline__ int npts(int n) {
     return D == 1 ? n : (D == 2 ? n * n : n * n * n);
 }
 
-// Call f(x, y, z, i) for every point of an n^D level owned by this thread.
-template <int D, typename F>
-__device__ __forceinline__ void for_points(int n, F&& f) {
+// Call f(q, ok, x, y, z, i) for slots s0 + q, q < CH, of this thread on an
+// n^D level (ok: the point lies in the level).
+template <int D, int CH, typename F>
+__device__ __forceinline__ void slots(int n, int s0, F&& f) {
     using L = TailLayout<D>;
     const int tx = threadIdx.x % L::X;
     const int ty = (threadIdx.x / L::X) % L::Y;
     const int tz = threadIdx.x / (L::X * L::Y);
-    for (int z = tz; z < (D == 3 ? n : 1); z += L::Z)
-        for (int y = ty; y < (D >= 2 ? n : 1); y += L::Y)
-            for (int x = tx; x < n; x += L::X) f(x, y, z, D == 1 ? x : (z * n + y) * n + x);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int s = s0 + q;
+        const int x = D == 1 ? tx + L::X * s : tx;
+        const int y = D == 2 ? ty + L::Y * s : (D == 3 ? ty : 0);
+        const int z = D == 3 ? tz + L::Z * s : 0;
+        // slot coordinate beyond the level: the same for the whole wave
+        const int sc = D == 1 ? L::X * s : (D == 2 ? L::Y * s : s);
+        if (sc >= n) break;
+        const bool ok = x < n && (D < 2 || y < n) && (D < 3 || z < n);
+        f(q, ok, x, y, z, D == 1 ? x : (z * n + y) * n + x);
+    }
+}
+
+// Run a phase in chunks of slots: compute all values of a chunk, then store
+// them (the callers only ever read locations no chunk of the phase writes).
+template <int D> constexpr int chunk_of() { return D == 3 ? 1 : 4; }
+template <typename T, int D, typename Compute>
+__device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
+    constexpr int P = TailLayout<D>::P;
+    constexpr int CH = chunk_of<D>();
+#pragma unroll 1
+    for (int s0 = 0; s0 < P; s0 += CH) {
+        T v[CH];
+        int idx[CH];
+        bool wr[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) wr[q] = false;
+        slots<D, CH>(n, s0, [&](int q, bool ok, int x, int y, int z, int i) {
+            idx[q] = i;
+            wr[q] = compute(ok, x, y, z, i, v[q]);
+        });
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+            if (wr[q]) out[idx[q]] = v[q];
+    }
 }
 
 template <typename T, int D>
@@ -324,34 +359,85 @@ __device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int 
     return s;
 }
 
+// Linear interpolation of the coarse iterate ec (nc points per axis) at fine
+// point (x, y, z): per axis, odd -> (i-1)/2, even -> mean of i/2-1 and i/2,
+// with zeros outside the coarse grid.
+template <typename T, int D>
+__device__ __forceinline__ T interp_at(const T* ec, int nc, int x, int y, int z) {
+    auto tap = [&](int X, int Y, int Z) -> T {
+        if ((unsigned)X >= (unsigned)nc) return T(0);
+        if (D >= 2 && (unsigned)Y >= (unsigned)nc) return T(0);
+        if (D == 3 && (unsigned)Z >= (unsigned)nc) return T(0);
+        return ec[D == 1 ? X : (Z * nc + Y) * nc + X];
+    };
+    const int xa = (x & 1) ? (x - 1) / 2 : x / 2 - 1;
+    auto row = [&](int Y, int Z) -> T {
+        return (x & 1) ? tap(xa, Y, Z) : T(0.5) * tap(xa, Y, Z) + T(0.5) * tap(xa + 1, Y, Z);
+    };
+    auto plane = [&](int Z) -> T {
+        if (D < 2) return row(0, Z);
+        if (y & 1) return row((y - 1) / 2, Z);
+        return T(0.5) * row(y / 2 - 1, Z) + T(0.5) * row(y / 2, Z);
+    };
+    if (D < 3) return plane(0);
+    if (z & 1) return plane((z - 1) / 2);
+    return T(0.5) * plane(z / 2 - 1) + T(0.5) * plane(z / 2);
+}
+
+// Neighbour sum of the corrected iterate e + P ec, in the order of nb_lds.
+template <typename T, int D>
+__device__ __forceinline__ T nb_corrected(const T* e, const T* ec, int n, int nc, int x, int y, int z, int i) {
+    T s = T(0);
+    if (x > 0) s += e[i - 1] + interp_at<T, D>(ec, nc, x - 1, y, z);
+    if (x < n - 1) s += e[i + 1] + interp_at<T, D>(ec, nc, x + 1, y, z);
+    if (D >= 2) {
+        if (y > 0) s += e[i - n] + interp_at<T, D>(ec, nc, x, y - 1, z);
+        if (y < n - 1) s += e[i + n] + interp_at<T, D>(ec, nc, x, y + 1, z);
+    }
+    if (D == 3) {
+        if (z > 0) s += e[i - n * n] + interp_at<T, D>(ec, nc, x, y, z - 1);
+        if (z < n - 1) s += e[i + n * n] + interp_at<T, D>(ec, nc, x, y, z + 1);
+    }
+    return s;
+}
+
 template <typename T, int D>
 __device__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invdiag, T w, int smoother) {
     if (smoother == ISDC_SMOOTH_RBGS) {
         for (int colour = 0; colour < 2; ++colour) {
-            for_points<D>(n, [&](int x, int y, int z, int i) {
-                if (((x + y + z) & 1) == colour) e[i] = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
+            // a colour reads only the other colour: no barrier between compute and store
+            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+                if (!ok || ((x + y + z) & 1) != colour) return false;
+                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
+                return true;
             });
             __syncthreads();
         }
     } else {
-        for_points<D>(n, [&](int x, int y, int z, int i) {
-            T c = e[i];
-            tmp[i] = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, i))) * invdiag);
+        phase<T, D>(n, tmp, [&](bool ok, int x, int y, int z, int i, T& v) {
+            if (!ok) return false;
+            const T c = e[i];
+            v = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, i))) * invdiag);
+            return true;
         });
         __syncthreads();
-        for_points<D>(n, [&](int x, int y, int z, int i) { e[i] = tmp[i]; });
+        phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+            if (!ok) return false;
+            v = tmp[i];
+            return true;
+        });
         __syncthreads();
     }
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
-k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, double c, double h_t, int smoother, int nu1,
-       int nu2, double omega, int zero_guess) {
+k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
+       double omega, int zero_guess) {
     using L = TailLayout<D>;
     __shared__ T le[L::total];
     __shared__ T lr[L::total];
-    __shared__ T lt[D == 1 ? 2048 : (D == 2 ? 3969 : 3375)];
+    __shared__ T lt[L::big];
     int nlev = 0, off[16], nn[16];
     for (int o = 0, n = n_t;; n = (n - 1) / 2) {
         off[nlev] = o;
@@ -369,11 +455,9 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, double c, doub
     }
     __syncthreads();
     const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    double h = h_t;
     for (int l = 0; l < nlev; ++l) {
         const int n = nn[l];
-        const double ad = c / (h * h);
-        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
+        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
         T* e = le + off[l];
         T* r = lr + off[l];
         if (n == 1) {
@@ -382,85 +466,71 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, double c, doub
             break;
         }
         for (int k = 0; k < nu1; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
-        for_points<D>(n, [&](int x, int y, int z, int i) {
-            lt[i] = r[i] - (diag * e[i] - a * nb_lds<T, D>(e, n, x, y, z, i));
+        phase<T, D>(n, lt, [&](bool ok, int x, int y, int z, int i, T& v) {
+            if (!ok) return false;
+            v = r[i] - (diag * e[i] - a * nb_lds<T, D>(e, n, x, y, z, i));
+            return true;
         });
         __syncthreads();
         const int nc = (n - 1) / 2;
         T* rc = lr + off[l + 1];
         T* ec = le + off[l + 1];
-        for_points<D>(nc, [&](int X, int Y, int Z, int I) {
+        phase<T, D>(nc, rc, [&](bool ok, int X, int Y, int Z, int I, T& v) {
+            if (!ok) return false;
             T acc = T(0);
+#pragma unroll
             for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz)
+#pragma unroll
                 for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
                     const int fy = D >= 2 ? 2 * Y + oy : 0, fz = D == 3 ? 2 * Z + oz : 0;
                     const int base = (D == 1 ? 0 : (fz * n + fy) * n) + 2 * X;
                     T row = wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2];
                     acc += (D >= 2 ? wts[oy] : T(1)) * (D == 3 ? wts[oz] : T(1)) * row;
                 }
-            rc[I] = acc;
+            v = acc;
             ec[I] = T(0);
+            return true;
         });
         __syncthreads();
-        h *= 2.0;
     }
     for (int l = nlev - 2; l >= 0; --l) {
-        h *= 0.5;
         const int n = nn[l];
         const int nc = nn[l + 1];
-        const double ad = c / (h * h);
-        const T a = T(ad), diag = T(1.0 + 2.0 * D * ad), invdiag = T(1.0 / (1.0 + 2.0 * D * ad));
+        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
         T* e = le + off[l];
         T* r = lr + off[l];
         const T* ec = le + off[l + 1];
-        for_points<D>(n, [&](int x, int y, int z, int i) {
-            // linear interpolation, one axis at a time: odd -> (i-1)/2, even -> mean of i/2-1, i/2
-            int ix0, ix1, iy0 = 0, iy1 = 0, iz0 = 0, iz1 = 0;
-            T wx0, wx1, wy0 = T(1), wy1 = T(0), wz0 = T(1), wz1 = T(0);
-            if (x & 1) { ix0 = ix1 = (x - 1) / 2; wx0 = T(1); wx1 = T(0); }
-            else { ix0 = x / 2 - 1; ix1 = x / 2; wx0 = wx1 = T(0.5); }
-            if (D >= 2) {
-                if (y & 1) { iy0 = iy1 = (y - 1) / 2; }
-                else { iy0 = y / 2 - 1; iy1 = y / 2; wy0 = wy1 = T(0.5); }
-            }
-            if (D == 3) {
-                if (z & 1) { iz0 = iz1 = (z - 1) / 2; }
-                else { iz0 = z / 2 - 1; iz1 = z / 2; wz0 = wz1 = T(0.5); }
-            }
-            auto at = [&](int X, int Y, int Z) -> T {
-                if (X < 0 || X >= nc) return T(0);
-                if (D >= 2 && (Y < 0 || Y >= nc)) return T(0);
-                if (D == 3 && (Z < 0 || Z >= nc)) return T(0);
-                return ec[(D == 1) ? X : ((Z * nc + Y) * nc + X)];
-            };
-            T acc = T(0);
-            const int nzt = D == 3 ? 2 : 1, nyt = D >= 2 ? 2 : 1;
-            for (int cz = 0; cz < nzt; ++cz)
-                for (int cy = 0; cy < nyt; ++cy) {
-                    const int Y = cy ? iy1 : iy0, Z = cz ? iz1 : iz0;
-                    const T wyz = (cy ? wy1 : wy0) * (cz ? wz1 : wz0);
-                    if (wyz == T(0)) continue;
-                    T row = wx0 * at(ix0, Y, Z);
-                    if (wx1 != T(0)) row += wx1 * at(ix1, Y, Z);
-                    acc += wyz * row;
-                }
-            e[i] += acc;
-        });
-        __syncthreads();
-        for (int k = 0; k < nu2; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
+        int k0 = 0;
+        if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
+            // first red pass on the corrected iterate e + P ec without storing the
+            // correction: red reads only black values, black overwrites black
+            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+                if (!ok || ((x + y + z) & 1)) return false;
+                v = (r[i] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, i)) * invdiag;
+                return true;
+            });
+            __syncthreads();
+            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+                if (!ok || !((x + y + z) & 1)) return false;
+                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
+                return true;
+            });
+            __syncthreads();
+            k0 = 1;
+        } else {
+            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+                if (!ok) return false;
+                v = e[i] + interp_at<T, D>(ec, nc, x, y, z);
+                return true;
+            });
+            __syncthreads();
+        }
+        for (int k = k0; k < nu2; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
     }
     {
         const int N0 = npts<D>(n_t);
         for (int i = threadIdx.x; i < N0; i += kTail) e_g[i] = le[i];
     }
-}
-
-template <int D>
-inline void tile_counts(int n, int TX, int TY, int TZ, int& ntx, int& nty, int& nb) {
-    ntx = (n + TX - 1) / TX;
-    nty = D >= 2 ? (n + TY - 1) / TY : 1;
-    int ntz = D == 3 ? (n + TZ - 1) / TZ : 1;
-    nb = ntx * nty * ntz;
 }
 
 }  // namespace
@@ -499,6 +569,23 @@ hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, con
 }
 
 template <typename T>
+hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
+                                     T* rc, hipStream_t s) {
+    if (d == 3) return hipErrorInvalidValue;  // 3D uses the separate kernels (LDS budget)
+    ISDC_DISPATCH_D(d, {
+        if constexpr (D < 3) {
+            int ntx, nty, nb;
+            tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
+            if (zero)
+                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+            else
+                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+        }
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
                                     T* e_out, const double* g, double* u_out, int mode, hipStream_t s) {
     ISDC_DISPATCH_D(d, {
@@ -522,8 +609,17 @@ template <typename T>
 hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero_guess, const T* rhs, T* e,
                        hipStream_t s) {
     if (n > tail_max_n(cfg.d)) return hipErrorInvalidValue;
+    TailCoefs tc;
+    double hl = h;
+    for (int l = 0, m = n; l < 16; ++l, m = (m - 1) / 2, hl *= 2.0) {
+        const Coef<double> co = make_coef<double>(c, hl, cfg.d, cfg.omega);
+        tc.a[l] = co.a;
+        tc.diag[l] = co.diag;
+        tc.invdiag[l] = co.invdiag;
+        if (m == 1) break;
+    }
     ISDC_DISPATCH_D(cfg.d, {
-        hipLaunchKernelGGL((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, c, h, cfg.smoother, cfg.nu_pre,
+        hipLaunchKernelGGL((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, cfg.smoother, cfg.nu_pre,
                            cfg.nu_post, cfg.omega, zero_guess ? 1 : 0);
     });
     return hipGetLastError();
@@ -532,6 +628,8 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
 #define ISDC_INST_T(T)                                                                                          \
     template hipError_t launch_rbgs_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_restrict_tile<T>(int, int, const Coef<T>&, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_rbgs_restrict_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, T*,    \
+                                                     hipStream_t);                                                 \
     template hipError_t launch_prolong_rbgs_tile<T>(int, int, const Coef<T>&, const T*, const T*, const T*, T*,  \
                                                     const double*, double*, int, hipStream_t);                  \
     template hipError_t launch_tail<T>(const MGConfig&, int, double, double, bool, const T*, T*, hipStream_t);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -148,7 +149,8 @@ size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_pl
         h *= 2.0;
         ++l;
     }
-    void* part = take(kReduceBlocks * sizeof(double));
+    const int nparts = quad_partials(d, pb.n) > kReduceBlocks ? quad_partials(d, pb.n) : kReduceBlocks;
+    void* part = take((size_t)nparts * sizeof(double));
     void* sc = take(16 * sizeof(double));
     if (p) {
         p->partial = (double*)part;
@@ -212,13 +214,21 @@ bool vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T*
     Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
     T* cur = e;
     T* other = tmp;
-    smooth_steps<T>(p, p->mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
-    if (zero) {  // no pre-smoothing and a zero iterate
-        HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
-        zero = false;
-    }
     const Level& C = p->lev[l + 1];
-    HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
+    if (rbgs && p->mg.nu_pre >= 1 && p->d <= 2) {
+        // pre-smoothing steps; the last one fused with residual + restriction
+        smooth_steps<T>(p, p->mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s);
+        HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s));
+        std::swap(cur, other);
+        zero = false;
+    } else {
+        smooth_steps<T>(p, p->mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
+        if (zero) {  // no pre-smoothing and a zero iterate
+            HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
+            zero = false;
+        }
+        HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
+    }
     vcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
     bool fused = false;
     if (rbgs && p->mg.nu_post >= 1) {
@@ -639,6 +649,89 @@ extern "C" int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, 
             mg_op_impl<double>(plan, op, level, c, d_a, d_b, d_out, (hipStream_t)stream, h_scalar);
         else if (precision == ISDC_PREC_MIXED)
             mg_op_impl<float>(plan, op, level, c, d_a, d_b, d_out, (hipStream_t)stream, h_scalar);
+        else
+            fail(ISDC_E_INVAL, "unknown precision");
+    });
+}
+
+namespace {
+
+template <typename T>
+void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, hipStream_t s, double* avg_us,
+                      double* bytes) {
+    const int d = p->d;
+    const size_t w = sizeof(T);
+    if (kernel != ISDC_KERNEL_TAIL && kernel != ISDC_KERNEL_QUAD && (level < 0 || level >= p->tail))
+        fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
+    std::function<void()> launch;
+    double b = 0.0;
+    if (kernel == ISDC_KERNEL_SMOOTH_RESTRICT || kernel == ISDC_KERNEL_PROLONG_SMOOTH || kernel == ISDC_KERNEL_SMOOTH) {
+        const Level& L = p->lev[level];
+        const Level& C = p->lev[level + 1];
+        const Coef<T> co = make_coef<T>(c, L.h, d, p->mg.omega);
+        const double N = (double)L.N, Nc = (double)C.N;
+        if (kernel == ISDC_KERNEL_SMOOTH_RESTRICT) {
+            if (d == 3) fail(ISDC_E_UNSUPPORTED, "the fused smoothing + restriction kernel is 1D/2D only");
+            launch = [=]() { HIPCHK(launch_rbgs_restrict_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, (T*)C.r, s)); };
+            b = (3.0 * N + Nc) * w;
+        } else if (kernel == ISDC_KERNEL_PROLONG_SMOOTH) {
+            launch = [=]() { HIPCHK(launch_prolong_rbgs_tile<T>(d, L.n, co, (const T*)L.r, (const T*)L.e2, (const T*)C.e, (T*)L.e, nullptr, nullptr, 0, s)); };
+            b = (3.0 * N + Nc) * w;
+        } else {
+            launch = [=]() { HIPCHK(launch_rbgs_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, s)); };
+            b = 3.0 * N * w;
+        }
+    } else if (kernel == ISDC_KERNEL_TAIL) {
+        const Level& L = p->lev[p->tail];
+        launch = [=]() { HIPCHK(launch_tail<T>(p->mg, L.n, c, L.h, true, (const T*)L.r, (T*)L.e, s)); };
+        b = 2.0 * (double)L.N * w;
+    } else if (kernel == ISDC_KERNEL_QUAD) {
+        if (!p->begun) fail(ISDC_E_INVAL, "ISDC_KERNEL_QUAD needs a step in progress");
+        // quadrature + residual of the current iterate; S*F arrays are rewritten with the same values
+        launch = [=]() { quad_residual(p, p->cur, s); };
+        int reads = 1;  // u_0
+        for (int j = 1; j <= p->M; ++j)
+            if (p->cur[j] != p->u0) ++reads;
+        int writes = 0;
+        for (int m = 0; m < p->M; ++m)
+            if (p->SF[m]) ++writes;
+        b = (double)(reads + writes) * (double)p->N * 8.0;
+    } else {
+        fail(ISDC_E_INVAL, "unknown kernel");
+    }
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    launch();  // warm-up
+    for (int k = 0; k < reps; ++k) {
+        HIPCHK(hipEventRecord(ev[2 * k], s));
+        launch();
+        HIPCHK(hipEventRecord(ev[2 * k + 1], s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (int k = 0; k < reps; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        tot += ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    *avg_us = tot / reps * 1e3;
+    *bytes = b;
+}
+
+}  // namespace
+
+extern "C" int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision,
+                                int32_t reps, void* stream, double* h_avg_us, double* h_bytes) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!std::isfinite(c) || c < 0) fail(ISDC_E_INVAL, "c must be finite and >= 0");
+        if (reps < 1 || reps > 100000) fail(ISDC_E_INVAL, "reps must be in 1..100000");
+        if (!h_avg_us || !h_bytes) fail(ISDC_E_INVAL, "NULL output");
+        if (precision == ISDC_PREC_FP64)
+            time_kernel_impl<double>(plan, kernel, level, c, reps, (hipStream_t)stream, h_avg_us, h_bytes);
+        else if (precision == ISDC_PREC_MIXED)
+            time_kernel_impl<float>(plan, kernel, level, c, reps, (hipStream_t)stream, h_avg_us, h_bytes);
         else
             fail(ISDC_E_INVAL, "unknown precision");
     });

@@ -5,12 +5,13 @@
 #include <cmath>
 
 #include "internal.h"
+#include "tile_common.h"
 
 namespace isdc {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kThreads;
 
 __device__ __forceinline__ double nanmax(double a, double b) {
     if (a != a) return a;
@@ -52,45 +53,73 @@ __device__ __forceinline__ double fexp(double u, int fe) { return fe == ISDC_FE_
 
 template <int D>
 __device__ __forceinline__ void split(size_t i, int n, int& x, int& y, int& z) {
-    x = (int)(i % n);
-    size_t t = i / n;
-    y = (D >= 2) ? (int)(t % n) : 0;
-    z = (D == 3) ? (int)(t / n) : 0;
+    // N < 2^31 for every admissible grid, so 32-bit division suffices
+    const unsigned ii = (unsigned)i, un = (unsigned)n;
+    x = (int)(ii % un);
+    const unsigned t = ii / un;
+    y = (D >= 2) ? (int)(t % un) : 0;
+    z = (D == 3) ? (int)(t / un) : 0;
 }
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_quad_residual(QuadArgs qa, double* __restrict__ partial) {
-    const int n = qa.n, M = qa.M;
-    const size_t N = (D == 1) ? (size_t)n : (D == 2 ? (size_t)n * n : (size_t)n * n * n);
-    double mx = 0.0;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-        int x, y, z;
-        split<D>(i, n, x, y, z);
-        double f[ISDC_MAX_M], uc[ISDC_MAX_M];
+// Tiled form of the quadrature + residual kernel: one tile of points per
+// workgroup, each node array staged in LDS (tile plus a halo of 1) in turn.
+// Per point: f_j = nu L_h u_j + f^E(u_j); sf_m = sum_j dt s_{m,j} f_j;
+// acc_m = u_0 + sum_j dt q_{m,j} f_j - u_m, and the tile's max |acc_m| goes
+// to partial[workgroup].
+template <int D, int M>
+__global__ void __launch_bounds__(kThreads) k_quad_residual_tile(QuadArgs qa, int ntx, int nty, double* __restrict__ partial) {
+    using B1 = HaloBox<D, 1>;
+    using B0 = HaloBox<D, 0>;
+    constexpr int P = B0::N / kThreads;
+    __shared__ double su[B1::N];
+    const int n = qa.n;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
+    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
+    double sf[M][P], acc[M][P];
+    bool ok[P];
+    size_t gi[P];
+    int li[P];
 #pragma unroll
-        for (int j = 0; j < ISDC_MAX_M; ++j) {
-            if (j < M) {
-                const double* u = qa.u[j + 1];
-                double c = u[i];
-                uc[j] = c;
-                f[j] = qa.nu_h2 * lap_sum<D>(u, n, x, y, z, i, c) + fexp(c, qa.fe);
-            }
+    for (int s = 0; s < P; ++s) {
+        int lx, ly, lz;
+        B0::split(threadIdx.x + kThreads * s, lx, ly, lz);
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        ok[s] = inside<D>(x, y, z, n);
+        gi[s] = ok[s] ? gidx<D>(x, y, z, n) : 0;
+        li[s] = ((lz + hz) * B1::Y + (ly + hy)) * B1::X + (lx + 1);
+        const double u0 = ok[s] ? qa.u[0][gi[s]] : 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            sf[m][s] = 0.0;
+            acc[m][s] = u0;
         }
-        const double u0 = qa.u[0][i];
+    }
 #pragma unroll
-        for (int m = 0; m < ISDC_MAX_M; ++m) {
-            if (m < M) {
-                double sf = 0.0, q = 0.0;
+    for (int j = 0; j < M; ++j) {
+        if (j > 0) __syncthreads();
+        stage<double, D, B1>(su, qa.u[j + 1], n, x0 - 1, y0 - hy, z0 - hz, false);
+        __syncthreads();
 #pragma unroll
-                for (int j = 0; j < ISDC_MAX_M; ++j) {
-                    if (j < M) {
-                        sf += qa.dtS[m * ISDC_MAX_M + j] * f[j];
-                        q += qa.dtQ[m * ISDC_MAX_M + j] * f[j];
-                    }
-                }
-                if (qa.sf[m]) qa.sf[m][i] = sf;
-                mx = nanmax(mx, fabs(u0 + q - uc[m]));
+        for (int s = 0; s < P; ++s) {
+            const double c = su[li[s]];
+            const double f = qa.nu_h2 * (lds_nbsum<double, D, B1>(su, li[s]) - 2.0 * D * c) + fexp(c, qa.fe);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                sf[m][s] += qa.dtS[m * ISDC_MAX_M + j] * f;
+                acc[m][s] += qa.dtQ[m * ISDC_MAX_M + j] * f;
             }
+            acc[j][s] -= c;
+        }
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        if (!ok[s]) continue;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (qa.sf[m]) qa.sf[m][gi[s]] = sf[m][s];
+            mx = nanmax(mx, fabs(acc[m][s]));
         }
     }
     mx = block_max(mx);
@@ -150,12 +179,34 @@ inline int grid_for(size_t N, int cap) {
         default: return hipErrorInvalidValue;                \
     }
 
-hipError_t launch_quad_residual(int d, const QuadArgs& qa, double* partial, int* nblocks, hipStream_t s) {
-    size_t N = d == 1 ? (size_t)qa.n : (d == 2 ? (size_t)qa.n * qa.n : (size_t)qa.n * qa.n * qa.n);
-    int nb = grid_for(N, kReduceBlocks);
+int quad_partials(int d, int n) {
+    int ntx = 0, nty = 0, nb = 0;
+    if (d == 1) tile_counts<1>(n, Tile<1>::X, Tile<1>::Y, Tile<1>::Z, ntx, nty, nb);
+    else if (d == 2) tile_counts<2>(n, Tile<2>::X, Tile<2>::Y, Tile<2>::Z, ntx, nty, nb);
+    else tile_counts<3>(n, Tile<3>::X, Tile<3>::Y, Tile<3>::Z, ntx, nty, nb);
+    return nb;
+}
+
+template <int D>
+static hipError_t launch_quad_d(const QuadArgs& qa, double* partial, int* nblocks, hipStream_t s) {
+    int ntx, nty, nb;
+    tile_counts<D>(qa.n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
     *nblocks = nb;
-    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_quad_residual<D>), dim3(nb), dim3(kBlock), 0, s, qa, partial); });
+    switch (qa.M) {
+#define ISDC_QM(MM) \
+    case MM: hipLaunchKernelGGL((k_quad_residual_tile<D, MM>), dim3(nb), dim3(kThreads), 0, s, qa, ntx, nty, partial); break;
+        ISDC_QM(1) ISDC_QM(2) ISDC_QM(3) ISDC_QM(4) ISDC_QM(5) ISDC_QM(6) ISDC_QM(7) ISDC_QM(8) ISDC_QM(9)
+#undef ISDC_QM
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_quad_residual(int d, const QuadArgs& qa, double* partial, int* nblocks, hipStream_t s) {
+    if (d == 1) return launch_quad_d<1>(qa, partial, nblocks, s);
+    if (d == 2) return launch_quad_d<2>(qa, partial, nblocks, s);
+    if (d == 3) return launch_quad_d<3>(qa, partial, nblocks, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>

@@ -1,0 +1,113 @@
+// Tiling helpers shared by the LDS-tiled kernels (device code).
+//
+// A launch covers the grid with tiles of Tile<D> points, one workgroup per
+// tile.  Workgroups are renumbered so that each of the 8 XCDs (the hardware
+// hands workgroup b to XCD b mod 8) gets a contiguous band of tiles, which
+// keeps halo re-reads inside one XCD's L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace isdc {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int D> struct Tile;
+template <> struct Tile<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
+template <> struct Tile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
+template <> struct Tile<3> { static constexpr int X = 32, Y = 8, Z = 4; };
+
+// Coarse tile of the restriction kernel.
+template <int D> struct CTile;
+template <> struct CTile<1> { static constexpr int X = 512, Y = 1, Z = 1; };
+template <> struct CTile<2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <> struct CTile<3> { static constexpr int X = 8, Y = 4, Z = 4; };
+
+// A box of extents (X, Y, Z) in the used dimensions (unused ones are 1).
+template <int D, int EX, int EY, int EZ>
+struct Box {
+    static constexpr int X = EX;
+    static constexpr int Y = D >= 2 ? EY : 1;
+    static constexpr int Z = D == 3 ? EZ : 1;
+    static constexpr int N = X * Y * Z;
+    static constexpr int SY = X;      // stride of y
+    static constexpr int SZ = X * Y;  // stride of z
+    __device__ static __forceinline__ void split(int k, int& lx, int& ly, int& lz) {
+        lx = k % X;
+        int t = k / X;
+        ly = t % Y;
+        lz = t / Y;
+    }
+};
+
+template <int D, int H>
+using HaloBox = Box<D, Tile<D>::X + 2 * H, Tile<D>::Y + 2 * H, Tile<D>::Z + 2 * H>;
+
+template <int D>
+__device__ __forceinline__ bool inside(int x, int y, int z, int n) {
+    bool ok = (unsigned)x < (unsigned)n;
+    if (D >= 2) ok = ok && (unsigned)y < (unsigned)n;
+    if (D == 3) ok = ok && (unsigned)z < (unsigned)n;
+    return ok;
+}
+
+template <int D>
+__device__ __forceinline__ size_t gidx(int x, int y, int z, int n) {
+    if (D == 1) return (size_t)x;
+    if (D == 2) return (size_t)y * n + x;
+    return ((size_t)z * n + y) * n + x;
+}
+
+// Logical tile of this workgroup: XCD k gets a contiguous range of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int xcd = b & 7, slot = b >> 3;
+    return xcd * q + (xcd < rem ? xcd : rem) + slot;
+}
+
+__device__ __forceinline__ void tile_origin(int ntx, int nty, int TX, int TY, int TZ, int& x0, int& y0, int& z0) {
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    int tx = t % ntx;
+    int r = t / ntx;
+    int ty = r % nty;
+    int tz = r / nty;
+    x0 = tx * TX;
+    y0 = ty * TY;
+    z0 = tz * TZ;
+}
+
+// Sum of the 2d neighbours of LDS point i in box B (ghosts already zero).
+template <typename T, int D, typename B>
+__device__ __forceinline__ T lds_nbsum(const T* s, int i) {
+    T v = s[i - 1] + s[i + 1];
+    if (D >= 2) v += s[i - B::SY] + s[i + B::SY];
+    if (D == 3) v += s[i - B::SZ] + s[i + B::SZ];
+    return v;
+}
+
+// Stage a box of a global array whose origin is (ox, oy, oz); outside the
+// domain the box holds zeros (homogeneous Dirichlet ghosts).
+template <typename T, int D, typename B>
+__device__ __forceinline__ void stage(T* s, const T* __restrict__ g, int n, int ox, int oy, int oz, bool zero) {
+    for (int k = threadIdx.x; k < B::N; k += kThreads) {
+        int lx, ly, lz;
+        B::split(k, lx, ly, lz);
+        int x = ox + lx, y = oy + ly, z = oz + lz;
+        T v = T(0);
+        if (!zero && inside<D>(x, y, z, n)) v = g[gidx<D>(x, y, z, n)];
+        s[k] = v;
+    }
+}
+
+template <int D>
+inline void tile_counts(int n, int TX, int TY, int TZ, int& ntx, int& nty, int& nb) {
+    ntx = (n + TX - 1) / TX;
+    nty = D >= 2 ? (n + TY - 1) / TY : 1;
+    int ntz = D == 3 ? (n + TZ - 1) / TZ : 1;
+    nb = ntx * nty * ntz;
+}
+
+
+}  // namespace
+}  // namespace isdc

@@ -157,3 +157,10 @@ class Plan:
         A.check(self.lib.isdc_mg_op(self._h, op, level, c, prec, _dev_ptr(a), _dev_ptr(b), _dev_ptr(out),
                                     _stream_handle(stream), C.byref(res)))
         return res.value
+
+    def time_kernel(self, kernel: int, level: int, c: float, precision: int, reps: int = 100, stream=None):
+        """(average microseconds per launch, algorithmic bytes per launch) of one library kernel."""
+        us, b = C.c_double(), C.c_double()
+        A.check(self.lib.isdc_time_kernel(self._h, kernel, level, c, precision, reps, _stream_handle(stream),
+                                          C.byref(us), C.byref(b)))
+        return us.value, b.value

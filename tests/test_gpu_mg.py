@@ -163,3 +163,22 @@ def test_residual_norm_parity():
     r = p.mg_op(O_op("RESIDUAL_NORM"), 0, c, a=dev(rhs), b=dev(u))
     ref = float(np.max(np.abs(rhs - O.apply_shifted(u, c, h))))
     assert abs(r - ref) <= 1e-13 * ref
+
+
+def test_time_kernel_reports_durations_and_bytes():
+    announce("time_kernel")
+    import paper_1401_7824_amd as P
+    n = 255
+    p = _plan(2, n, RBGS)
+    h = 1.0 / (n + 1)
+    c = 10 * h * h
+    N, Nc = n * n, 127 * 127
+    for k, expect in [(P.KERNEL_SMOOTH_RESTRICT, (3 * N + Nc) * 8), (P.KERNEL_PROLONG_SMOOTH, (3 * N + Nc) * 8),
+                      (P.KERNEL_SMOOTH, 3 * N * 8), (P.KERNEL_TAIL, 2 * 63 * 63 * 8)]:
+        us, b = p.time_kernel(k, 0, c, 0, reps=5)
+        assert 0.0 < us < 1e4
+        assert b == expect
+    with pytest.raises(Exception):
+        p.time_kernel(P.KERNEL_QUAD, 0, c, 0, reps=2)  # no step in progress
+    with pytest.raises(Exception):
+        p.time_kernel(P.KERNEL_SMOOTH, 3, c, 0, reps=2)  # level 3 is the coarse tail
