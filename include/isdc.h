@@ -212,6 +212,61 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
 int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision, int32_t reps,
                      void* stream, double* h_avg_us, double* h_bytes);
 
+/* ---------------------------------------------------------------- batches
+ * A batch advances many independent ISDC instances ("slots") together: every
+ * phase of a sweep is one kernel launch covering all running slots, so small
+ * and uneven instances fill the GPU together.  Slots may differ in grid size,
+ * nu, f^E, dt, node family, M, tolerance, max_sweeps and number of steps; all
+ * slots of a batch share the dimension, the V-cycle precision and L, and run
+ * red-black Gauss-Seidel V(1,1) cycles warm-started from the previous sweep
+ * (Sec. 3, Sec. 4.3) -- other parameters return ISDC_E_UNSUPPORTED.  A
+ * slot's results are bitwise those of isdc_step on the same instance. */
+typedef struct isdc_batch isdc_batch;
+
+/* Slot states reported by isdc_batch_slot_info. */
+enum { ISDC_SLOT_FREE = 0, ISDC_SLOT_RUNNING = 1, ISDC_SLOT_FINISHED = 2 };
+
+/* Device workspace bytes of a batch with `capacity` slots (1..4096): slot
+ * descriptors, states, residuals and launch maps.  Host only. */
+int isdc_batch_workspace_bytes(int32_t capacity, size_t* out_bytes);
+
+/* Create a batch over caller-owned device workspace (256-byte aligned, at
+ * least isdc_batch_workspace_bytes).  dim, precision (ISDC_PREC_*) and
+ * vcycles (L >= 1) are common to all slots.  Host only. */
+int isdc_batch_create(int32_t capacity, int32_t dim, int32_t precision, int32_t vcycles, void* d_workspace,
+                      size_t bytes, isdc_batch** out);
+
+/* Destroy a batch (NULL is ignored); frees its slot plans and pinned host
+ * staging, not the caller's workspaces. */
+void isdc_batch_destroy(isdc_batch* batch);
+
+/* Occupy a slot that is not running: the instance (prob, par) over its own
+ * plan workspace d_plan_workspace (>= isdc_workspace_bytes(prob, par) bytes,
+ * 256-byte aligned), state d_u (n^d float64: u_0 on entry, u after the last
+ * step when the slot finishes; it must stay valid until then), step size dt
+ * and nsteps >= 1 steps.  The slot starts at the next isdc_batch_advance.
+ * Host only. */
+int isdc_batch_set(isdc_batch* batch, int32_t slot, const isdc_problem* prob, const isdc_params* par,
+                   void* d_plan_workspace, size_t plan_bytes, double* d_u, double dt, int32_t nsteps);
+
+/* One sweep of every running slot (slots that start a step are initialised
+ * first).  Synchronises `stream` once to read one residual per slot; a slot
+ * whose step converged (residual < sdc_tol) writes u_M to its state and
+ * either starts its next step at the next call or finishes; a slot whose
+ * residual is non-finite or that reaches max_sweeps finishes with
+ * ISDC_E_DIVERGED / ISDC_E_NOT_CONVERGED and its last iterate written.  Other
+ * slots are not affected.  *h_running (may be NULL) receives the number of
+ * slots still running. */
+int isdc_batch_advance(isdc_batch* batch, void* stream, int32_t* h_running);
+
+/* State (ISDC_SLOT_*), status of a finished slot, steps completed and the
+ * statistics of its last completed step.  Host only; outputs may be NULL. */
+int isdc_batch_slot_info(const isdc_batch* batch, int32_t slot, int32_t* state, int32_t* status,
+                         int32_t* steps_done, isdc_stats* last_step);
+
+/* Free a slot (finished or not) for reuse.  Host only. */
+int isdc_batch_release(isdc_batch* batch, int32_t slot);
+
 #ifdef __cplusplus
 }
 #endif

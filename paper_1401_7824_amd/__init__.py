@@ -9,13 +9,14 @@ from ._capi import (  # noqa: F401
     PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
     OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, load,
     KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD,
+    SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED,
 )
 
 
 def __getattr__(name):
     # the torch-based binding is imported lazily so that the C-ABI checks and the
     # input generators work without touching a GPU
-    if name in ("Plan", "StepStats", "tables", "make_params", "make_problem", "workspace_bytes"):
+    if name in ("Plan", "Batch", "StepStats", "tables", "make_params", "make_problem", "workspace_bytes"):
         from . import isdc
         return getattr(isdc, name)
     raise AttributeError(name)

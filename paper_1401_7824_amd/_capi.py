@@ -21,6 +21,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
 OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM = 0, 1, 2, 3, 4
 KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD = 0, 1, 2, 3, 4
+SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED = 0, 1, 2
 MAX_M = 9
 HIST = 128
 
@@ -61,6 +62,15 @@ SIGNATURES = [
     ("isdc_vcycle", C.c_int, [_VP, C.c_double, C.c_int32, _VP, _VP, C.c_int32, _VP, _DP]),
     ("isdc_mg_op", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _DP]),
     ("isdc_time_kernel", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, _VP, _DP, _DP]),
+    ("isdc_batch_workspace_bytes", C.c_int, [C.c_int32, _SZP]),
+    ("isdc_batch_create", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.c_size_t, C.POINTER(_VP)]),
+    ("isdc_batch_destroy", None, [_VP]),
+    ("isdc_batch_set", C.c_int, [_VP, C.c_int32, C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, _VP,
+                                 C.c_double, C.c_int32]),
+    ("isdc_batch_advance", C.c_int, [_VP, _VP, C.POINTER(C.c_int32)]),
+    ("isdc_batch_slot_info", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(Stats)]),
+    ("isdc_batch_release", C.c_int, [_VP, C.c_int32]),
 ]
 
 _lib = None

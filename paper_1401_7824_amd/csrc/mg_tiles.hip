@@ -18,519 +18,53 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
-#include "tile_common.h"
+#include "mg_device.h"
 
 namespace isdc {
 
 namespace {
 
-// Red update on the tile plus a halo of 1, then black on the tile, in LDS.
-// se: box with halo 2 (origin tile - 2), sr: box with halo 1 (origin tile - 1).
-template <typename T, int D>
-__device__ __forceinline__ void rbgs_in_lds(T* se, const T* sr, int n, int x0, int y0, int z0, T a, T invdiag) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
-    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    for (int k = threadIdx.x; k < B1::N; k += kThreads) {
-        int lx, ly, lz;
-        B1::split(k, lx, ly, lz);
-        int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
-        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) continue;
-        int i = ((lz + hz) * B2::Y + (ly + hy)) * B2::X + (lx + 1);
-        se[i] = (sr[k] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) continue;
-        int i = ((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2);
-        int k1 = ((lz + hz) * B1::Y + (ly + hy)) * B1::X + (lx + 1);
-        se[i] = (sr[k1] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
-    }
-    __syncthreads();
-}
-
 template <typename T, int D, bool ZERO>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
             T a, T invdiag) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
-    __shared__ T se[B2::N];
-    __shared__ T sr[B1::N];
     int x0, y0, z0;
     tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    stage<T, D, B2>(se, e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, ZERO);
-    stage<T, D, B1>(sr, r, n, x0 - 1, y0 - hy, z0 - hz, false);
-    __syncthreads();
-    rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n)) continue;
-        e_out[gidx<D>(x, y, z, n)] = se[((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2)];
-    }
+    rbgs_tile_body<T, D, ZERO>(r, e_in, e_out, n, x0, y0, z0, a, invdiag);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kThreads)
 k_restrict_tile(const T* __restrict__ r, const T* __restrict__ e, T* __restrict__ rc, int n, int ntx, int nty,
                 T a, T diag) {
-    using C = CTile<D>;
-    using FB = Box<D, 2 * C::X + 1, 2 * C::Y + 1, 2 * C::Z + 1>;  // fine points under the coarse tile
-    using EB = Box<D, 2 * C::X + 3, 2 * C::Y + 3, 2 * C::Z + 3>;  // ... plus a halo of 1
-    __shared__ T se[EB::N];
-    __shared__ T sres[FB::N];
-    const int nc = (n - 1) / 2;
     int X0, Y0, Z0;
-    tile_origin(ntx, nty, C::X, C::Y, C::Z, X0, Y0, Z0);
-    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    const int fx = 2 * X0, fy = 2 * Y0 * hy, fz = 2 * Z0 * hz;  // fine origin of FB
-    stage<T, D, EB>(se, e, n, fx - 1, fy - hy, fz - hz, false);
-    stage<T, D, FB>(sres, r, n, fx, fy, fz, false);
-    __syncthreads();
-    for (int k = threadIdx.x; k < FB::N; k += kThreads) {
-        int lx, ly, lz;
-        FB::split(k, lx, ly, lz);
-        if (!inside<D>(fx + lx, fy + ly, fz + lz, n)) continue;
-        int i = ((lz + hz) * EB::Y + (ly + hy)) * EB::X + (lx + 1);
-        sres[k] = sres[k] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
-    }
-    __syncthreads();
-    const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int k = threadIdx.x; k < C::X * (D >= 2 ? C::Y : 1) * (D == 3 ? C::Z : 1); k += kThreads) {
-        int cx = k % C::X;
-        int t = k / C::X;
-        int cy = D >= 2 ? t % C::Y : 0;
-        int cz = D == 3 ? t / C::Y : 0;
-        int X = X0 + cx, Y = Y0 + cy, Z = Z0 + cz;
-        if (!inside<D>(X, Y, Z, nc)) continue;
-        T acc = T(0);
-#pragma unroll
-        for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz) {
-#pragma unroll
-            for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
-                const int base = ((2 * cz + oz) * FB::Y + (2 * cy + oy)) * FB::X + 2 * cx;
-                T row = w[0] * sres[base] + w[1] * sres[base + 1] + w[2] * sres[base + 2];
-                T wyz = (D >= 2 ? w[oy] : T(1)) * (D == 3 ? w[oz] : T(1));
-                acc += wyz * row;
-            }
-        }
-        rc[gidx<D>(X, Y, Z, nc)] = acc;
-    }
+    tile_origin(ntx, nty, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, X0, Y0, Z0);
+    restrict_tile_body<T, D>(r, e, rc, n, X0, Y0, Z0, a, diag);
 }
 
-// One red-black step from e_in to e_out fused with the residual of the new
-// iterate and its full-weighting restriction to rc.  The tile's new iterate
-// is computed on the tile plus a halo of 1 (red on a halo of 2), so the
-// residual is available on every fine point under the tile's coarse points.
 template <typename T, int D, bool ZERO>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_restrict_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
                      int n, int ntx, int nty, T a, T diag, T invdiag) {
-    using TL = Tile<D>;
-    using EB = Box<D, TL::X + 7, TL::Y + 7, TL::Z + 7>;  // old iterate, origin tile - 3
-    using RB = Box<D, TL::X + 5, TL::Y + 5, TL::Z + 5>;  // rhs (later residual), origin tile - 2
-    using BB = Box<D, TL::X + 3, TL::Y + 3, TL::Z + 3>;  // black region, origin tile - 1
-    using RP = Box<D, TL::X + 1, TL::Y + 1, TL::Z + 1>;  // residual region, origin tile
-    using B0 = Box<D, TL::X, TL::Y, TL::Z>;
-    __shared__ T se[EB::N];
-    __shared__ T sr[RB::N];
-    const int nc = (n - 1) / 2;
     int x0, y0, z0;
-    tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
-    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    stage<T, D, EB>(se, e_in, n, x0 - 3, y0 - 3 * hy, z0 - 3 * hz, ZERO);
-    stage<T, D, RB>(sr, r, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
-    __syncthreads();
-    auto eidx = [&](int lx, int ly, int lz, int off) {  // EB index of a point given in a box with origin tile - off
-        return ((lz + (3 - off) * hz) * EB::Y + (ly + (3 - off) * hy)) * EB::X + (lx + 3 - off);
-    };
-    for (int k = threadIdx.x; k < RB::N; k += kThreads) {  // red on the halo-2 region
-        int lx, ly, lz;
-        RB::split(k, lx, ly, lz);
-        int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
-        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) continue;
-        int i = eidx(lx, ly, lz, 2);
-        se[i] = (sr[k] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < BB::N; k += kThreads) {  // black on the halo-1 region
-        int lx, ly, lz;
-        BB::split(k, lx, ly, lz);
-        int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
-        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) continue;
-        int i = eidx(lx, ly, lz, 1);
-        int kr = ((lz + hz) * RB::Y + (ly + hy)) * RB::X + (lx + 1);
-        se[i] = (sr[kr] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (inside<D>(x, y, z, n)) e_out[gidx<D>(x, y, z, n)] = se[eidx(lx, ly, lz, 0)];
-    }
-    for (int k = threadIdx.x; k < RP::N; k += kThreads) {  // residual, in place of the rhs
-        int lx, ly, lz;
-        RP::split(k, lx, ly, lz);
-        if (!inside<D>(x0 + lx, y0 + ly, z0 + lz, n)) continue;
-        int i = eidx(lx, ly, lz, 0);
-        int kr = ((lz + 2 * hz) * RB::Y + (ly + 2 * hy)) * RB::X + (lx + 2);
-        sr[kr] = sr[kr] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
-    }
-    __syncthreads();
-    const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    constexpr int CX = TL::X / 2, CY = D >= 2 ? TL::Y / 2 : 1, CZ = D == 3 ? TL::Z / 2 : 1;
-    for (int k = threadIdx.x; k < CX * CY * CZ; k += kThreads) {
-        int cx = k % CX;
-        int t = k / CX;
-        int cy = t % CY;
-        int cz = t / CY;
-        int X = x0 / 2 + cx, Y = (y0 / 2 + cy) * hy, Z = (z0 / 2 + cz) * hz;
-        if (!inside<D>(X, Y, Z, nc)) continue;
-        T acc = T(0);
-#pragma unroll
-        for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz) {
-#pragma unroll
-            for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
-                const int base = ((2 * cz + oz + 2 * hz) * RB::Y + (2 * cy + oy + 2 * hy)) * RB::X + 2 * cx + 2;
-                T row = w[0] * sr[base] + w[1] * sr[base + 1] + w[2] * sr[base + 2];
-                T wyz = (D >= 2 ? w[oy] : T(1)) * (D == 3 ? w[oz] : T(1));
-                acc += wyz * row;
-            }
-        }
-        rc[gidx<D>(X, Y, Z, nc)] = acc;
-    }
+    tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
+    rbgs_restrict_body<T, D, ZERO>(r, e_in, e_out, rc, n, x0, y0, z0, a, diag, invdiag);
 }
 
 template <typename T, int D, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
                     int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
-    using CB = Box<D, Tile<D>::X / 2 + 4, Tile<D>::Y / 2 + 4, Tile<D>::Z / 2 + 4>;
-    __shared__ T se[B2::N];
-    __shared__ T sr[B1::N];
-    __shared__ T sc[CB::N];
-    const int nc = (n - 1) / 2;
     int x0, y0, z0;
     tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    const int cxo = x0 / 2 - 2, cyo = (y0 / 2 - 2) * hy, czo = (z0 / 2 - 2) * hz;
-    stage<T, D, B2>(se, e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
-    stage<T, D, B1>(sr, r, n, x0 - 1, y0 - hy, z0 - hz, false);
-    stage<T, D, CB>(sc, ec, nc, cxo, cyo, czo, false);
-    __syncthreads();
-    // coarse-grid correction on the whole halo-2 box
-    for (int k = threadIdx.x; k < B2::N; k += kThreads) {
-        int lx, ly, lz;
-        B2::split(k, lx, ly, lz);
-        int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
-        if (!inside<D>(x, y, z, n)) continue;
-        // linear interpolation per axis: odd index -> one coarse point, even
-        // index -> mean of two; zeros outside [0, nc) are already staged
-        int ix0, iy0 = 0, iz0 = 0;
-        T wx1 = T(0), wy1 = T(0), wz1 = T(0), wx0 = T(1), wy0 = T(1), wz0 = T(1);
-        if (x & 1) { ix0 = (x - 1) / 2 - cxo; }
-        else { ix0 = x / 2 - 1 - cxo; wx0 = wx1 = T(0.5); }
-        if (D >= 2) {
-            if (y & 1) { iy0 = (y - 1) / 2 - cyo; }
-            else { iy0 = y / 2 - 1 - cyo; wy0 = wy1 = T(0.5); }
-        }
-        if (D == 3) {
-            if (z & 1) { iz0 = (z - 1) / 2 - czo; }
-            else { iz0 = z / 2 - 1 - czo; wz0 = wz1 = T(0.5); }
-        }
-        // weights of the second tap are zero for odd indices, so reading it is harmless
-        const int b00 = (iz0 * CB::Y + iy0) * CB::X + ix0;
-        T acc = wy0 * (wx0 * sc[b00] + wx1 * sc[b00 + 1]);
-        if (D >= 2) acc += wy1 * (wx0 * sc[b00 + CB::SY] + wx1 * sc[b00 + CB::SY + 1]);
-        if (D == 3) {
-            T acc1 = wy0 * (wx0 * sc[b00 + CB::SZ] + wx1 * sc[b00 + CB::SZ + 1]);
-            acc1 += wy1 * (wx0 * sc[b00 + CB::SZ + CB::SY] + wx1 * sc[b00 + CB::SZ + CB::SY + 1]);
-            acc = wz0 * acc + wz1 * acc1;
-        }
-        se[k] += acc;
-    }
-    __syncthreads();
-    rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n)) continue;
-        const size_t gi = gidx<D>(x, y, z, n);
-        const T v = se[((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2)];
-        if (MODE == 0) e_out[gi] = v;
-        else if (MODE == 1) u_out[gi] = g[gi] + (double)v;
-        else u_out[gi] = (double)v;
-    }
-}
-
-// ---------------------------------------------------------------- coarse tail
-// All levels n_t, (n_t-1)/2, ..., 1 in one workgroup with every level's
-// iterate, right-hand side and a residual scratch in LDS.  Threads form a
-// fixed (X, Y, Z) block; thread (tx, ty, tz) owns at most P points of a level
-// (its "slots", strided along the last used axis), so no index needs a
-// division.  Each phase first computes all of a thread's values and only then
-// stores them, letting the LDS reads of all slots overlap.
-
-constexpr int kTail = 1024;
-// X * Y * Z = kTail; slots run along the last used axis, so a slot beyond the
-// level is skipped by whole waves (the slot coordinate is uniform per wave).
-template <int D> struct TailLayout;
-template <> struct TailLayout<1> { static constexpr int X = 1024, Y = 1, Z = 1, P = 2, nmax = 2047, total = 4096, big = 2047; };
-template <> struct TailLayout<2> { static constexpr int X = 64, Y = 16, Z = 1, P = 4, nmax = 63, total = 5216, big = 3969; };
-template <> struct TailLayout<3> { static constexpr int X = 16, Y = 16, Z = 4, P = 4, nmax = 15, total = 3752, big = 3375; };
-
-template <int D>
-__device__ __forceinline__ int npts(int n) {
-    return D == 1 ? n : (D == 2 ? n * n : n * n * n);
-}
-
-// Call f(q, ok, x, y, z, i) for slots s0 + q, q < CH, of this thread on an
-// n^D level (ok: the point lies in the level).
-template <int D, int CH, typename F>
-__device__ __forceinline__ void slots(int n, int s0, F&& f) {
-    using L = TailLayout<D>;
-    const int tx = threadIdx.x % L::X;
-    const int ty = (threadIdx.x / L::X) % L::Y;
-    const int tz = threadIdx.x / (L::X * L::Y);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int s = s0 + q;
-        const int x = D == 1 ? tx + L::X * s : tx;
-        const int y = D == 2 ? ty + L::Y * s : (D == 3 ? ty : 0);
-        const int z = D == 3 ? tz + L::Z * s : 0;
-        // slot coordinate beyond the level: the same for the whole wave
-        const int sc = D == 1 ? L::X * s : (D == 2 ? L::Y * s : s);
-        if (sc >= n) break;
-        const bool ok = x < n && (D < 2 || y < n) && (D < 3 || z < n);
-        f(q, ok, x, y, z, D == 1 ? x : (z * n + y) * n + x);
-    }
-}
-
-// Run a phase in chunks of slots: compute all values of a chunk, then store
-// them (the callers only ever read locations no chunk of the phase writes).
-template <int D> constexpr int chunk_of() { return D == 3 ? 1 : 4; }
-template <typename T, int D, typename Compute>
-__device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
-    constexpr int P = TailLayout<D>::P;
-    constexpr int CH = chunk_of<D>();
-#pragma unroll 1
-    for (int s0 = 0; s0 < P; s0 += CH) {
-        T v[CH];
-        int idx[CH];
-        bool wr[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q) wr[q] = false;
-        slots<D, CH>(n, s0, [&](int q, bool ok, int x, int y, int z, int i) {
-            idx[q] = i;
-            wr[q] = compute(ok, x, y, z, i, v[q]);
-        });
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-            if (wr[q]) out[idx[q]] = v[q];
-    }
-}
-
-template <typename T, int D>
-__device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int i) {
-    T s = T(0);
-    if (x > 0) s += e[i - 1];
-    if (x < n - 1) s += e[i + 1];
-    if (D >= 2) {
-        if (y > 0) s += e[i - n];
-        if (y < n - 1) s += e[i + n];
-    }
-    if (D == 3) {
-        if (z > 0) s += e[i - n * n];
-        if (z < n - 1) s += e[i + n * n];
-    }
-    return s;
-}
-
-// Linear interpolation of the coarse iterate ec (nc points per axis) at fine
-// point (x, y, z): per axis, odd -> (i-1)/2, even -> mean of i/2-1 and i/2,
-// with zeros outside the coarse grid.
-template <typename T, int D>
-__device__ __forceinline__ T interp_at(const T* ec, int nc, int x, int y, int z) {
-    auto tap = [&](int X, int Y, int Z) -> T {
-        if ((unsigned)X >= (unsigned)nc) return T(0);
-        if (D >= 2 && (unsigned)Y >= (unsigned)nc) return T(0);
-        if (D == 3 && (unsigned)Z >= (unsigned)nc) return T(0);
-        return ec[D == 1 ? X : (Z * nc + Y) * nc + X];
-    };
-    const int xa = (x & 1) ? (x - 1) / 2 : x / 2 - 1;
-    auto row = [&](int Y, int Z) -> T {
-        return (x & 1) ? tap(xa, Y, Z) : T(0.5) * tap(xa, Y, Z) + T(0.5) * tap(xa + 1, Y, Z);
-    };
-    auto plane = [&](int Z) -> T {
-        if (D < 2) return row(0, Z);
-        if (y & 1) return row((y - 1) / 2, Z);
-        return T(0.5) * row(y / 2 - 1, Z) + T(0.5) * row(y / 2, Z);
-    };
-    if (D < 3) return plane(0);
-    if (z & 1) return plane((z - 1) / 2);
-    return T(0.5) * plane(z / 2 - 1) + T(0.5) * plane(z / 2);
-}
-
-// Neighbour sum of the corrected iterate e + P ec, in the order of nb_lds.
-template <typename T, int D>
-__device__ __forceinline__ T nb_corrected(const T* e, const T* ec, int n, int nc, int x, int y, int z, int i) {
-    T s = T(0);
-    if (x > 0) s += e[i - 1] + interp_at<T, D>(ec, nc, x - 1, y, z);
-    if (x < n - 1) s += e[i + 1] + interp_at<T, D>(ec, nc, x + 1, y, z);
-    if (D >= 2) {
-        if (y > 0) s += e[i - n] + interp_at<T, D>(ec, nc, x, y - 1, z);
-        if (y < n - 1) s += e[i + n] + interp_at<T, D>(ec, nc, x, y + 1, z);
-    }
-    if (D == 3) {
-        if (z > 0) s += e[i - n * n] + interp_at<T, D>(ec, nc, x, y, z - 1);
-        if (z < n - 1) s += e[i + n * n] + interp_at<T, D>(ec, nc, x, y, z + 1);
-    }
-    return s;
-}
-
-template <typename T, int D>
-__device__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invdiag, T w, int smoother) {
-    if (smoother == ISDC_SMOOTH_RBGS) {
-        for (int colour = 0; colour < 2; ++colour) {
-            // a colour reads only the other colour: no barrier between compute and store
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || ((x + y + z) & 1) != colour) return false;
-                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-        }
-    } else {
-        phase<T, D>(n, tmp, [&](bool ok, int x, int y, int z, int i, T& v) {
-            if (!ok) return false;
-            const T c = e[i];
-            v = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, i))) * invdiag);
-            return true;
-        });
-        __syncthreads();
-        phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-            if (!ok) return false;
-            v = tmp[i];
-            return true;
-        });
-        __syncthreads();
-    }
+    prolong_rbgs_body<T, D, MODE>(r, e_in, ec, e_out, n, x0, y0, z0, a, invdiag, g, u_out);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
        double omega, int zero_guess) {
-    using L = TailLayout<D>;
-    __shared__ T le[L::total];
-    __shared__ T lr[L::total];
-    __shared__ T lt[L::big];
-    int nlev = 0, off[16], nn[16];
-    for (int o = 0, n = n_t;; n = (n - 1) / 2) {
-        off[nlev] = o;
-        nn[nlev] = n;
-        o += npts<D>(n);
-        ++nlev;
-        if (n == 1) break;
-    }
-    {
-        const int N0 = npts<D>(n_t);
-        for (int i = threadIdx.x; i < N0; i += kTail) {
-            lr[i] = rhs_g[i];
-            le[i] = zero_guess ? T(0) : e_g[i];
-        }
-    }
-    __syncthreads();
-    const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int l = 0; l < nlev; ++l) {
-        const int n = nn[l];
-        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
-        T* e = le + off[l];
-        T* r = lr + off[l];
-        if (n == 1) {
-            if (threadIdx.x == 0) e[0] = r[0] / diag;
-            __syncthreads();
-            break;
-        }
-        for (int k = 0; k < nu1; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
-        phase<T, D>(n, lt, [&](bool ok, int x, int y, int z, int i, T& v) {
-            if (!ok) return false;
-            v = r[i] - (diag * e[i] - a * nb_lds<T, D>(e, n, x, y, z, i));
-            return true;
-        });
-        __syncthreads();
-        const int nc = (n - 1) / 2;
-        T* rc = lr + off[l + 1];
-        T* ec = le + off[l + 1];
-        phase<T, D>(nc, rc, [&](bool ok, int X, int Y, int Z, int I, T& v) {
-            if (!ok) return false;
-            T acc = T(0);
-#pragma unroll
-            for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz)
-#pragma unroll
-                for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
-                    const int fy = D >= 2 ? 2 * Y + oy : 0, fz = D == 3 ? 2 * Z + oz : 0;
-                    const int base = (D == 1 ? 0 : (fz * n + fy) * n) + 2 * X;
-                    T row = wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2];
-                    acc += (D >= 2 ? wts[oy] : T(1)) * (D == 3 ? wts[oz] : T(1)) * row;
-                }
-            v = acc;
-            ec[I] = T(0);
-            return true;
-        });
-        __syncthreads();
-    }
-    for (int l = nlev - 2; l >= 0; --l) {
-        const int n = nn[l];
-        const int nc = nn[l + 1];
-        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
-        T* e = le + off[l];
-        T* r = lr + off[l];
-        const T* ec = le + off[l + 1];
-        int k0 = 0;
-        if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
-            // first red pass on the corrected iterate e + P ec without storing the
-            // correction: red reads only black values, black overwrites black
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || ((x + y + z) & 1)) return false;
-                v = (r[i] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || !((x + y + z) & 1)) return false;
-                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-            k0 = 1;
-        } else {
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok) return false;
-                v = e[i] + interp_at<T, D>(ec, nc, x, y, z);
-                return true;
-            });
-            __syncthreads();
-        }
-        for (int k = k0; k < nu2; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
-    }
-    {
-        const int N0 = npts<D>(n_t);
-        for (int i = threadIdx.x; i < N0; i += kTail) e_g[i] = le[i];
-    }
+    tail_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
 }
 
 }  // namespace

@@ -1,0 +1,93 @@
+// Host-side plan structure and error plumbing shared by the runtime and the
+// batch engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace isdc {
+
+std::string& last_error();
+
+#define HIPCHK(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            throw ::isdc::Error{ISDC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline size_t pow_d(size_t n, int d) { return d == 1 ? n : (d == 2 ? n * n : n * n * n); }
+
+// Run f, turning exceptions into a status code and the thread's last error.
+template <typename F>
+int guarded(F&& f) {
+    try {
+        f();
+        last_error().clear();
+        return ISDC_OK;
+    } catch (const Error& e) {
+        last_error() = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        last_error() = e.what();
+        return ISDC_E_HIP;
+    } catch (...) {
+        last_error() = "unknown error";
+        return ISDC_E_HIP;
+    }
+}
+
+struct Level {
+    int n;
+    double h;
+    size_t N;
+    void* r;
+    void* e;
+    void* e2;  // ping-pong partner of the out-of-place smoothers
+};
+
+void validate(const isdc_problem* pb, const isdc_params* pr);
+size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p);
+
+}  // namespace isdc
+
+struct isdc_plan {
+    isdc_problem prob;
+    isdc_params par;
+    int d, n;
+    size_t N;
+    double h;
+    int M;
+    double tau[ISDC_MAX_M], Q[ISDC_MAX_M * ISDC_MAX_M], S[ISDC_MAX_M * ISDC_MAX_M];
+    double dtau[ISDC_MAX_M];  // tau_{m+1} - tau_m, tau_0 = 0
+    isdc::MGConfig mg;
+    std::vector<isdc::Level> lev;
+    int tail;  // index of the level run by the single-workgroup tail kernel
+
+    double* U[2][ISDC_MAX_M + 1];  // node arrays written by sweeps (index 0 unused)
+    double* SF[ISDC_MAX_M];        // S_m^{m+1} F for substep m (NULL if dt_m = 0)
+    double* partial;
+    double* scalars;
+
+    // step state
+    const double* u0 = nullptr;
+    double dt = 0.0;
+    const double* cur[ISDC_MAX_M + 1];  // current iterate per node (0 = u_0)
+    int wbuf = 0;                       // which U table the next sweep writes
+    bool begun = false;
+    isdc_stats stats;
+    double* h_pinned = nullptr;
+};
+
+namespace isdc {
+// Fill a freshly allocated plan from validated arguments (host only).
+void init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* par, void* d_workspace);
+}  // namespace isdc

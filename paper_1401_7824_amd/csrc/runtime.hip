@@ -10,65 +10,16 @@
 #include <vector>
 
 #include "internal.h"
+#include "plan.h"
 
 using namespace isdc;
 
-namespace {
-
-thread_local std::string g_last_error;
-
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            throw Error{ISDC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
-    } while (0)
-
-[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-inline size_t pow_d(size_t n, int d) { return d == 1 ? n : (d == 2 ? n * n : n * n * n); }
-
-struct Level {
-    int n;
-    double h;
-    size_t N;
-    void* r;
-    void* e;
-    void* e2;  // Jacobi ping-pong partner
-};
-
-}  // namespace
-
-struct isdc_plan {
-    isdc_problem prob;
-    isdc_params par;
-    int d, n;
-    size_t N;
-    double h;
-    int M;
-    double tau[ISDC_MAX_M], Q[ISDC_MAX_M * ISDC_MAX_M], S[ISDC_MAX_M * ISDC_MAX_M];
-    double dtau[ISDC_MAX_M];  // tau_{m+1} - tau_m, tau_0 = 0
-    MGConfig mg;
-    std::vector<Level> lev;
-    int tail;  // index of the level run by the single-workgroup tail kernel
-
-    double* U[2][ISDC_MAX_M + 1];  // node arrays written by sweeps (index 0 unused)
-    double* SF[ISDC_MAX_M];        // S_m^{m+1} F for substep m (NULL if dt_m = 0)
-    double* partial;
-    double* scalars;
-
-    // step state
-    const double* u0 = nullptr;
-    double dt = 0.0;
-    const double* cur[ISDC_MAX_M + 1];  // current iterate per node (0 = u_0)
-    int wbuf = 0;                       // which U table the next sweep writes
-    bool begun = false;
-    isdc_stats stats;
-    double* h_pinned = nullptr;
-};
+namespace isdc {
+std::string& last_error() {
+    thread_local std::string msg;
+    return msg;
+}
+}  // namespace isdc
 
 namespace {
 
@@ -80,7 +31,9 @@ bool valid_n(int d, int n) {
     return k <= kmax;
 }
 
-void validate(const isdc_problem* pb, const isdc_params* pr) {
+}  // namespace
+
+void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
     if (!pb || !pr) fail(ISDC_E_INVAL, "NULL problem or params");
     if (pb->dim < 1 || pb->dim > 3) fail(ISDC_E_INVAL, "dim must be 1, 2 or 3");
     if (!valid_n(pb->dim, pb->n)) fail(ISDC_E_INVAL, "n must be 2^k - 1 within the size limit for dim");
@@ -106,7 +59,7 @@ void validate(const isdc_problem* pb, const isdc_params* pr) {
 }
 
 // Lay the plan's arrays out from `base` (nullptr: sizing only); returns the byte count.
-size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p) {
+size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p) {
     const int d = pb.dim, M = pr.M;
     const size_t N = pow_d((size_t)pb.n, d);
     size_t off = 0;
@@ -159,6 +112,8 @@ size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_pl
     (void)tau;
     return off;
 }
+
+namespace {
 
 void ensure_pinned(isdc_plan* p) {
     if (!p->h_pinned) {
@@ -372,29 +327,33 @@ void end_impl(isdc_plan* p, double* d_out, hipStream_t s) {
     p->begun = false;
 }
 
-template <typename F>
-int guarded(F&& f) {
-    try {
-        f();
-        g_last_error.clear();
-        return ISDC_OK;
-    } catch (const Error& e) {
-        g_last_error = e.msg;
-        return e.code;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return ISDC_E_HIP;
-    } catch (...) {
-        g_last_error = "unknown error";
-        return ISDC_E_HIP;
-    }
-}
-
 void check_plan(const isdc_plan* p) {
     if (!p) fail(ISDC_E_INVAL, "plan is NULL");
 }
 
 }  // namespace
+
+
+void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* par, void* d_workspace) {
+    p->prob = *prob;
+    p->par = *par;
+    p->d = prob->dim;
+    p->n = prob->n;
+    p->N = pow_d((size_t)prob->n, prob->dim);
+    p->h = 1.0 / (prob->n + 1);
+    p->M = par->M;
+    tables(par->node_kind, par->M, p->tau, p->Q, p->S);
+    double prev = 0.0;
+    for (int m = 0; m < p->M; ++m) {
+        p->dtau[m] = p->tau[m] - prev;
+        prev = p->tau[m];
+    }
+    p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post, 2.0 * p->d / (2.0 * p->d + 1.0)};
+    std::memset(p->U, 0, sizeof(p->U));
+    std::memset(p->SF, 0, sizeof(p->SF));
+    layout(*prob, *par, (char*)d_workspace, p);
+    std::memset(&p->stats, 0, sizeof(p->stats));
+}
 
 // ================================================================ C ABI
 
@@ -409,7 +368,7 @@ int isdc_abi_sizes(size_t* problem, size_t* params, size_t* stats) {
     return ISDC_OK;
 }
 
-const char* isdc_last_error(void) { return g_last_error.c_str(); }
+const char* isdc_last_error(void) { return isdc::last_error().c_str(); }
 
 int isdc_default_params(isdc_params* p) {
     return guarded([&] {
@@ -454,24 +413,7 @@ int isdc_create(const isdc_problem* prob, const isdc_params* par, void* d_worksp
         if (((uintptr_t)d_workspace) % kAlign) fail(ISDC_E_WORKSPACE, "workspace must be 256-byte aligned");
         if (bytes < need) fail(ISDC_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
         isdc_plan* p = new isdc_plan();
-        p->prob = *prob;
-        p->par = *par;
-        p->d = prob->dim;
-        p->n = prob->n;
-        p->N = pow_d((size_t)prob->n, prob->dim);
-        p->h = 1.0 / (prob->n + 1);
-        p->M = par->M;
-        tables(par->node_kind, par->M, p->tau, p->Q, p->S);
-        double prev = 0.0;
-        for (int m = 0; m < p->M; ++m) {
-            p->dtau[m] = p->tau[m] - prev;
-            prev = p->tau[m];
-        }
-        p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post, 2.0 * p->d / (2.0 * p->d + 1.0)};
-        std::memset(p->U, 0, sizeof(p->U));
-        std::memset(p->SF, 0, sizeof(p->SF));
-        layout(*prob, *par, (char*)d_workspace, p);
-        std::memset(&p->stats, 0, sizeof(p->stats));
+        init_plan(p, prob, par, d_workspace);
         *out_plan = p;
     });
 }
@@ -528,9 +470,9 @@ int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats*
     });
     if (rc != ISDC_OK) return rc;
     if (status == ISDC_E_NOT_CONVERGED)
-        g_last_error = "SDC residual " + std::to_string(plan->stats.residual) + " not below sdc_tol after max_sweeps";
+        isdc::last_error() = "SDC residual " + std::to_string(plan->stats.residual) + " not below sdc_tol after max_sweeps";
     else if (status == ISDC_E_DIVERGED)
-        g_last_error = "non-finite SDC residual";
+        isdc::last_error() = "non-finite SDC residual";
     return status;
 }
 

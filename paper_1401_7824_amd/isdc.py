@@ -164,3 +164,81 @@ class Plan:
         A.check(self.lib.isdc_time_kernel(self._h, kernel, level, c, precision, reps, _stream_handle(stream),
                                           C.byref(us), C.byref(b)))
         return us.value, b.value
+
+
+class Batch:
+    """Many independent ISDC instances advanced together (one launch per sweep
+    phase for all running slots).  Device memory for the batch tables and for
+    every slot's plan comes from torch; the state tensors stay owned by the
+    caller and are kept alive here until their slot is released."""
+
+    def __init__(self, capacity: int, dim: int, precision: int = A.PREC_FP64, vcycles: int = 2, device=None):
+        self.lib = A.load()
+        self.capacity, self.dim, self.precision, self.vcycles = capacity, dim, precision, vcycles
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        nbytes = C.c_size_t()
+        A.check(self.lib.isdc_batch_workspace_bytes(capacity, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        A.check(self.lib.isdc_batch_create(capacity, dim, precision, vcycles, C.c_void_p(self.workspace.data_ptr()),
+                                           nbytes.value, C.byref(h)))
+        self._h = h
+        self._keep = [None] * capacity
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.isdc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def workspace_bytes_for(n: int, dim: int, nu: float, fe_kind: int = A.FE_ZERO, **params) -> int:
+        return workspace_bytes(make_problem(dim, n, nu, fe_kind), make_params(**params))
+
+    def set(self, slot: int, u: torch.Tensor, dt: float, nsteps: int, nu: float, fe_kind: int = A.FE_ZERO,
+            workspace: torch.Tensor = None, **params):
+        """Start instance (u, nu, f^E, params) in `slot` for nsteps steps of size dt.
+        u (float64, shape (n,)*dim) is advanced in place."""
+        n = u.shape[0]
+        params.setdefault("vcycles", self.vcycles)
+        params.setdefault("precision", self.precision)
+        prob = make_problem(self.dim, n, nu, fe_kind)
+        par = make_params(**params)
+        need = workspace_bytes(prob, par)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        A.check(self.lib.isdc_batch_set(self._h, slot, C.byref(prob), C.byref(par),
+                                        C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                        _dev_ptr(u, torch.float64, n ** self.dim), dt, nsteps))
+        self._keep[slot] = (workspace, u)
+
+    def advance(self, stream=None) -> int:
+        running = C.c_int32()
+        A.check(self.lib.isdc_batch_advance(self._h, _stream_handle(stream), C.byref(running)))
+        return running.value
+
+    def info(self, slot: int):
+        state, status, steps = C.c_int32(), C.c_int32(), C.c_int32()
+        st = A.Stats()
+        A.check(self.lib.isdc_batch_slot_info(self._h, slot, C.byref(state), C.byref(status), C.byref(steps),
+                                              C.byref(st)))
+        return state.value, A.STATUS_NAMES.get(status.value, status.value), steps.value, StepStats.from_c(st, status.value)
+
+    def release(self, slot: int):
+        A.check(self.lib.isdc_batch_release(self._h, slot))
+        self._keep[slot] = None
+
+    def run(self, stream=None, max_advances: int = 1_000_000) -> int:
+        """Advance until no slot is running; returns the number of batch sweeps."""
+        k = 0
+        while self.advance(stream) > 0:
+            k += 1
+            if k >= max_advances:
+                raise RuntimeError("batch did not finish")
+        return k + 1

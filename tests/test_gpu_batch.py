@@ -1,0 +1,162 @@
+"""Batched ISDC on the GPU: every slot's result must be bitwise the result of
+the same instance run alone with isdc_step (same kernel bodies, same
+coefficients), whatever else shares the batch, whenever it joins, and even
+when a neighbour fails."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1401_7824_amd import workloads as W
+from gpu_helpers import announce, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+LOB, RAD = O.NODES_LOBATTO, O.NODES_RADAU_RIGHT
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _alone(d, n, nu, fe, u0, dt, nsteps, **par):
+    from paper_1401_7824_amd import Plan
+    p = Plan(d, n, nu, fe, **par)
+    u = dev(u0)
+    stats = [p.step(u, dt) for _ in range(nsteps)]
+    return host(u), stats
+
+
+def _instances(d, prec, count, seed):
+    rng = np.random.default_rng(seed)
+    sizes = {1: [127, 1023, 4095], 2: [31, 63, 127, 255], 3: [15, 31, 63]}[d]
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        M = int(rng.choice([3, 5]))
+        kind = LOB if rng.random() < 0.7 else RAD
+        fe = O.FE_CUBIC if rng.random() < 0.5 else O.FE_ZERO
+        nu = float(rng.uniform(0.05, 1.0))
+        dt = float(rng.uniform(2e-4, 5e-3))
+        u0 = 2.0 * W.sine_field(n, d, W.draw_modes(d, 6, seed=seed * 100 + i, max_wave=8 if d == 1 else 4))
+        out.append(dict(d=d, n=n, nu=nu, fe=fe, dt=dt, u0=u0,
+                        par=dict(node_kind=kind, M=M, precision=prec, sdc_tol=1e-10 if prec == 0 else 1e-9)))
+    return out
+
+
+@pytest.mark.parametrize("d,prec", [(2, 0), (2, 1), (1, 0), (3, 1)])
+def test_batch_slots_equal_single_instance_runs(d, prec):
+    from paper_1401_7824_amd import Batch
+    announce("batch equal", d, prec)
+    inst = _instances(d, prec, 7, seed=10 + d + 4 * prec)
+    b = Batch(8, d, precision=prec, vcycles=2)
+    us = []
+    for i, x in enumerate(inst):
+        u = dev(x["u0"])
+        b.set(i, u, x["dt"], 2, x["nu"], x["fe"], **x["par"])
+        us.append(u)
+    b.run()
+    for i, x in enumerate(inst):
+        state, status, steps, st = b.info(i)
+        ref, rstats = _alone(d, x["n"], x["nu"], x["fe"], x["u0"], x["dt"], 2, **x["par"])
+        assert status == "ok" and steps == 2, (i, status)
+        assert np.array_equal(host(us[i]), ref), f"slot {i} differs from the single-instance run"
+        assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
+
+
+def test_continuous_batching_join_and_leave():
+    # slots join while others are mid-step and a finished slot is reused;
+    # every result equals its run alone
+    from paper_1401_7824_amd import Batch
+    announce("batch continuous")
+    inst = _instances(2, 0, 6, seed=31)
+    b = Batch(3, 2, precision=0, vcycles=2)
+    us = {}
+    pending = list(range(len(inst)))
+    done = []
+    free = [0, 1, 2]
+    where = {}
+    sweeps = 0
+    while pending or any(s is not None for s in where.values()):
+        while free and pending:
+            k = pending.pop(0)
+            slot = free.pop(0)
+            x = inst[k]
+            u = dev(x["u0"])
+            b.set(slot, u, x["dt"], 1 + k % 2, x["nu"], x["fe"], **x["par"])
+            us[k] = u
+            where[slot] = k
+        b.advance()
+        sweeps += 1
+        for slot, k in list(where.items()):
+            if k is None:
+                continue
+            state, status, steps, _ = b.info(slot)
+            if state == 2:
+                assert status == "ok"
+                done.append(k)
+                b.release(slot)
+                where[slot] = None
+                free.append(slot)
+        assert sweeps < 5000
+    assert sorted(done) == list(range(len(inst)))
+    for k, x in enumerate(inst):
+        ref, _ = _alone(2, x["n"], x["nu"], x["fe"], x["u0"], x["dt"], 1 + k % 2, **x["par"])
+        assert np.array_equal(host(us[k]), ref), f"instance {k}"
+
+
+def test_failing_slot_does_not_disturb_neighbours():
+    from paper_1401_7824_amd import Batch
+    announce("batch failure isolation")
+    inst = _instances(2, 0, 3, seed=41)
+    bad = inst[1]["u0"].copy()
+    bad[3, 4] = np.nan
+    inst[1]["u0"] = bad
+    inst[2]["par"]["max_sweeps"] = 2
+    inst[2]["par"]["sdc_tol"] = 1e-15
+    b = Batch(3, 2, precision=0, vcycles=2)
+    us = []
+    for i, x in enumerate(inst):
+        u = dev(x["u0"])
+        b.set(i, u, x["dt"], 1, x["nu"], x["fe"], **x["par"])
+        us.append(u)
+    b.run()
+    assert b.info(0)[1] == "ok"
+    assert b.info(1)[1] == "diverged"
+    assert b.info(2)[1] == "not_converged" and b.info(2)[3].sweeps == 2
+    ref0, _ = _alone(2, inst[0]["n"], inst[0]["nu"], inst[0]["fe"], inst[0]["u0"], inst[0]["dt"], 1, **inst[0]["par"])
+    assert np.array_equal(host(us[0]), ref0)
+    ref2, _ = _alone(2, inst[2]["n"], inst[2]["nu"], inst[2]["fe"], inst[2]["u0"], inst[2]["dt"], 1, **inst[2]["par"])
+    assert np.array_equal(host(us[2]), ref2)
+
+
+def test_batch_matches_oracle_collocation():
+    # a batched heat instance also lands on the direct collocation solution
+    from paper_1401_7824_amd import Batch
+    announce("batch vs collocation")
+    n, nu, dt = 127, 0.5, 2e-3
+    u0 = W.sine_field(n, 2, W.draw_modes(2, 8, seed=5))
+    b = Batch(2, 2, precision=1, vcycles=2)
+    u = dev(u0)
+    b.set(0, u, dt, 1, nu, O.FE_ZERO, node_kind=LOB, M=5, sdc_tol=1e-11)
+    b.run()
+    coll = O.collocation_heat_modal(u0, dt, nu, 1.0 / (n + 1), LOB, 5)
+    got = host(u)
+    assert np.linalg.norm(got - coll) / np.linalg.norm(coll) < 1e-8
+
+
+def test_batch_rejects_unsupported_parameters():
+    from paper_1401_7824_amd import Batch, ISDCError
+    announce("batch unsupported")
+    b = Batch(2, 2, precision=0, vcycles=2)
+    u = dev(np.zeros((31, 31)))
+    with pytest.raises(ISDCError):
+        b.set(0, u, 1e-3, 1, 1.0, smoother=1, nu_pre=2, nu_post=2)
+    with pytest.raises(ISDCError):
+        b.set(0, u, 1e-3, 1, 1.0, guess=1)
+    with pytest.raises(ISDCError):
+        b.set(0, u, 1e-3, 1, 1.0, precision=1)  # batch is FP64
+    with pytest.raises(ISDCError):
+        b.set(5, u, 1e-3, 1, 1.0)  # slot out of range
