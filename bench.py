@@ -33,7 +33,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d"])
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve"])
+    ap.add_argument("--serve-count", type=int, default=120)
+    ap.add_argument("--serve-budget-gb", type=float, default=24.0)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true",
@@ -182,6 +186,109 @@ def cpu_baseline(cfg, sweeps_per_step):
                        f"({per_sweep:.2f} s/sweep), scaled by {sweeps_per_step:.1f} sweeps/step")
 
 
+def run_batch(args, torch):
+    """256 uneven 2D reaction-diffusion instances (side 63..511, nu, dt, M drawn
+    per instance, float32 V-cycles, tolerance 1e-8), each advanced
+    --batch-steps steps: all in one batch, then one instance after another with
+    isdc_step.  Reports both throughputs in instance-steps/s and checks that
+    the two give bitwise the same states."""
+    import numpy as np
+    from paper_1401_7824_amd import Batch, Plan
+    from paper_1401_7824_amd import workloads as W
+    inst = W.batch_instances(args.batch_count)
+    u0s = [W.sine_field(x["n"], 2, W.draw_modes(2, x["n_modes"], x["seed"])) for x in inst]
+    steps = args.batch_steps
+    par = lambda x: dict(node_kind=x["node_kind"], M=x["M"], precision=x["precision"], sdc_tol=x["sdc_tol"])  # noqa: E731
+    b = Batch(len(inst), 2, precision=1, vcycles=2)
+    ws = [torch.empty(Batch.workspace_bytes_for(x["n"], 2, x["nu"], x["fe_kind"], **par(x)), dtype=torch.uint8,
+                      device="cuda") for x in inst]
+    # warm-up of every kernel shape on a copy
+    for rep in range(2):
+        ub = [torch.from_numpy(u).cuda() for u in u0s]
+        for i, x in enumerate(inst):
+            b.set(i, ub[i], x["dt"], 1 if rep == 0 else steps, x["nu"], x["fe_kind"], workspace=ws[i], **par(x))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweeps = b.run()
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+    states = [b.info(i) for i in range(len(inst))]
+    assert all(st[1] == "ok" for st in states), [st[1] for st in states]
+    # one instance after another
+    uref = [torch.from_numpy(u).cuda() for u in u0s]
+    plans = {}
+    t0 = time.perf_counter()
+    for i, x in enumerate(inst):
+        key = (x["n"], x["M"])
+        p = Plan(2, x["n"], x["nu"], x["fe_kind"], **par(x))
+        for _ in range(steps):
+            st = p.step(uref[i], x["dt"])
+            assert st.status == "ok"
+        plans[key] = p
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    same = all(torch.equal(ub[i], uref[i]) for i in range(len(inst)))
+    total = len(inst) * steps
+    return {
+        "metric": METRIC, "value": round(total / t_batch, 3), "unit": "instance-steps/s", "n_gpus": 1,
+        "steps": total, "warmup": 1, "ms_per_step": round(t_batch / total * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"batch: {len(inst)} 2D reaction-diffusion instances, side 63..511, "
+                               f"{steps} steps each, float32 V-cycles, tol 1e-8",
+                   "batch_sweeps": sweeps, "sizes": {str(k): sum(1 for x in inst if x['n'] == k) for k in (63, 127, 255, 511)}},
+        "per_instance_baseline": {"value": round(total / t_single, 3), "unit": "instance-steps/s",
+                                  "seconds": round(t_single, 3)},
+        "speedup_vs_per_instance": round(t_single / t_batch, 2),
+        "bitwise_equal_to_per_instance": bool(same),
+        "batch_seconds": round(t_batch, 3),
+    }
+
+
+def run_serve(args, torch):
+    """Serving: Poisson arrivals of mixed 2D (127^2..1023^2) and 3D (31^3..255^3)
+    heat / reaction-diffusion requests (tolerance 1e-5 or 1e-8, 1..20 steps),
+    admitted under an HBM budget into continuously batched slots.  The
+    saturated capacity is measured first (all requests at t = 0); then the
+    arrival rate is swept at 0.25 .. 1.1 of it, reporting p50 / p99 latency;
+    the one-request-at-a-time baseline runs at the lowest rate."""
+    from paper_1401_7824_amd.serve import Server, make_requests, serve_sequential
+    budget = int(args.serve_budget_gb * 2 ** 30)
+    count = args.serve_count
+
+    def server():
+        return Server(budget, slots_per_batch=64, precision=1, vcycles=2)
+
+    warm = make_requests(8, rate=0.0, seed=99)
+    server().serve(warm)
+    sat = server().serve(make_requests(count, rate=0.0, seed=5))
+    cap = sat.completed / sat.makespan
+    print(f"[serve] saturated: {sat.completed} requests in {sat.makespan:.2f} s", file=sys.stderr, flush=True)
+    rows = []
+    for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
+        reqs = make_requests(count, rate=frac * cap, seed=5)
+        st = server().serve(reqs).summary()
+        st["rate_req_s"] = round(frac * cap, 3)
+        st["rate_frac_of_capacity"] = frac
+        rows.append(st)
+        print(f"[serve] rate {frac:.2f} x capacity: p50 {st['p50_ms']} ms, p99 {st['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+    seq = serve_sequential(make_requests(count, rate=0.25 * cap, seed=5), precision=1, vcycles=2).summary()
+    seq_sat = serve_sequential(make_requests(count, rate=0.0, seed=5), precision=1, vcycles=2).summary()
+    print(f"[serve] sequential saturated: {seq_sat['throughput_req_s']} req/s", file=sys.stderr, flush=True)
+    steps = sum(r.nsteps for r in make_requests(count, rate=0.0, seed=5))
+    return {
+        "metric": METRIC, "value": round(cap, 4), "unit": "requests/s", "n_gpus": 1, "steps": steps,
+        "warmup": 8, "ms_per_step": round(sat.makespan / steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"serve: {count} requests, half 2D 127..1023, half 3D 31..255, heat / "
+                               f"reaction-diffusion, tol 1e-5 / 1e-8, 1..20 steps, HBM budget "
+                               f"{args.serve_budget_gb} GiB, 64 slots per dimension"},
+        "saturated": sat.summary(), "rate_sweep": rows, "sequential_baseline_at_0.25": seq,
+        "sequential_baseline_saturated": seq_sat,
+        "capacity_vs_sequential": round(cap / seq_sat["throughput_req_s"], 2) if seq_sat["throughput_req_s"] else None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -194,6 +301,12 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     P.load()
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args, torch)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, torch)), flush=True)
+        return
     cfg = dict(W.WORKLOADS[args.workload])
     plan = make_plan(cfg)
     u = torch.from_numpy(W.workload_u0(cfg)).cuda()

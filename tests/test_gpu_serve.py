@@ -1,0 +1,65 @@
+"""Continuous-batching server on the GPU: requests that arrive while others
+run are admitted under the HBM budget, and each result is bitwise the result
+of the same request run alone."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import announce, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _alone(req, precision, vcycles):
+    from paper_1401_7824_amd import Plan
+    p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(precision, vcycles))
+    u = torch.from_numpy(np.ascontiguousarray(req.u0)).cuda()
+    for _ in range(req.nsteps):
+        assert p.step(u, req.dt).status == "ok"
+    return host(u)
+
+
+def test_serving_results_equal_alone_under_budget():
+    from paper_1401_7824_amd.serve import Server, make_requests
+    announce("serve small")
+    reqs = make_requests(14, rate=400.0, seed=7, big=False)
+    prec, L = 1, 2
+    sizes = sorted(r.device_bytes(prec, L) for r in reqs)
+    budget = sizes[-1] + sizes[-2] + sizes[-3]  # forces requests to wait for memory
+    srv = Server(budget, slots_per_batch=4, precision=prec, vcycles=L)
+    stats = srv.serve(reqs)
+    s = stats.summary()
+    assert s["completed"] == len(reqs) and s["failed"] == 0
+    assert stats.peak_bytes <= budget
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+    assert any(r.admitted > r.arrival for r in reqs)  # someone had to wait
+    for r in reqs:
+        assert r.status == "ok"
+        assert np.array_equal(host(r.result), _alone(r, prec, L)), f"request {r.rid}"
+
+
+def test_sequential_baseline_matches_batched_results():
+    from paper_1401_7824_amd.serve import Server, make_requests, serve_sequential
+    announce("serve sequential")
+    a = make_requests(5, rate=0.0, seed=9, big=False)
+    b = make_requests(5, rate=0.0, seed=9, big=False)
+    Server(1 << 34, slots_per_batch=8, precision=1, vcycles=2).serve(a)
+    st = serve_sequential(b, precision=1, vcycles=2)
+    assert st.completed == 5
+    for x, y in zip(a, b):
+        assert np.array_equal(host(x.result), host(y.result))
+
+
+def test_request_larger_than_budget_is_rejected():
+    from paper_1401_7824_amd.serve import Server, make_requests
+    announce("serve reject")
+    reqs = make_requests(1, rate=0.0, seed=3, big=False)
+    srv = Server(1024, slots_per_batch=2, precision=1, vcycles=2)
+    with pytest.raises(ValueError):
+        srv.serve(reqs)
