@@ -26,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ISDC steps/s, V-cycle HBM GB/s (% of peak), p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+# sources of the fine-level multigrid kernels; counter figures taken before a
+# change to any of them are stale
+TRAFFIC_SOURCES = ("paper_1401_7824_amd/csrc/mg_tiles.hip", "paper_1401_7824_amd/csrc/mg_device.h",
+                   "paper_1401_7824_amd/csrc/tile_common.h")
 
 
 def parse():
@@ -33,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve"])
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve", "table1"])
     ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--batch-count", type=int, default=256)
@@ -80,6 +84,40 @@ KERNEL_NAMES = {
 }
 
 
+def accuracy_vs_collocation(cfg, torch):
+    """One step of a linear (heat) workload in float32-V-cycle and all-float64
+    form, each compared with the direct collocation solution: the sine-mode
+    expansion of u_0 with every mode multiplied by the collocation stability
+    function R(z) = last entry of (I - z Q)^{-1} (1, ..., 1), z = dt nu lambda_a
+    (Sec. 2), with Q from the library's own tables.  Also times both variants."""
+    import numpy as np
+    from paper_1401_7824_amd import tables, workloads as W
+    n, d, M = cfg["n"], cfg["dim"], cfg["M"]
+    modes = W.workload_modes(cfg)
+    u0 = W.sine_field(n, d, modes)
+    h = 1.0 / (n + 1)
+    Q = np.array(tables(cfg["node_kind"], M)[1])
+    lam = [sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in modes]
+    R = [np.linalg.solve(np.eye(M) - cfg["dt"] * cfg["nu"] * l * Q, np.ones(M))[-1] for l in lam]
+    coll = W.sine_field(n, d, [(amp * r, a) for (amp, a), r in zip(modes, R)])
+    out = {}
+    for prec in (1, 0):
+        c = dict(cfg, precision=prec)
+        p = make_plan(c)
+        u = torch.from_numpy(u0).cuda()
+        st = p.step(u, cfg["dt"])
+        got = u.cpu().numpy()
+        err = float(np.linalg.norm(got - coll) / np.linalg.norm(coll))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            p.step(u, cfg["dt"])
+        torch.cuda.synchronize()
+        out["mixed" if prec else "fp64"] = dict(rel_l2_vs_collocation=err, sweeps=st.sweeps, status=st.status,
+                                                 steps_per_s=round(3 / (time.perf_counter() - t0), 3))
+    return out
+
+
 def counter_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
     counter runs (profiles/traffic.json), or None if the kernel's sources have
@@ -92,7 +130,7 @@ def counter_traffic(kernel: str):
     if rec is None:
         return None
     h = hashlib.sha256()
-    for f in ("paper_1401_7824_amd/csrc/mg_tiles.hip", "paper_1401_7824_amd/csrc/tile_common.h"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != rec["sources_sha256"]:
@@ -115,9 +153,12 @@ def kernel_probe(plan, cfg, reps, torch):
     out = {}
     kinds = [("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH),
              ("tail", P.KERNEL_TAIL)]
+    tail_n = {1: 2047, 2: 63, 3: 15}[cfg["dim"]]
     for name, k in kinds:
         if name == "smooth_restrict" and cfg["dim"] == 3:
             continue
+        if name != "tail" and cfg["n"] <= tail_n:
+            continue  # the whole V-cycle is the single-workgroup coarse solve
         us, b = plan.time_kernel(k, 0, c, prec, reps)
         out[name] = dict(kernel=KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"]), avg_us=round(us, 3),
                          alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1))
@@ -160,18 +201,27 @@ def vcycle_probe(plan, cfg, reps, torch):
 
 
 def cpu_baseline(cfg, sweeps_per_step):
-    """The oracle (numpy, one thread) on a bounded sample: a few sweeps of one
-    step at full size, scaled to steps/s with the GPU's sweeps per step."""
+    """The oracle (numpy, one thread) on a bounded sample: sweeps of one step
+    at full size, scaled to steps/s with the GPU's sweeps per step.  Above
+    2^22 points a single full-size sweep would exceed the sample budget, so
+    the sample runs on the grid with side (n+1)/2 - 1 and is scaled by the
+    ratio of point counts (the oracle's work is linear in the points)."""
     import numpy as np
     import oracle as O  # noqa: F401  (test infrastructure: the CPU baseline only)
     from oracle.sdc import SDCConfig, sdc_begin, sdc_sweep
     from paper_1401_7824_amd import workloads as W
-    u0 = W.workload_u0(cfg)
-    sc = SDCConfig(nu=cfg["nu"], fe_kind=cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"],
-                   precision=cfg["precision"], tol=cfg["sdc_tol"])
-    h = 1.0 / (cfg["n"] + 1)
+    c = dict(cfg)
+    scale = 1.0
+    while c["n"] ** c["dim"] > 2 ** 22:
+        small = (c["n"] + 1) // 2 - 1
+        scale *= (c["n"] / small) ** c["dim"]
+        c["n"] = small
+    u0 = W.workload_u0(c)
+    sc = SDCConfig(nu=c["nu"], fe_kind=c["fe_kind"], node_kind=c["node_kind"], M=c["M"],
+                   precision=c["precision"], tol=c["sdc_tol"])
+    h = 1.0 / (c["n"] + 1)
     t0 = time.perf_counter()
-    st = sdc_begin(u0, cfg["dt"], h, sc)
+    st = sdc_begin(u0, c["dt"], h, sc)
     nsw = 0
     while True:
         sdc_sweep(st)
@@ -179,11 +229,12 @@ def cpu_baseline(cfg, sweeps_per_step):
         el = time.perf_counter() - t0
         if el > 10.0 or nsw >= sweeps_per_step:
             break
-    per_sweep = el / nsw
+    per_sweep = el / nsw * scale
     del np
-    return dict(value=round(1.0 / (per_sweep * sweeps_per_step), 5), unit="steps/s", cores=1, kind="oracle",
-                sample=f"{nsw} sweeps of one {cfg['n']}^{cfg['dim']} step on 1 host core "
-                       f"({per_sweep:.2f} s/sweep), scaled by {sweeps_per_step:.1f} sweeps/step")
+    where = f"one {c['n']}^{c['dim']} step" + (f", scaled x{scale:.2f} to {cfg['n']}^{cfg['dim']}" if scale != 1 else "")
+    return dict(value=round(1.0 / (per_sweep * sweeps_per_step), 6), unit="steps/s", cores=1, kind="oracle",
+                sample=f"{nsw} sweeps of {where} on 1 host core ({per_sweep:.2f} s/sweep), "
+                       f"scaled by {sweeps_per_step:.1f} sweeps/step")
 
 
 def run_batch(args, torch):
@@ -289,6 +340,76 @@ def run_serve(args, torch):
     }
 
 
+def run_table1(args, torch):
+    """Table 1(a) replay (Sec. 4) with the second-order stencil: 2D heat on
+    [0,1]^2, u0 = sin(pi x) sin(pi y), n = 63 (h = 1/64), dt = 1e-3,
+    Gauss-Lobatto M in {3, 5, 7}, nu in {1, 10, 100}, sweeps until the
+    max-norm SDC residual < 5e-8.  Multigrid: weighted-Jacobi V(3,3)
+    (omega = 4/5).  Classical SDC cycles each implicit solve until its
+    max-norm residual <= 1e-9; ISDC stops after L = 2 cycles or earlier at
+    that tolerance.  Reports accumulated V-cycles and sweeps of
+    both beside the printed ones and the GPU time of one step of each;
+    `value` is the V-cycle saving of ISDC summed over the nine rows."""
+    import csv
+    import numpy as np
+    from paper_1401_7824_amd import Plan
+    n, dt = 63, 1e-3
+    x = np.arange(1, n + 1) / (n + 1)
+    u0 = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    printed = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1.csv")) as fh:
+        for r in csv.DictReader(line for line in fh if not line.startswith("#")):
+            if r["problem"] == "heat":
+                printed[(float(r["nu"]), int(r["M"]))] = r
+    rows = []
+    tot = {"sdc": 0, "isdc": 0}
+    ms_tot = {"sdc": 0.0, "isdc": 0.0}
+    for nu in (1.0, 10.0, 100.0):
+        for M in (3, 5, 7):
+            row = {"nu": nu, "M": M}
+            for name, mode in (("sdc", dict(vcycles=0)), ("isdc", dict(vcycles=2, early_exit=1))):
+                p = Plan(2, n, nu, 0, node_kind=0, M=M, sdc_tol=5e-8, inner_tol=1e-9, max_sweeps=100,
+                         smoother=1, nu_pre=3, nu_post=3, **mode)
+                u0d = torch.from_numpy(u0).cuda()
+                u = u0d.clone()
+                st = p.step(u, dt)
+                reps = max(1, args.steps)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    u.copy_(u0d)
+                    p.step(u, dt)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / reps * 1e3
+                row[name] = {"vcycles": st.vcycles, "sweeps": st.sweeps, "status": st.status, "ms_per_step": round(ms, 3)}
+                tot[name] += st.vcycles
+                ms_tot[name] += ms
+            pr = printed[(nu, M)]
+            row["savings_pct"] = round(100.0 * (1 - row["isdc"]["vcycles"] / row["sdc"]["vcycles"]), 1)
+            row["time_savings_pct"] = round(100.0 * (1 - row["isdc"]["ms_per_step"] / row["sdc"]["ms_per_step"]), 1)
+            row["printed"] = {"sdc": f"{pr['sdc_cycles']}({pr['sdc_sweeps']})",
+                              "isdc": f"{pr['isdc_cycles']}({pr['isdc_sweeps']})", "savings_pct": int(pr["savings_pct"])}
+            rows.append(row)
+            print(f"[table1] nu={nu:5.0f} M={M}: SDC {row['sdc']['vcycles']}({row['sdc']['sweeps']}) "
+                  f"ISDC {row['isdc']['vcycles']}({row['isdc']['sweeps']}) save {row['savings_pct']}% | "
+                  f"printed {row['printed']['sdc']} {row['printed']['isdc']} {pr['savings_pct']}%",
+                  file=sys.stderr, flush=True)
+    save = 100.0 * (1 - tot["isdc"] / tot["sdc"])
+    return {
+        "metric": "Table 1(a) replay: accumulated V-cycles of classical SDC vs ISDC", "value": round(save, 2),
+        "unit": "% V-cycles saved (9 rows)", "n_gpus": 1, "steps": 18 * max(1, args.steps), "warmup": 18,
+        "ms_per_step": round((ms_tot["sdc"] + ms_tot["isdc"]) / 18, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "table1: 2D heat n=63 (h=1/64) u0=sin(pi x)sin(pi y) dt=1e-3 Lobatto M=3,5,7 "
+                               "nu=1,10,100 tol 5e-8; SDC inner_tol 1e-9; ISDC L=2 early exit; weighted-Jacobi V(3,3), "
+                               "second-order stencil"},
+        "time_savings_pct": round(100.0 * (1 - ms_tot["isdc"] / ms_tot["sdc"]), 2),
+        "totals": {"sdc_vcycles": tot["sdc"], "isdc_vcycles": tot["isdc"],
+                   "sdc_ms": round(ms_tot["sdc"], 3), "isdc_ms": round(ms_tot["isdc"], 3)},
+        "rows": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -307,18 +428,24 @@ def main():
     if args.workload == "serve":
         print(json.dumps(run_serve(args, torch)), flush=True)
         return
+    if args.workload == "table1":
+        print(json.dumps(run_table1(args, torch)), flush=True)
+        return
     cfg = dict(W.WORKLOADS[args.workload])
     plan = make_plan(cfg)
     u = torch.from_numpy(W.workload_u0(cfg)).cuda()
+    accuracy = None
+    if cfg["fe_kind"] == W.FE_ZERO:
+        accuracy = accuracy_vs_collocation(cfg, torch)
     elapsed, wall, stats = time_steps(plan, u, cfg["dt"], args.steps, args.warmup, torch)
     sweeps = sum(s.sweeps for s in stats) / len(stats)
     vcyc = sum(s.vcycles for s in stats) / len(stats)
     kp = kernel_probe(plan, cfg, args.probe_reps, torch)
     vc = vcycle_probe(plan, cfg, 20, torch)
-    dom = kp.get("smooth_restrict") or kp["prolong_smooth"]
+    dom = kp.get("smooth_restrict") or kp.get("prolong_smooth") or kp["tail"]
     traffic = counter_traffic(dom["kernel"]) if args.workload == "rd2d" else None
     roof = dict(bound="hbm", achieved=dom["gbps"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(dom["gbps"] / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["kernel"] + " (fine level)",
+                frac=round(dom["gbps"] / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["kernel"] + " (finest level)",
                 avg_launch_us=dom["avg_us"], alg_bytes_per_launch=dom["alg_bytes"])
     out = {
         "metric": METRIC,
@@ -343,6 +470,8 @@ def main():
         "vcycle": vc,
         "kernels": kp,
     }
+    if accuracy is not None:
+        out["accuracy"] = accuracy
     if args.calib_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
