@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve", "table1"])
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve", "table1", "kernels"])
     ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--batch-count", type=int, default=256)
@@ -340,6 +340,62 @@ def run_serve(args, torch):
     }
 
 
+def run_kernels(args, torch):
+    """Streaming efficiency of the fine-level multigrid kernels against grid
+    size: per-launch time of each kernel (HIP events around every launch,
+    isdc_time_kernel), its algorithmic bytes (each array it touches read or
+    written once) and the achieved GB/s, beside a plain device-to-device copy
+    of one array of the same size.  Working sets from inside the 256 MB
+    Infinity Cache (1023^2) to far outside it (8191^2, 511^3)."""
+    import paper_1401_7824_amd as P
+    from paper_1401_7824_amd import Plan
+    rows = []
+    cases = [(2, n, prec) for n in (1023, 2047, 4095, 8191) for prec in (0, 1)] + \
+            [(3, n, prec) for n in (255, 511) for prec in (0, 1)]
+    for d, n, prec in cases:
+        p = Plan(d, n, 1.0, 0, node_kind=0, M=3, precision=prec)
+        c = 1e-3 * 0.5
+        row = {"dim": d, "n": n, "dtype": "f64" if prec == 0 else "f32"}
+        kinds = [("smooth", P.KERNEL_SMOOTH), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH)]
+        if d < 3:
+            kinds.insert(0, ("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT))
+        for name, k in kinds:
+            us, b = p.time_kernel(k, 0, c, prec, args.probe_reps)
+            row[name] = {"us": round(us, 2), "alg_bytes": int(b), "gbps": round(b / (us * 1e-6) / 1e9, 1),
+                         "frac": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        dt = torch.float64 if prec == 0 else torch.float32
+        src = torch.empty((n,) * d, dtype=dt, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.probe_reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / args.probe_reps
+        row["copy"] = {"us": round(us, 2), "gbps": round(2 * src.numel() * src.element_size() / (us * 1e-6) / 1e9, 1)}
+        rows.append(row)
+        print(f"[kernels] {d}D n={n} {row['dtype']}: " + ", ".join(
+            f"{k} {v['gbps']} GB/s" for k, v in row.items() if isinstance(v, dict)), file=sys.stderr, flush=True)
+        del p, src, dst
+        torch.cuda.empty_cache()
+    big = [r for r in rows if r["dim"] == 2 and r["n"] == 8191 and r["dtype"] == "f64"][0]
+    best = big["smooth_restrict"]
+    return {
+        "metric": METRIC, "value": best["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.probe_reps,
+        "warmup": 1, "ms_per_step": round(best["us"] / 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "kernels: fine-level multigrid kernels, 2D 1023^2..8191^2 and 3D 255^3..511^3, "
+                               "f64 and f32; value = fused smoothing + restriction at 8191^2 f64"},
+        "roofline": {"bound": "hbm", "achieved": best["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": best["frac"], "traffic": None, "kernel": "k_rbgs_restrict_tile<double,2,false> (8191^2)",
+                     "avg_launch_us": best["us"], "alg_bytes_per_launch": best["alg_bytes"]},
+        "rows": rows,
+    }
+
+
 def run_table1(args, torch):
     """Table 1(a) replay (Sec. 4) with the second-order stencil: 2D heat on
     [0,1]^2, u0 = sin(pi x) sin(pi y), n = 63 (h = 1/64), dt = 1e-3,
@@ -430,6 +486,9 @@ def main():
         return
     if args.workload == "table1":
         print(json.dumps(run_table1(args, torch)), flush=True)
+        return
+    if args.workload == "kernels":
+        print(json.dumps(run_kernels(args, torch)), flush=True)
         return
     cfg = dict(W.WORKLOADS[args.workload])
     plan = make_plan(cfg)

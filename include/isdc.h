@@ -77,7 +77,7 @@ enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KER
 typedef struct {
     int32_t dim;      /* d = 1, 2 or 3                                                */
     int32_t n;        /* interior points per axis, 2^k - 1 with 1 <= k <= 15 (d = 1),  */
-                      /* k <= 12 (d = 2), k <= 10 (d = 3)                             */
+                      /* k <= 13 (d = 2), k <= 10 (d = 3)                             */
     double nu;        /* diffusion coefficient, finite and >= 0                       */
     int32_t fe_kind;  /* ISDC_FE_*                                                    */
 } isdc_problem;

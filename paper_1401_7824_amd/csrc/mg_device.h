@@ -15,30 +15,29 @@ namespace {
 
 // Red update on the tile plus a halo of 1, then black on the tile, in LDS.
 // se: box with halo 2 (origin tile - 2), sr: box with halo 1 (origin tile - 1).
+// A colour's update reads only the other colour, so each is one lds_pass.
 template <typename T, int D>
 __device__ __forceinline__ void rbgs_in_lds(T* se, const T* sr, int n, int x0, int y0, int z0, T a, T invdiag) {
     using B2 = HaloBox<D, 2>;
     using B1 = HaloBox<D, 1>;
     using B0 = HaloBox<D, 0>;
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    for (int k = threadIdx.x; k < B1::N; k += kThreads) {
-        int lx, ly, lz;
-        B1::split(k, lx, ly, lz);
-        int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
-        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) continue;
-        int i = ((lz + hz) * B2::Y + (ly + hy)) * B2::X + (lx + 1);
-        se[i] = (sr[k] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
-    }
+    lds_pass<T, B1>(se, [&](int k, int lx, int ly, int lz, T& v) {
+        const int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
+        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) return -1;
+        const int i = ((lz + hz) * B2::Y + (ly + hy)) * B2::X + (lx + 1);
+        v = (sr[k] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
+        return i;
+    });
     __syncthreads();
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) continue;
-        int i = ((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2);
-        int k1 = ((lz + hz) * B1::Y + (ly + hy)) * B1::X + (lx + 1);
-        se[i] = (sr[k1] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
-    }
+    lds_pass<T, B0>(se, [&](int, int lx, int ly, int lz, T& v) {
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) return -1;
+        const int i = ((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2);
+        const int k1 = ((lz + hz) * B1::Y + (ly + hy)) * B1::X + (lx + 1);
+        v = (sr[k1] + a * lds_nbsum<T, D, B2>(se, i)) * invdiag;
+        return i;
+    });
     __syncthreads();
 }
 
@@ -51,17 +50,21 @@ __device__ __forceinline__ void rbgs_tile_body(const T* __restrict__ r, const T*
     __shared__ T se[B2::N];
     __shared__ T sr[B1::N];
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    stage<T, D, B2>(se, e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, ZERO);
-    stage<T, D, B1>(sr, r, n, x0 - 1, y0 - hy, z0 - hz, false);
+    {
+        Staged<T, D, B2> le;
+        Staged<T, D, B1> lr;
+        le.load(e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, ZERO);
+        lr.load(r, n, x0 - 1, y0 - hy, z0 - hz, false);
+        le.store(se);
+        lr.store(sr);
+    }
     __syncthreads();
     rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n)) continue;
-        e_out[gidx<D>(x, y, z, n)] = se[((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2)];
-    }
+    for_box<B0>([&](int, int lx, int ly, int lz) {
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (inside<D>(x, y, z, n))
+            e_out[gidx<D>(x, y, z, n)] = se[((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2)];
+    });
 }
 
 template <typename T, int D>
@@ -70,30 +73,32 @@ __device__ __forceinline__ void restrict_tile_body(const T* __restrict__ r, cons
     using C = CTile<D>;
     using FB = Box<D, 2 * C::X + 1, 2 * C::Y + 1, 2 * C::Z + 1>;  // fine points under the coarse tile
     using EB = Box<D, 2 * C::X + 3, 2 * C::Y + 3, 2 * C::Z + 3>;  // ... plus a halo of 1
+    using CB = Box<D, C::X, C::Y, C::Z>;
     __shared__ T se[EB::N];
     __shared__ T sres[FB::N];
     const int nc = (n - 1) / 2;
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
     const int fx = 2 * X0, fy = 2 * Y0 * hy, fz = 2 * Z0 * hz;  // fine origin of FB
-    stage<T, D, EB>(se, e, n, fx - 1, fy - hy, fz - hz, false);
-    stage<T, D, FB>(sres, r, n, fx, fy, fz, false);
-    __syncthreads();
-    for (int k = threadIdx.x; k < FB::N; k += kThreads) {
-        int lx, ly, lz;
-        FB::split(k, lx, ly, lz);
-        if (!inside<D>(fx + lx, fy + ly, fz + lz, n)) continue;
-        int i = ((lz + hz) * EB::Y + (ly + hy)) * EB::X + (lx + 1);
-        sres[k] = sres[k] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
+    {
+        Staged<T, D, EB> le;
+        Staged<T, D, FB> lr;
+        le.load(e, n, fx - 1, fy - hy, fz - hz, false);
+        lr.load(r, n, fx, fy, fz, false);
+        le.store(se);
+        lr.store(sres);
     }
     __syncthreads();
+    lds_pass<T, FB>(sres, [&](int k, int lx, int ly, int lz, T& v) {
+        if (!inside<D>(fx + lx, fy + ly, fz + lz, n)) return -1;
+        const int i = ((lz + hz) * EB::Y + (ly + hy)) * EB::X + (lx + 1);
+        v = sres[k] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
+        return k;
+    });
+    __syncthreads();
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int k = threadIdx.x; k < C::X * (D >= 2 ? C::Y : 1) * (D == 3 ? C::Z : 1); k += kThreads) {
-        int cx = k % C::X;
-        int t = k / C::X;
-        int cy = D >= 2 ? t % C::Y : 0;
-        int cz = D == 3 ? t / C::Y : 0;
-        int X = X0 + cx, Y = Y0 + cy, Z = Z0 + cz;
-        if (!inside<D>(X, Y, Z, nc)) continue;
+    for_box<CB>([&](int, int cx, int cy, int cz) {
+        const int X = X0 + cx, Y = Y0 + cy, Z = Z0 + cz;
+        if (!inside<D>(X, Y, Z, nc)) return;
         T acc = T(0);
 #pragma unroll
         for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz) {
@@ -106,7 +111,7 @@ __device__ __forceinline__ void restrict_tile_body(const T* __restrict__ r, cons
             }
         }
         rc[gidx<D>(X, Y, Z, nc)] = acc;
-    }
+    });
 }
 
 // One red-black step from e_in to e_out fused with the residual of the new
@@ -123,59 +128,57 @@ __device__ __forceinline__ void rbgs_restrict_body(const T* __restrict__ r, cons
     using BB = Box<D, TL::X + 3, TL::Y + 3, TL::Z + 3>;  // black region, origin tile - 1
     using RP = Box<D, TL::X + 1, TL::Y + 1, TL::Z + 1>;  // residual region, origin tile
     using B0 = Box<D, TL::X, TL::Y, TL::Z>;
+    constexpr int CX = TL::X / 2, CY = D >= 2 ? TL::Y / 2 : 1, CZ = D == 3 ? TL::Z / 2 : 1;
+    using CB = Box<D, CX, CY, CZ>;
     __shared__ T se[EB::N];
     __shared__ T sr[RB::N];
     const int nc = (n - 1) / 2;
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
-    stage<T, D, EB>(se, e_in, n, x0 - 3, y0 - 3 * hy, z0 - 3 * hz, ZERO);
-    stage<T, D, RB>(sr, r, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
+    {
+        Staged<T, D, EB> le;
+        Staged<T, D, RB> lr;
+        le.load(e_in, n, x0 - 3, y0 - 3 * hy, z0 - 3 * hz, ZERO);
+        lr.load(r, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
+        le.store(se);
+        lr.store(sr);
+    }
     __syncthreads();
     auto eidx = [&](int lx, int ly, int lz, int off) {  // EB index of a point given in a box with origin tile - off
         return ((lz + (3 - off) * hz) * EB::Y + (ly + (3 - off) * hy)) * EB::X + (lx + 3 - off);
     };
-    for (int k = threadIdx.x; k < RB::N; k += kThreads) {  // red on the halo-2 region
-        int lx, ly, lz;
-        RB::split(k, lx, ly, lz);
-        int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
-        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) continue;
-        int i = eidx(lx, ly, lz, 2);
-        se[i] = (sr[k] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
-    }
+    lds_pass<T, RB>(se, [&](int k, int lx, int ly, int lz, T& v) {  // red on the halo-2 region
+        const int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
+        if (!inside<D>(x, y, z, n) || ((x + y + z) & 1)) return -1;
+        const int i = eidx(lx, ly, lz, 2);
+        v = (sr[k] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
+        return i;
+    });
     __syncthreads();
-    for (int k = threadIdx.x; k < BB::N; k += kThreads) {  // black on the halo-1 region
-        int lx, ly, lz;
-        BB::split(k, lx, ly, lz);
-        int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
-        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) continue;
-        int i = eidx(lx, ly, lz, 1);
-        int kr = ((lz + hz) * RB::Y + (ly + hy)) * RB::X + (lx + 1);
-        se[i] = (sr[kr] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
-    }
+    lds_pass<T, BB>(se, [&](int, int lx, int ly, int lz, T& v) {  // black on the halo-1 region
+        const int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
+        if (!inside<D>(x, y, z, n) || !((x + y + z) & 1)) return -1;
+        const int i = eidx(lx, ly, lz, 1);
+        const int kr = ((lz + hz) * RB::Y + (ly + hy)) * RB::X + (lx + 1);
+        v = (sr[kr] + a * lds_nbsum<T, D, EB>(se, i)) * invdiag;
+        return i;
+    });
     __syncthreads();
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    for_box<B0>([&](int, int lx, int ly, int lz) {
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (inside<D>(x, y, z, n)) e_out[gidx<D>(x, y, z, n)] = se[eidx(lx, ly, lz, 0)];
-    }
-    for (int k = threadIdx.x; k < RP::N; k += kThreads) {  // residual, in place of the rhs
-        int lx, ly, lz;
-        RP::split(k, lx, ly, lz);
-        if (!inside<D>(x0 + lx, y0 + ly, z0 + lz, n)) continue;
-        int i = eidx(lx, ly, lz, 0);
-        int kr = ((lz + 2 * hz) * RB::Y + (ly + 2 * hy)) * RB::X + (lx + 2);
-        sr[kr] = sr[kr] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
-    }
+    });
+    lds_pass<T, RP>(sr, [&](int, int lx, int ly, int lz, T& v) {  // residual, in place of the rhs
+        if (!inside<D>(x0 + lx, y0 + ly, z0 + lz, n)) return -1;
+        const int i = eidx(lx, ly, lz, 0);
+        const int kr = ((lz + 2 * hz) * RB::Y + (ly + 2 * hy)) * RB::X + (lx + 2);
+        v = sr[kr] - (diag * se[i] - a * lds_nbsum<T, D, EB>(se, i));
+        return kr;
+    });
     __syncthreads();
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    constexpr int CX = TL::X / 2, CY = D >= 2 ? TL::Y / 2 : 1, CZ = D == 3 ? TL::Z / 2 : 1;
-    for (int k = threadIdx.x; k < CX * CY * CZ; k += kThreads) {
-        int cx = k % CX;
-        int t = k / CX;
-        int cy = t % CY;
-        int cz = t / CY;
-        int X = x0 / 2 + cx, Y = (y0 / 2 + cy) * hy, Z = (z0 / 2 + cz) * hz;
-        if (!inside<D>(X, Y, Z, nc)) continue;
+    for_box<CB>([&](int, int cx, int cy, int cz) {
+        const int X = x0 / 2 + cx, Y = (y0 / 2 + cy) * hy, Z = (z0 / 2 + cz) * hz;
+        if (!inside<D>(X, Y, Z, nc)) return;
         T acc = T(0);
 #pragma unroll
         for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz) {
@@ -188,7 +191,7 @@ __device__ __forceinline__ void rbgs_restrict_body(const T* __restrict__ r, cons
             }
         }
         rc[gidx<D>(X, Y, Z, nc)] = acc;
-    }
+    });
 }
 
 template <typename T, int D, int MODE>
@@ -206,16 +209,22 @@ __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const
     const int nc = (n - 1) / 2;
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
     const int cxo = x0 / 2 - 2, cyo = (y0 / 2 - 2) * hy, czo = (z0 / 2 - 2) * hz;
-    stage<T, D, B2>(se, e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
-    stage<T, D, B1>(sr, r, n, x0 - 1, y0 - hy, z0 - hz, false);
-    stage<T, D, CB>(sc, ec, nc, cxo, cyo, czo, false);
+    {
+        Staged<T, D, B2> le;
+        Staged<T, D, B1> lr;
+        Staged<T, D, CB> lc;
+        le.load(e_in, n, x0 - 2, y0 - 2 * hy, z0 - 2 * hz, false);
+        lr.load(r, n, x0 - 1, y0 - hy, z0 - hz, false);
+        lc.load(ec, nc, cxo, cyo, czo, false);
+        le.store(se);
+        lr.store(sr);
+        lc.store(sc);
+    }
     __syncthreads();
     // coarse-grid correction on the whole halo-2 box
-    for (int k = threadIdx.x; k < B2::N; k += kThreads) {
-        int lx, ly, lz;
-        B2::split(k, lx, ly, lz);
-        int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
-        if (!inside<D>(x, y, z, n)) continue;
+    lds_pass<T, B2>(se, [&](int k, int lx, int ly, int lz, T& v) {
+        const int x = x0 - 2 + lx, y = y0 - 2 * hy + ly, z = z0 - 2 * hz + lz;
+        if (!inside<D>(x, y, z, n)) return -1;
         // linear interpolation per axis: odd index -> one coarse point, even
         // index -> mean of two; zeros outside [0, nc) are already staged
         int ix0, iy0 = 0, iz0 = 0;
@@ -239,21 +248,20 @@ __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const
             acc1 += wy1 * (wx0 * sc[b00 + CB::SZ + CB::SY] + wx1 * sc[b00 + CB::SZ + CB::SY + 1]);
             acc = wz0 * acc + wz1 * acc1;
         }
-        se[k] += acc;
-    }
+        v = se[k] + acc;
+        return k;
+    });
     __syncthreads();
     rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
-    for (int k = threadIdx.x; k < B0::N; k += kThreads) {
-        int lx, ly, lz;
-        B0::split(k, lx, ly, lz);
-        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (!inside<D>(x, y, z, n)) continue;
+    for_box<B0>([&](int, int lx, int ly, int lz) {
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (!inside<D>(x, y, z, n)) return;
         const size_t gi = gidx<D>(x, y, z, n);
         const T v = se[((lz + 2 * hz) * B2::Y + (ly + 2 * hy)) * B2::X + (lx + 2)];
         if (MODE == 0) e_out[gi] = v;
         else if (MODE == 1) u_out[gi] = g[gi] + (double)v;
         else u_out[gi] = (double)v;
-    }
+    });
 }
 
 // ---------------------------------------------------------------- coarse tail

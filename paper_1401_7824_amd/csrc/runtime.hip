@@ -27,7 +27,7 @@ bool valid_n(int d, int n) {
     if (n < 1 || ((n + 1) & n) != 0) return false;
     int k = 0;
     while ((1 << k) - 1 < n) ++k;
-    int kmax = d == 1 ? 15 : (d == 2 ? 12 : 10);
+    int kmax = d == 1 ? 15 : (d == 2 ? 13 : 10);
     return k <= kmax;
 }
 

@@ -63,7 +63,8 @@ __device__ __forceinline__ void split(size_t i, int n, int& x, int& y, int& z) {
 }
 
 // Tiled form of the quadrature + residual kernel: one tile of points per
-// workgroup, each node array staged in LDS (tile plus a halo of 1) in turn.
+// workgroup, each node array staged in LDS (tile plus a halo of 1) in turn,
+// the next one's loads in flight while the current one is used.
 // Per point: f_j = nu L_h u_j + f^E(u_j); sf_m = sum_j dt s_{m,j} f_j;
 // acc_m = u_0 + sum_j dt q_{m,j} f_j - u_m, and the tile's max |acc_m| goes
 // to partial[workgroup].
@@ -95,11 +96,15 @@ __device__ __forceinline__ double quad_residual_body(const QuadArgs& qa, int x0,
             acc[m][s] = u0;
         }
     }
+    // node j + 1's box is loaded into registers while node j is worked on
+    Staged<double, D, B1> next;
+    next.load(qa.u[1], n, x0 - 1, y0 - hy, z0 - hz, false);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if (j > 0) __syncthreads();
-        stage<double, D, B1>(su, qa.u[j + 1], n, x0 - 1, y0 - hy, z0 - hz, false);
+        next.store(su);
         __syncthreads();
+        if (j + 1 < M) next.load(qa.u[j + 2], n, x0 - 1, y0 - hy, z0 - hz, false);
 #pragma unroll
         for (int s = 0; s < P; ++s) {
             const double c = su[li[s]];

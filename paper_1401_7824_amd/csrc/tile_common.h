@@ -86,17 +86,75 @@ __device__ __forceinline__ T lds_nbsum(const T* s, int i) {
     return v;
 }
 
-// Stage a box of a global array whose origin is (ox, oy, oz); outside the
-// domain the box holds zeros (homogeneous Dirichlet ghosts).
+// A box of a global array held in registers on its way to LDS: load() issues
+// every load of this thread before any is waited on (a fully unrolled loop of
+// compile-time length), store() writes them to LDS.  Outside the domain the
+// box holds zeros (homogeneous Dirichlet ghosts).  Loading several boxes
+// before storing any keeps all of a tile's global reads in flight at once.
+template <typename T, int D, typename B>
+struct Staged {
+    static constexpr int kIter = (B::N + kThreads - 1) / kThreads;
+    T v[kIter];
+    __device__ __forceinline__ void load(const T* __restrict__ g, int n, int ox, int oy, int oz, bool zero) {
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            int lx, ly, lz;
+            B::split(k, lx, ly, lz);
+            const int x = ox + lx, y = oy + ly, z = oz + lz;
+            T val = T(0);
+            if (!zero && k < B::N && inside<D>(x, y, z, n)) val = g[gidx<D>(x, y, z, n)];
+            v[it] = val;
+        }
+    }
+    __device__ __forceinline__ void store(T* s) const {
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            if (k < B::N) s[k] = v[it];
+        }
+    }
+};
+
 template <typename T, int D, typename B>
 __device__ __forceinline__ void stage(T* s, const T* __restrict__ g, int n, int ox, int oy, int oz, bool zero) {
-    for (int k = threadIdx.x; k < B::N; k += kThreads) {
+    Staged<T, D, B> st;
+    st.load(g, n, ox, oy, oz, zero);
+    st.store(s);
+}
+
+// One pass over the points of box B in LDS: f(k, lx, ly, lz, v) returns the
+// LDS index to write v to, or -1 for none.  All of a thread's values are
+// computed before any is stored, so their LDS reads overlap; f must not read
+// a location that another point of the same pass writes.
+template <typename T, typename B, typename F>
+__device__ __forceinline__ void lds_pass(T* s, F&& f) {
+    constexpr int I = (B::N + kThreads - 1) / kThreads;
+    T v[I];
+    int at[I];
+#pragma unroll
+    for (int it = 0; it < I; ++it) {
+        const int k = threadIdx.x + it * kThreads;
         int lx, ly, lz;
         B::split(k, lx, ly, lz);
-        int x = ox + lx, y = oy + ly, z = oz + lz;
-        T v = T(0);
-        if (!zero && inside<D>(x, y, z, n)) v = g[gidx<D>(x, y, z, n)];
-        s[k] = v;
+        at[it] = k < B::N ? f(k, lx, ly, lz, v[it]) : -1;
+    }
+#pragma unroll
+    for (int it = 0; it < I; ++it)
+        if (at[it] >= 0) s[at[it]] = v[it];
+}
+
+// Visit the points of box B (fully unrolled; f(k, lx, ly, lz)).
+template <typename B, typename F>
+__device__ __forceinline__ void for_box(F&& f) {
+    constexpr int I = (B::N + kThreads - 1) / kThreads;
+#pragma unroll
+    for (int it = 0; it < I; ++it) {
+        const int k = threadIdx.x + it * kThreads;
+        if (k >= B::N) break;
+        int lx, ly, lz;
+        B::split(k, lx, ly, lz);
+        f(k, lx, ly, lz);
     }
 }
 
