@@ -25,6 +25,7 @@
 
 #include "internal.h"
 #include "mg_device.h"
+#include "mg_march.h"
 #include "plan.h"
 #include "sdc_device.h"
 
@@ -133,9 +134,16 @@ __global__ void __launch_bounds__(kThreads) kb_rbgs(BArgs a) {
     const SlotDesc& s = a.desc[i];
     const int l = a.level, p = a.p;
     int x0, y0, z0;
-    tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    rbgs_tile_body<T, D, ZERO>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], s.ln[l], x0, y0, z0, T(s.la[p][l]),
-                               T(s.linv[p][l]));
+    const int mz = D == 3 ? march_depth(s.ln[l]) : 0;
+    if (D == 3 && mz > 0) {
+        tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
+        march_rbgs_body<T, false, 0, ZERO>((const T*)s.lr[l], (const T*)s.le[l], nullptr, (T*)s.le2[l], s.ln[l], x0, y0,
+                                           z0, mz, T(s.la[p][l]), T(s.linv[p][l]), nullptr, nullptr);
+    } else {
+        tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
+        rbgs_tile_body<T, D, ZERO>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], s.ln[l], x0, y0, z0,
+                                   T(s.la[p][l]), T(s.linv[p][l]));
+    }
 }
 
 template <typename T, int D>
@@ -168,12 +176,20 @@ __global__ void __launch_bounds__(kThreads) kb_prolong_rbgs(BArgs a) {
     const SlotDesc& s = a.desc[i];
     const int l = a.level, p = a.p;
     int x0, y0, z0;
-    tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
     const int par = a.st[i].parity, m = s.sub[p];
     const double* g = MODE == 1 ? s.U[par ^ 1][m + 1] : nullptr;
     double* u_out = MODE == 1 ? s.U[par][m + 1] : nullptr;
-    prolong_rbgs_body<T, D, MODE>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1], (T*)s.le[l], s.ln[l],
-                                  x0, y0, z0, T(s.la[p][l]), T(s.linv[p][l]), g, u_out);
+    const int mz = D == 3 ? march_depth(s.ln[l]) : 0;
+    if (D == 3 && mz > 0) {
+        tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
+        march_rbgs_body<T, true, MODE, false>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1],
+                                              (T*)s.le[l], s.ln[l], x0, y0, z0, mz, T(s.la[p][l]), T(s.linv[p][l]), g,
+                                              u_out);
+    } else {
+        tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
+        prolong_rbgs_body<T, D, MODE>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1], (T*)s.le[l],
+                                      s.ln[l], x0, y0, z0, T(s.la[p][l]), T(s.linv[p][l]), g, u_out);
+    }
 }
 
 // u_{m+1}^{k+1} = u_{m+1}^k + e for slots whose finest level is the tail.
@@ -323,6 +339,11 @@ int tiles_fine(int d, int n) {
     return d == 1 ? ntiles_of<1>(n, Tile<1>::X, 1, 1)
                   : (d == 2 ? ntiles_of<2>(n, Tile<2>::X, Tile<2>::Y, 1)
                             : ntiles_of<3>(n, Tile<3>::X, Tile<3>::Y, Tile<3>::Z));
+}
+
+// Workgroups of the smoothing kernels on an n^d level (3D: marched columns).
+int tiles_smooth(int d, int n) {
+    return (d == 3 && march_depth(n) > 0) ? ntiles_of<3>(n, MTile::X, MTile::Y, march_depth(n)) : tiles_fine(d, n);
 }
 
 int tiles_coarse(int d, int nc) {
@@ -485,7 +506,7 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
             mtail[p].add(i, 1);
             if (sd.nlev == 0) mupd[p].add(i, ceil_div(sd.N, kChunkPts));
             for (int l = 0; l < sd.nlev; ++l) {
-                mlev[p][l].add(i, tiles_fine(D, sd.ln[l]));
+                mlev[p][l].add(i, tiles_smooth(D, sd.ln[l]));
                 mres[p][l].add(i, tiles_coarse(D, (sd.ln[l] - 1) / 2));
             }
         }

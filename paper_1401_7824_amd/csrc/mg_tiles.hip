@@ -10,7 +10,9 @@
 //   k_restrict_tile     residual rhs - A e and its full-weighting restriction;
 //   k_prolong_rbgs_tile e + P e_c (linear interpolation) followed by one
 //                       red-black step; optionally writes g + e to a float64
-//                       node array instead of e (the node update of eq. (4)).
+//                       node array instead of e (the node update of eq. (4));
+//   k_march_rbgs        the 3D form of the two red-black kernels above:
+//                       columns of planes marched in z instead of 3D tiles.
 //
 // Workgroups are numbered so that each of the 8 XCDs (the hardware hands
 // workgroup b to XCD b mod 8) receives a contiguous band of tiles, keeping the
@@ -19,6 +21,7 @@
 
 #include "internal.h"
 #include "mg_device.h"
+#include "mg_march.h"
 
 namespace isdc {
 
@@ -60,6 +63,17 @@ k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T
     prolong_rbgs_body<T, D, MODE>(r, e_in, ec, e_out, n, x0, y0, z0, a, invdiag, g, u_out);
 }
 
+// 3D red-black step (optionally after the prolongation, with the node
+// update) by z-marching columns of mz planes (march_depth of the level).
+template <typename T, bool PRO, int MODE, bool ZERO>
+__global__ void __launch_bounds__(kThreads)
+k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
+             int n, int ntx, int nty, int mz, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
+    int x0, y0, z0;
+    tile_origin(ntx, nty, MTile::X, MTile::Y, mz, x0, y0, z0);
+    march_rbgs_body<T, PRO, MODE, ZERO>(r, e_in, ec, e_out, n, x0, y0, z0, mz, a, invdiag, g, u_out);
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
@@ -80,6 +94,16 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, 
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                             hipStream_t s) {
+    if (d == 3 && march_depth(n) > 0) {
+        const int mz = march_depth(n);
+        int ntx, nty, nb;
+        tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
+        if (zero)
+            hipLaunchKernelGGL((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+        else
+            hipLaunchKernelGGL((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+        return hipGetLastError();
+    }
     ISDC_DISPATCH_D(d, {
         int ntx, nty, nb;
         tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
@@ -122,6 +146,18 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
 template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
                                     T* e_out, const double* g, double* u_out, int mode, hipStream_t s) {
+    if (d == 3 && march_depth(n) > 0) {
+        const int mz = march_depth(n);
+        int ntx, nty, nb;
+        tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
+        if (mode == 0)
+            hipLaunchKernelGGL((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+        else if (mode == 1)
+            hipLaunchKernelGGL((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+        else
+            hipLaunchKernelGGL((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+        return hipGetLastError();
+    }
     ISDC_DISPATCH_D(d, {
         int ntx, nty, nb;
         tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
