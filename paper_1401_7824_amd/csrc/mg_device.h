@@ -331,6 +331,40 @@ __device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
     }
 }
 
+// One colour ((x + y + z) & 1 == colour) of an n^D level: thread t takes the
+// colour's points t and t + kTail (1D: t only), packed two per pair of x
+// positions, so every lane of a wave has a point where a plain phase would
+// leave every other lane idle.  compute(x, y, z, i, v) returns whether to
+// store v at i; as in phase, all values are computed before any is stored.
+template <typename T, int D, typename Compute>
+__device__ __forceinline__ void phase_colour(int n, int colour, T* out, Compute&& compute) {
+    constexpr int CP = D == 1 ? 1 : 2;
+    T v[CP];
+    int idx[CP];
+    bool wr[CP];
+#pragma unroll
+    for (int q = 0; q < CP; ++q) {
+        const int k = threadIdx.x + kTail * q;
+        int x, y = 0, z = 0;
+        if (D == 1) {
+            x = 2 * k + colour;
+        } else if (D == 2) {
+            y = k >> 5;
+            x = 2 * (k & 31) + ((y + colour) & 1);
+        } else {
+            y = (k >> 3) & 15;
+            z = k >> 7;
+            x = 2 * (k & 7) + ((y + z + colour) & 1);
+        }
+        const bool ok = x < n && (D < 2 || y < n) && (D < 3 || z < n);
+        idx[q] = D == 1 ? x : (z * n + y) * n + x;
+        wr[q] = ok && compute(x, y, z, idx[q], v[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < CP; ++q)
+        if (wr[q]) out[idx[q]] = v[q];
+}
+
 template <typename T, int D>
 __device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int i) {
     T s = T(0);
@@ -394,8 +428,7 @@ __device__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invd
     if (smoother == ISDC_SMOOTH_RBGS) {
         for (int colour = 0; colour < 2; ++colour) {
             // a colour reads only the other colour: no barrier between compute and store
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || ((x + y + z) & 1) != colour) return false;
+            phase_colour<T, D>(n, colour, e, [&](int x, int y, int z, int i, T& v) {
                 v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
                 return true;
             });
@@ -426,28 +459,48 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
     __shared__ T le[L::total];
     __shared__ T lr[L::total];
     __shared__ T lt[L::big];
-    int nlev = 0, off[16], nn[16];
-    for (int o = 0, n = n_t;; n = (n - 1) / 2) {
-        off[nlev] = o;
-        nn[nlev] = n;
-        o += npts<D>(n);
-        ++nlev;
-        if (n == 1) break;
-    }
+    __shared__ T lc[3][16];  // per-level a, diag, 1/diag
+    // level l has nn(l) = (n_t + 1) / 2^l - 1 points per axis and starts at
+    // off(l) in the level arrays (uniform scalars, recomputed where needed)
+    auto nn = [&](int l) { return ((n_t + 1) >> l) - 1; };
+    auto off = [&](int l) {
+        int o = 0;
+        for (int j = 0; j < l; ++j) o += npts<D>(nn(j));
+        return o;
+    };
+    int nlev = 1;
+    while (nn(nlev - 1) > 1) ++nlev;
     {
+        // every load of the finest level is issued before any is waited on
+        constexpr int I = (L::big + kTail - 1) / kTail;
         const int N0 = npts<D>(n_t);
-        for (int i = threadIdx.x; i < N0; i += kTail) {
-            lr[i] = rhs_g[i];
-            le[i] = zero_guess ? T(0) : e_g[i];
+        T vr[I], ve[I];
+#pragma unroll
+        for (int it = 0; it < I; ++it) {
+            const int i = threadIdx.x + it * kTail;
+            vr[it] = i < N0 ? rhs_g[i] : T(0);
+            ve[it] = (i < N0 && !zero_guess) ? e_g[i] : T(0);
+        }
+        if (threadIdx.x < 48) {
+            const int q = threadIdx.x >> 4, l = threadIdx.x & 15;
+            lc[q][l] = T(q == 0 ? tc.a[l] : (q == 1 ? tc.diag[l] : tc.invdiag[l]));
+        }
+#pragma unroll
+        for (int it = 0; it < I; ++it) {
+            const int i = threadIdx.x + it * kTail;
+            if (i < N0) {
+                lr[i] = vr[it];
+                le[i] = ve[it];
+            }
         }
     }
     __syncthreads();
     const T wts[3] = {T(0.25), T(0.5), T(0.25)};
     for (int l = 0; l < nlev; ++l) {
-        const int n = nn[l];
-        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
-        T* e = le + off[l];
-        T* r = lr + off[l];
+        const int n = nn(l);
+        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
+        T* e = le + off(l);
+        T* r = lr + off(l);
         if (n == 1) {
             if (threadIdx.x == 0) e[0] = r[0] / diag;
             __syncthreads();
@@ -461,8 +514,8 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
         });
         __syncthreads();
         const int nc = (n - 1) / 2;
-        T* rc = lr + off[l + 1];
-        T* ec = le + off[l + 1];
+        T* rc = lr + off(l + 1);
+        T* ec = le + off(l + 1);
         phase<T, D>(nc, rc, [&](bool ok, int X, int Y, int Z, int I, T& v) {
             if (!ok) return false;
             T acc = T(0);
@@ -482,24 +535,22 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
         __syncthreads();
     }
     for (int l = nlev - 2; l >= 0; --l) {
-        const int n = nn[l];
-        const int nc = nn[l + 1];
-        const T a = T(tc.a[l]), diag = T(tc.diag[l]), invdiag = T(tc.invdiag[l]);
-        T* e = le + off[l];
-        T* r = lr + off[l];
-        const T* ec = le + off[l + 1];
+        const int n = nn(l);
+        const int nc = nn(l + 1);
+        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
+        T* e = le + off(l);
+        T* r = lr + off(l);
+        const T* ec = le + off(l + 1);
         int k0 = 0;
         if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
             // first red pass on the corrected iterate e + P ec without storing the
             // correction: red reads only black values, black overwrites black
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || ((x + y + z) & 1)) return false;
+            phase_colour<T, D>(n, 0, e, [&](int x, int y, int z, int i, T& v) {
                 v = (r[i] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, i)) * invdiag;
                 return true;
             });
             __syncthreads();
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok || !((x + y + z) & 1)) return false;
+            phase_colour<T, D>(n, 1, e, [&](int x, int y, int z, int i, T& v) {
                 v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
                 return true;
             });
@@ -516,8 +567,13 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
         for (int k = k0; k < nu2; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
     }
     {
+        constexpr int I = (L::big + kTail - 1) / kTail;
         const int N0 = npts<D>(n_t);
-        for (int i = threadIdx.x; i < N0; i += kTail) e_g[i] = le[i];
+#pragma unroll
+        for (int it = 0; it < I; ++it) {
+            const int i = threadIdx.x + it * kTail;
+            if (i < N0) e_g[i] = le[i];
+        }
     }
 }
 
