@@ -26,11 +26,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ISDC steps/s, V-cycle HBM GB/s (% of peak), p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
-# sources of the fine-level multigrid kernels; counter figures taken before a
-# change to any of them are stale
-TRAFFIC_SOURCES = ("paper_1401_7824_amd/csrc/mg_tiles.hip", "paper_1401_7824_amd/csrc/mg_device.h",
-                   "paper_1401_7824_amd/csrc/tile_common.h")
-
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -84,6 +79,14 @@ KERNEL_NAMES = {
 }
 
 
+def kernel_name(name, cfg, T):
+    """rocprof name of the kernel bench.py times for `name` on the finest level
+    (3D levels of 127^3 and up run the z-marching form)."""
+    if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
+        return f"k_march_rbgs<{T},true,0,false>"
+    return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"])
+
+
 def accuracy_vs_collocation(cfg, torch):
     """One step of a linear (heat) workload in float32-V-cycle and all-float64
     form, each compared with the direct collocation solution: the sine-mode
@@ -118,22 +121,17 @@ def accuracy_vs_collocation(cfg, torch):
     return out
 
 
-def counter_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs (profiles/traffic.json), or None if the kernel's sources have
-    changed since the counters were taken."""
-    import hashlib
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on the finest level of `workload` from the
+    committed FETCH_SIZE / WRITE_SIZE counter runs (profiles/traffic.json, written
+    by paper_1401_7824_amd.profiling), or None if there is no such record or the
+    kernel sources have changed since the counters were taken."""
+    from paper_1401_7824_amd.profiling import sources_sha256
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(kernel)
-    if rec is None:
-        return None
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    rec = json.load(open(path)).get(f"{workload}:{kernel}")
+    if rec is None or rec.get("sources_sha256") != sources_sha256(ROOT):
         return None
     return rec["bytes_per_launch"]
 
@@ -160,7 +158,7 @@ def kernel_probe(plan, cfg, reps, torch):
         if name != "tail" and cfg["n"] <= tail_n:
             continue  # the whole V-cycle is the single-workgroup coarse solve
         us, b = plan.time_kernel(k, 0, c, prec, reps)
-        out[name] = dict(kernel=KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"]), avg_us=round(us, 3),
+        out[name] = dict(kernel=kernel_name(name, cfg, T), avg_us=round(us, 3),
                          alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1))
     return out
 
@@ -502,7 +500,7 @@ def main():
     kp = kernel_probe(plan, cfg, args.probe_reps, torch)
     vc = vcycle_probe(plan, cfg, 20, torch)
     dom = kp.get("smooth_restrict") or kp.get("prolong_smooth") or kp["tail"]
-    traffic = counter_traffic(dom["kernel"]) if args.workload == "rd2d" else None
+    traffic = counter_traffic(dom["kernel"], args.workload)
     roof = dict(bound="hbm", achieved=dom["gbps"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(dom["gbps"] / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["kernel"] + " (finest level)",
                 avg_launch_us=dom["avg_us"], alg_bytes_per_launch=dom["alg_bytes"])

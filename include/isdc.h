@@ -193,9 +193,10 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
                const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
 
 /* Time one of the plan's kernels as the step launches it: `reps` launches on
- * `stream`, each bracketed by its own pair of HIP events, on the plan's own
- * buffers at `level` (their contents are whatever the last solve left; the
- * timing does not depend on the values).  Writes the average duration per
+ * `stream`, back to back between one pair of HIP events (so the average
+ * includes the short gap between consecutive launches but no per-launch
+ * event cost), on the plan's own buffers at `level` (their contents are
+ * whatever the last solve left; the timing does not depend on the values).  Writes the average duration per
  * launch in microseconds to *h_avg_us and the kernel's algorithmic bytes per
  * launch (every array element read or written once) to *h_bytes, and
  * synchronises `stream`.  For measurement; leaves the plan's workspace

@@ -641,23 +641,19 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
     } else {
         fail(ISDC_E_INVAL, "unknown kernel");
     }
-    std::vector<hipEvent_t> ev(2 * reps);
+    // one event pair around `reps` back-to-back launches: a pair around every
+    // launch would add the events' own cost to each (a few us per launch)
+    hipEvent_t ev[2];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     launch();  // warm-up
-    for (int k = 0; k < reps; ++k) {
-        HIPCHK(hipEventRecord(ev[2 * k], s));
-        launch();
-        HIPCHK(hipEventRecord(ev[2 * k + 1], s));
-    }
+    HIPCHK(hipEventRecord(ev[0], s));
+    for (int k = 0; k < reps; ++k) launch();
+    HIPCHK(hipEventRecord(ev[1], s));
     HIPCHK(hipStreamSynchronize(s));
-    double tot = 0.0;
-    for (int k = 0; k < reps; ++k) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
-        tot += ms;
-    }
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
     for (auto& e : ev) (void)hipEventDestroy(e);
-    *avg_us = tot / reps * 1e3;
+    *avg_us = (double)ms / reps * 1e3;
     *bytes = b;
 }
 
