@@ -19,12 +19,15 @@ Module map (each function cites the passage it follows):
   exact shifted-Laplacian solve by sine transform.
 * ``multigrid`` -- the geometric multigrid V-cycle used as the inner solver
   (Sec. 3), in float64 or float32.
-* ``sdc`` -- the semi-implicit SDC sweep of eq. (4) with exact, classical
-  (solve to tolerance) and inexact (L V-cycles) inner solves, the SDC
-  residual of Sec. 3, and the time step.
+* ``compact`` -- the fourth-order compact Laplacian A_h and its weighting
+  matrix W (Sec. 3, eq. (5)), their exact solves by sine transform and the
+  weighted-Jacobi V-cycle for W - c A_h.
+* ``sdc`` -- the semi-implicit SDC sweep of eq. (4) (and of eq. (5) for the
+  compact stencil) with exact, classical (solve to tolerance) and inexact
+  (L V-cycles) inner solves, the SDC residual of Sec. 3, and the time step.
 
-Parity pins for every function live in ``tests/test_oracle_*.py`` and are
-listed in DESIGN.md.  Nothing here is "parity unpinned".
+Parity pins for every function live in ``tests/test_oracle_*.py``.  Nothing
+here is "parity unpinned".
 """
 
 from .collocation import (  # noqa: F401
@@ -56,7 +59,18 @@ from .multigrid import (  # noqa: F401
     prolong_linear,
     level_sizes,
 )
+from .compact import (  # noqa: F401
+    laplacian_compact,
+    weight,
+    compact_eigenvalues,
+    solve_weight_exact,
+    solve_compact_shifted_exact,
+    apply_compact_shifted,
+    vcycle_compact,
+)
 from .sdc import (  # noqa: F401
+    STENCIL_2ND,
+    STENCIL_COMPACT4,
     SDCConfig,
     SDCStats,
     sdc_step,

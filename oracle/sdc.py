@@ -28,6 +28,12 @@ Paper basis:
   right-hand side rounded to float32 and u = g + e accumulated in float64.
   The fixed point of the sweep is unchanged because that right-hand side
   vanishes at the collocation solution.
+* Compact stencil (``stencil = STENCIL_COMPACT4``, eq. (5)): f~(u) =
+  W f^E(u) + nu A_h u is kept per node, the implicit system is
+  (W - dt_m nu A_h) u_{m+1}^{k+1} = W u_m^{k+1} + dt_m W [f^E(u_m^{k+1}) -
+  f^E(u_m^k)] - dt_m nu A_h u_{m+1}^k + S_m^{m+1} F~(u^k), and the residual is
+  u_0 + W^{-1} (dt sum_j q_{m,j} f~(u_j)) - u_m (W and A_h in compact.py).
+  Its multigrid is the weighted-Jacobi V-cycle of compact.py.
 """
 
 from __future__ import annotations
@@ -37,8 +43,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .collocation import qmatrix, smatrix, nodes, NODES_LOBATTO
+from .compact import (laplacian_compact, weight, solve_weight_exact, apply_compact_shifted,
+                      solve_compact_shifted_exact, vcycle_compact, residual_compact_inf)
 from .multigrid import SMOOTH_RBGS, vcycle, residual_inf
 from .operators import FE_ZERO, f_explicit, f_implicit, apply_shifted, solve_shifted_exact
+
+STENCIL_2ND = 0
+STENCIL_COMPACT4 = 1
 
 GUESS_PREV_SWEEP = 0
 GUESS_ZERO = 1
@@ -75,6 +86,7 @@ class SDCConfig:
     precision: int = PREC_FP64
     guess: int = GUESS_PREV_SWEEP
     max_classical_cycles: int = 100
+    stencil: int = STENCIL_2ND
 
 
 @dataclass
@@ -101,6 +113,9 @@ class SDCState:
 
 
 def _f(u, cfg, h):
+    """f(u) = nu L_h u + f^E(u); for the compact stencil f~(u) = W f^E(u) + nu A_h u."""
+    if cfg.stencil == STENCIL_COMPACT4:
+        return weight(f_explicit(u, cfg.fe_kind), h) + cfg.nu * laplacian_compact(u, h)
     return f_implicit(u, cfg.nu, h) + f_explicit(u, cfg.fe_kind)
 
 
@@ -112,7 +127,10 @@ def sdc_residual(state: SDCState) -> float:
         quad = np.zeros_like(state.u0)
         for j in range(1, cfg.M + 1):
             quad = quad + state.Q[m - 1, j - 1] * state.F[j]
-        r = state.u0 + state.dt * quad - state.U[m]
+        if cfg.stencil == STENCIL_COMPACT4:  # the stored values are W f: invert W once per node
+            r = state.u0 + solve_weight_exact(state.dt * quad, state.h) - state.U[m]
+        else:
+            r = state.u0 + state.dt * quad - state.U[m]
         per_node.append(np.max(np.abs(r)))
     return float(np.max(per_node))  # np.max propagates NaN
 
@@ -130,20 +148,29 @@ def sdc_begin(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig) -> SDCState:
 
 
 def _inner_solve(rhs, guess, c, h, cfg):
-    """Solve (I - c L_h) u = rhs; returns (u, number of V-cycles)."""
+    """Solve (I - c L_h) u = rhs (compact: (W - c A_h) u = rhs); returns (u, V-cycles)."""
+    compact = cfg.stencil == STENCIL_COMPACT4
     if cfg.inner == "exact":
-        return solve_shifted_exact(rhs, c, h), 0
+        return (solve_compact_shifted_exact(rhs, c, h) if compact else solve_shifted_exact(rhs, c, h)), 0
+    apply_op = apply_compact_shifted if compact else apply_shifted
+    res_inf = residual_compact_inf if compact else residual_inf
+
+    def cycle(v, b):
+        if compact:
+            return vcycle_compact(v, b, c, h, cfg.nu1, cfg.nu2, cfg.omega if cfg.omega is not None else 1.0)
+        return vcycle(v, b, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
+
     if cfg.precision == PREC_FP64:
         u = guess.copy()
 
         def inner_res():
-            return residual_inf(u, rhs, c, h)
+            return res_inf(u, rhs, c, h)
     else:
-        r32 = (rhs - apply_shifted(guess, c, h)).astype(np.float32)
+        r32 = (rhs - apply_op(guess, c, h)).astype(np.float32)
         e = np.zeros_like(r32)
 
         def inner_res():
-            return residual_inf(e, r32, c, h)
+            return res_inf(e, r32, c, h)
 
     classical = cfg.vcycles == 0
     limit = cfg.max_classical_cycles if classical else cfg.vcycles
@@ -153,9 +180,9 @@ def _inner_solve(rhs, guess, c, h, cfg):
         if check and inner_res() <= cfg.inner_tol:
             break
         if cfg.precision == PREC_FP64:
-            u = vcycle(u, rhs, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
+            u = cycle(u, rhs)
         else:
-            e = vcycle(e, r32, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
+            e = cycle(e, r32)
         ncyc += 1
     if cfg.precision == PREC_FP64:
         return u, ncyc
@@ -182,11 +209,15 @@ def sdc_sweep(state: SDCState) -> float:
     for m in range(M):
         dtm = dt * (tau_ext[m + 1] - tau_ext[m])
         um_new, um_old, up_old = Unew[m], Uold[m], Uold[m + 1]
-        rhs = (um_new + dtm * (f_explicit(um_new, cfg.fe_kind) - f_explicit(um_old, cfg.fe_kind))
-               - dtm * f_implicit(up_old, cfg.nu, h) + SF[m])
         c = dtm * cfg.nu
+        explicit = um_new + dtm * (f_explicit(um_new, cfg.fe_kind) - f_explicit(um_old, cfg.fe_kind))
+        if cfg.stencil == STENCIL_COMPACT4:  # eq. (5)
+            rhs = weight(explicit, h) - c * laplacian_compact(up_old, h) + SF[m]
+        else:  # eq. (4)
+            rhs = explicit - dtm * f_implicit(up_old, cfg.nu, h) + SF[m]
         if dtm == 0.0:
-            u = rhs  # degenerate substep (tau_1 = 0 for Gauss-Lobatto): identity operator
+            # degenerate substep (tau_1 = 0 for Gauss-Lobatto): the operator is I (or W)
+            u = solve_weight_exact(rhs, h) if cfg.stencil == STENCIL_COMPACT4 else rhs
         else:
             if cfg.guess == GUESS_PREV_SWEEP:
                 g = up_old
