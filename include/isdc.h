@@ -15,6 +15,12 @@
  * from the previous sweep (Sec. 3, Sec. 4.3), and sweeps continue until the
  * max-norm SDC residual (Sec. 3) is below a tolerance.
  *
+ * With the fourth-order compact stencil (isdc_problem.stencil, 2D only) f^I
+ * is nu W^{-1} A_h with the 9-point A_h = L_h + (h^2/6) D_x D_y and the
+ * weighting matrix W = I + (h^2/12) L_h; the sweep is eq. (5), whose systems
+ * (W - dt_m nu A_h) u = rhs are solved by weighted-Jacobi V-cycles, and the
+ * SDC residual inverts W once per node (Sec. 3).
+ *
  * Conventions shared by every entry point:
  *  - Grid arrays are dense, row-major n^d arrays of the interior points with
  *    the x index fastest (numpy C order of shape (n,)*d).  No ghost points.
@@ -54,8 +60,13 @@ typedef enum {
 enum { ISDC_NODES_LOBATTO = 0, ISDC_NODES_RADAU_RIGHT = 1 };
 /* Explicit part f^E of eq. (4). */
 enum { ISDC_FE_ZERO = 0, ISDC_FE_CUBIC = 1 };
+/* Spatial discretisation of the Laplacian: the second-order (2d+1)-point
+ * stencil (W = I, eq. (4)) or the fourth-order compact stencil with its
+ * weighting matrix W (Sec. 3, eq. (5); 2D, weighted Jacobi with omega = 1,
+ * warm-started V-cycles only). */
+enum { ISDC_STENCIL_2ND = 0, ISDC_STENCIL_COMPACT4 = 1 };
 /* Multigrid smoother: red-black Gauss-Seidel (red = even index sum, first) or
- * weighted Jacobi with omega = 2d/(2d+1). */
+ * weighted Jacobi with omega = 2d/(2d+1) (omega = 1 with the compact stencil). */
 enum { ISDC_SMOOTH_RBGS = 0, ISDC_SMOOTH_JACOBI = 1 };
 /* Arithmetic of the V-cycles.  The SDC residual, the S*F quadrature, the
  * right-hand side and the node update are always float64. */
@@ -80,6 +91,8 @@ typedef struct {
                       /* k <= 13 (d = 2), k <= 10 (d = 3)                             */
     double nu;        /* diffusion coefficient, finite and >= 0                       */
     int32_t fe_kind;  /* ISDC_FE_*                                                    */
+    int32_t stencil;  /* ISDC_STENCIL_* (COMPACT4: dim = 2, smoother JACOBI, guess     */
+                      /* PREV_SWEEP, not in batches; else ISDC_E_UNSUPPORTED)          */
 } isdc_problem;
 
 typedef struct {
@@ -176,7 +189,10 @@ int isdc_get_stats(const isdc_plan* plan, isdc_stats* out);
  * precision selects float64 (ISDC_PREC_FP64: d_rhs, d_u are double*) or
  * float32 (ISDC_PREC_MIXED: float*).  c >= 0 is dt_m * nu.  If h_res_inf is
  * not NULL, max|rhs - (I - c L_h) u| after the cycles is written there and
- * `stream` is synchronised. */
+ * `stream` is synchronised.  For a compact-stencil plan the operator here and
+ * in isdc_mg_op is B_H = I + (h^2/12) L_H - c A_H on the level of spacing H
+ * (h the finest spacing, so B_h = W - c A_h) and the smoother is weighted
+ * Jacobi with omega = 1. */
 int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs, void* d_u,
                 int32_t ncycles, void* stream, double* h_res_inf);
 
@@ -196,11 +212,12 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * `stream`, back to back between one pair of HIP events (so the average
  * includes the short gap between consecutive launches but no per-launch
  * event cost), on the plan's own buffers at `level` (their contents are
- * whatever the last solve left; the timing does not depend on the values).  Writes the average duration per
- * launch in microseconds to *h_avg_us and the kernel's algorithmic bytes per
- * launch (every array element read or written once) to *h_bytes, and
- * synchronises `stream`.  For measurement; leaves the plan's workspace
- * arrays with unspecified contents, so call it only between steps.
+ * whatever the last solve left; the timing does not depend on the values).
+ * Writes the average duration per launch in microseconds to *h_avg_us and
+ * the kernel's algorithmic bytes per launch (every array element read or
+ * written once) to *h_bytes, and synchronises `stream`.  For measurement;
+ * leaves the plan's workspace arrays with unspecified contents, so call it
+ * only between steps.  Second-order plans only (compact: ISDC_E_UNSUPPORTED).
  *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
  *                                full-weighting restriction (levels above the
  *                                coarse tail, d = 1 or 2)

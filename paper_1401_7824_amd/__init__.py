@@ -5,8 +5,8 @@ package is a thin binding over it.  The library is loaded on first use and
 its absence is an error.
 """
 from ._capi import (  # noqa: F401
-    ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, SMOOTH_RBGS, SMOOTH_JACOBI,
-    PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
+    ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, STENCIL_2ND, STENCIL_COMPACT4,
+    SMOOTH_RBGS, SMOOTH_JACOBI, PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
     OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, load,
     KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD,
     SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED,

@@ -16,6 +16,7 @@ STATUS_NAMES = {OK: "ok", E_INVAL: "invalid", E_WORKSPACE: "workspace", E_HIP: "
                 E_NOT_CONVERGED: "not_converged", E_DIVERGED: "diverged", E_UNSUPPORTED: "unsupported"}
 NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
 FE_ZERO, FE_CUBIC = 0, 1
+STENCIL_2ND, STENCIL_COMPACT4 = 0, 1
 SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
@@ -27,7 +28,8 @@ HIST = 128
 
 
 class Problem(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("fe_kind", C.c_int32)]
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("fe_kind", C.c_int32),
+                ("stencil", C.c_int32)]
 
 
 class Params(C.Structure):

@@ -145,4 +145,70 @@ template <typename T>
 hipError_t launch_node_update(size_t N, int guess, const double* up_old, const double* um_new,
                               const T* e, double* u_out, hipStream_t s);
 
+// ---------------------------------------------------------------- compact stencil (2D, compact.hip)
+// B_H = I + w L_H - c A_H on a level of spacing H: centre b0, the 4 edge
+// neighbours bf, the 4 corners bc; omega of the weighted-Jacobi smoother.
+template <typename T>
+struct CCoef {
+    T b0, bf, bc, inv_b0, omega;
+};
+template <typename T>
+CCoef<T> make_ccoef(double c, double w, double H, double omega);
+
+struct CTailCoefs {
+    double b0[16], bf[16], bc[16];
+};
+
+struct CRhsArgs {
+    const double* um_new;  // u_m^{k+1}
+    const double* um_old;  // u_m^k
+    const double* up_old;  // u_{m+1}^k (the guess)
+    const double* sf;      // S_m^{m+1} F~(u^k)
+    double dtm;
+    int n;
+    int fe;
+};
+
+struct CQuadArgs {
+    const double* u[ISDC_MAX_M + 1];  // u_0 .. u_M
+    double* sf[ISDC_MAX_M];           // S_m^{m+1} F~ (NULL: not needed)
+    double* y[ISDC_MAX_M];            // dt Q_m F~    (NULL: not needed)
+    double dtS[ISDC_MAX_M * ISDC_MAX_M];
+    double dtQ[ISDC_MAX_M * ISDC_MAX_M];
+    double nu_6h2;                    // nu / (6 h^2)
+    int n, fe, M;
+};
+
+constexpr int kCResBlocks = 256;
+struct CResArgs {
+    const double* u0;
+    const double* um[ISDC_MAX_M];  // u_m of the nodes taking part
+    const double* xm[ISDC_MAX_M];  // W^{-1} Y_m of the same nodes
+    size_t N;
+    int count;
+};
+
+// One weighted-Jacobi step e_out = e + omega (r - B e) / b0 (zero: e = 0).
+template <typename T>
+hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, hipStream_t s);
+// rc = full weighting of r - B e, an n^2 level to ((n-1)/2)^2.
+template <typename T>
+hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, hipStream_t s);
+// Per-block maxima of |r - B e| in partial[0 .. *nblocks).
+template <typename T>
+hipError_t launch_cresnorm(int n, const CCoef<T>& k, const T* r, const T* e, double* partial, int* nblocks,
+                           hipStream_t s);
+// r = W [u_m^{k+1} - g + dt_m (f^E(u_m^{k+1}) - f^E(u_m^k))] + S_m F~.
+template <typename T>
+hipError_t launch_crhs(const CRhsArgs& a, T* out, hipStream_t s);
+// S F~ and dt Q F~ of the current node values.
+hipError_t launch_cquad(const CQuadArgs& a, int M, hipStream_t s);
+// Per-node maxima of |u_0 + x_m - u_m|; kCResBlocks * count partials.
+hipError_t launch_cres(const CResArgs& a, double* partial, int* nblocks, hipStream_t s);
+// One V-cycle of B (weighted Jacobi V(nu_pre, nu_post)) on a level of at
+// most 63^2 points in one workgroup.
+template <typename T>
+hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h, bool zero, const T* rhs, T* e,
+                        hipStream_t s);
+
 }  // namespace isdc

@@ -2,6 +2,7 @@
 // workspace, the V-cycle schedule, the SDC sweep of eq. (4) and the step loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -56,6 +57,14 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
         fail(ISDC_E_INVAL, "nu_pre, nu_post must be in 0..8 with nu_pre + nu_post >= 1");
     if (pr->precision != ISDC_PREC_FP64 && pr->precision != ISDC_PREC_MIXED) fail(ISDC_E_INVAL, "unknown precision");
     if (pr->guess < ISDC_GUESS_PREV_SWEEP || pr->guess > ISDC_GUESS_PREV_NODE) fail(ISDC_E_INVAL, "unknown guess");
+    if (pb->stencil != ISDC_STENCIL_2ND && pb->stencil != ISDC_STENCIL_COMPACT4) fail(ISDC_E_INVAL, "unknown stencil");
+    if (pb->stencil == ISDC_STENCIL_COMPACT4) {
+        if (pb->dim != 2) fail(ISDC_E_UNSUPPORTED, "the compact stencil is implemented in 2D");
+        if (pr->smoother != ISDC_SMOOTH_JACOBI)
+            fail(ISDC_E_UNSUPPORTED, "the compact stencil needs the Jacobi smoother (red-black is not Gauss-Seidel for 9 points)");
+        if (pr->guess != ISDC_GUESS_PREV_SWEEP)
+            fail(ISDC_E_UNSUPPORTED, "the compact stencil warm-starts from the previous sweep only");
+    }
 }
 
 // Lay the plan's arrays out from `base` (nullptr: sizing only); returns the byte count.
@@ -102,8 +111,23 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
         h *= 2.0;
         ++l;
     }
-    const int nparts = quad_partials(d, pb.n) > kReduceBlocks ? quad_partials(d, pb.n) : kReduceBlocks;
-    void* part = take((size_t)nparts * sizeof(double));
+    const bool compact = pb.stencil == ISDC_STENCIL_COMPACT4;
+    if (compact)
+        for (int m = 0; m < M; ++m) {
+            bool zero_row = (m == 0 && pr.node_kind == ISDC_NODES_LOBATTO);  // Q row of tau_1 = 0
+            void* y = zero_row ? nullptr : take(N * sizeof(double));
+            void* x = zero_row ? nullptr : take(N * sizeof(double));
+            if (p) {
+                p->Yq[m] = (double*)y;
+                p->X[m] = (double*)x;
+            }
+        }
+    size_t nparts = quad_partials(d, pb.n) > kReduceBlocks ? quad_partials(d, pb.n) : kReduceBlocks;
+    if (compact) {
+        const size_t rows = (size_t)pb.n * ((pb.n + 255) / 256);  // residual-norm blocks of the finest level
+        nparts = std::max(nparts, std::max(rows, (size_t)kCResBlocks * M));
+    }
+    void* part = take(nparts * sizeof(double));
     void* sc = take(16 * sizeof(double));
     if (p) {
         p->partial = (double*)part;
@@ -141,13 +165,13 @@ struct Fuse {
 };
 
 template <typename T>
-void smooth_steps(isdc_plan* p, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs, T*& cur, T*& other,
-                  hipStream_t s) {
+void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs,
+                  T*& cur, T*& other, hipStream_t s) {
     for (int k = 0; k < nsteps; ++k) {
-        if (p->mg.smoother == ISDC_SMOOTH_RBGS)
+        if (mg.smoother == ISDC_SMOOTH_RBGS)
             HIPCHK(launch_rbgs_tile<T>(p->d, n, co, zero, rhs, cur, other, s));
         else
-            HIPCHK(launch_smooth<T>(p->mg, n, co, zero, rhs, cur, other, s));
+            HIPCHK(launch_smooth<T>(mg, n, co, zero, rhs, cur, other, s));
         std::swap(cur, other);
         zero = false;
     }
@@ -158,45 +182,45 @@ void smooth_steps(isdc_plan* p, int nsteps, int n, const Coef<T>& co, bool& zero
 // fuse.u_out and `e` is left unspecified).  tmp: a scratch array of the
 // level's size.  Returns true if the fused update was done.
 template <typename T>
-bool vcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s,
+bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s,
                 const Fuse& fuse = Fuse()) {
     const Level& L = p->lev[l];
     if (l == p->tail) {
-        HIPCHK(launch_tail<T>(p->mg, L.n, c, L.h, zero, rhs, e, s));
+        HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
         return false;
     }
-    const bool rbgs = p->mg.smoother == ISDC_SMOOTH_RBGS;
-    Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
+    const bool rbgs = mg.smoother == ISDC_SMOOTH_RBGS;
+    Coef<T> co = make_coef<T>(c, L.h, p->d, mg.omega);
     T* cur = e;
     T* other = tmp;
     const Level& C = p->lev[l + 1];
-    if (rbgs && p->mg.nu_pre >= 1 && p->d <= 2) {
+    if (rbgs && mg.nu_pre >= 1 && p->d <= 2) {
         // pre-smoothing steps; the last one fused with residual + restriction
-        smooth_steps<T>(p, p->mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s);
         HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s));
         std::swap(cur, other);
         zero = false;
     } else {
-        smooth_steps<T>(p, p->mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
         if (zero) {  // no pre-smoothing and a zero iterate
             HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
             zero = false;
         }
         HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
     }
-    vcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    vcycle_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
     bool fused = false;
-    if (rbgs && p->mg.nu_post >= 1) {
+    if (rbgs && mg.nu_post >= 1) {
         // prolongation + correction fused with the first post-smoothing step
-        const bool last = p->mg.nu_post == 1;
+        const bool last = mg.nu_post == 1;
         const int mode = (last && fuse.mode) ? fuse.mode : 0;
         HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, mode, s));
         if (mode) return true;
         std::swap(cur, other);
-        smooth_steps<T>(p, p->mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s);
     } else {
         HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
-        smooth_steps<T>(p, p->mg.nu_post, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_post, L.n, co, zero, rhs, cur, other, s);
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
     return fused;
@@ -234,6 +258,125 @@ void quad_residual(isdc_plan* p, const double* const* nodes, hipStream_t s) {
     HIPCHK(launch_reduce_max(p->partial, nb, p->scalars, s));
 }
 
+// ---------------------------------------------------------------- compact stencil (eq. (5))
+
+// W^{-1} for the residual: red-black V(1,1) cycles on I + w L, from zero after
+// the first sweep of a step, then warm-started from the previous sweep's value.
+constexpr int kWColdCycles = 14;
+constexpr int kWWarmCycles = 6;
+
+// One V-cycle of B_H = I + w L_H - c A_H with weighted-Jacobi smoothing on
+// level l; same contract as vcycle_rec (result in e; tmp: scratch of the level).
+template <typename T>
+void cvcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s) {
+    const Level& L = p->lev[l];
+    if (l == p->tail) {
+        HIPCHK(launch_ctail<T>(p->mg, L.n, c, p->w, L.h, zero, rhs, e, s));
+        return;
+    }
+    const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
+    T* cur = e;
+    T* other = tmp;
+    for (int i = 0; i < p->mg.nu_pre; ++i) {
+        HIPCHK(launch_cjacobi<T>(L.n, k, zero, rhs, cur, other, s));
+        std::swap(cur, other);
+        zero = false;
+    }
+    if (zero) {
+        HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
+        zero = false;
+    }
+    const Level& C = p->lev[l + 1];
+    HIPCHK(launch_cresfw<T>(L.n, k, rhs, cur, (T*)C.r, s));
+    cvcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
+    for (int i = 0; i < p->mg.nu_post; ++i) {
+        HIPCHK(launch_cjacobi<T>(L.n, k, false, rhs, cur, other, s));
+        std::swap(cur, other);
+    }
+    if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
+}
+
+template <typename T>
+double cresnorm(isdc_plan* p, int l, double c, const T* rhs, const T* u, hipStream_t s) {
+    const Level& L = p->lev[l];
+    int nb = 0;
+    HIPCHK(launch_cresnorm<T>(L.n, make_ccoef<T>(c, p->w, L.h, p->mg.omega), rhs, u, p->partial, &nb, s));
+    HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 1, s));
+    return read_scalar(p, p->scalars + 1, s);
+}
+
+// The compact system of substep m in correction form (r in lev[0].r):
+// L V-cycles from e = 0 (or cycles until the inner residual <= inner_tol),
+// then u_out = g + e.
+template <typename T>
+int cinner_solve(isdc_plan* p, double c, const double* g, double* u_out, hipStream_t s) {
+    const Level& L0 = p->lev[0];
+    T* r0 = (T*)L0.r;
+    T* e0 = (T*)L0.e;
+    T* t0 = (T*)L0.e2;
+    const isdc_params& pr = p->par;
+    const bool classical = pr.vcycles == 0;
+    const bool check = classical || pr.early_exit;
+    const int limit = classical ? 100 : pr.vcycles;
+    int k = 0;
+    if (!check) {
+        for (; k < limit; ++k) cvcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s);
+    } else {
+        HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
+        for (; k < limit; ++k) {
+            if (cresnorm<T>(p, 0, c, r0, e0, s) <= pr.inner_tol) break;
+            cvcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+        }
+    }
+    HIPCHK(launch_node_update<T>(p->N, ISDC_GUESS_PREV_SWEEP, g, g, e0, u_out, s));
+    return k;
+}
+
+// S F~ for the next sweep and dt Q F~ for the residual from the node values.
+void cquad(isdc_plan* p, const double* const* nodes, hipStream_t s) {
+    CQuadArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int j = 0; j <= p->M; ++j) a.u[j] = nodes[j];
+    for (int m = 0; m < p->M; ++m) {
+        a.sf[m] = p->SF[m];
+        a.y[m] = p->Yq[m];
+        for (int j = 0; j < p->M; ++j) {
+            a.dtS[m * ISDC_MAX_M + j] = p->dt * p->S[m * p->M + j];
+            a.dtQ[m * ISDC_MAX_M + j] = p->dt * p->Q[m * p->M + j];
+        }
+    }
+    a.nu_6h2 = p->prob.nu / (6.0 * p->h * p->h);
+    a.n = p->n;
+    a.fe = p->prob.fe_kind;
+    a.M = p->M;
+    HIPCHK(launch_cquad(a, p->M, s));
+}
+
+// max over nodes and points of |u_0 + W^{-1} (dt Q F~)_m - u_m| (Sec. 3: W is
+// inverted once per node), after cquad of the same node values.
+double cresidual(isdc_plan* p, hipStream_t s) {
+    CResArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.u0 = p->u0;
+    ra.N = p->N;
+    const int ncyc = p->x_valid ? kWWarmCycles : kWColdCycles;
+    for (int m = 0; m < p->M; ++m) {
+        if (!p->Yq[m]) continue;
+        for (int k = 0; k < ncyc; ++k)
+            vcycle_rec<double>(p, p->wmg, 0, -p->w, !p->x_valid && k == 0, p->Yq[m], p->X[m],
+                               (double*)p->lev[0].e2, s);
+        ra.um[ra.count] = p->cur[m + 1];
+        ra.xm[ra.count] = p->X[m];
+        ++ra.count;
+    }
+    p->x_valid = true;
+    int nb = 0;
+    HIPCHK(launch_cres(ra, p->partial, &nb, s));
+    HIPCHK(launch_reduce_max(p->partial, nb, p->scalars, s));
+    return read_scalar(p, p->scalars, s);
+}
+
 // The implicit solve of substep m in correction form: the right-hand side
 // r = rhs - A g is in lev[0].r; L V-cycles from e = 0 (or cycles until the
 // inner residual <= inner_tol), then u_out = g + e.  The update is fused into
@@ -251,13 +394,13 @@ int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
     int k = 0;
     bool fused = false;
     if (!check) {
-        for (; k < limit; ++k) fused = vcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse());
+        for (; k < limit; ++k) fused = vcycle_rec<T>(p, p->mg, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse());
     } else {
         HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
         for (; k < limit; ++k) {
             double res = resnorm<T>(p, 0, c, r0, e0, s);
             if (res <= pr.inner_tol) break;
-            vcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+            vcycle_rec<T>(p, p->mg, 0, c, false, r0, e0, t0, s);
         }
     }
     if (!fused) {
@@ -279,6 +422,12 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
     for (int m = 0; m < M; ++m) {
         if (p->dtau[m] == 0.0) continue;  // tau_1 = 0 (Lobatto): u_1 = u_0, no solve
         const double dtm = p->dt * p->dtau[m];
+        if (p->compact) {  // eq. (5)
+            CRhsArgs ca{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, p->n, p->prob.fe_kind};
+            HIPCHK(launch_crhs<T>(ca, (T*)p->lev[0].r, s));
+            p->stats.vcycles += cinner_solve<T>(p, dtm * p->prob.nu, p->cur[m + 1], (double*)nw[m + 1], s);
+            continue;
+        }
         RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
                    p->prob.fe_kind, p->par.guess};
         HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
@@ -294,8 +443,14 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
     }
     for (int j = 0; j <= M; ++j) p->cur[j] = nw[j];
     p->wbuf ^= 1;
-    quad_residual(p, p->cur, s);
-    double res = read_scalar(p, p->scalars, s);
+    double res;
+    if (p->compact) {
+        cquad(p, p->cur, s);
+        res = cresidual(p, s);
+    } else {
+        quad_residual(p, p->cur, s);
+        res = read_scalar(p, p->scalars, s);
+    }
     p->stats.sweeps += 1;
     p->stats.residual = res;
     if (p->stats.hist_len < ISDC_HIST) p->stats.residual_hist[p->stats.hist_len++] = res;
@@ -311,7 +466,12 @@ void begin_impl(isdc_plan* p, const double* d_u0, double dt, hipStream_t s) {
     p->wbuf = 0;
     p->begun = true;
     std::memset(&p->stats, 0, sizeof(p->stats));
-    quad_residual(p, p->cur, s);  // S*F(u^0) for sweep 1
+    if (p->compact) {
+        cquad(p, p->cur, s);  // S*F~(u^0) for sweep 1
+        p->x_valid = false;
+    } else {
+        quad_residual(p, p->cur, s);  // S*F(u^0) for sweep 1
+    }
 }
 
 double sweep_any(isdc_plan* p, hipStream_t s) {
@@ -348,7 +508,14 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
         p->dtau[m] = p->tau[m] - prev;
         prev = p->tau[m];
     }
-    p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post, 2.0 * p->d / (2.0 * p->d + 1.0)};
+    p->compact = prob->stencil == ISDC_STENCIL_COMPACT4;
+    p->w = p->h * p->h / 12.0;
+    p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post,
+                     p->compact ? 1.0 : 2.0 * p->d / (2.0 * p->d + 1.0)};
+    p->wmg = MGConfig{p->d, ISDC_SMOOTH_RBGS, 1, 1, 2.0 * p->d / (2.0 * p->d + 1.0)};
+    p->x_valid = false;
+    std::memset(p->Yq, 0, sizeof(p->Yq));
+    std::memset(p->X, 0, sizeof(p->X));
     std::memset(p->U, 0, sizeof(p->U));
     std::memset(p->SF, 0, sizeof(p->SF));
     layout(*prob, *par, (char*)d_workspace, p);
@@ -504,13 +671,25 @@ int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs,
         if (!d_rhs || !d_u) fail(ISDC_E_INVAL, "NULL rhs or u");
         if (ncycles < 0) fail(ISDC_E_INVAL, "ncycles must be >= 0");
         hipStream_t s = (hipStream_t)stream;
+        if (plan->compact) {
+            if (precision == ISDC_PREC_FP64) {
+                for (int k = 0; k < ncycles; ++k)
+                    cvcycle_rec<double>(plan, 0, c, false, (const double*)d_rhs, (double*)d_u, (double*)plan->lev[0].e2, s);
+                if (h_res_inf) *h_res_inf = cresnorm<double>(plan, 0, c, (const double*)d_rhs, (const double*)d_u, s);
+            } else {
+                for (int k = 0; k < ncycles; ++k)
+                    cvcycle_rec<float>(plan, 0, c, false, (const float*)d_rhs, (float*)d_u, (float*)plan->lev[0].e2, s);
+                if (h_res_inf) *h_res_inf = cresnorm<float>(plan, 0, c, (const float*)d_rhs, (const float*)d_u, s);
+            }
+            return;
+        }
         if (precision == ISDC_PREC_FP64) {
             for (int k = 0; k < ncycles; ++k)
-                vcycle_rec<double>(plan, 0, c, false, (const double*)d_rhs, (double*)d_u, (double*)plan->lev[0].e2, s);
+                vcycle_rec<double>(plan, plan->mg, 0, c, false, (const double*)d_rhs, (double*)d_u, (double*)plan->lev[0].e2, s);
             if (h_res_inf) *h_res_inf = resnorm<double>(plan, 0, c, (const double*)d_rhs, (const double*)d_u, s);
         } else {
             for (int k = 0; k < ncycles; ++k)
-                vcycle_rec<float>(plan, 0, c, false, (const float*)d_rhs, (float*)d_u, (float*)plan->lev[0].e2, s);
+                vcycle_rec<float>(plan, plan->mg, 0, c, false, (const float*)d_rhs, (float*)d_u, (float*)plan->lev[0].e2, s);
             if (h_res_inf) *h_res_inf = resnorm<float>(plan, 0, c, (const float*)d_rhs, (const float*)d_u, s);
         }
     });
@@ -532,6 +711,42 @@ void mg_op_impl(isdc_plan* p, int op, int level, double c, const void* a, const 
     }
     const size_t N = pow_d((size_t)n, d);
     Coef<T> co = make_coef<T>(c, h, d, p->mg.omega);
+    if (p->compact) {
+        const CCoef<T> k = make_ccoef<T>(c, p->w, h, p->mg.omega);
+        switch (op) {
+            case ISDC_OP_SMOOTH:
+                if (!a || !b || !out) fail(ISDC_E_INVAL, "SMOOTH needs rhs, iterate and output");
+                if (out == b) fail(ISDC_E_INVAL, "Jacobi SMOOTH needs a separate output array");
+                HIPCHK(launch_cjacobi<T>(n, k, false, (const T*)a, (const T*)b, (T*)out, s));
+                break;
+            case ISDC_OP_RESTRICT:
+                if (n < 3) fail(ISDC_E_INVAL, "RESTRICT needs a level with n >= 3");
+                if (!a || !b || !out) fail(ISDC_E_INVAL, "RESTRICT needs rhs, iterate and output");
+                HIPCHK(launch_cresfw<T>(n, k, (const T*)a, (const T*)b, (T*)out, s));
+                break;
+            case ISDC_OP_PROLONG:
+                if (n < 3) fail(ISDC_E_INVAL, "PROLONG needs a level with n >= 3");
+                if (!a || !out) fail(ISDC_E_INVAL, "PROLONG needs coarse input and output");
+                HIPCHK(launch_prolong<T>(d, n, (const T*)a, (T*)out, s));
+                break;
+            case ISDC_OP_COARSE:
+                if (n > tail_max_n(d)) fail(ISDC_E_INVAL, "COARSE level too large for one workgroup");
+                if (!a || !out) fail(ISDC_E_INVAL, "COARSE needs rhs and output");
+                HIPCHK(launch_ctail<T>(p->mg, n, c, p->w, h, true, (const T*)a, (T*)out, s));
+                break;
+            case ISDC_OP_RESIDUAL_NORM: {
+                if (!a || !b || !h_scalar) fail(ISDC_E_INVAL, "RESIDUAL_NORM needs rhs, iterate and h_scalar");
+                int nb = 0;
+                HIPCHK(launch_cresnorm<T>(n, k, (const T*)a, (const T*)b, p->partial, &nb, s));
+                HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 2, s));
+                *h_scalar = read_scalar(p, p->scalars + 2, s);
+                break;
+            }
+            default:
+                fail(ISDC_E_INVAL, "unknown op");
+        }
+        return;
+    }
     switch (op) {
         case ISDC_OP_SMOOTH: {
             if (!a || !b || !out) fail(ISDC_E_INVAL, "SMOOTH needs rhs, iterate and output");
@@ -603,6 +818,7 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
                       double* bytes) {
     const int d = p->d;
     const size_t w = sizeof(T);
+    if (p->compact) fail(ISDC_E_UNSUPPORTED, "kernel timing covers the second-order stencil's kernels");
     if (kernel != ISDC_KERNEL_TAIL && kernel != ISDC_KERNEL_QUAD && (level < 0 || level >= p->tail))
         fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
     std::function<void()> launch;

@@ -46,8 +46,8 @@ def _dev_ptr(t: torch.Tensor, dtype=None, numel=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_problem(dim, n, nu, fe_kind=A.FE_ZERO) -> A.Problem:
-    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind)
+def make_problem(dim, n, nu, fe_kind=A.FE_ZERO, stencil=A.STENCIL_2ND) -> A.Problem:
+    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind, stencil=stencil)
 
 
 def make_params(**kw) -> A.Params:
@@ -81,9 +81,10 @@ def workspace_bytes(problem: A.Problem, params: A.Params) -> int:
 class Plan:
     """One ISDC problem instance: the C plan plus its torch-owned workspace."""
 
-    def __init__(self, dim: int, n: int, nu: float, fe_kind: int = A.FE_ZERO, device=None, **params):
+    def __init__(self, dim: int, n: int, nu: float, fe_kind: int = A.FE_ZERO, device=None,
+                 stencil: int = A.STENCIL_2ND, **params):
         self.lib = A.load()
-        self.problem = make_problem(dim, n, nu, fe_kind)
+        self.problem = make_problem(dim, n, nu, fe_kind, stencil)
         self.params = make_params(**params)
         self.dim, self.n = dim, n
         self.N = n ** dim
@@ -202,13 +203,13 @@ class Batch:
         return workspace_bytes(make_problem(dim, n, nu, fe_kind), make_params(**params))
 
     def set(self, slot: int, u: torch.Tensor, dt: float, nsteps: int, nu: float, fe_kind: int = A.FE_ZERO,
-            workspace: torch.Tensor = None, **params):
+            workspace: torch.Tensor = None, stencil: int = A.STENCIL_2ND, **params):
         """Start instance (u, nu, f^E, params) in `slot` for nsteps steps of size dt.
         u (float64, shape (n,)*dim) is advanced in place."""
         n = u.shape[0]
         params.setdefault("vcycles", self.vcycles)
         params.setdefault("precision", self.precision)
-        prob = make_problem(self.dim, n, nu, fe_kind)
+        prob = make_problem(self.dim, n, nu, fe_kind, stencil)
         par = make_params(**params)
         need = workspace_bytes(prob, par)
         if workspace is None:
