@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "heat3d", "heat1d", "batch", "serve", "table1", "kernels"])
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "heat3d", "heat1d", "batch", "serve", "table1", "kernels"])
     ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--batch-count", type=int, default=256)
@@ -44,10 +44,17 @@ def parse():
     return ap.parse_args()
 
 
+def mg_params(cfg):
+    """Stencil and multigrid settings of a workload (defaults: second-order
+    stencil, red-black V(1,1))."""
+    return dict(stencil=cfg.get("stencil", 0), smoother=cfg.get("smoother", 0), nu_pre=cfg.get("nu_pre", 1),
+                nu_post=cfg.get("nu_post", 1))
+
+
 def make_plan(cfg):
     from paper_1401_7824_amd import Plan
     return Plan(cfg["dim"], cfg["n"], cfg["nu"], cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"],
-                precision=cfg["precision"], sdc_tol=cfg["sdc_tol"])
+                precision=cfg["precision"], sdc_tol=cfg["sdc_tol"], **mg_params(cfg))
 
 
 def time_steps(plan, u, dt, steps, warmup, torch):
@@ -82,6 +89,8 @@ KERNEL_NAMES = {
 def kernel_name(name, cfg, T):
     """rocprof name of the kernel bench.py times for `name` on the finest level
     (3D levels of 127^3 and up run the z-marching form)."""
+    if cfg.get("stencil", 0) == 1:
+        return {"smooth": f"k_cjacobi<{T},false>", "tail": f"k_ctail<{T}>"}[name]
     if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
         return f"k_march_rbgs<{T},true,0,false>"
     return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"])
@@ -151,6 +160,8 @@ def kernel_probe(plan, cfg, reps, torch):
     out = {}
     kinds = [("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH),
              ("tail", P.KERNEL_TAIL)]
+    if cfg.get("stencil", 0) == 1:  # compact plans: the weighted-Jacobi step and the compact tail
+        kinds = [("smooth", P.KERNEL_SMOOTH), ("tail", P.KERNEL_TAIL)]
     tail_n = {1: 2047, 2: 63, 3: 15}[cfg["dim"]]
     for name, k in kinds:
         if name == "smooth_restrict" and cfg["dim"] == 3:
@@ -189,9 +200,14 @@ def vcycle_probe(plan, cfg, reps, torch):
     # prolongation+smoothing; the tail reads its rhs and writes its iterate
     tail_n = {1: 2047, 2: 63, 3: 15}[d]
     b, m = 0.0, n
+    compact = cfg.get("stencil", 0) == 1
+    nsm = cfg.get("nu_pre", 1) + cfg.get("nu_post", 1)
     while m > tail_n:
         N, Nc = m ** d, ((m - 1) // 2) ** d
-        b += 2 * (3 * N + Nc) * w
+        if compact:  # Jacobi steps 3N each; residual + restriction 2N + Nc; prolongation 2N + Nc
+            b += (nsm * 3 * N + 4 * N + 2 * Nc) * w
+        else:        # smoothing + restriction 3N + Nc; prolongation + smoothing 3N + Nc
+            b += 2 * (3 * N + Nc) * w
         m = (m - 1) // 2
     b += 2 * m ** d * w
     return dict(us_per_vcycle=round(us, 2), alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1),
@@ -216,7 +232,8 @@ def cpu_baseline(cfg, sweeps_per_step):
         c["n"] = small
     u0 = W.workload_u0(c)
     sc = SDCConfig(nu=c["nu"], fe_kind=c["fe_kind"], node_kind=c["node_kind"], M=c["M"],
-                   precision=c["precision"], tol=c["sdc_tol"])
+                   precision=c["precision"], tol=c["sdc_tol"], stencil=c.get("stencil", 0),
+                   smoother=c.get("smoother", 0), nu1=c.get("nu_pre", 1), nu2=c.get("nu_post", 1))
     h = 1.0 / (c["n"] + 1)
     t0 = time.perf_counter()
     st = sdc_begin(u0, c["dt"], h, sc)
@@ -395,15 +412,16 @@ def run_kernels(args, torch):
 
 
 def run_table1(args, torch):
-    """Table 1(a) replay (Sec. 4) with the second-order stencil: 2D heat on
-    [0,1]^2, u0 = sin(pi x) sin(pi y), n = 63 (h = 1/64), dt = 1e-3,
-    Gauss-Lobatto M in {3, 5, 7}, nu in {1, 10, 100}, sweeps until the
-    max-norm SDC residual < 5e-8.  Multigrid: weighted-Jacobi V(3,3)
-    (omega = 4/5).  Classical SDC cycles each implicit solve until its
-    max-norm residual <= 1e-9; ISDC stops after L = 2 cycles or earlier at
-    that tolerance.  Reports accumulated V-cycles and sweeps of
-    both beside the printed ones and the GPU time of one step of each;
-    `value` is the V-cycle saving of ISDC summed over the nine rows."""
+    """Table 1(a) replay (Sec. 4): 2D heat on [0,1]^2, u0 = sin(pi x) sin(pi y),
+    n = 63 (h = 1/64), dt = 1e-3, Gauss-Lobatto M in {3, 5, 7}, nu in
+    {1, 10, 100}, sweeps until the max-norm SDC residual < 5e-8, with the
+    fourth-order compact stencil and weighting matrix W of the paper's runs
+    (eq. (5)) and with the second-order stencil.  Multigrid: weighted-Jacobi
+    V(3,3) (omega = 1 compact, 4/5 second order).  Classical SDC cycles each
+    implicit solve until its max-norm residual <= 1e-9; ISDC stops after
+    L = 2 cycles or earlier at that tolerance.  Reports accumulated V-cycles
+    and sweeps beside the printed ones and the GPU time of one step of each;
+    `value` is the compact stencil's V-cycle saving summed over the nine rows."""
     import csv
     import numpy as np
     from paper_1401_7824_amd import Plan
@@ -415,52 +433,61 @@ def run_table1(args, torch):
         for r in csv.DictReader(line for line in fh if not line.startswith("#")):
             if r["problem"] == "heat":
                 printed[(float(r["nu"]), int(r["M"]))] = r
-    rows = []
-    tot = {"sdc": 0, "isdc": 0}
-    ms_tot = {"sdc": 0.0, "isdc": 0.0}
-    for nu in (1.0, 10.0, 100.0):
-        for M in (3, 5, 7):
-            row = {"nu": nu, "M": M}
-            for name, mode in (("sdc", dict(vcycles=0)), ("isdc", dict(vcycles=2, early_exit=1))):
-                p = Plan(2, n, nu, 0, node_kind=0, M=M, sdc_tol=5e-8, inner_tol=1e-9, max_sweeps=100,
-                         smoother=1, nu_pre=3, nu_post=3, **mode)
-                u0d = torch.from_numpy(u0).cuda()
-                u = u0d.clone()
-                st = p.step(u, dt)
-                reps = max(1, args.steps)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    u.copy_(u0d)
-                    p.step(u, dt)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - t0) / reps * 1e3
-                row[name] = {"vcycles": st.vcycles, "sweeps": st.sweeps, "status": st.status, "ms_per_step": round(ms, 3)}
-                tot[name] += st.vcycles
-                ms_tot[name] += ms
-            pr = printed[(nu, M)]
-            row["savings_pct"] = round(100.0 * (1 - row["isdc"]["vcycles"] / row["sdc"]["vcycles"]), 1)
-            row["time_savings_pct"] = round(100.0 * (1 - row["isdc"]["ms_per_step"] / row["sdc"]["ms_per_step"]), 1)
-            row["printed"] = {"sdc": f"{pr['sdc_cycles']}({pr['sdc_sweeps']})",
-                              "isdc": f"{pr['isdc_cycles']}({pr['isdc_sweeps']})", "savings_pct": int(pr["savings_pct"])}
-            rows.append(row)
-            print(f"[table1] nu={nu:5.0f} M={M}: SDC {row['sdc']['vcycles']}({row['sdc']['sweeps']}) "
-                  f"ISDC {row['isdc']['vcycles']}({row['isdc']['sweeps']}) save {row['savings_pct']}% | "
-                  f"printed {row['printed']['sdc']} {row['printed']['isdc']} {pr['savings_pct']}%",
-                  file=sys.stderr, flush=True)
-    save = 100.0 * (1 - tot["isdc"] / tot["sdc"])
+    out = {}
+    for sname, stencil in (("compact4", 1), ("second_order", 0)):
+        rows = []
+        tot = {"sdc": 0, "isdc": 0}
+        ms_tot = {"sdc": 0.0, "isdc": 0.0}
+        for nu in (1.0, 10.0, 100.0):
+            for M in (3, 5, 7):
+                row = {"nu": nu, "M": M}
+                for name, mode in (("sdc", dict(vcycles=0)), ("isdc", dict(vcycles=2, early_exit=1))):
+                    p = Plan(2, n, nu, 0, stencil=stencil, node_kind=0, M=M, sdc_tol=5e-8, inner_tol=1e-9,
+                             max_sweeps=100, smoother=1, nu_pre=3, nu_post=3, **mode)
+                    u0d = torch.from_numpy(u0).cuda()
+                    u = u0d.clone()
+                    st = p.step(u, dt)
+                    reps = max(1, args.steps)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        u.copy_(u0d)
+                        p.step(u, dt)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) / reps * 1e3
+                    row[name] = {"vcycles": st.vcycles, "sweeps": st.sweeps, "status": st.status,
+                                 "ms_per_step": round(ms, 3)}
+                    tot[name] += st.vcycles
+                    ms_tot[name] += ms
+                pr = printed[(nu, M)]
+                row["savings_pct"] = round(100.0 * (1 - row["isdc"]["vcycles"] / row["sdc"]["vcycles"]), 1)
+                row["time_savings_pct"] = round(100.0 * (1 - row["isdc"]["ms_per_step"] / row["sdc"]["ms_per_step"]), 1)
+                row["printed"] = {"sdc": f"{pr['sdc_cycles']}({pr['sdc_sweeps']})",
+                                  "isdc": f"{pr['isdc_cycles']}({pr['isdc_sweeps']})",
+                                  "savings_pct": int(pr["savings_pct"])}
+                rows.append(row)
+                print(f"[table1 {sname}] nu={nu:5.0f} M={M}: SDC {row['sdc']['vcycles']}({row['sdc']['sweeps']}) "
+                      f"ISDC {row['isdc']['vcycles']}({row['isdc']['sweeps']}) save {row['savings_pct']}% | "
+                      f"printed {row['printed']['sdc']} {row['printed']['isdc']} {pr['savings_pct']}%",
+                      file=sys.stderr, flush=True)
+        out[sname] = {"savings_pct": round(100.0 * (1 - tot["isdc"] / tot["sdc"]), 2),
+                      "time_savings_pct": round(100.0 * (1 - ms_tot["isdc"] / ms_tot["sdc"]), 2),
+                      "totals": {"sdc_vcycles": tot["sdc"], "isdc_vcycles": tot["isdc"],
+                                 "sdc_ms": round(ms_tot["sdc"], 3), "isdc_ms": round(ms_tot["isdc"], 3)},
+                      "rows": rows}
+    printed_save = 100.0 * (1 - sum(int(r["isdc_cycles"]) for r in printed.values())
+                            / sum(int(r["sdc_cycles"]) for r in printed.values()))
+    c4 = out["compact4"]
     return {
-        "metric": "Table 1(a) replay: accumulated V-cycles of classical SDC vs ISDC", "value": round(save, 2),
-        "unit": "% V-cycles saved (9 rows)", "n_gpus": 1, "steps": 18 * max(1, args.steps), "warmup": 18,
-        "ms_per_step": round((ms_tot["sdc"] + ms_tot["isdc"]) / 18, 4), "higher_is_better": True,
+        "metric": "Table 1(a) replay: accumulated V-cycles of classical SDC vs ISDC", "value": c4["savings_pct"],
+        "unit": "% V-cycles saved (9 rows)", "n_gpus": 1, "steps": 36 * max(1, args.steps), "warmup": 36,
+        "ms_per_step": round((c4["totals"]["sdc_ms"] + c4["totals"]["isdc_ms"]) / 18, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "table1: 2D heat n=63 (h=1/64) u0=sin(pi x)sin(pi y) dt=1e-3 Lobatto M=3,5,7 "
-                               "nu=1,10,100 tol 5e-8; SDC inner_tol 1e-9; ISDC L=2 early exit; weighted-Jacobi V(3,3), "
-                               "second-order stencil"},
-        "time_savings_pct": round(100.0 * (1 - ms_tot["isdc"] / ms_tot["sdc"]), 2),
-        "totals": {"sdc_vcycles": tot["sdc"], "isdc_vcycles": tot["isdc"],
-                   "sdc_ms": round(ms_tot["sdc"], 3), "isdc_ms": round(ms_tot["isdc"], 3)},
-        "rows": rows,
+                               "nu=1,10,100 tol 5e-8; SDC inner_tol 1e-9; ISDC L=2 early exit; weighted-Jacobi "
+                               "V(3,3); value: fourth-order compact stencil with W"},
+        "printed_savings_pct_9_rows": round(printed_save, 2),
+        "stencils": out,
     }
 
 
@@ -499,7 +526,7 @@ def main():
     vcyc = sum(s.vcycles for s in stats) / len(stats)
     kp = kernel_probe(plan, cfg, args.probe_reps, torch)
     vc = vcycle_probe(plan, cfg, 20, torch)
-    dom = kp.get("smooth_restrict") or kp.get("prolong_smooth") or kp["tail"]
+    dom = kp.get("smooth_restrict") or kp.get("prolong_smooth") or kp.get("smooth") or kp["tail"]
     traffic = counter_traffic(dom["kernel"], args.workload)
     roof = dict(bound="hbm", achieved=dom["gbps"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(dom["gbps"] / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["kernel"] + " (finest level)",
@@ -520,7 +547,10 @@ def main():
         "config": {"workload": f"{args.workload}: {cfg['dim']}D n={cfg['n']} nu={cfg['nu']} "
                                f"fe={'cubic' if cfg['fe_kind'] else 'zero'} "
                                f"{'Lobatto' if cfg['node_kind'] == 0 else 'Radau-right'} M={cfg['M']} "
-                               f"dt={cfg['dt']} L=2 RBGS V(1,1) tol={cfg['sdc_tol']}",
+                               f"dt={cfg['dt']} L=2 "
+                               + ("compact 4th-order stencil with W, Jacobi "
+                                  f"V({cfg.get('nu_pre')},{cfg.get('nu_post')})" if cfg.get("stencil", 0) == 1
+                                  else "RBGS V(1,1)") + f" tol={cfg['sdc_tol']}",
                    "sweeps_per_step": sweeps, "vcycles_per_step": vcyc,
                    "host_wall_s": round(wall, 4)},
         "roofline": roof,

@@ -217,7 +217,8 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * the kernel's algorithmic bytes per launch (every array element read or
  * written once) to *h_bytes, and synchronises `stream`.  For measurement;
  * leaves the plan's workspace arrays with unspecified contents, so call it
- * only between steps.  Second-order plans only (compact: ISDC_E_UNSUPPORTED).
+ * only between steps.  Compact-stencil plans time ISDC_KERNEL_SMOOTH (one
+ * weighted-Jacobi step of B) and ISDC_KERNEL_TAIL (the compact tail) only.
  *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
  *                                full-weighting restriction (levels above the
  *                                coarse tail, d = 1 or 2)

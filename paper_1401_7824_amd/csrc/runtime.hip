@@ -818,11 +818,26 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
                       double* bytes) {
     const int d = p->d;
     const size_t w = sizeof(T);
-    if (p->compact) fail(ISDC_E_UNSUPPORTED, "kernel timing covers the second-order stencil's kernels");
-    if (kernel != ISDC_KERNEL_TAIL && kernel != ISDC_KERNEL_QUAD && (level < 0 || level >= p->tail))
-        fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
     std::function<void()> launch;
     double b = 0.0;
+    if (p->compact) {
+        // compact plans: the weighted-Jacobi step (SMOOTH) and the compact tail
+        if (kernel == ISDC_KERNEL_SMOOTH) {
+            if (level < 0 || level >= p->tail) fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
+            const Level& L = p->lev[level];
+            const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
+            launch = [=]() { HIPCHK(launch_cjacobi<T>(L.n, k, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, s)); };
+            b = 3.0 * (double)L.N * w;
+        } else if (kernel == ISDC_KERNEL_TAIL) {
+            const Level& L = p->lev[p->tail];
+            launch = [=]() { HIPCHK(launch_ctail<T>(p->mg, L.n, c, p->w, L.h, true, (const T*)L.r, (T*)L.e, s)); };
+            b = 2.0 * (double)L.N * w;
+        } else {
+            fail(ISDC_E_UNSUPPORTED, "compact plans time ISDC_KERNEL_SMOOTH and ISDC_KERNEL_TAIL only");
+        }
+    } else {
+    if (kernel != ISDC_KERNEL_TAIL && kernel != ISDC_KERNEL_QUAD && (level < 0 || level >= p->tail))
+        fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
     if (kernel == ISDC_KERNEL_SMOOTH_RESTRICT || kernel == ISDC_KERNEL_PROLONG_SMOOTH || kernel == ISDC_KERNEL_SMOOTH) {
         const Level& L = p->lev[level];
         const Level& C = p->lev[level + 1];
@@ -856,6 +871,7 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
         b = (double)(reads + writes) * (double)p->N * 8.0;
     } else {
         fail(ISDC_E_INVAL, "unknown kernel");
+    }
     }
     // one event pair around `reps` back-to-back launches: a pair around every
     // launch would add the events' own cost to each (a few us per launch)

@@ -215,7 +215,7 @@ def test_compact_table1_counts_equal_oracle(nu, M, isdc):
 
 
 def test_compact_unsupported_combinations():
-    from paper_1401_7824_amd import Plan, Batch, ISDCError, STENCIL_COMPACT4 as SC, KERNEL_TAIL
+    from paper_1401_7824_amd import Plan, Batch, ISDCError, STENCIL_COMPACT4 as SC, KERNEL_TAIL, KERNEL_SMOOTH_RESTRICT
     announce("compact unsupported")
     with pytest.raises(ISDCError):
         Plan(3, 15, 1.0, stencil=SC, smoother=1)
@@ -225,7 +225,9 @@ def test_compact_unsupported_combinations():
         Plan(2, 31, 1.0, stencil=SC, smoother=1, guess=1)
     p = Plan(2, 31, 1.0, stencil=SC, smoother=1)
     with pytest.raises(ISDCError):
-        p.time_kernel(KERNEL_TAIL, 0, 1e-3, 0, 1)
+        p.time_kernel(KERNEL_SMOOTH_RESTRICT, 0, 1e-3, 0, 1)
+    us, nbytes = p.time_kernel(KERNEL_TAIL, 0, 1e-3, 0, 2)
+    assert us > 0 and nbytes == 2 * 31 * 31 * 8
     b = Batch(2, 2)
     u = dev(np.zeros((31, 31)))
     with pytest.raises(ISDCError):
