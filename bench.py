@@ -252,6 +252,42 @@ def cpu_baseline(cfg, sweeps_per_step):
                        f"scaled by {sweeps_per_step:.1f} sweeps/step")
 
 
+def _oracle_instance_steps(job):
+    """One oracle step of one batched instance (a process-pool task of the batch CPU baseline)."""
+    import numpy as np
+    from oracle.sdc import SDCConfig, sdc_step
+    from paper_1401_7824_amd import workloads as W
+    x = job
+    u0 = W.sine_field(x["n"], 2, W.draw_modes(2, x["n_modes"], x["seed"]))
+    cfg = SDCConfig(nu=x["nu"], fe_kind=x["fe_kind"], node_kind=x["node_kind"], M=x["M"], precision=x["precision"],
+                    tol=x["sdc_tol"], max_sweeps=200)
+    t0 = time.perf_counter()
+    _, st = sdc_step(u0, x["dt"], 1.0 / (x["n"] + 1), cfg)
+    del np
+    return time.perf_counter() - t0, st.sweeps
+
+
+def batch_cpu_baseline(inst, budget_s=20.0):
+    """The oracle on the host cores (a process pool, one instance step per task) over a
+    bounded sample of the batched instances, in instance-steps/s: every fourth
+    instance is sampled until the pool has spent about budget_s seconds of wall time."""
+    import multiprocessing as mp
+    cores = min(16, len(os.sched_getaffinity(0)))  # the GPU host's CPU share is 16 cores
+    sample = inst[::4]
+    t0 = time.perf_counter()
+    done = 0
+    with mp.get_context("spawn").Pool(cores) as pool:
+        for _ in pool.imap_unordered(_oracle_instance_steps, sample):
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                pool.terminate()
+                break
+    el = time.perf_counter() - t0
+    return dict(value=round(done / el, 4), unit="instance-steps/s", cores=cores, kind="oracle",
+                sample=f"{done} one-step tasks of every fourth batched instance (sides 63..511) in a pool of "
+                       f"{cores} processes, {el:.1f} s wall")
+
+
 def run_batch(args, torch):
     """256 uneven 2D reaction-diffusion instances (side 63..511, nu, dt, M drawn
     per instance, float32 V-cycles, tolerance 1e-8), each advanced
@@ -295,7 +331,7 @@ def run_batch(args, torch):
     t_single = time.perf_counter() - t0
     same = all(torch.equal(ub[i], uref[i]) for i in range(len(inst)))
     total = len(inst) * steps
-    return {
+    out = {
         "metric": METRIC, "value": round(total / t_batch, 3), "unit": "instance-steps/s", "n_gpus": 1,
         "steps": total, "warmup": 1, "ms_per_step": round(t_batch / total * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
@@ -308,6 +344,9 @@ def run_batch(args, torch):
         "bitwise_equal_to_per_instance": bool(same),
         "batch_seconds": round(t_batch, 3),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(inst)
+    return out
 
 
 def run_serve(args, torch):
