@@ -22,6 +22,9 @@ Module map (each function cites the passage it follows):
 * ``compact`` -- the fourth-order compact Laplacian A_h and its weighting
   matrix W (Sec. 3, eq. (5)), their exact solves by sine transform and the
   weighted-Jacobi V-cycle for W - c A_h.
+* ``periodic`` -- periodic grids on [-1, 1)^d, the periodic compact stencil,
+  its Fourier solves and multigrid, and the WENO5 advection of viscous
+  Burgers (Sec. 4.1).
 * ``sdc`` -- the semi-implicit SDC sweep of eq. (4) (and of eq. (5) for the
   compact stencil) with exact, classical (solve to tolerance) and inexact
   (L V-cycles) inner solves, the SDC residual of Sec. 3, and the time step.
@@ -68,9 +71,19 @@ from .compact import (  # noqa: F401
     apply_compact_shifted,
     vcycle_compact,
 )
+from .periodic import (  # noqa: F401
+    grid_p,
+    laplacian_compact_p,
+    weight_p,
+    burgers_advection,
+    vcycle_compact_p,
+)
 from .sdc import (  # noqa: F401
     STENCIL_2ND,
     STENCIL_COMPACT4,
+    BC_DIRICHLET,
+    BC_PERIODIC,
+    FE_BURGERS,
     SDCConfig,
     SDCStats,
     sdc_step,

@@ -28,6 +28,8 @@ Paper basis:
   right-hand side rounded to float32 and u = g + e accumulated in float64.
   The fixed point of the sweep is unchanged because that right-hand side
   vanishes at the collocation solution.
+* Periodic boundaries (``bc = BC_PERIODIC``, compact stencil only) and the
+  WENO5 Burgers advection (``fe_kind = FE_BURGERS``) follow periodic.py.
 * Compact stencil (``stencil = STENCIL_COMPACT4``, eq. (5)): f~(u) =
   W f^E(u) + nu A_h u is kept per node, the implicit system is
   (W - dt_m nu A_h) u_{m+1}^{k+1} = W u_m^{k+1} + dt_m W [f^E(u_m^{k+1}) -
@@ -43,13 +45,18 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .collocation import qmatrix, smatrix, nodes, NODES_LOBATTO
-from .compact import (laplacian_compact, weight, solve_weight_exact, apply_compact_shifted,
-                      solve_compact_shifted_exact, vcycle_compact, residual_compact_inf)
+from . import compact as _cd
+from . import periodic as _cp
 from .multigrid import SMOOTH_RBGS, vcycle, residual_inf
 from .operators import FE_ZERO, f_explicit, f_implicit, apply_shifted, solve_shifted_exact
 
 STENCIL_2ND = 0
 STENCIL_COMPACT4 = 1
+
+BC_DIRICHLET = 0
+BC_PERIODIC = 1            # [-1, 1)^d, compact stencil only (the Burgers setup of Sec. 4.1)
+
+FE_BURGERS = 2             # f^E = -(d/dx + d/dy)(u^2/2), WENO5 (periodic only)
 
 GUESS_PREV_SWEEP = 0
 GUESS_ZERO = 1
@@ -87,6 +94,7 @@ class SDCConfig:
     guess: int = GUESS_PREV_SWEEP
     max_classical_cycles: int = 100
     stencil: int = STENCIL_2ND
+    bc: int = BC_DIRICHLET
 
 
 @dataclass
@@ -112,11 +120,42 @@ class SDCState:
     stats: SDCStats
 
 
+class _Compact:
+    """The compact-stencil operators of the configured boundary condition."""
+
+    def __init__(self, bc):
+        if bc == BC_PERIODIC:
+            self.weight, self.lap = _cp.weight_p, _cp.laplacian_compact_p
+            self.solve_w, self.solve = _cp.solve_weight_exact_p, _cp.solve_compact_shifted_exact_p
+            self.apply, self.vcycle, self.res = (_cp.apply_compact_shifted_p, _cp.vcycle_compact_p,
+                                                 _cp.residual_compact_inf_p)
+        else:
+            self.weight, self.lap = _cd.weight, _cd.laplacian_compact
+            self.solve_w, self.solve = _cd.solve_weight_exact, _cd.solve_compact_shifted_exact
+            self.apply, self.vcycle, self.res = (_cd.apply_compact_shifted, _cd.vcycle_compact,
+                                                 _cd.residual_compact_inf)
+
+
+def _check(cfg):
+    if cfg.bc == BC_PERIODIC and cfg.stencil != STENCIL_COMPACT4:
+        raise ValueError("periodic boundaries are provided with the compact stencil only")
+    if cfg.fe_kind == FE_BURGERS and cfg.bc != BC_PERIODIC:
+        raise ValueError("the WENO5 Burgers advection needs periodic boundaries")
+
+
+def _fe(u, cfg, h):
+    """f^E(u): pointwise kinds, or the periodic WENO5 Burgers advection."""
+    if cfg.fe_kind == FE_BURGERS:
+        return _cp.burgers_advection(u, h)
+    return f_explicit(u, cfg.fe_kind)
+
+
 def _f(u, cfg, h):
     """f(u) = nu L_h u + f^E(u); for the compact stencil f~(u) = W f^E(u) + nu A_h u."""
     if cfg.stencil == STENCIL_COMPACT4:
-        return weight(f_explicit(u, cfg.fe_kind), h) + cfg.nu * laplacian_compact(u, h)
-    return f_implicit(u, cfg.nu, h) + f_explicit(u, cfg.fe_kind)
+        op = _Compact(cfg.bc)
+        return op.weight(_fe(u, cfg, h), h) + cfg.nu * op.lap(u, h)
+    return f_implicit(u, cfg.nu, h) + _fe(u, cfg, h)
 
 
 def sdc_residual(state: SDCState) -> float:
@@ -128,7 +167,7 @@ def sdc_residual(state: SDCState) -> float:
         for j in range(1, cfg.M + 1):
             quad = quad + state.Q[m - 1, j - 1] * state.F[j]
         if cfg.stencil == STENCIL_COMPACT4:  # the stored values are W f: invert W once per node
-            r = state.u0 + solve_weight_exact(state.dt * quad, state.h) - state.U[m]
+            r = state.u0 + _Compact(cfg.bc).solve_w(state.dt * quad, state.h) - state.U[m]
         else:
             r = state.u0 + state.dt * quad - state.U[m]
         per_node.append(np.max(np.abs(r)))
@@ -137,6 +176,7 @@ def sdc_residual(state: SDCState) -> float:
 
 def sdc_begin(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig) -> SDCState:
     """Spread u_0 to every node and evaluate f there (initial iterate k = 0)."""
+    _check(cfg)
     u0 = np.asarray(u0, dtype=np.float64)
     f0 = _f(u0, cfg, h)
     M = cfg.M
@@ -150,14 +190,15 @@ def sdc_begin(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig) -> SDCState:
 def _inner_solve(rhs, guess, c, h, cfg):
     """Solve (I - c L_h) u = rhs (compact: (W - c A_h) u = rhs); returns (u, V-cycles)."""
     compact = cfg.stencil == STENCIL_COMPACT4
+    op = _Compact(cfg.bc)
     if cfg.inner == "exact":
-        return (solve_compact_shifted_exact(rhs, c, h) if compact else solve_shifted_exact(rhs, c, h)), 0
-    apply_op = apply_compact_shifted if compact else apply_shifted
-    res_inf = residual_compact_inf if compact else residual_inf
+        return (op.solve(rhs, c, h) if compact else solve_shifted_exact(rhs, c, h)), 0
+    apply_op = op.apply if compact else apply_shifted
+    res_inf = op.res if compact else residual_inf
 
     def cycle(v, b):
         if compact:
-            return vcycle_compact(v, b, c, h, cfg.nu1, cfg.nu2, cfg.omega if cfg.omega is not None else 1.0)
+            return op.vcycle(v, b, c, h, cfg.nu1, cfg.nu2, cfg.omega if cfg.omega is not None else 1.0)
         return vcycle(v, b, c, h, cfg.smoother, cfg.nu1, cfg.nu2, cfg.omega)
 
     if cfg.precision == PREC_FP64:
@@ -210,14 +251,15 @@ def sdc_sweep(state: SDCState) -> float:
         dtm = dt * (tau_ext[m + 1] - tau_ext[m])
         um_new, um_old, up_old = Unew[m], Uold[m], Uold[m + 1]
         c = dtm * cfg.nu
-        explicit = um_new + dtm * (f_explicit(um_new, cfg.fe_kind) - f_explicit(um_old, cfg.fe_kind))
+        explicit = um_new + dtm * (_fe(um_new, cfg, h) - _fe(um_old, cfg, h))
         if cfg.stencil == STENCIL_COMPACT4:  # eq. (5)
-            rhs = weight(explicit, h) - c * laplacian_compact(up_old, h) + SF[m]
+            op = _Compact(cfg.bc)
+            rhs = op.weight(explicit, h) - c * op.lap(up_old, h) + SF[m]
         else:  # eq. (4)
             rhs = explicit - dtm * f_implicit(up_old, cfg.nu, h) + SF[m]
         if dtm == 0.0:
             # degenerate substep (tau_1 = 0 for Gauss-Lobatto): the operator is I (or W)
-            u = solve_weight_exact(rhs, h) if cfg.stencil == STENCIL_COMPACT4 else rhs
+            u = _Compact(cfg.bc).solve_w(rhs, h) if cfg.stencil == STENCIL_COMPACT4 else rhs
         else:
             if cfg.guess == GUESS_PREV_SWEEP:
                 g = up_old
