@@ -58,8 +58,17 @@ typedef enum {
 
 /* Collocation node families (Sec. 1; Sec. 2 after eq. (2)). Both end on tau_M = 1. */
 enum { ISDC_NODES_LOBATTO = 0, ISDC_NODES_RADAU_RIGHT = 1 };
-/* Explicit part f^E of eq. (4). */
-enum { ISDC_FE_ZERO = 0, ISDC_FE_CUBIC = 1 };
+/* Explicit part f^E of eq. (4): zero, u - u^3, or the viscous Burgers
+ * advection -(d/dx + d/dy)(u^2/2) by a fifth-order WENO scheme (Jiang-Shu
+ * weights, epsilon = 1e-6, local Lax-Friedrichs flux splitting with
+ * alpha = max(|u_i|, |u_{i+1}|) per interface), conservative flux differences
+ * (Sec. 4.1; periodic boundaries only). */
+enum { ISDC_FE_ZERO = 0, ISDC_FE_CUBIC = 1, ISDC_FE_BURGERS = 2 };
+/* Boundary conditions: homogeneous Dirichlet on (0, 1)^d with n = 2^k - 1
+ * interior points per axis (h = 1/(n+1)), or periodic on [-1, 1)^d with
+ * n = 2^k points per axis (h = 2/n; the Burgers setup of Sec. 4.1; compact
+ * stencil, 2D, 2 <= k <= 13). */
+enum { ISDC_BC_DIRICHLET = 0, ISDC_BC_PERIODIC = 1 };
 /* Spatial discretisation of the Laplacian: the second-order (2d+1)-point
  * stencil (W = I, eq. (4)) or the fourth-order compact stencil with its
  * weighting matrix W (Sec. 3, eq. (5); 2D, weighted Jacobi with omega = 1,
@@ -76,23 +85,26 @@ enum { ISDC_PREC_FP64 = 0, ISDC_PREC_MIXED = 1 /* float32 V-cycles */ };
 enum { ISDC_GUESS_PREV_SWEEP = 0, ISDC_GUESS_ZERO = 1, ISDC_GUESS_PREV_NODE = 2 };
 /* Component operators for isdc_mg_op (parity and roofline probes). */
 enum { ISDC_OP_SMOOTH = 0, ISDC_OP_RESTRICT = 1, ISDC_OP_PROLONG = 2, ISDC_OP_COARSE = 3,
-       ISDC_OP_RESIDUAL_NORM = 4 };
+       ISDC_OP_RESIDUAL_NORM = 4, ISDC_OP_EXPLICIT = 5 };
 
 /* Kernels that isdc_time_kernel can time (see there). */
 enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KERNEL_SMOOTH = 2,
-       ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4 };
+       ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4, ISDC_KERNEL_EXPLICIT = 5 };
 
 #define ISDC_MAX_M 9
 #define ISDC_HIST 128
 
 typedef struct {
     int32_t dim;      /* d = 1, 2 or 3                                                */
-    int32_t n;        /* interior points per axis, 2^k - 1 with 1 <= k <= 15 (d = 1),  */
-                      /* k <= 13 (d = 2), k <= 10 (d = 3)                             */
+    int32_t n;        /* points per axis: Dirichlet 2^k - 1 interior points with      */
+                      /* 1 <= k <= 15 (d = 1), k <= 13 (d = 2), k <= 10 (d = 3);      */
+                      /* periodic 2^k with 2 <= k <= 13                               */
     double nu;        /* diffusion coefficient, finite and >= 0                       */
     int32_t fe_kind;  /* ISDC_FE_*                                                    */
     int32_t stencil;  /* ISDC_STENCIL_* (COMPACT4: dim = 2, smoother JACOBI, guess     */
                       /* PREV_SWEEP, not in batches; else ISDC_E_UNSUPPORTED)          */
+    int32_t bc;       /* ISDC_BC_* (PERIODIC: stencil COMPACT4, n = 2^k, 2 <= k <= 13, */
+                      /* not in batches; FE_BURGERS needs PERIODIC)                    */
 } isdc_problem;
 
 typedef struct {
@@ -192,7 +204,8 @@ int isdc_get_stats(const isdc_plan* plan, isdc_stats* out);
  * `stream` is synchronised.  For a compact-stencil plan the operator here and
  * in isdc_mg_op is B_H = I + (h^2/12) L_H - c A_H on the level of spacing H
  * (h the finest spacing, so B_h = W - c A_h) and the smoother is weighted
- * Jacobi with omega = 1. */
+ * Jacobi with omega = 1; on periodic grids coarse point I sits on fine point
+ * 2I (n_l = n / 2^l) and indices wrap. */
 int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs, void* d_u,
                 int32_t ncycles, void* stream, double* h_res_inf);
 
@@ -204,6 +217,9 @@ int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs,
  *   ISDC_OP_PROLONG:       d_out (level)  += linear interpolation of d_a (level+1)
  *   ISDC_OP_COARSE:        d_out <- one V-cycle from zero for rhs d_a on this level
  *   ISDC_OP_RESIDUAL_NORM: *h_scalar <- max|d_a - (I - c L) d_b| (synchronises)
+ *   ISDC_OP_EXPLICIT:      d_out <- f^E(d_a) on the finest grid, float64 (level 0,
+ *                          c and precision ignored; plans with fe_kind
+ *                          ISDC_FE_BURGERS, else ISDC_E_UNSUPPORTED)
  * Unused pointers may be NULL. */
 int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t precision,
                const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
@@ -218,7 +234,8 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * written once) to *h_bytes, and synchronises `stream`.  For measurement;
  * leaves the plan's workspace arrays with unspecified contents, so call it
  * only between steps.  Compact-stencil plans time ISDC_KERNEL_SMOOTH (one
- * weighted-Jacobi step of B) and ISDC_KERNEL_TAIL (the compact tail) only.
+ * weighted-Jacobi step of B), ISDC_KERNEL_TAIL (the compact tail) and
+ * ISDC_KERNEL_EXPLICIT only.
  *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
  *                                full-weighting restriction (levels above the
  *                                coarse tail, d = 1 or 2)
@@ -227,6 +244,8 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  *   ISDC_KERNEL_TAIL             the single-workgroup coarse tail (level ignored)
  *   ISDC_KERNEL_QUAD             S*F quadrature + SDC residual of the current
  *                                iterate (a step must be in progress; level ignored)
+ *   ISDC_KERNEL_EXPLICIT         the WENO5 Burgers advection of the finest grid
+ *                                (ISDC_FE_BURGERS plans; level ignored)
  * precision selects the V-cycle arithmetic as in isdc_vcycle. */
 int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision, int32_t reps,
                      void* stream, double* h_avg_us, double* h_bytes);

@@ -5,10 +5,11 @@ package is a thin binding over it.  The library is loaded on first use and
 its absence is an error.
 """
 from ._capi import (  # noqa: F401
-    ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, STENCIL_2ND, STENCIL_COMPACT4,
+    ISDCError, NODES_LOBATTO, NODES_RADAU_RIGHT, FE_ZERO, FE_CUBIC, FE_BURGERS, STENCIL_2ND, STENCIL_COMPACT4,
+    BC_DIRICHLET, BC_PERIODIC,
     SMOOTH_RBGS, SMOOTH_JACOBI, PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
-    OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, load,
-    KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD,
+    OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, OP_EXPLICIT, load,
+    KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD, KERNEL_EXPLICIT,
     SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED,
 )
 

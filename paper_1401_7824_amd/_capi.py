@@ -15,13 +15,14 @@ OK, E_INVAL, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_UNSUPPORTED = 0,
 STATUS_NAMES = {OK: "ok", E_INVAL: "invalid", E_WORKSPACE: "workspace", E_HIP: "hip",
                 E_NOT_CONVERGED: "not_converged", E_DIVERGED: "diverged", E_UNSUPPORTED: "unsupported"}
 NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
-FE_ZERO, FE_CUBIC = 0, 1
+FE_ZERO, FE_CUBIC, FE_BURGERS = 0, 1, 2
 STENCIL_2ND, STENCIL_COMPACT4 = 0, 1
+BC_DIRICHLET, BC_PERIODIC = 0, 1
 SMOOTH_RBGS, SMOOTH_JACOBI = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
-OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM = 0, 1, 2, 3, 4
-KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD = 0, 1, 2, 3, 4
+OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, OP_EXPLICIT = 0, 1, 2, 3, 4, 5
+KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD, KERNEL_EXPLICIT = 0, 1, 2, 3, 4, 5
 SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED = 0, 1, 2
 MAX_M = 9
 HIST = 128
@@ -29,7 +30,7 @@ HIST = 128
 
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("fe_kind", C.c_int32),
-                ("stencil", C.c_int32)]
+                ("stencil", C.c_int32), ("bc", C.c_int32)]
 
 
 class Params(C.Structure):

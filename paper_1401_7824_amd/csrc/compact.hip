@@ -1,4 +1,6 @@
-// Fourth-order compact stencil (Sec. 3, eq. (5)), 2D.
+// Fourth-order compact stencil (Sec. 3, eq. (5)), 2D, with homogeneous
+// Dirichlet or periodic boundaries, and the WENO5 advection of viscous
+// Burgers (Sec. 4.1).
 //
 // The compact scheme carries a weighting matrix W = I + (h^2/12) L_h next to
 // its 9-point Laplacian A_h = L_h + (h^2/6) D_x D_y:
@@ -15,10 +17,15 @@
 // Multigrid for B_H = I + w L_H - c A_H (w = h^2/12 of the finest grid, so
 // B_h = W - c A_h): weighted-Jacobi smoothing (red-black ordering is not a
 // Gauss-Seidel sweep for a 9-point stencil), the residual fused with its full
-// weighting, linear prolongation (the plain kernel), and a single-workgroup
-// tail for the levels of 63^2 points and fewer.  On a level with spacing H the stencil is
+// weighting, linear prolongation and a single-workgroup tail for the levels
+// of at most 63^2 (Dirichlet) or 32^2 (periodic) points.  On a level with
+// spacing H the stencil is
 //   centre b0 = 1 - 4 w/H^2 + (10/3) c/H^2,  edges bf = w/H^2 - (2/3) c/H^2,
 //   corners bc = -c / (6 H^2).
+// Dirichlet grids have n = 2^k - 1 interior points per axis (coarse point I on
+// fine point 2I+1, zero ghosts); periodic grids have n = 2^k points on
+// [-1, 1) (coarse point I on fine point 2I, indices wrap, and on one point
+// every neighbour is the point itself, so B_H = I there).
 // These are the plain one-thread-per-point forms; the arrays stay in L2
 // between neighbouring threads.
 #include <hip/hip_runtime.h>
@@ -33,28 +40,36 @@ namespace {
 
 constexpr int kB = 256;
 
-template <typename T>
+// u at (x, y); outside the grid zero (Dirichlet) or wrapped (periodic,
+// offsets of at most n).
+template <bool PER, typename T>
 __device__ __forceinline__ T at(const T* __restrict__ u, int n, int x, int y) {
+    if (PER) {
+        x = x < 0 ? x + n : (x >= n ? x - n : x);
+        y = y < 0 ? y + n : (y >= n ? y - n : y);
+        return u[(size_t)y * n + x];
+    }
     return ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n) ? u[(size_t)y * n + x] : T(0);
 }
 
-// Sums of the edge and of the corner neighbours (zero ghosts).
-template <typename T>
+// Sums of the edge and of the corner neighbours.
+template <bool PER, typename T>
 __device__ __forceinline__ void nb9(const T* __restrict__ u, int n, int x, int y, T& edges, T& corners) {
-    edges = at(u, n, x - 1, y) + at(u, n, x + 1, y) + at(u, n, x, y - 1) + at(u, n, x, y + 1);
-    corners = at(u, n, x - 1, y - 1) + at(u, n, x + 1, y - 1) + at(u, n, x - 1, y + 1) + at(u, n, x + 1, y + 1);
+    edges = at<PER>(u, n, x - 1, y) + at<PER>(u, n, x + 1, y) + at<PER>(u, n, x, y - 1) + at<PER>(u, n, x, y + 1);
+    corners = at<PER>(u, n, x - 1, y - 1) + at<PER>(u, n, x + 1, y - 1) + at<PER>(u, n, x - 1, y + 1) +
+              at<PER>(u, n, x + 1, y + 1);
 }
 
-template <typename T>
+template <bool PER, typename T>
 __device__ __forceinline__ T apply_b(const T* __restrict__ u, int n, int x, int y, T uc, const CCoef<T>& k) {
     T edges, corners;
-    nb9(u, n, x, y, edges, corners);
+    nb9<PER>(u, n, x, y, edges, corners);
     return k.b0 * uc + k.bf * edges + k.bc * corners;
 }
 
 __device__ __forceinline__ double fe_of(double v, int fe) { return fe == ISDC_FE_CUBIC ? v - v * v * v : 0.0; }
 
-template <typename T, bool ZERO>
+template <typename T, bool ZERO, bool PER>
 __global__ void __launch_bounds__(kB)
 k_cjacobi(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, CCoef<T> k) {
     const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
@@ -64,59 +79,86 @@ k_cjacobi(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e
         e_out[i] = k.omega * r[i] * k.inv_b0;
     } else {
         const T uc = e_in[i];
-        e_out[i] = uc + k.omega * (r[i] - apply_b(e_in, n, x, y, uc, k)) * k.inv_b0;
+        e_out[i] = uc + k.omega * (r[i] - apply_b<PER>(e_in, n, x, y, uc, k)) * k.inv_b0;
     }
 }
 
 // Residual r - B e on the fine points under each coarse point and its full
-// weighting (1/4, 1/2, 1/4 per axis; fine index 2X+1 sits on coarse X).
-template <typename T>
+// weighting (1/4, 1/2, 1/4 per axis; coarse X sits on fine 2X+1, or on fine
+// 2X with wrapped neighbours for periodic grids).
+template <typename T, bool PER>
 __global__ void __launch_bounds__(kB)
 k_cresfw(const T* __restrict__ r, const T* __restrict__ e, T* __restrict__ rc, int n, CCoef<T> k) {
-    const int nc = (n - 1) / 2;
+    const int nc = PER ? n / 2 : (n - 1) / 2;
     const int X = blockIdx.x * kB + threadIdx.x, Y = blockIdx.y;
     if (X >= nc) return;
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
     T acc = T(0);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const int y = 2 * Y + b;
+        int y = PER ? 2 * Y + b - 1 : 2 * Y + b;
+        if (PER) y = y < 0 ? y + n : y;
         T row = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int x = 2 * X + a;
+            int x = PER ? 2 * X + a - 1 : 2 * X + a;
+            if (PER) x = x < 0 ? x + n : x;
             const size_t i = (size_t)y * n + x;
-            row += w[a] * (r[i] - apply_b(e, n, x, y, e[i], k));
+            row += w[a] * (r[i] - apply_b<PER>(e, n, x, y, e[i], k));
         }
         acc += w[b] * row;
     }
     rc[(size_t)Y * nc + X] = acc;
 }
 
+// Periodic linear interpolation added to u: fine 2I takes coarse I, fine
+// 2I+1 the mean of coarse I and I+1 (wrapped), per axis.
 template <typename T>
+__global__ void __launch_bounds__(kB) k_cprolong_p(const T* __restrict__ ec, T* __restrict__ u, int n) {
+    const int nc = n / 2;
+    const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
+    if (x >= n) return;
+    const int X0 = x >> 1, Y0 = y >> 1;
+    const int X1 = (x & 1) ? (X0 + 1 == nc ? 0 : X0 + 1) : X0;
+    const int Y1 = (y & 1) ? (Y0 + 1 == nc ? 0 : Y0 + 1) : Y0;
+    const T wx = (x & 1) ? T(0.5) : T(1), wy = (y & 1) ? T(0.5) : T(1);
+    const T wx1 = (x & 1) ? T(0.5) : T(0), wy1 = (y & 1) ? T(0.5) : T(0);
+    const T* r0 = ec + (size_t)Y0 * nc;
+    const T* r1 = ec + (size_t)Y1 * nc;
+    u[(size_t)y * n + x] += wy * (wx * r0[X0] + wx1 * r0[X1]) + wy1 * (wx * r1[X0] + wx1 * r1[X1]);
+}
+
+template <typename T, bool PER>
 __global__ void __launch_bounds__(kB)
 k_cresnorm(const T* __restrict__ r, const T* __restrict__ e, int n, CCoef<T> k, double* __restrict__ partial) {
     const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
     double v = 0.0;
     if (x < n) {
         const size_t i = (size_t)y * n + x;
-        v = fabs((double)(r[i] - apply_b(e, n, x, y, e[i], k)));
+        v = fabs((double)(r[i] - apply_b<PER>(e, n, x, y, e[i], k)));
     }
     v = block_max(v);
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
-// r = W base + SF_m, base = u_m^{k+1} - u_{m+1}^k + dt_m (f^E(u_m^{k+1}) - f^E(u_m^k)).
-template <typename T>
+// r = W base + SF_m, base = u_m^{k+1} - u_{m+1}^k + dt_m (f^E(u_m^{k+1}) - f^E(u_m^k)),
+// f^E pointwise or from the node arrays fe_new / fe_old.
+template <typename T, bool PER>
 __global__ void __launch_bounds__(kB) k_crhs(CRhsArgs a, T* __restrict__ out) {
     const int n = a.n;
     const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
     if (x >= n) return;
     auto base = [&](int xx, int yy) -> double {
-        if ((unsigned)xx >= (unsigned)n || (unsigned)yy >= (unsigned)n) return 0.0;
+        if (PER) {
+            xx = xx < 0 ? xx + n : (xx >= n ? xx - n : xx);
+            yy = yy < 0 ? yy + n : (yy >= n ? yy - n : yy);
+        } else if ((unsigned)xx >= (unsigned)n || (unsigned)yy >= (unsigned)n) {
+            return 0.0;
+        }
         const size_t j = (size_t)yy * n + xx;
-        const double un = a.um_new[j], uo = a.um_old[j];
-        return un - a.up_old[j] + a.dtm * (fe_of(un, a.fe) - fe_of(uo, a.fe));
+        const double un = a.um_new[j];
+        const double dfe = a.fe_new ? a.fe_new[j] - a.fe_old[j] : fe_of(un, a.fe) - fe_of(a.um_old[j], a.fe);
+        return un - a.up_old[j] + a.dtm * dfe;
     };
     const double bc = base(x, y);
     const double edges = base(x - 1, y) + base(x + 1, y) + base(x, y - 1) + base(x, y + 1);
@@ -126,7 +168,7 @@ __global__ void __launch_bounds__(kB) k_crhs(CRhsArgs a, T* __restrict__ out) {
 
 // f~_j = W f^E(u_j) + nu A_h u_j at every node; SF_m = sum_j dt s_{m,j} f~_j
 // and Y_m = sum_j dt q_{m,j} f~_j (the residual's right-hand side before W^{-1}).
-template <int M>
+template <int M, bool PER>
 __global__ void __launch_bounds__(kB) k_cquad(CQuadArgs a) {
     const int n = a.n;
     const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
@@ -140,12 +182,20 @@ __global__ void __launch_bounds__(kB) k_cquad(CQuadArgs a) {
         const double* u = a.u[j + 1];
         const double uc = u[i];
         double edges, corners;
-        nb9(u, n, x, y, edges, corners);
-        double fe_edges = 0.0;
-        if (a.fe == ISDC_FE_CUBIC)
-            fe_edges = fe_of(at(u, n, x - 1, y), a.fe) + fe_of(at(u, n, x + 1, y), a.fe) +
-                       fe_of(at(u, n, x, y - 1), a.fe) + fe_of(at(u, n, x, y + 1), a.fe);
-        const double fec = fe_of(uc, a.fe);
+        nb9<PER>(u, n, x, y, edges, corners);
+        double fec, fe_edges;
+        if (a.feu[j + 1]) {
+            const double* g = a.feu[j + 1];
+            fec = g[i];
+            fe_edges = at<PER>(g, n, x - 1, y) + at<PER>(g, n, x + 1, y) + at<PER>(g, n, x, y - 1) +
+                       at<PER>(g, n, x, y + 1);
+        } else {
+            fec = fe_of(uc, a.fe);
+            fe_edges = 0.0;
+            if (a.fe == ISDC_FE_CUBIC)
+                fe_edges = fe_of(at<PER>(u, n, x - 1, y), a.fe) + fe_of(at<PER>(u, n, x + 1, y), a.fe) +
+                           fe_of(at<PER>(u, n, x, y - 1), a.fe) + fe_of(at<PER>(u, n, x, y + 1), a.fe);
+        }
         const double f = fec + (fe_edges - 4.0 * fec) / 12.0 + a.nu_6h2 * (4.0 * edges + corners - 20.0 * uc);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -161,7 +211,7 @@ __global__ void __launch_bounds__(kB) k_cquad(CQuadArgs a) {
 }
 
 // Per-node partial maxima of |u_0 + x_m - u_m| (x_m = W^{-1} Y_m): block
-// (b, k) covers a stride of node a.node[k]'s points.
+// (b, k) covers a stride of node k's points.
 __global__ void __launch_bounds__(kB) k_cres(CResArgs a, double* __restrict__ partial) {
     const int k = blockIdx.y;
     const double* um = a.um[k];
@@ -173,30 +223,88 @@ __global__ void __launch_bounds__(kB) k_cres(CResArgs a, double* __restrict__ pa
     if (threadIdx.x == 0) partial[(size_t)k * gridDim.x + blockIdx.x] = v;
 }
 
-// ---------------------------------------------------------------- compact tail
-// One V-cycle of B on levels n_t (<= 63), ..., 1 in one workgroup, every
-// level in LDS (same layout and phases as the second-order tail), weighted
-// Jacobi smoothing.
+// ---------------------------------------------------------------- WENO5 advection
+// f^E(u) = -sum over axes of (F_{i+1/2} - F_{i-1/2}) / h for the flux u^2/2
+// (periodic).  F_{i+1/2} is the fifth-order WENO reconstruction (Jiang-Shu
+// smoothness indicators and linear weights 1/10, 6/10, 3/10, epsilon 1e-6) of
+// the split fluxes (u^2/2 +/- alpha u) / 2, alpha = max(|u_i|, |u_{i+1}|):
+// the + part from u_{i-2..i+2}, the - part mirrored from u_{i+3..i-1}.
 
-template <typename T>
+__device__ __forceinline__ double weno5_face(double a, double b, double c, double d, double e) {
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+    const double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+    const double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+    const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, s1 = b - d;
+    const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+    const double b0 = 13.0 / 12.0 * t0 * t0 + 0.25 * s0 * s0;
+    const double b1 = 13.0 / 12.0 * t1 * t1 + 0.25 * s1 * s1;
+    const double b2 = 13.0 / 12.0 * t2 * t2 + 0.25 * s2 * s2;
+    const double eps = 1e-6;
+    const double a0 = 0.1 / ((eps + b0) * (eps + b0));
+    const double a1 = 0.6 / ((eps + b1) * (eps + b1));
+    const double a2 = 0.3 / ((eps + b2) * (eps + b2));
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Flux at the face between v[2] and v[3] from v[0..5] = u_{i-2..i+3}.
+__device__ __forceinline__ double weno5_flux(const double* v) {
+    const double alpha = fmax(fabs(v[2]), fabs(v[3]));
+    double fp[6], fm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double f = 0.5 * v[k] * v[k];
+        fp[k] = 0.5 * (f + alpha * v[k]);
+        fm[k] = 0.5 * (f - alpha * v[k]);
+    }
+    return weno5_face(fp[0], fp[1], fp[2], fp[3], fp[4]) + weno5_face(fm[5], fm[4], fm[3], fm[2], fm[1]);
+}
+
+__global__ void __launch_bounds__(kB) k_weno_burgers(const double* __restrict__ u, double* __restrict__ out, int n,
+                                                    double inv_h) {
+    const int x = blockIdx.x * kB + threadIdx.x, y = blockIdx.y;
+    if (x >= n) return;
+    double vx[7], vy[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        vx[k] = at<true>(u, n, x + k - 3, y);
+        vy[k] = at<true>(u, n, x, y + k - 3);
+    }
+    const double dy = weno5_flux(vy + 1) - weno5_flux(vy);
+    const double dx = weno5_flux(vx + 1) - weno5_flux(vx);
+    out[(size_t)y * n + x] = -(dy * inv_h) - dx * inv_h;
+}
+
+// ---------------------------------------------------------------- compact tail
+// One V-cycle of B on levels n_t, ..., 1 in one workgroup, every level in LDS
+// (same layout and phases as the second-order tail), weighted Jacobi.
+
+template <bool PER, typename T>
 __device__ __forceinline__ T capply_lds(const T* e, int n, int x, int y, int i, T b0, T bf, T bc) {
     T edges = T(0), corners = T(0);
-    if (x > 0) edges += e[i - 1];
-    if (x < n - 1) edges += e[i + 1];
-    if (y > 0) edges += e[i - n];
-    if (y < n - 1) edges += e[i + n];
-    if (y > 0) {
-        if (x > 0) corners += e[i - n - 1];
-        if (x < n - 1) corners += e[i - n + 1];
-    }
-    if (y < n - 1) {
-        if (x > 0) corners += e[i + n - 1];
-        if (x < n - 1) corners += e[i + n + 1];
+    if (PER) {
+        const int xm = x == 0 ? n - 1 : x - 1, xp = x == n - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? n - 1 : y - 1, yp = y == n - 1 ? 0 : y + 1;
+        edges = e[y * n + xm] + e[y * n + xp] + e[ym * n + x] + e[yp * n + x];
+        corners = e[ym * n + xm] + e[ym * n + xp] + e[yp * n + xm] + e[yp * n + xp];
+    } else {
+        if (x > 0) edges += e[i - 1];
+        if (x < n - 1) edges += e[i + 1];
+        if (y > 0) edges += e[i - n];
+        if (y < n - 1) edges += e[i + n];
+        if (y > 0) {
+            if (x > 0) corners += e[i - n - 1];
+            if (x < n - 1) corners += e[i - n + 1];
+        }
+        if (y < n - 1) {
+            if (x > 0) corners += e[i + n - 1];
+            if (x < n - 1) corners += e[i + n + 1];
+        }
     }
     return b0 * e[i] + bf * edges + bc * corners;
 }
 
-template <typename T>
+template <typename T, bool PER>
 __global__ void __launch_bounds__(kTail)
 k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc, int nu1, int nu2, double omega,
         int zero_guess) {
@@ -204,7 +312,7 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
     __shared__ T le[L::total];
     __shared__ T lr[L::total];
     __shared__ T lt[L::big];
-    auto nn = [&](int l) { return ((n_t + 1) >> l) - 1; };
+    auto nn = [&](int l) { return PER ? n_t >> l : ((n_t + 1) >> l) - 1; };
     auto off = [&](int l) {
         int o = 0;
         for (int j = 0; j < l; ++j) o += nn(j) * nn(j);
@@ -238,7 +346,7 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
         const T inv = T(1) / b0;
         phase<T, 2>(n, lt, [&](bool ok, int x, int y, int, int i, T& v) {
             if (!ok) return false;
-            v = e[i] + w * (r[i] - capply_lds(e, n, x, y, i, b0, bf, bc)) * inv;
+            v = e[i] + w * (r[i] - capply_lds<PER>(e, n, x, y, i, b0, bf, bc)) * inv;
             return true;
         });
         __syncthreads();
@@ -255,18 +363,20 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
         T* e = le + off(l);
         T* r = lr + off(l);
         if (n == 1) {
-            if (threadIdx.x == 0) e[0] = r[0] / b0;
+            // Dirichlet: every neighbour is a zero ghost; periodic: every
+            // neighbour is the point itself and B = I
+            if (threadIdx.x == 0) e[0] = PER ? r[0] : r[0] / b0;
             __syncthreads();
             break;
         }
         for (int k = 0; k < nu1; ++k) jacobi(e, r, n, b0, bf, bc);
         phase<T, 2>(n, lt, [&](bool ok, int x, int y, int, int i, T& v) {
             if (!ok) return false;
-            v = r[i] - capply_lds(e, n, x, y, i, b0, bf, bc);
+            v = r[i] - capply_lds<PER>(e, n, x, y, i, b0, bf, bc);
             return true;
         });
         __syncthreads();
-        const int nc = (n - 1) / 2;
+        const int nc = PER ? n / 2 : (n - 1) / 2;
         T* rc = lr + off(l + 1);
         T* ec = le + off(l + 1);
         phase<T, 2>(nc, rc, [&](bool ok, int X, int Y, int, int I, T& v) {
@@ -274,8 +384,16 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
             T acc = T(0);
 #pragma unroll
             for (int oy = 0; oy < 3; ++oy) {
-                const int base = (2 * Y + oy) * n + 2 * X;
-                acc += wts[oy] * (wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2]);
+                if (PER) {
+                    int fy = 2 * Y + oy - 1;
+                    fy = fy < 0 ? fy + n : fy;
+                    const int fx0 = 2 * X == 0 ? n - 1 : 2 * X - 1;
+                    acc += wts[oy] * (wts[0] * lt[fy * n + fx0] + wts[1] * lt[fy * n + 2 * X] +
+                                      wts[2] * lt[fy * n + 2 * X + 1]);
+                } else {
+                    const int base = (2 * Y + oy) * n + 2 * X;
+                    acc += wts[oy] * (wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2]);
+                }
             }
             v = acc;
             ec[I] = T(0);
@@ -292,7 +410,17 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
         const T* ec = le + off(l + 1);
         phase<T, 2>(n, e, [&](bool ok, int x, int y, int, int i, T& v) {
             if (!ok) return false;
-            v = e[i] + interp_at<T, 2>(ec, nc, x, y, 0);
+            if (PER) {
+                const int X0 = x >> 1, Y0 = y >> 1;
+                const int X1 = (x & 1) ? (X0 + 1 == nc ? 0 : X0 + 1) : X0;
+                const int Y1 = (y & 1) ? (Y0 + 1 == nc ? 0 : Y0 + 1) : Y0;
+                const T wx = (x & 1) ? T(0.5) : T(1), wy = (y & 1) ? T(0.5) : T(1);
+                const T wx1 = (x & 1) ? T(0.5) : T(0), wy1 = (y & 1) ? T(0.5) : T(0);
+                v = e[i] + (wy * (wx * ec[Y0 * nc + X0] + wx1 * ec[Y0 * nc + X1]) +
+                            wy1 * (wx * ec[Y1 * nc + X0] + wx1 * ec[Y1 * nc + X1]));
+            } else {
+                v = e[i] + interp_at<T, 2>(ec, nc, x, y, 0);
+            }
             return true;
         });
         __syncthreads();
@@ -327,38 +455,65 @@ CCoef<T> make_ccoef(double c, double w, double H, double omega) {
 }
 
 template <typename T>
-hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, hipStream_t s) {
-    if (zero)
-        hipLaunchKernelGGL((k_cjacobi<T, true>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, bool per,
+                          hipStream_t s) {
+    if (per) {
+        if (zero)
+            hipLaunchKernelGGL((k_cjacobi<T, true, true>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+        else
+            hipLaunchKernelGGL((k_cjacobi<T, false, true>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+    } else {
+        if (zero)
+            hipLaunchKernelGGL((k_cjacobi<T, true, false>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+        else
+            hipLaunchKernelGGL((k_cjacobi<T, false, false>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, bool per, hipStream_t s) {
+    if (per)
+        hipLaunchKernelGGL((k_cresfw<T, true>), grid2(n / 2), dim3(kB), 0, s, r, e, rc, n, k);
     else
-        hipLaunchKernelGGL((k_cjacobi<T, false>), grid2(n), dim3(kB), 0, s, r, e_in, e_out, n, k);
+        hipLaunchKernelGGL((k_cresfw<T, false>), grid2((n - 1) / 2), dim3(kB), 0, s, r, e, rc, n, k);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, hipStream_t s) {
-    hipLaunchKernelGGL((k_cresfw<T>), grid2((n - 1) / 2), dim3(kB), 0, s, r, e, rc, n, k);
+hipError_t launch_cprolong_p(int n, const T* ec, T* u, hipStream_t s) {
+    hipLaunchKernelGGL((k_cprolong_p<T>), grid2(n), dim3(kB), 0, s, ec, u, n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cresnorm(int n, const CCoef<T>& k, const T* r, const T* e, double* partial, int* nblocks,
+hipError_t launch_cresnorm(int n, const CCoef<T>& k, const T* r, const T* e, double* partial, int* nblocks, bool per,
                            hipStream_t s) {
     const dim3 g = grid2(n);
     *nblocks = (int)(g.x * g.y);
-    hipLaunchKernelGGL((k_cresnorm<T>), g, dim3(kB), 0, s, r, e, n, k, partial);
+    if (per)
+        hipLaunchKernelGGL((k_cresnorm<T, true>), g, dim3(kB), 0, s, r, e, n, k, partial);
+    else
+        hipLaunchKernelGGL((k_cresnorm<T, false>), g, dim3(kB), 0, s, r, e, n, k, partial);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_crhs(const CRhsArgs& a, T* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_crhs<T>), grid2(a.n), dim3(kB), 0, s, a, out);
+hipError_t launch_crhs(const CRhsArgs& a, T* out, bool per, hipStream_t s) {
+    if (per)
+        hipLaunchKernelGGL((k_crhs<T, true>), grid2(a.n), dim3(kB), 0, s, a, out);
+    else
+        hipLaunchKernelGGL((k_crhs<T, false>), grid2(a.n), dim3(kB), 0, s, a, out);
     return hipGetLastError();
 }
 
-hipError_t launch_cquad(const CQuadArgs& a, int M, hipStream_t s) {
+hipError_t launch_cquad(const CQuadArgs& a, int M, bool per, hipStream_t s) {
     switch (M) {
-#define ISDC_CQ(MM) case MM: hipLaunchKernelGGL((k_cquad<MM>), grid2(a.n), dim3(kB), 0, s, a); break;
+#define ISDC_CQ(MM)                                                                          \
+    case MM:                                                                                 \
+        if (per) hipLaunchKernelGGL((k_cquad<MM, true>), grid2(a.n), dim3(kB), 0, s, a);      \
+        else hipLaunchKernelGGL((k_cquad<MM, false>), grid2(a.n), dim3(kB), 0, s, a);         \
+        break;
         ISDC_CQ(1) ISDC_CQ(2) ISDC_CQ(3) ISDC_CQ(4) ISDC_CQ(5) ISDC_CQ(6) ISDC_CQ(7) ISDC_CQ(8) ISDC_CQ(9)
 #undef ISDC_CQ
         default: return hipErrorInvalidValue;
@@ -373,10 +528,15 @@ hipError_t launch_cres(const CResArgs& a, double* partial, int* nblocks, hipStre
     return hipGetLastError();
 }
 
+hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_weno_burgers, grid2(n), dim3(kB), 0, s, u, out, n, 1.0 / h);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h, bool zero, const T* rhs, T* e,
-                        hipStream_t s) {
-    if (n > TailLayout<2>::nmax) return hipErrorInvalidValue;
+                        bool per, hipStream_t s) {
+    if (n > (per ? kCTailMaxPeriodic : TailLayout<2>::nmax)) return hipErrorInvalidValue;
     CTailCoefs tc;
     double H = h;
     for (int l = 0; l < 16; ++l) {
@@ -386,18 +546,24 @@ hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h,
         tc.bc[l] = k.bc;
         H *= 2.0;
     }
-    hipLaunchKernelGGL((k_ctail<T>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, mg.nu_pre, mg.nu_post, mg.omega,
-                       zero ? 1 : 0);
+    if (per)
+        hipLaunchKernelGGL((k_ctail<T, true>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, mg.nu_pre, mg.nu_post,
+                           mg.omega, zero ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_ctail<T, false>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, mg.nu_pre, mg.nu_post,
+                           mg.omega, zero ? 1 : 0);
     return hipGetLastError();
 }
 
-#define ISDC_CINST(T)                                                                                          \
-    template CCoef<T> make_ccoef<T>(double, double, double, double);                                           \
-    template hipError_t launch_cjacobi<T>(int, const CCoef<T>&, bool, const T*, const T*, T*, hipStream_t);     \
-    template hipError_t launch_cresfw<T>(int, const CCoef<T>&, const T*, const T*, T*, hipStream_t);            \
-    template hipError_t launch_cresnorm<T>(int, const CCoef<T>&, const T*, const T*, double*, int*, hipStream_t); \
-    template hipError_t launch_crhs<T>(const CRhsArgs&, T*, hipStream_t);                                      \
-    template hipError_t launch_ctail<T>(const MGConfig&, int, double, double, double, bool, const T*, T*, hipStream_t);
+#define ISDC_CINST(T)                                                                                              \
+    template CCoef<T> make_ccoef<T>(double, double, double, double);                                               \
+    template hipError_t launch_cjacobi<T>(int, const CCoef<T>&, bool, const T*, const T*, T*, bool, hipStream_t);   \
+    template hipError_t launch_cresfw<T>(int, const CCoef<T>&, const T*, const T*, T*, bool, hipStream_t);          \
+    template hipError_t launch_cprolong_p<T>(int, const T*, T*, hipStream_t);                                       \
+    template hipError_t launch_cresnorm<T>(int, const CCoef<T>&, const T*, const T*, double*, int*, bool, hipStream_t); \
+    template hipError_t launch_crhs<T>(const CRhsArgs&, T*, bool, hipStream_t);                                    \
+    template hipError_t launch_ctail<T>(const MGConfig&, int, double, double, double, bool, const T*, T*, bool,     \
+                                        hipStream_t);
 ISDC_CINST(float)
 ISDC_CINST(double)
 #undef ISDC_CINST

@@ -167,10 +167,13 @@ struct CRhsArgs {
     double dtm;
     int n;
     int fe;
+    const double* fe_new;  // f^E(u_m^{k+1}) and f^E(u_m^k) as arrays (stencil f^E), or NULL:
+    const double* fe_old;  // then f^E is evaluated pointwise from fe
 };
 
 struct CQuadArgs {
     const double* u[ISDC_MAX_M + 1];  // u_0 .. u_M
+    const double* feu[ISDC_MAX_M + 1];  // f^E(u_j) as arrays (stencil f^E), or NULL: pointwise
     double* sf[ISDC_MAX_M];           // S_m^{m+1} F~ (NULL: not needed)
     double* y[ISDC_MAX_M];            // dt Q_m F~    (NULL: not needed)
     double dtS[ISDC_MAX_M * ISDC_MAX_M];
@@ -180,6 +183,7 @@ struct CQuadArgs {
 };
 
 constexpr int kCResBlocks = 256;
+constexpr int kCTailMaxPeriodic = 32;  // largest periodic level of the compact tail
 struct CResArgs {
     const double* u0;
     const double* um[ISDC_MAX_M];  // u_m of the nodes taking part
@@ -188,27 +192,35 @@ struct CResArgs {
     int count;
 };
 
+// Compact-stencil launchers; per selects periodic wrap-around (n = 2^k,
+// coarse n/2) instead of zero Dirichlet ghosts (n = 2^k - 1, coarse (n-1)/2).
 // One weighted-Jacobi step e_out = e + omega (r - B e) / b0 (zero: e = 0).
 template <typename T>
-hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, hipStream_t s);
-// rc = full weighting of r - B e, an n^2 level to ((n-1)/2)^2.
+hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, bool per,
+                          hipStream_t s);
+// rc = full weighting of r - B e on the next coarser level.
 template <typename T>
-hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, hipStream_t s);
+hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, bool per, hipStream_t s);
+// u += periodic linear interpolation of ec ((n/2)^2 -> n^2).
+template <typename T>
+hipError_t launch_cprolong_p(int n, const T* ec, T* u, hipStream_t s);
 // Per-block maxima of |r - B e| in partial[0 .. *nblocks).
 template <typename T>
-hipError_t launch_cresnorm(int n, const CCoef<T>& k, const T* r, const T* e, double* partial, int* nblocks,
+hipError_t launch_cresnorm(int n, const CCoef<T>& k, const T* r, const T* e, double* partial, int* nblocks, bool per,
                            hipStream_t s);
 // r = W [u_m^{k+1} - g + dt_m (f^E(u_m^{k+1}) - f^E(u_m^k))] + S_m F~.
 template <typename T>
-hipError_t launch_crhs(const CRhsArgs& a, T* out, hipStream_t s);
+hipError_t launch_crhs(const CRhsArgs& a, T* out, bool per, hipStream_t s);
 // S F~ and dt Q F~ of the current node values.
-hipError_t launch_cquad(const CQuadArgs& a, int M, hipStream_t s);
+hipError_t launch_cquad(const CQuadArgs& a, int M, bool per, hipStream_t s);
 // Per-node maxima of |u_0 + x_m - u_m|; kCResBlocks * count partials.
 hipError_t launch_cres(const CResArgs& a, double* partial, int* nblocks, hipStream_t s);
+// out = the periodic WENO5 Burgers advection -div(u^2/2) of u (n^2, spacing h).
+hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hipStream_t s);
 // One V-cycle of B (weighted Jacobi V(nu_pre, nu_post)) on a level of at
-// most 63^2 points in one workgroup.
+// most 63^2 (Dirichlet) or 32^2 (periodic) points in one workgroup.
 template <typename T>
 hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h, bool zero, const T* rhs, T* e,
-                        hipStream_t s);
+                        bool per, hipStream_t s);
 
 }  // namespace isdc

@@ -80,16 +80,22 @@ struct isdc_plan {
     // compact stencil (eq. (5)): B = W - c A_h, weighted Jacobi; W inverted
     // for the residual by red-black V-cycles (wmg) of I + w L
     bool compact = false;
+    bool periodic = false;         // [-1, 1)^2 with n = 2^k points per axis, h = 2 / n
     double w = 0.0;                // h^2 / 12
     isdc::MGConfig wmg;
     double* Yq[ISDC_MAX_M];        // dt Q_m F~ per node m+1 (NULL: node with Q row 0)
     double* X[ISDC_MAX_M];         // W^{-1} Yq[m], warm start of the next sweep's solve
     bool x_valid = false;
+    // stencil f^E (WENO5 Burgers): f^E of u_0 and of every node array
+    bool fe_arrays = false;
+    double* FE0 = nullptr;
+    double* FEU[2][ISDC_MAX_M + 1];  // f^E(U[w][j]) (NULL where U[w][j] is)
 
     // step state
     const double* u0 = nullptr;
     double dt = 0.0;
     const double* cur[ISDC_MAX_M + 1];  // current iterate per node (0 = u_0)
+    const double* curfe[ISDC_MAX_M + 1];  // f^E of cur[j] (fe_arrays only)
     int wbuf = 0;                       // which U table the next sweep writes
     bool begun = false;
     isdc_stats stats;

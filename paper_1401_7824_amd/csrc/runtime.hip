@@ -37,9 +37,16 @@ bool valid_n(int d, int n) {
 void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
     if (!pb || !pr) fail(ISDC_E_INVAL, "NULL problem or params");
     if (pb->dim < 1 || pb->dim > 3) fail(ISDC_E_INVAL, "dim must be 1, 2 or 3");
-    if (!valid_n(pb->dim, pb->n)) fail(ISDC_E_INVAL, "n must be 2^k - 1 within the size limit for dim");
+    if (pb->bc != ISDC_BC_DIRICHLET && pb->bc != ISDC_BC_PERIODIC) fail(ISDC_E_INVAL, "unknown bc");
+    if (pb->bc == ISDC_BC_PERIODIC) {
+        if (pb->n < 4 || pb->n > 8192 || (pb->n & (pb->n - 1)) != 0)
+            fail(ISDC_E_INVAL, "periodic grids need n = 2^k points with 2 <= k <= 13");
+    } else if (!valid_n(pb->dim, pb->n)) {
+        fail(ISDC_E_INVAL, "n must be 2^k - 1 within the size limit for dim");
+    }
     if (!std::isfinite(pb->nu) || pb->nu < 0) fail(ISDC_E_INVAL, "nu must be finite and >= 0");
-    if (pb->fe_kind != ISDC_FE_ZERO && pb->fe_kind != ISDC_FE_CUBIC) fail(ISDC_E_INVAL, "unknown fe_kind");
+    if (pb->fe_kind != ISDC_FE_ZERO && pb->fe_kind != ISDC_FE_CUBIC && pb->fe_kind != ISDC_FE_BURGERS)
+        fail(ISDC_E_INVAL, "unknown fe_kind");
     if (pr->node_kind == ISDC_NODES_LOBATTO) {
         if (pr->M < 2 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "Gauss-Lobatto needs 2 <= M <= 9");
     } else if (pr->node_kind == ISDC_NODES_RADAU_RIGHT) {
@@ -65,7 +72,29 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
         if (pr->guess != ISDC_GUESS_PREV_SWEEP)
             fail(ISDC_E_UNSUPPORTED, "the compact stencil warm-starts from the previous sweep only");
     }
+    if (pb->bc == ISDC_BC_PERIODIC && pb->stencil != ISDC_STENCIL_COMPACT4)
+        fail(ISDC_E_UNSUPPORTED, "periodic boundaries are implemented with the compact stencil only");
+    if (pb->fe_kind == ISDC_FE_BURGERS && pb->bc != ISDC_BC_PERIODIC)
+        fail(ISDC_E_UNSUPPORTED, "the WENO5 Burgers advection needs periodic boundaries");
 }
+
+namespace {
+// Points per axis and spacing of multigrid level l (periodic: n -> n/2 on
+// [-1, 1); Dirichlet: n -> (n-1)/2 interior points of (0, 1)).
+void level_size(bool periodic, int n0, int l, int& n, double& h) {
+    n = n0;
+    h = periodic ? 2.0 / n0 : 1.0 / (n0 + 1);
+    for (int i = 0; i < l; ++i) {
+        n = periodic ? n / 2 : (n - 1) / 2;
+        h *= 2.0;
+    }
+}
+int level_count(bool periodic, int n0) {
+    int nl = 1;
+    for (int n = n0; n > 1; n = periodic ? n / 2 : (n - 1) / 2) ++nl;
+    return nl;
+}
+}  // namespace
 
 // Lay the plan's arrays out from `base` (nullptr: sizing only); returns the byte count.
 size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p) {
@@ -90,10 +119,21 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
         void* ptr = degenerate ? nullptr : take(N * sizeof(double));
         if (p) p->SF[m] = (double*)ptr;
     }
+    const bool periodic = pb.bc == ISDC_BC_PERIODIC;
+    if (pb.fe_kind == ISDC_FE_BURGERS) {  // f^E arrays beside u_0 and every node array
+        void* f0 = take(N * sizeof(double));
+        if (p) p->FE0 = (double*)f0;
+        for (int w = 0; w < 2; ++w)
+            for (int j = 1; j <= M; ++j) {
+                bool alias_u0 = (j == 1 && pr.node_kind == ISDC_NODES_LOBATTO);
+                void* ptr = alias_u0 ? nullptr : take(N * sizeof(double));
+                if (p) p->FEU[w][j] = (double*)ptr;
+            }
+    }
     // multigrid hierarchy: 8 bytes per entry so either precision fits
-    const int tmax = tail_max_n(d);
+    const int tmax = periodic ? kCTailMaxPeriodic : tail_max_n(d);
     int n = pb.n;
-    double h = 1.0 / (pb.n + 1);
+    double h = periodic ? 2.0 / pb.n : 1.0 / (pb.n + 1);
     int l = 0;
     if (p) p->lev.clear();
     while (true) {
@@ -107,7 +147,7 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
             if (is_tail) p->tail = l;
         }
         if (is_tail) break;
-        n = (n - 1) / 2;
+        n = periodic ? n / 2 : (n - 1) / 2;
         h *= 2.0;
         ++l;
     }
@@ -268,17 +308,19 @@ constexpr int kWWarmCycles = 6;
 // One V-cycle of B_H = I + w L_H - c A_H with weighted-Jacobi smoothing on
 // level l; same contract as vcycle_rec (result in e; tmp: scratch of the level).
 template <typename T>
-void cvcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s) {
+void cvcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp,
+                 hipStream_t s) {
     const Level& L = p->lev[l];
+    const bool per = p->periodic;
     if (l == p->tail) {
-        HIPCHK(launch_ctail<T>(p->mg, L.n, c, p->w, L.h, zero, rhs, e, s));
+        HIPCHK(launch_ctail<T>(mg, L.n, c, p->w, L.h, zero, rhs, e, per, s));
         return;
     }
-    const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
+    const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, mg.omega);
     T* cur = e;
     T* other = tmp;
-    for (int i = 0; i < p->mg.nu_pre; ++i) {
-        HIPCHK(launch_cjacobi<T>(L.n, k, zero, rhs, cur, other, s));
+    for (int i = 0; i < mg.nu_pre; ++i) {
+        HIPCHK(launch_cjacobi<T>(L.n, k, zero, rhs, cur, other, per, s));
         std::swap(cur, other);
         zero = false;
     }
@@ -287,11 +329,14 @@ void cvcycle_rec(isdc_plan* p, int l, double c, bool zero, const T* rhs, T* e, T
         zero = false;
     }
     const Level& C = p->lev[l + 1];
-    HIPCHK(launch_cresfw<T>(L.n, k, rhs, cur, (T*)C.r, s));
-    cvcycle_rec<T>(p, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
-    HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
-    for (int i = 0; i < p->mg.nu_post; ++i) {
-        HIPCHK(launch_cjacobi<T>(L.n, k, false, rhs, cur, other, s));
+    HIPCHK(launch_cresfw<T>(L.n, k, rhs, cur, (T*)C.r, per, s));
+    cvcycle_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    if (per)
+        HIPCHK(launch_cprolong_p<T>(L.n, (const T*)C.e, cur, s));
+    else
+        HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
+    for (int i = 0; i < mg.nu_post; ++i) {
+        HIPCHK(launch_cjacobi<T>(L.n, k, false, rhs, cur, other, per, s));
         std::swap(cur, other);
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
@@ -301,7 +346,7 @@ template <typename T>
 double cresnorm(isdc_plan* p, int l, double c, const T* rhs, const T* u, hipStream_t s) {
     const Level& L = p->lev[l];
     int nb = 0;
-    HIPCHK(launch_cresnorm<T>(L.n, make_ccoef<T>(c, p->w, L.h, p->mg.omega), rhs, u, p->partial, &nb, s));
+    HIPCHK(launch_cresnorm<T>(L.n, make_ccoef<T>(c, p->w, L.h, p->mg.omega), rhs, u, p->partial, &nb, p->periodic, s));
     HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 1, s));
     return read_scalar(p, p->scalars + 1, s);
 }
@@ -321,23 +366,27 @@ int cinner_solve(isdc_plan* p, double c, const double* g, double* u_out, hipStre
     const int limit = classical ? 100 : pr.vcycles;
     int k = 0;
     if (!check) {
-        for (; k < limit; ++k) cvcycle_rec<T>(p, 0, c, k == 0, r0, e0, t0, s);
+        for (; k < limit; ++k) cvcycle_rec<T>(p, p->mg, 0, c, k == 0, r0, e0, t0, s);
     } else {
         HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
         for (; k < limit; ++k) {
             if (cresnorm<T>(p, 0, c, r0, e0, s) <= pr.inner_tol) break;
-            cvcycle_rec<T>(p, 0, c, false, r0, e0, t0, s);
+            cvcycle_rec<T>(p, p->mg, 0, c, false, r0, e0, t0, s);
         }
     }
     HIPCHK(launch_node_update<T>(p->N, ISDC_GUESS_PREV_SWEEP, g, g, e0, u_out, s));
     return k;
 }
 
-// S F~ for the next sweep and dt Q F~ for the residual from the node values.
-void cquad(isdc_plan* p, const double* const* nodes, hipStream_t s) {
+// S F~ for the next sweep and dt Q F~ for the residual from the node values
+// (and their f^E arrays when f^E is a stencil).
+void cquad(isdc_plan* p, const double* const* nodes, const double* const* fe, hipStream_t s) {
     CQuadArgs a;
     std::memset(&a, 0, sizeof(a));
-    for (int j = 0; j <= p->M; ++j) a.u[j] = nodes[j];
+    for (int j = 0; j <= p->M; ++j) {
+        a.u[j] = nodes[j];
+        a.feu[j] = p->fe_arrays ? fe[j] : nullptr;
+    }
     for (int m = 0; m < p->M; ++m) {
         a.sf[m] = p->SF[m];
         a.y[m] = p->Yq[m];
@@ -350,11 +399,13 @@ void cquad(isdc_plan* p, const double* const* nodes, hipStream_t s) {
     a.n = p->n;
     a.fe = p->prob.fe_kind;
     a.M = p->M;
-    HIPCHK(launch_cquad(a, p->M, s));
+    HIPCHK(launch_cquad(a, p->M, p->periodic, s));
 }
 
 // max over nodes and points of |u_0 + W^{-1} (dt Q F~)_m - u_m| (Sec. 3: W is
-// inverted once per node), after cquad of the same node values.
+// inverted once per node), after cquad of the same node values.  W = I + w L:
+// Dirichlet plans invert it with red-black V(1,1) cycles of the second-order
+// solver (c = -w); periodic plans with the compact Jacobi cycle at c = 0.
 double cresidual(isdc_plan* p, hipStream_t s) {
     CResArgs ra;
     std::memset(&ra, 0, sizeof(ra));
@@ -363,9 +414,13 @@ double cresidual(isdc_plan* p, hipStream_t s) {
     const int ncyc = p->x_valid ? kWWarmCycles : kWColdCycles;
     for (int m = 0; m < p->M; ++m) {
         if (!p->Yq[m]) continue;
-        for (int k = 0; k < ncyc; ++k)
-            vcycle_rec<double>(p, p->wmg, 0, -p->w, !p->x_valid && k == 0, p->Yq[m], p->X[m],
-                               (double*)p->lev[0].e2, s);
+        for (int k = 0; k < ncyc; ++k) {
+            const bool zero = !p->x_valid && k == 0;
+            if (p->periodic)
+                cvcycle_rec<double>(p, p->wmg, 0, 0.0, zero, p->Yq[m], p->X[m], (double*)p->lev[0].e2, s);
+            else
+                vcycle_rec<double>(p, p->wmg, 0, -p->w, zero, p->Yq[m], p->X[m], (double*)p->lev[0].e2, s);
+        }
         ra.um[ra.count] = p->cur[m + 1];
         ra.xm[ra.count] = p->X[m];
         ++ra.count;
@@ -416,16 +471,26 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
     const int M = p->M;
     double* const* W = p->U[p->wbuf];
     const double* nw[ISDC_MAX_M + 1];
+    const double* nfe[ISDC_MAX_M + 1];  // f^E(nw[j]) (fe_arrays only)
     nw[0] = p->u0;
-    for (int j = 1; j <= M; ++j) nw[j] = W[j] ? W[j] : p->u0;  // Lobatto node 1 is u_0
+    nfe[0] = p->FE0;
+    for (int j = 1; j <= M; ++j) {
+        nw[j] = W[j] ? W[j] : p->u0;  // Lobatto node 1 is u_0
+        nfe[j] = W[j] ? p->FEU[p->wbuf][j] : p->FE0;
+    }
     const double nu_h2 = p->prob.nu / (p->h * p->h);
     for (int m = 0; m < M; ++m) {
         if (p->dtau[m] == 0.0) continue;  // tau_1 = 0 (Lobatto): u_1 = u_0, no solve
         const double dtm = p->dt * p->dtau[m];
         if (p->compact) {  // eq. (5)
-            CRhsArgs ca{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, p->n, p->prob.fe_kind};
-            HIPCHK(launch_crhs<T>(ca, (T*)p->lev[0].r, s));
+            CRhsArgs ca{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, p->n, p->prob.fe_kind, nullptr, nullptr};
+            if (p->fe_arrays) {
+                ca.fe_new = nfe[m];
+                ca.fe_old = p->curfe[m];
+            }
+            HIPCHK(launch_crhs<T>(ca, (T*)p->lev[0].r, p->periodic, s));
             p->stats.vcycles += cinner_solve<T>(p, dtm * p->prob.nu, p->cur[m + 1], (double*)nw[m + 1], s);
+            if (p->fe_arrays) HIPCHK(launch_weno_burgers(p->n, p->h, nw[m + 1], (double*)nfe[m + 1], s));
             continue;
         }
         RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
@@ -441,11 +506,14 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
         }
         p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, upd, s);
     }
-    for (int j = 0; j <= M; ++j) p->cur[j] = nw[j];
+    for (int j = 0; j <= M; ++j) {
+        p->cur[j] = nw[j];
+        p->curfe[j] = nfe[j];
+    }
     p->wbuf ^= 1;
     double res;
     if (p->compact) {
-        cquad(p, p->cur, s);
+        cquad(p, p->cur, p->curfe, s);
         res = cresidual(p, s);
     } else {
         quad_residual(p, p->cur, s);
@@ -466,8 +534,12 @@ void begin_impl(isdc_plan* p, const double* d_u0, double dt, hipStream_t s) {
     p->wbuf = 0;
     p->begun = true;
     std::memset(&p->stats, 0, sizeof(p->stats));
+    if (p->fe_arrays) {
+        HIPCHK(launch_weno_burgers(p->n, p->h, d_u0, p->FE0, s));
+        for (int j = 0; j <= p->M; ++j) p->curfe[j] = p->FE0;
+    }
     if (p->compact) {
-        cquad(p, p->cur, s);  // S*F~(u^0) for sweep 1
+        cquad(p, p->cur, p->curfe, s);  // S*F~(u^0) for sweep 1
         p->x_valid = false;
     } else {
         quad_residual(p, p->cur, s);  // S*F(u^0) for sweep 1
@@ -500,7 +572,8 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->d = prob->dim;
     p->n = prob->n;
     p->N = pow_d((size_t)prob->n, prob->dim);
-    p->h = 1.0 / (prob->n + 1);
+    p->periodic = prob->bc == ISDC_BC_PERIODIC;
+    p->h = p->periodic ? 2.0 / prob->n : 1.0 / (prob->n + 1);
     p->M = par->M;
     tables(par->node_kind, par->M, p->tau, p->Q, p->S);
     double prev = 0.0;
@@ -512,7 +585,14 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->w = p->h * p->h / 12.0;
     p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post,
                      p->compact ? 1.0 : 2.0 * p->d / (2.0 * p->d + 1.0)};
-    p->wmg = MGConfig{p->d, ISDC_SMOOTH_RBGS, 1, 1, 2.0 * p->d / (2.0 * p->d + 1.0)};
+    // W solves of the residual: red-black V(1,1) of the second-order solver
+    // (Dirichlet), or the compact weighted-Jacobi V(2,2) cycle at c = 0 (periodic)
+    p->wmg = p->periodic ? MGConfig{p->d, ISDC_SMOOTH_JACOBI, 2, 2, 1.0}
+                         : MGConfig{p->d, ISDC_SMOOTH_RBGS, 1, 1, 2.0 * p->d / (2.0 * p->d + 1.0)};
+    p->fe_arrays = prob->fe_kind == ISDC_FE_BURGERS;
+    p->FE0 = nullptr;
+    std::memset(p->FEU, 0, sizeof(p->FEU));
+    std::memset(p->curfe, 0, sizeof(p->curfe));
     p->x_valid = false;
     std::memset(p->Yq, 0, sizeof(p->Yq));
     std::memset(p->X, 0, sizeof(p->X));
@@ -674,11 +754,13 @@ int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs,
         if (plan->compact) {
             if (precision == ISDC_PREC_FP64) {
                 for (int k = 0; k < ncycles; ++k)
-                    cvcycle_rec<double>(plan, 0, c, false, (const double*)d_rhs, (double*)d_u, (double*)plan->lev[0].e2, s);
+                    cvcycle_rec<double>(plan, plan->mg, 0, c, false, (const double*)d_rhs, (double*)d_u,
+                                        (double*)plan->lev[0].e2, s);
                 if (h_res_inf) *h_res_inf = cresnorm<double>(plan, 0, c, (const double*)d_rhs, (const double*)d_u, s);
             } else {
                 for (int k = 0; k < ncycles; ++k)
-                    cvcycle_rec<float>(plan, 0, c, false, (const float*)d_rhs, (float*)d_u, (float*)plan->lev[0].e2, s);
+                    cvcycle_rec<float>(plan, plan->mg, 0, c, false, (const float*)d_rhs, (float*)d_u,
+                                       (float*)plan->lev[0].e2, s);
                 if (h_res_inf) *h_res_inf = cresnorm<float>(plan, 0, c, (const float*)d_rhs, (const float*)d_u, s);
             }
             return;
@@ -703,41 +785,52 @@ template <typename T>
 void mg_op_impl(isdc_plan* p, int op, int level, double c, const void* a, const void* b, void* out, hipStream_t s,
                 double* h_scalar) {
     const int d = p->d;
-    int n = p->n;
-    double h = p->h;
-    for (int l = 0; l < level; ++l) {
-        n = (n - 1) / 2;
-        h *= 2.0;
+    if (op == ISDC_OP_EXPLICIT) {
+        if (!p->fe_arrays) fail(ISDC_E_UNSUPPORTED, "EXPLICIT probes the WENO5 Burgers advection only");
+        if (level != 0) fail(ISDC_E_INVAL, "EXPLICIT acts on the finest level");
+        if (!a || !out) fail(ISDC_E_INVAL, "EXPLICIT needs input and output");
+        if (a == out) fail(ISDC_E_INVAL, "EXPLICIT needs a separate output array");
+        HIPCHK(launch_weno_burgers(p->n, p->h, (const double*)a, (double*)out, s));
+        return;
     }
+    int n;
+    double h;
+    level_size(p->periodic, p->n, level, n, h);
     const size_t N = pow_d((size_t)n, d);
     Coef<T> co = make_coef<T>(c, h, d, p->mg.omega);
     if (p->compact) {
+        const bool per = p->periodic;
+        const int nmin = per ? 2 : 3;
         const CCoef<T> k = make_ccoef<T>(c, p->w, h, p->mg.omega);
         switch (op) {
             case ISDC_OP_SMOOTH:
                 if (!a || !b || !out) fail(ISDC_E_INVAL, "SMOOTH needs rhs, iterate and output");
                 if (out == b) fail(ISDC_E_INVAL, "Jacobi SMOOTH needs a separate output array");
-                HIPCHK(launch_cjacobi<T>(n, k, false, (const T*)a, (const T*)b, (T*)out, s));
+                HIPCHK(launch_cjacobi<T>(n, k, false, (const T*)a, (const T*)b, (T*)out, per, s));
                 break;
             case ISDC_OP_RESTRICT:
-                if (n < 3) fail(ISDC_E_INVAL, "RESTRICT needs a level with n >= 3");
+                if (n < nmin) fail(ISDC_E_INVAL, "RESTRICT needs a level with a coarser level below it");
                 if (!a || !b || !out) fail(ISDC_E_INVAL, "RESTRICT needs rhs, iterate and output");
-                HIPCHK(launch_cresfw<T>(n, k, (const T*)a, (const T*)b, (T*)out, s));
+                HIPCHK(launch_cresfw<T>(n, k, (const T*)a, (const T*)b, (T*)out, per, s));
                 break;
             case ISDC_OP_PROLONG:
-                if (n < 3) fail(ISDC_E_INVAL, "PROLONG needs a level with n >= 3");
+                if (n < nmin) fail(ISDC_E_INVAL, "PROLONG needs a level with a coarser level below it");
                 if (!a || !out) fail(ISDC_E_INVAL, "PROLONG needs coarse input and output");
-                HIPCHK(launch_prolong<T>(d, n, (const T*)a, (T*)out, s));
+                if (per)
+                    HIPCHK(launch_cprolong_p<T>(n, (const T*)a, (T*)out, s));
+                else
+                    HIPCHK(launch_prolong<T>(d, n, (const T*)a, (T*)out, s));
                 break;
             case ISDC_OP_COARSE:
-                if (n > tail_max_n(d)) fail(ISDC_E_INVAL, "COARSE level too large for one workgroup");
+                if (n > (per ? kCTailMaxPeriodic : tail_max_n(d)))
+                    fail(ISDC_E_INVAL, "COARSE level too large for one workgroup");
                 if (!a || !out) fail(ISDC_E_INVAL, "COARSE needs rhs and output");
-                HIPCHK(launch_ctail<T>(p->mg, n, c, p->w, h, true, (const T*)a, (T*)out, s));
+                HIPCHK(launch_ctail<T>(p->mg, n, c, p->w, h, true, (const T*)a, (T*)out, per, s));
                 break;
             case ISDC_OP_RESIDUAL_NORM: {
                 if (!a || !b || !h_scalar) fail(ISDC_E_INVAL, "RESIDUAL_NORM needs rhs, iterate and h_scalar");
                 int nb = 0;
-                HIPCHK(launch_cresnorm<T>(n, k, (const T*)a, (const T*)b, p->partial, &nb, s));
+                HIPCHK(launch_cresnorm<T>(n, k, (const T*)a, (const T*)b, p->partial, &nb, per, s));
                 HIPCHK(launch_reduce_max(p->partial, nb, p->scalars + 2, s));
                 *h_scalar = read_scalar(p, p->scalars + 2, s);
                 break;
@@ -796,12 +889,7 @@ extern "C" int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, 
     return guarded([&] {
         check_plan(plan);
         if (!std::isfinite(c) || c < 0) fail(ISDC_E_INVAL, "c must be finite and >= 0");
-        int nl = 0;
-        for (int n = plan->n; n >= 1; n = (n - 1) / 2) {
-            ++nl;
-            if (n == 1) break;
-        }
-        if (level < 0 || level >= nl) fail(ISDC_E_INVAL, "level out of range");
+        if (level < 0 || level >= level_count(plan->periodic, plan->n)) fail(ISDC_E_INVAL, "level out of range");
         if (precision == ISDC_PREC_FP64)
             mg_op_impl<double>(plan, op, level, c, d_a, d_b, d_out, (hipStream_t)stream, h_scalar);
         else if (precision == ISDC_PREC_MIXED)
@@ -826,14 +914,22 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
             if (level < 0 || level >= p->tail) fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
             const Level& L = p->lev[level];
             const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
-            launch = [=]() { HIPCHK(launch_cjacobi<T>(L.n, k, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, s)); };
+            const bool per = p->periodic;
+            launch = [=]() { HIPCHK(launch_cjacobi<T>(L.n, k, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, per, s)); };
             b = 3.0 * (double)L.N * w;
         } else if (kernel == ISDC_KERNEL_TAIL) {
             const Level& L = p->lev[p->tail];
-            launch = [=]() { HIPCHK(launch_ctail<T>(p->mg, L.n, c, p->w, L.h, true, (const T*)L.r, (T*)L.e, s)); };
+            launch = [=]() {
+                HIPCHK(launch_ctail<T>(p->mg, L.n, c, p->w, L.h, true, (const T*)L.r, (T*)L.e, p->periodic, s));
+            };
             b = 2.0 * (double)L.N * w;
+        } else if (kernel == ISDC_KERNEL_EXPLICIT) {
+            if (!p->fe_arrays) fail(ISDC_E_UNSUPPORTED, "ISDC_KERNEL_EXPLICIT times the WENO5 Burgers advection only");
+            const Level& L = p->lev[0];
+            launch = [=]() { HIPCHK(launch_weno_burgers(p->n, p->h, (const double*)L.r, (double*)L.e, s)); };
+            b = 2.0 * (double)p->N * 8.0;
         } else {
-            fail(ISDC_E_UNSUPPORTED, "compact plans time ISDC_KERNEL_SMOOTH and ISDC_KERNEL_TAIL only");
+            fail(ISDC_E_UNSUPPORTED, "compact plans time ISDC_KERNEL_SMOOTH, ISDC_KERNEL_TAIL and ISDC_KERNEL_EXPLICIT only");
         }
     } else {
     if (kernel != ISDC_KERNEL_TAIL && kernel != ISDC_KERNEL_QUAD && (level < 0 || level >= p->tail))

@@ -46,8 +46,8 @@ def _dev_ptr(t: torch.Tensor, dtype=None, numel=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_problem(dim, n, nu, fe_kind=A.FE_ZERO, stencil=A.STENCIL_2ND) -> A.Problem:
-    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind, stencil=stencil)
+def make_problem(dim, n, nu, fe_kind=A.FE_ZERO, stencil=A.STENCIL_2ND, bc=A.BC_DIRICHLET) -> A.Problem:
+    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind, stencil=stencil, bc=bc)
 
 
 def make_params(**kw) -> A.Params:
@@ -82,11 +82,12 @@ class Plan:
     """One ISDC problem instance: the C plan plus its torch-owned workspace."""
 
     def __init__(self, dim: int, n: int, nu: float, fe_kind: int = A.FE_ZERO, device=None,
-                 stencil: int = A.STENCIL_2ND, **params):
+                 stencil: int = A.STENCIL_2ND, bc: int = A.BC_DIRICHLET, **params):
         self.lib = A.load()
-        self.problem = make_problem(dim, n, nu, fe_kind, stencil)
+        self.problem = make_problem(dim, n, nu, fe_kind, stencil, bc)
         self.params = make_params(**params)
         self.dim, self.n = dim, n
+        self.periodic = bc == A.BC_PERIODIC
         self.N = n ** dim
         self.shape = (n,) * dim
         nbytes = workspace_bytes(self.problem, self.params)
@@ -151,12 +152,22 @@ class Plan:
                                      ncycles, _stream_handle(stream), C.byref(res) if want_residual else None))
         return res.value if want_residual else None
 
+    def level_n(self, level: int) -> int:
+        """Points per axis of multigrid level `level` (periodic n / 2^l, else (n+1) / 2^l - 1)."""
+        return self.n >> level if self.periodic else ((self.n + 1) >> level) - 1
+
     def mg_op(self, op: int, level: int, c: float, a=None, b=None, out=None, stream=None):
         t = next(x for x in (a, b, out) if x is not None)
         prec = A.PREC_FP64 if t.dtype == torch.float64 else A.PREC_MIXED
+        dt = torch.float64 if prec == A.PREC_FP64 or op == A.OP_EXPLICIT else torch.float32
+        fine = self.level_n(level) ** self.dim
+        coarse = self.level_n(level + 1) ** self.dim if self.level_n(level) > 1 else 0
+        sizes = {A.OP_SMOOTH: (fine, fine, fine), A.OP_RESTRICT: (fine, fine, coarse),
+                 A.OP_PROLONG: (coarse, None, fine), A.OP_COARSE: (fine, None, fine),
+                 A.OP_RESIDUAL_NORM: (fine, fine, None), A.OP_EXPLICIT: (fine, None, fine)}.get(op, (None,) * 3)
+        ptrs = [_dev_ptr(x, dt, sz) for x, sz in zip((a, b, out), sizes)]
         res = C.c_double()
-        A.check(self.lib.isdc_mg_op(self._h, op, level, c, prec, _dev_ptr(a), _dev_ptr(b), _dev_ptr(out),
-                                    _stream_handle(stream), C.byref(res)))
+        A.check(self.lib.isdc_mg_op(self._h, op, level, c, prec, *ptrs, _stream_handle(stream), C.byref(res)))
         return res.value
 
     def time_kernel(self, kernel: int, level: int, c: float, precision: int, reps: int = 100, stream=None):
@@ -203,13 +214,13 @@ class Batch:
         return workspace_bytes(make_problem(dim, n, nu, fe_kind), make_params(**params))
 
     def set(self, slot: int, u: torch.Tensor, dt: float, nsteps: int, nu: float, fe_kind: int = A.FE_ZERO,
-            workspace: torch.Tensor = None, stencil: int = A.STENCIL_2ND, **params):
+            workspace: torch.Tensor = None, stencil: int = A.STENCIL_2ND, bc: int = A.BC_DIRICHLET, **params):
         """Start instance (u, nu, f^E, params) in `slot` for nsteps steps of size dt.
         u (float64, shape (n,)*dim) is advanced in place."""
         n = u.shape[0]
         params.setdefault("vcycles", self.vcycles)
         params.setdefault("precision", self.precision)
-        prob = make_problem(self.dim, n, nu, fe_kind, stencil)
+        prob = make_problem(self.dim, n, nu, fe_kind, stencil, bc)
         par = make_params(**params)
         need = workspace_bytes(prob, par)
         if workspace is None:

@@ -10,6 +10,11 @@ satisfy the homogeneous Dirichlet boundary condition:
 * each amplitude is standard normal divided by |a|^2 (a smooth field, as for
   the paper's smooth initial data in Sec. 4.1).
 
+Periodic inputs live on the n points x_i = -1 + i h, h = 2 / n of [-1, 1)
+per axis: the Gaussian exp(-|x|^2 / sigma^2) of the Burgers runs (Sec. 4.1,
+sigma = 0.1), and seeded smooth fields sum_k amp_k cos(pi a.x + phi_k) with
+integer wave vectors a (period 2 in every coordinate).
+
 The workload table mirrors the benchmark configurations (sizes, nodes, time
 step, precision); no public dataset is involved.
 """
@@ -18,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
-FE_ZERO, FE_CUBIC = 0, 1
+FE_ZERO, FE_CUBIC, FE_BURGERS = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -63,6 +68,37 @@ def sine_field_at(n: int, modes, points: np.ndarray) -> np.ndarray:
     return out
 
 
+def periodic_axis(n: int) -> np.ndarray:
+    """The n grid coordinates of [-1, 1) (spacing 2 / n)."""
+    return -1.0 + (2.0 / n) * np.arange(n)
+
+
+def gaussian_periodic(n: int, sigma: float = 0.1, d: int = 2) -> np.ndarray:
+    """exp(-|x|^2 / sigma^2) on the periodic n^d grid of [-1, 1)^d (float64)."""
+    x = periodic_axis(n)
+    r2 = np.zeros((n,) * d)
+    for ax in range(d):
+        shape = [1] * d
+        shape[ax] = n
+        r2 = r2 + (x ** 2).reshape(shape)
+    return np.exp(-r2 / sigma ** 2)
+
+
+def periodic_field(n: int, seed: int, n_modes: int = 8, max_wave: int = 6, d: int = 2) -> np.ndarray:
+    """Seeded smooth periodic field: sum of n_modes cos(pi a.x + phi), a in
+    {-max_wave..max_wave}^d, amplitude N(0,1) / (1 + |a|^2), phase U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    x = periodic_axis(n)
+    grids = np.meshgrid(*([x] * d), indexing="ij")
+    out = np.zeros((n,) * d)
+    for _ in range(n_modes):
+        a = rng.integers(-max_wave, max_wave + 1, size=d)
+        amp = rng.standard_normal() / (1.0 + float(np.dot(a, a)))
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        out += amp * np.cos(np.pi * sum(ai * g for ai, g in zip(a, grids)) + phi)
+    return out
+
+
 # The five workloads of the benchmark: sizes, nodes, step and precision.
 WORKLOADS = {
     "heat1d": dict(dim=1, n=127, nu=1.0, fe_kind=FE_ZERO, node_kind=NODES_LOBATTO, M=3, dt=0.01, steps=1,
@@ -76,6 +112,11 @@ WORKLOADS = {
     "rd2d_compact": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
                          precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2, stencil=1, smoother=1,
                          nu_pre=2, nu_post=2),
+    # 2D viscous Burgers of Sec. 4.1 on [-1, 1)^2, periodic, 128^2 points (h = 1/64),
+    # Gaussian sigma = 0.1, nu = 1 (diffusive CFL 4.1), WENO5 advection, compact stencil
+    "burgers2d": dict(dim=2, n=128, nu=1.0, fe_kind=FE_BURGERS, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
+                      precision=PREC_FP64, sdc_tol=1e-10, stencil=1, bc=1, smoother=1, nu_pre=3, nu_post=3,
+                      gaussian_sigma=0.1),
 }
 
 
@@ -88,6 +129,8 @@ def workload_modes(cfg: dict):
 def workload_u0(cfg: dict, n: int | None = None) -> np.ndarray:
     """Initial value of a workload (optionally on a smaller grid of the same modes)."""
     n = cfg["n"] if n is None else n
+    if "gaussian_sigma" in cfg:
+        return gaussian_periodic(n, cfg["gaussian_sigma"], cfg["dim"])
     return sine_field(n, cfg["dim"], workload_modes(cfg))
 
 

@@ -106,6 +106,36 @@ def test_validation_rejects(bad):
     assert A.load().isdc_last_error() != b""
 
 
+def _pbytes(dim, n, stencil, bc, fe=A.FE_ZERO, **kw):
+    lib = A.load()
+    out = C.c_size_t()
+    prob = A.Problem(dim=dim, n=n, nu=1.0, fe_kind=fe, stencil=stencil, bc=bc)
+    par = _params(**dict(dict(smoother=A.SMOOTH_JACOBI), **kw))
+    return lib.isdc_workspace_bytes(C.byref(prob), C.byref(par), C.byref(out)), out.value
+
+
+def test_periodic_and_burgers_validation():
+    SC, S2, BP, BD = A.STENCIL_COMPACT4, A.STENCIL_2ND, A.BC_PERIODIC, A.BC_DIRICHLET
+    for n in (4, 128, 8192):
+        assert _pbytes(2, n, SC, BP)[0] == 0
+        assert _pbytes(2, n, SC, BP, A.FE_BURGERS)[0] == 0
+    for n in (2, 3, 31, 127, 16384):  # n = 2^k with 2 <= k <= 13
+        assert _pbytes(2, n, SC, BP)[0] == A.E_INVAL
+    assert _pbytes(2, 63, SC, 2)[0] == A.E_INVAL  # unknown bc
+    assert _pbytes(2, 64, S2, BP)[0] == A.E_UNSUPPORTED  # periodic second-order stencil
+    assert _pbytes(3, 64, SC, BP)[0] == A.E_UNSUPPORTED  # compact stencil is 2D
+    assert _pbytes(2, 63, SC, BD, A.FE_BURGERS)[0] == A.E_UNSUPPORTED  # Burgers needs periodic
+    assert _pbytes(2, 63, S2, BD, A.FE_BURGERS)[0] == A.E_UNSUPPORTED
+
+
+def test_burgers_workspace_holds_fe_arrays():
+    # f^E arrays: u_0 plus 2 (M - 1) node arrays beside the plain periodic plan (Lobatto, M = 3)
+    rc0, b0 = _pbytes(2, 256, A.STENCIL_COMPACT4, A.BC_PERIODIC)
+    rc1, b1 = _pbytes(2, 256, A.STENCIL_COMPACT4, A.BC_PERIODIC, A.FE_BURGERS)
+    assert rc0 == 0 and rc1 == 0
+    assert b1 - b0 == (1 + 2 * 2) * 256 * 256 * 8
+
+
 def test_create_checks_workspace_without_touching_it():
     lib = A.load()
     prob = A.Problem(2, 63, 1.0, A.FE_ZERO)
