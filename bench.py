@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "heat3d", "heat1d", "batch", "serve", "table1", "kernels"])
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "heat3d", "heat1d", "burgers2d", "batch", "serve", "table1",
+                             "table1b", "kernels"])
     ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--batch-count", type=int, default=256)
@@ -45,10 +46,27 @@ def parse():
 
 
 def mg_params(cfg):
-    """Stencil and multigrid settings of a workload (defaults: second-order
-    stencil, red-black V(1,1))."""
-    return dict(stencil=cfg.get("stencil", 0), smoother=cfg.get("smoother", 0), nu_pre=cfg.get("nu_pre", 1),
-                nu_post=cfg.get("nu_post", 1))
+    """Stencil, boundary and multigrid settings of a workload (defaults:
+    second-order stencil, Dirichlet, red-black V(1,1))."""
+    return dict(stencil=cfg.get("stencil", 0), bc=cfg.get("bc", 0), smoother=cfg.get("smoother", 0),
+                nu_pre=cfg.get("nu_pre", 1), nu_post=cfg.get("nu_post", 1))
+
+
+def grid_h(cfg, n=None):
+    """Grid spacing: periodic [-1, 1) with n points, else (0, 1) with n interior points."""
+    n = cfg["n"] if n is None else n
+    return 2.0 / n if cfg.get("bc", 0) == 1 else 1.0 / (n + 1)
+
+
+def tail_n(cfg):
+    """Largest level the single-workgroup tail takes."""
+    if cfg.get("bc", 0) == 1:
+        return 32
+    return {1: 2047, 2: 63, 3: 15}[cfg["dim"]]
+
+
+def coarser(cfg, m):
+    return m // 2 if cfg.get("bc", 0) == 1 else (m - 1) // 2
 
 
 def make_plan(cfg):
@@ -90,7 +108,9 @@ def kernel_name(name, cfg, T):
     """rocprof name of the kernel bench.py times for `name` on the finest level
     (3D levels of 127^3 and up run the z-marching form)."""
     if cfg.get("stencil", 0) == 1:
-        return {"smooth": f"k_cjacobi<{T},false>", "tail": f"k_ctail<{T}>"}[name]
+        per = "true" if cfg.get("bc", 0) == 1 else "false"
+        return {"smooth": f"k_cjacobi<{T},false,{per}>", "tail": f"k_ctail<{T},{per}>",
+                "explicit": "k_weno_burgers"}[name]
     if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
         return f"k_march_rbgs<{T},true,0,false>"
     return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"])
@@ -162,11 +182,12 @@ def kernel_probe(plan, cfg, reps, torch):
              ("tail", P.KERNEL_TAIL)]
     if cfg.get("stencil", 0) == 1:  # compact plans: the weighted-Jacobi step and the compact tail
         kinds = [("smooth", P.KERNEL_SMOOTH), ("tail", P.KERNEL_TAIL)]
-    tail_n = {1: 2047, 2: 63, 3: 15}[cfg["dim"]]
+    if cfg["fe_kind"] == 2:  # the WENO5 Burgers advection
+        kinds.append(("explicit", P.KERNEL_EXPLICIT))
     for name, k in kinds:
         if name == "smooth_restrict" and cfg["dim"] == 3:
             continue
-        if name != "tail" and cfg["n"] <= tail_n:
+        if name not in ("tail", "explicit") and cfg["n"] <= tail_n(cfg):
             continue  # the whole V-cycle is the single-workgroup coarse solve
         us, b = plan.time_kernel(k, 0, c, prec, reps)
         out[name] = dict(kernel=kernel_name(name, cfg, T), avg_us=round(us, 3),
@@ -198,17 +219,16 @@ def vcycle_probe(plan, cfg, reps, torch):
     us = e0.elapsed_time(e1) * 1e3 / reps
     # per multi-workgroup level: (3N + Nc) for smoothing+restriction and for
     # prolongation+smoothing; the tail reads its rhs and writes its iterate
-    tail_n = {1: 2047, 2: 63, 3: 15}[d]
     b, m = 0.0, n
     compact = cfg.get("stencil", 0) == 1
     nsm = cfg.get("nu_pre", 1) + cfg.get("nu_post", 1)
-    while m > tail_n:
-        N, Nc = m ** d, ((m - 1) // 2) ** d
+    while m > tail_n(cfg):
+        N, Nc = m ** d, coarser(cfg, m) ** d
         if compact:  # Jacobi steps 3N each; residual + restriction 2N + Nc; prolongation 2N + Nc
             b += (nsm * 3 * N + 4 * N + 2 * Nc) * w
         else:        # smoothing + restriction 3N + Nc; prolongation + smoothing 3N + Nc
             b += 2 * (3 * N + Nc) * w
-        m = (m - 1) // 2
+        m = coarser(cfg, m)
     b += 2 * m ** d * w
     return dict(us_per_vcycle=round(us, 2), alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1),
                 frac=round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
@@ -218,8 +238,9 @@ def cpu_baseline(cfg, sweeps_per_step):
     """The oracle (numpy, one thread) on a bounded sample: sweeps of one step
     at full size, scaled to steps/s with the GPU's sweeps per step.  Above
     2^22 points a single full-size sweep would exceed the sample budget, so
-    the sample runs on the grid with side (n+1)/2 - 1 and is scaled by the
-    ratio of point counts (the oracle's work is linear in the points)."""
+    the sample runs on the next coarser grid (side (n-1)/2, or n/2 periodic)
+    and is scaled by the ratio of point counts (the oracle's work is linear in
+    the points)."""
     import numpy as np
     import oracle as O  # noqa: F401  (test infrastructure: the CPU baseline only)
     from oracle.sdc import SDCConfig, sdc_begin, sdc_sweep
@@ -227,14 +248,14 @@ def cpu_baseline(cfg, sweeps_per_step):
     c = dict(cfg)
     scale = 1.0
     while c["n"] ** c["dim"] > 2 ** 22:
-        small = (c["n"] + 1) // 2 - 1
+        small = coarser(c, c["n"])
         scale *= (c["n"] / small) ** c["dim"]
         c["n"] = small
     u0 = W.workload_u0(c)
     sc = SDCConfig(nu=c["nu"], fe_kind=c["fe_kind"], node_kind=c["node_kind"], M=c["M"],
-                   precision=c["precision"], tol=c["sdc_tol"], stencil=c.get("stencil", 0),
+                   precision=c["precision"], tol=c["sdc_tol"], stencil=c.get("stencil", 0), bc=c.get("bc", 0),
                    smoother=c.get("smoother", 0), nu1=c.get("nu_pre", 1), nu2=c.get("nu_post", 1))
-    h = 1.0 / (c["n"] + 1)
+    h = grid_h(c)
     t0 = time.perf_counter()
     st = sdc_begin(u0, c["dt"], h, sc)
     nsw = 0
@@ -530,6 +551,78 @@ def run_table1(args, torch):
     }
 
 
+def run_table1b(args, torch):
+    """Table 1(b) replay (Sec. 4.1): 2D viscous Burgers on [-1, 1)^2, periodic,
+    n = 128 (h = 1/64, diffusive CFL 0.41 / 4.1 / 41), u0 = exp(-|x|^2 / 0.1^2),
+    WENO5 advection, fourth-order compact stencil with W, dt = 1e-3,
+    Gauss-Lobatto M in {3, 5, 7}, nu in {0.1, 1, 10}, sweeps until the max-norm
+    SDC residual < 5e-8; weighted-Jacobi V(3,3) (omega = 1).  Classical SDC
+    cycles each implicit solve until its max-norm residual <= 1e-9; ISDC stops
+    after L = 2 cycles or earlier at that tolerance.  `value` is the V-cycle
+    saving summed over the nine rows."""
+    import csv
+    from paper_1401_7824_amd import Plan, workloads as W
+    n, dt = 128, 1e-3
+    u0 = W.gaussian_periodic(n, 0.1)
+    printed = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1.csv")) as fh:
+        for r in csv.DictReader(line for line in fh if not line.startswith("#")):
+            if r["problem"] == "burgers":
+                printed[(float(r["nu"]), int(r["M"]))] = r
+    rows = []
+    tot = {"sdc": 0, "isdc": 0}
+    ms_tot = {"sdc": 0.0, "isdc": 0.0}
+    for nu in (0.1, 1.0, 10.0):
+        for M in (3, 5, 7):
+            row = {"nu": nu, "M": M}
+            for name, mode in (("sdc", dict(vcycles=0)), ("isdc", dict(vcycles=2, early_exit=1))):
+                p = Plan(2, n, nu, W.FE_BURGERS, stencil=1, bc=1, node_kind=0, M=M, sdc_tol=5e-8, inner_tol=1e-9,
+                         max_sweeps=100, smoother=1, nu_pre=3, nu_post=3, **mode)
+                u0d = torch.from_numpy(u0).cuda()
+                u = u0d.clone()
+                st = p.step(u, dt)
+                reps = max(1, args.steps)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    u.copy_(u0d)
+                    p.step(u, dt)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / reps * 1e3
+                row[name] = {"vcycles": st.vcycles, "sweeps": st.sweeps, "status": st.status,
+                             "ms_per_step": round(ms, 3)}
+                tot[name] += st.vcycles
+                ms_tot[name] += ms
+            pr = printed[(nu, M)]
+            row["savings_pct"] = round(100.0 * (1 - row["isdc"]["vcycles"] / row["sdc"]["vcycles"]), 1)
+            row["time_savings_pct"] = round(100.0 * (1 - row["isdc"]["ms_per_step"] / row["sdc"]["ms_per_step"]), 1)
+            row["printed"] = {"sdc": f"{pr['sdc_cycles']}({pr['sdc_sweeps']})",
+                              "isdc": f"{pr['isdc_cycles']}({pr['isdc_sweeps']})",
+                              "savings_pct": int(pr["savings_pct"])}
+            rows.append(row)
+            print(f"[table1b] nu={nu:5.1f} M={M}: SDC {row['sdc']['vcycles']}({row['sdc']['sweeps']}) "
+                  f"ISDC {row['isdc']['vcycles']}({row['isdc']['sweeps']}) save {row['savings_pct']}% | "
+                  f"printed {row['printed']['sdc']} {row['printed']['isdc']} {pr['savings_pct']}%",
+                  file=sys.stderr, flush=True)
+    printed_save = 100.0 * (1 - sum(int(r["isdc_cycles"]) for r in printed.values())
+                            / sum(int(r["sdc_cycles"]) for r in printed.values()))
+    return {
+        "metric": "Table 1(b) replay: accumulated V-cycles of classical SDC vs ISDC",
+        "value": round(100.0 * (1 - tot["isdc"] / tot["sdc"]), 2),
+        "unit": "% V-cycles saved (9 rows)", "n_gpus": 1, "steps": 18 * max(1, args.steps), "warmup": 18,
+        "ms_per_step": round((ms_tot["sdc"] + ms_tot["isdc"]) / 18, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "table1b: 2D viscous Burgers periodic [-1,1)^2 n=128 (h=1/64) Gaussian sigma=0.1 "
+                               "WENO5 compact stencil with W dt=1e-3 Lobatto M=3,5,7 nu=0.1,1,10 tol 5e-8; "
+                               "SDC inner_tol 1e-9; ISDC L=2 early exit; weighted-Jacobi V(3,3)"},
+        "time_savings_pct": round(100.0 * (1 - ms_tot["isdc"] / ms_tot["sdc"]), 2),
+        "totals": {"sdc_vcycles": tot["sdc"], "isdc_vcycles": tot["isdc"],
+                   "sdc_ms": round(ms_tot["sdc"], 3), "isdc_ms": round(ms_tot["isdc"], 3)},
+        "printed_savings_pct_9_rows": round(printed_save, 2),
+        "rows": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -551,6 +644,9 @@ def main():
     if args.workload == "table1":
         print(json.dumps(run_table1(args, torch)), flush=True)
         return
+    if args.workload == "table1b":
+        print(json.dumps(run_table1b(args, torch)), flush=True)
+        return
     if args.workload == "kernels":
         print(json.dumps(run_kernels(args, torch)), flush=True)
         return
@@ -558,7 +654,7 @@ def main():
     plan = make_plan(cfg)
     u = torch.from_numpy(W.workload_u0(cfg)).cuda()
     accuracy = None
-    if cfg["fe_kind"] == W.FE_ZERO:
+    if cfg["fe_kind"] == W.FE_ZERO and cfg.get("bc", 0) == 0:
         accuracy = accuracy_vs_collocation(cfg, torch)
     elapsed, wall, stats = time_steps(plan, u, cfg["dt"], args.steps, args.warmup, torch)
     sweeps = sum(s.sweeps for s in stats) / len(stats)
@@ -583,8 +679,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if cfg["precision"] == 0 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {cfg['dim']}D n={cfg['n']} nu={cfg['nu']} "
-                               f"fe={'cubic' if cfg['fe_kind'] else 'zero'} "
+        "config": {"workload": f"{args.workload}: {cfg['dim']}D n={cfg['n']} "
+                               f"{'periodic' if cfg.get('bc', 0) == 1 else 'Dirichlet'} nu={cfg['nu']} "
+                               f"fe={['zero', 'cubic', 'WENO5 Burgers'][cfg['fe_kind']]} "
                                f"{'Lobatto' if cfg['node_kind'] == 0 else 'Radau-right'} M={cfg['M']} "
                                f"dt={cfg['dt']} L=2 "
                                + ("compact 4th-order stencil with W, Jacobi "
