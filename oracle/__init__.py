@@ -36,7 +36,9 @@ here is "parity unpinned".
 from .collocation import (  # noqa: F401
     NODES_LOBATTO,
     NODES_RADAU_RIGHT,
+    NODES_LEGENDRE,
     nodes,
+    end_weights,
     qmatrix,
     smatrix,
     collocation_heat_modal,

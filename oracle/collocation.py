@@ -6,8 +6,11 @@ Paper basis:
 
 * The nodes are those of a spectral collocation rule (Gauss-Legendre,
   Gauss-Radau or Gauss-Lobatto; Sec. 1, and Sec. 2 right after eq. (2)).  This
-  oracle provides the two families that end on the right end point of the step:
-  Gauss-Lobatto and right Gauss-Radau.
+  oracle provides Gauss-Lobatto, right Gauss-Radau and Gauss-Legendre.  The
+  first two end on the right end point of the step, so u(T_{n+1}) is the last
+  node value; Gauss-Legendre nodes are all interior, and the step's result is
+  the collocation polynomial at the end point, u_0 + dt * sum_j b_j f(u_j) with
+  b_j the integral of l_j over the whole step (``end_weights``).
 * eq. (2): the node-to-node integral over [t_m, t_{m+1}] is approximated by
   dt * sum_j s_{m,j} f(u_j) = S_m^{m+1} F(u), with F(u) = (f(u_1), ..., f(u_M)).
 * eq. (1) written at the nodes gives the collocation problem
@@ -29,6 +32,7 @@ from numpy.polynomial import legendre as npleg
 
 NODES_LOBATTO = 0
 NODES_RADAU_RIGHT = 1
+NODES_LEGENDRE = 2
 
 _DPS = 40  # working precision (decimal digits) for node and weight polishing
 
@@ -63,6 +67,10 @@ def _nodes_mp(kind: int, M: int):
             start = np.sort(np.real(npleg.legroots(coef)))
             g = lambda x: mp.legendre(M, x) - mp.legendre(M - 1, x)  # noqa: E731
             pts = [_polish(g, x) for x in start[:-1]] + [mp.mpf(1)]
+        elif kind == NODES_LEGENDRE:
+            if M < 1:
+                raise ValueError("Gauss-Legendre needs M >= 1")
+            pts = _gauss_legendre_mp(M)[0]  # roots of P_M, all interior
         else:
             raise ValueError(f"unknown node kind {kind}")
         return sorted(pts)
@@ -71,8 +79,9 @@ def _nodes_mp(kind: int, M: int):
 def nodes(kind: int, M: int) -> np.ndarray:
     """Collocation nodes tau_1..tau_M on the unit step [0, 1] (float64).
 
-    Sec. 1 and Sec. 2 (after eq. (2)): Gauss-Lobatto (both end points) or right
-    Gauss-Radau (right end point only); tau = (1 + x) / 2 for x in [-1, 1].
+    Sec. 1 and Sec. 2 (after eq. (2)): Gauss-Lobatto (both end points), right
+    Gauss-Radau (right end point only) or Gauss-Legendre (no end point);
+    tau = (1 + x) / 2 for x in [-1, 1].
     """
     with mp.workdps(_DPS):
         return np.array([float((1 + x) / 2) for x in _nodes_mp(kind, M)])
@@ -114,6 +123,32 @@ def _q_mp(kind: int, M: int):
         return tau, Q
 
 
+def end_weights(kind: int, M: int) -> np.ndarray:
+    """b_j = integral over the whole step [0, 1] of l_j (the collocation rule's
+    quadrature weights); u(T_{n+1}) = u_0 + dt * sum_j b_j f(u_j).  For the node
+    families that end on tau_M = 1 this is the last row of Q."""
+    with mp.workdps(_DPS):
+        tau = [(1 + x) / 2 for x in _nodes_mp(kind, M)]
+        gx, gw = _gauss_legendre_mp(M + 1)
+        out = []
+        for j in range(M):
+            acc = mp.mpf(0)
+            for x, w in zip(gx, gw):
+                s = (x + 1) / 2
+                v = mp.mpf(1)
+                for i in range(M):
+                    if i != j:
+                        v *= (s - tau[i]) / (tau[j] - tau[i])
+                acc += w * v
+            out.append(float(acc / 2))
+        return np.array(out)
+
+
+def ends_on_node(kind: int) -> bool:
+    """True if tau_M = 1, so that the last node value is the step's result."""
+    return kind in (NODES_LOBATTO, NODES_RADAU_RIGHT)
+
+
 def qmatrix(kind: int, M: int) -> np.ndarray:
     """Cumulative collocation matrix, Q[m-1, j-1] = integral_0^{tau_m} l_j.
 
@@ -144,15 +179,18 @@ def stability_function(z, kind: int, M: int):
     """Collocation stability function R(z) for u' = lambda u, z = dt * lambda.
 
     The collocation problem (Sec. 1) for a scalar linear ODE is the M-by-M
-    system (I - z Q) U = u_0 * 1; R(z) = U_M / u_0 since tau_M = 1 for both node
-    families provided here.  ``z`` may be a scalar or an array.
+    system (I - z Q) U = u_0 * 1; R(z) = U_M / u_0 where tau_M = 1 (Lobatto,
+    Radau), else R(z) = 1 + z * sum_j b_j U_j / u_0 (Gauss-Legendre).  ``z``
+    may be a scalar or an array.
     """
     Q = qmatrix(kind, M)
     z = np.asarray(z, dtype=np.float64)
     flat = z.reshape(-1)
     A = np.eye(M)[None, :, :] - flat[:, None, None] * Q[None, :, :]
-    U = np.linalg.solve(A, np.ones((flat.size, M, 1)))
-    return U[:, -1, 0].reshape(z.shape)
+    U = np.linalg.solve(A, np.ones((flat.size, M, 1)))[:, :, 0]
+    if ends_on_node(kind):
+        return U[:, -1].reshape(z.shape)
+    return (1.0 + flat * (U @ end_weights(kind, M))).reshape(z.shape)
 
 
 def collocation_heat_modal(u0: np.ndarray, dt: float, nu: float, h: float,
@@ -180,7 +218,7 @@ def collocation_dense(u0: np.ndarray, dt: float, nu: float, h: float, fe_kind: i
 
     Sec. 1: U_m = u_0 + dt sum_j q_{m,j} f(U_j) for all m at once, with
     f = nu L_h + f^E.  Dense linear algebra, so only for tiny grids.
-    Returns U_M = u(T_{n+1}).
+    Returns u(T_{n+1}): U_M, or u_0 + dt sum_j b_j f(U_j) for Gauss-Legendre.
     """
     from .operators import f_explicit, laplacian, laplacian_matrix, f_explicit_derivative
 
@@ -203,4 +241,8 @@ def collocation_dense(u0: np.ndarray, dt: float, nu: float, h: float, fe_kind: i
         U = U - delta.reshape(M, N)
         if np.max(np.abs(delta)) < tol:
             break
-    return U[-1].reshape(shape)
+    if ends_on_node(kind):
+        return U[-1].reshape(shape)
+    F = np.stack([nu * laplacian(U[j].reshape(shape), h).reshape(N)
+                  + f_explicit(U[j].reshape(shape), fe_kind).reshape(N) for j in range(M)])
+    return (u0.reshape(N) + dt * (end_weights(kind, M) @ F)).reshape(shape)

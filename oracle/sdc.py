@@ -44,7 +44,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .collocation import qmatrix, smatrix, nodes, NODES_LOBATTO
+from .collocation import qmatrix, smatrix, nodes, end_weights, ends_on_node, NODES_LOBATTO
 from . import compact as _cd
 from . import periodic as _cp
 from .multigrid import SMOOTH_RBGS, vcycle, residual_inf
@@ -306,7 +306,23 @@ def sdc_step(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig,
             st.stats.status = "not_converged"
             if raise_on_failure:
                 raise NotConverged(f"residual {st.stats.residual:.3e} after {nmax} sweeps")
-    return st.U[cfg.M].copy(), st.stats
+    return sdc_result(st), st.stats
+
+
+def sdc_result(state: SDCState) -> np.ndarray:
+    """u(T_{n+1}) of the current iterate: the last node value where tau_M = 1,
+    else (Gauss-Legendre) the collocation polynomial at the end of the step,
+    u_0 + dt sum_j b_j f_j (compact stencil: u_0 + W^{-1}(dt sum_j b_j f~_j))."""
+    cfg = state.cfg
+    if ends_on_node(cfg.node_kind):
+        return state.U[cfg.M].copy()
+    b = end_weights(cfg.node_kind, cfg.M)
+    acc = np.zeros_like(state.u0)
+    for j in range(1, cfg.M + 1):
+        acc = acc + b[j - 1] * state.F[j]
+    if cfg.stencil == STENCIL_COMPACT4:
+        return state.u0 + _Compact(cfg.bc).solve_w(state.dt * acc, state.h)
+    return state.u0 + state.dt * acc
 
 
 def sdc_run(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig, nsteps: int):

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from oracle.collocation import NODES_LOBATTO as LOB, NODES_RADAU_RIGHT as RAD
+from oracle.collocation import NODES_LOBATTO as LOB, NODES_RADAU_RIGHT as RAD, NODES_LEGENDRE as LEG
 
 
 # ---- nodes: closed forms of the Gauss-Lobatto / right Gauss-Radau points ----
@@ -189,3 +189,96 @@ def test_pointwise_ode_closed_form():
     got = O.collocation_dense(u0, dt, 0.0, 0.25, O.FE_CUBIC, LOB, 5)
     expect = u0 * math.exp(dt) / np.sqrt(1 - u0 ** 2 + u0 ** 2 * math.exp(2 * dt))
     np.testing.assert_allclose(got, expect, atol=1e-11)
+
+
+# ---- Gauss-Legendre nodes: interior points, end value by the quadrature ----
+
+def test_legendre_nodes_and_weights_closed_form():
+    r3, r15 = math.sqrt(3.0), math.sqrt(15.0)
+    np.testing.assert_allclose(O.nodes(LEG, 1), [0.5], atol=1e-16)
+    np.testing.assert_allclose(O.nodes(LEG, 2), [0.5 - r3 / 6, 0.5 + r3 / 6], atol=1e-16)
+    np.testing.assert_allclose(O.nodes(LEG, 3), [0.5 - r15 / 10, 0.5, 0.5 + r15 / 10], atol=1e-16)
+    np.testing.assert_allclose(O.end_weights(LEG, 1), [1.0], atol=1e-16)
+    np.testing.assert_allclose(O.end_weights(LEG, 2), [0.5, 0.5], atol=1e-16)
+    np.testing.assert_allclose(O.end_weights(LEG, 3), [5 / 18, 4 / 9, 5 / 18], atol=1e-16)
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 7, 9])
+def test_legendre_quadrature_exact_to_degree_2m_minus_1(M):
+    # Gauss quadrature: the end weights integrate s^p over [0, 1] exactly for
+    # p <= 2M - 1, which only the roots of P_M achieve; Q still integrates
+    # degree <= M - 1 up to every node
+    tau, b, Q = O.nodes(LEG, M), O.end_weights(LEG, M), O.qmatrix(LEG, M)
+    assert np.all(tau > 0) and np.all(tau < 1) and np.all(np.diff(tau) > 0)
+    for p in range(2 * M):
+        assert abs(b @ tau ** p - 1.0 / (p + 1)) < 4e-15
+    for p in range(M):
+        np.testing.assert_allclose(Q @ tau ** p, tau ** (p + 1) / (p + 1), atol=2e-15)
+    S = O.smatrix(LEG, M)
+    np.testing.assert_allclose(np.cumsum(S, axis=0), Q, atol=3e-16)
+    assert np.all(np.abs(S[0]) > 0)  # tau_1 > 0: no degenerate first substep
+
+
+def test_end_weights_are_last_q_row_where_tau_m_is_one():
+    for kind, M in [(LOB, 3), (LOB, 6), (RAD, 2), (RAD, 5)]:
+        np.testing.assert_allclose(O.end_weights(kind, M), O.qmatrix(kind, M)[-1], atol=2e-16)
+
+
+def test_q_legendre_is_gauss_tableau():
+    r3, r15 = math.sqrt(3.0), math.sqrt(15.0)
+    np.testing.assert_allclose(O.qmatrix(LEG, 2), [[0.25, 0.25 - r3 / 6], [0.25 + r3 / 6, 0.25]], atol=2e-16)
+    ref = [[5 / 36, 2 / 9 - r15 / 15, 5 / 36 - r15 / 30],
+           [5 / 36 + r15 / 24, 2 / 9, 5 / 36 - r15 / 24],
+           [5 / 36 + r15 / 30, 2 / 9 + r15 / 15, 5 / 36]]
+    np.testing.assert_allclose(O.qmatrix(LEG, 3), ref, atol=3e-16)
+
+
+def _pade_gauss(M):
+    # diagonal (M, M) Pade approximant of e^z
+    def coef(k):
+        return math.factorial(2 * M - k) * math.factorial(M) / (math.factorial(2 * M) * math.factorial(k)
+                                                               * math.factorial(M - k))
+
+    def R(z):
+        num = sum(coef(k) * z ** k for k in range(M + 1))
+        den = sum(coef(k) * (-z) ** k for k in range(M + 1))
+        return num / den
+    return R
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
+def test_legendre_stability_function_is_diagonal_pade(M):
+    z = np.array([0.0, -0.01, -0.5, -1.0, -3.0, -10.0, -100.0, 0.3])
+    np.testing.assert_allclose(O.stability_function(z, LEG, M), _pade_gauss(M)(z), rtol=2e-14, atol=1e-15)
+    if M == 3:  # written out: (1 + z/2 + z^2/10 + z^3/120) / (1 - z/2 + z^2/10 - z^3/120)
+        zz = -2.5
+        ref = (1 + zz / 2 + zz ** 2 / 10 + zz ** 3 / 120) / (1 - zz / 2 + zz ** 2 / 10 - zz ** 3 / 120)
+        assert abs(O.stability_function(zz, LEG, 3) - ref) < 1e-15
+
+
+def test_legendre_order_2m():
+    for M, z1 in [(2, -0.2), (3, -0.6)]:
+        e1 = abs(O.stability_function(z1, LEG, M) - math.exp(z1))
+        e2 = abs(O.stability_function(z1 / 2, LEG, M) - math.exp(z1 / 2))
+        assert 2 ** (2 * M + 1) * 0.6 < e1 / e2 < 2 ** (2 * M + 1) * 1.3
+
+
+@pytest.mark.parametrize("d,n,M", [(1, 15, 3), (2, 7, 2)])
+def test_legendre_dense_collocation_equals_modal_for_heat(d, n, M):
+    rng = np.random.default_rng(12)
+    u0 = rng.standard_normal((n,) * d)
+    h = 1.0 / (n + 1)
+    dense = O.collocation_dense(u0, 0.02, 0.7, h, O.FE_ZERO, LEG, M)
+    modal = O.collocation_heat_modal(u0, 0.02, 0.7, h, LEG, M)
+    np.testing.assert_allclose(dense, modal, atol=1e-13)
+
+
+def test_legendre_pointwise_ode_order():
+    # nu = 0, u' = u - u^3 pointwise: Gauss M = 3 has order 6 at the end point
+    u0 = np.array([[0.3, -0.7], [0.9, 0.05]])
+    errs = []
+    for dt in (0.4, 0.2):
+        got = O.collocation_dense(u0, dt, 0.0, 0.25, O.FE_CUBIC, LEG, 3)
+        expect = u0 * math.exp(dt) / np.sqrt(1 - u0 ** 2 + u0 ** 2 * math.exp(2 * dt))
+        errs.append(np.max(np.abs(got - expect)))
+    assert errs[1] < 1e-7 and 2 ** 7 * 0.5 < errs[0] / errs[1] < 2 ** 7 * 1.5

@@ -195,7 +195,8 @@ def _compact_collocation(u0, dt, nu, h, kind, M):
 
 
 @pytest.mark.parametrize("inner,kind,M,prec", [("exact", LOB, 5, 0), ("mg", LOB, 3, 0), ("mg", RAD, 3, 0),
-                                                ("mg", LOB, 5, PREC_MIXED)])
+                                                ("mg", LOB, 5, PREC_MIXED), ("exact", O.NODES_LEGENDRE, 3, 0),
+                                                ("mg", O.NODES_LEGENDRE, 2, 0)])
 def test_compact_sdc_converges_to_compact_collocation(inner, kind, M, prec):
     n = 31
     x, h = _grid(n)

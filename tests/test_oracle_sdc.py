@@ -296,3 +296,47 @@ def test_exact_sdc_reproduces_table1_sdc_sweep_counts():
         if st.sweeps != printed:
             mismatches.append(((nu, M), st.sweeps, printed))
     assert mismatches == [(("1", "3"), 3, 4)]
+
+
+# ---- Gauss-Legendre nodes: the step's result is the end-point quadrature ----
+
+LEG = O.NODES_LEGENDRE
+
+
+@pytest.mark.parametrize("d,n,M,nu,dt", [(1, 63, 3, 1.0, 0.01), (2, 15, 2, 0.5, 0.01), (2, 15, 4, 1.0, 5e-3)])
+def test_legendre_exact_sdc_converges_to_collocation(d, n, M, nu, dt):
+    u0, h = _smooth_u0(n, d, 31)
+    cfg = SDCConfig(nu=nu, node_kind=LEG, M=M, inner="exact")
+    u, st = sdc_step(u0, dt, h, cfg, fixed_sweeps=40)
+    assert st.residual < 1e-12
+    assert _rel(u, O.collocation_heat_modal(u0, dt, nu, h, LEG, M)) < 1e-13
+
+
+def test_legendre_isdc_and_cubic_reach_collocation():
+    u0, h = _smooth_u0(7, 2, 32)
+    u0 = 3.0 * u0
+    cfg = SDCConfig(nu=0.2, fe_kind=O.FE_CUBIC, node_kind=LEG, M=3, inner="exact")
+    u, st = sdc_step(u0, 0.05, h, cfg, fixed_sweeps=40)
+    assert _rel(u, O.collocation_dense(u0, 0.05, 0.2, h, O.FE_CUBIC, LEG, 3)) < 1e-12
+    u0, h = _smooth_u0(31, 2, 33)
+    cfg = SDCConfig(nu=1.0, node_kind=LEG, M=3, inner="mg", vcycles=2, tol=1e-12, max_sweeps=200)
+    u, st = sdc_step(u0, 2e-3, h, cfg)
+    assert st.status == "ok"
+    assert _rel(u, O.collocation_heat_modal(u0, 2e-3, 1.0, h, LEG, 3)) < 1e-11
+
+
+def test_legendre_first_sweep_then_end_quadrature():
+    # M = 1 (implicit midpoint as collocation): one sweep solves (I - dt/2 nu L) u_1 = u_0
+    # at tau_1 = 1/2; the result is u_0 + dt nu L u_1 (weight b_1 = 1)
+    from oracle.operators import laplacian_matrix
+    n = 9
+    u0, h = _smooth_u0(n, 1, 34)
+    dt, nu = 0.02, 0.9
+    cfg = SDCConfig(nu=nu, node_kind=LEG, M=1, inner="exact")
+    u, st = sdc_step(u0, dt, h, cfg, fixed_sweeps=1)
+    Lm = laplacian_matrix(n, 1, h)
+    u1 = np.linalg.solve(np.eye(n) - 0.5 * dt * nu * Lm, u0)
+    assert np.max(np.abs(u - (u0 + dt * nu * Lm @ u1))) < 1e-13
+    # which is the Crank-Nicolson / trapezoidal value (I - dt/2 A)^{-1} (I + dt/2 A) u_0
+    cn = np.linalg.solve(np.eye(n) - 0.5 * dt * nu * Lm, u0 + 0.5 * dt * nu * Lm @ u0)
+    assert np.max(np.abs(u - cn)) < 1e-13
