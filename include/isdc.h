@@ -56,8 +56,12 @@ typedef enum {
     ISDC_E_UNSUPPORTED = -6     /* valid request this build does not implement          */
 } isdc_status;
 
-/* Collocation node families (Sec. 1; Sec. 2 after eq. (2)). Both end on tau_M = 1. */
-enum { ISDC_NODES_LOBATTO = 0, ISDC_NODES_RADAU_RIGHT = 1 };
+/* Collocation node families (Sec. 1; Sec. 2 after eq. (2)).  Gauss-Lobatto
+ * and right Gauss-Radau end on tau_M = 1, so a step's result is u_M;
+ * Gauss-Legendre nodes are all interior and a step's result is the end-point
+ * quadrature u_0 + dt sum_j b_j f(u_j) (isdc_end_weights; compact stencil:
+ * u_0 + W^{-1}(dt sum_j b_j f~_j)). */
+enum { ISDC_NODES_LOBATTO = 0, ISDC_NODES_RADAU_RIGHT = 1, ISDC_NODES_LEGENDRE = 2 };
 /* Explicit part f^E of eq. (4): zero, u - u^3, or the viscous Burgers
  * advection -(d/dx + d/dy)(u^2/2) by a fifth-order WENO scheme (Jiang-Shu
  * weights, epsilon = 1e-6, local Lax-Friedrichs flux splitting with
@@ -109,7 +113,7 @@ typedef struct {
 
 typedef struct {
     int32_t node_kind;   /* ISDC_NODES_*                                                   */
-    int32_t M;           /* collocation nodes: 2..9 (Lobatto), 1..9 (right Radau)          */
+    int32_t M;           /* collocation nodes: 2..9 (Lobatto), 1..9 (right Radau, Legendre) */
     int32_t vcycles;     /* L V-cycles per implicit solve (Sec. 3); 0 = classical SDC:     */
                          /* cycle until the inner residual <= inner_tol (at most 100)      */
     double inner_tol;    /* max-norm inner residual tolerance (classical / early exit)     */
@@ -157,6 +161,12 @@ int isdc_default_params(isdc_params* p);
  *                   node-to-node weights of eq. (2), m = 0..M-1 (may be NULL).
  * Arrays are owned by the caller (M, M*M, M*M doubles). */
 int isdc_tables(int32_t node_kind, int32_t M, double* h_tau, double* h_Q, double* h_S);
+
+/* Whole-step weights of the collocation rule (Sec. 1), host only, float64:
+ * h_b[j] = integral over [0, 1] of l_{j+1} (M doubles, caller-owned).  They
+ * give u(T_{n+1}) for Gauss-Legendre nodes; for the node families that end on
+ * tau_M = 1 they equal the last row of Q. */
+int isdc_end_weights(int32_t node_kind, int32_t M, double* h_b);
 
 /* Bytes of device workspace a plan for (prob, par) needs (256-byte aligned
  * start required).  Host only. */

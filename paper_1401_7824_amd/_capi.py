@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libisdc.so"
 OK, E_INVAL, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_DIVERGED, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {OK: "ok", E_INVAL: "invalid", E_WORKSPACE: "workspace", E_HIP: "hip",
                 E_NOT_CONVERGED: "not_converged", E_DIVERGED: "diverged", E_UNSUPPORTED: "unsupported"}
-NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
+NODES_LOBATTO, NODES_RADAU_RIGHT, NODES_LEGENDRE = 0, 1, 2
 FE_ZERO, FE_CUBIC, FE_BURGERS = 0, 1, 2
 STENCIL_2ND, STENCIL_COMPACT4 = 0, 1
 BC_DIRICHLET, BC_PERIODIC = 0, 1
@@ -53,6 +53,7 @@ SIGNATURES = [
     ("isdc_last_error", C.c_char_p, []),
     ("isdc_default_params", C.c_int, [C.POINTER(Params)]),
     ("isdc_tables", C.c_int, [C.c_int32, C.c_int32, _DP, _DP, _DP]),
+    ("isdc_end_weights", C.c_int, [C.c_int32, C.c_int32, _DP]),
     ("isdc_workspace_bytes", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _SZP]),
     ("isdc_create", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)]),
     ("isdc_destroy", None, [_VP]),

@@ -356,6 +356,8 @@ void check_batch_params(const isdc_batch* b, const isdc_problem* pb, const isdc_
     if (pb->dim != b->d) fail(ISDC_E_INVAL, "slot dimension differs from the batch's");
     if (pb->stencil != ISDC_STENCIL_2ND) fail(ISDC_E_UNSUPPORTED, "batches run the second-order stencil only");
     if (pb->bc != ISDC_BC_DIRICHLET) fail(ISDC_E_UNSUPPORTED, "batches run Dirichlet problems only");
+    if (pr->node_kind == ISDC_NODES_LEGENDRE)
+        fail(ISDC_E_UNSUPPORTED, "batches run node families that end on tau_M = 1 only");
     if (pr->precision != b->prec) fail(ISDC_E_INVAL, "slot precision differs from the batch's");
     if (pr->vcycles != b->L) fail(ISDC_E_INVAL, "slot vcycles differs from the batch's");
     if (pr->smoother != ISDC_SMOOTH_RBGS || pr->nu_pre != 1 || pr->nu_post != 1)

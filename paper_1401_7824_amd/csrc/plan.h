@@ -68,6 +68,9 @@ struct isdc_plan {
     int M;
     double tau[ISDC_MAX_M], Q[ISDC_MAX_M * ISDC_MAX_M], S[ISDC_MAX_M * ISDC_MAX_M];
     double dtau[ISDC_MAX_M];  // tau_{m+1} - tau_m, tau_0 = 0
+    double b[ISDC_MAX_M];     // whole-step weights (end value of Gauss-Legendre steps)
+    bool end_quad = false;    // Gauss-Legendre: u_{n+1} by the end-point quadrature
+    double* END = nullptr;    // dt sum_j b_j f_j of the final iterate (end_quad only)
     isdc::MGConfig mg;
     std::vector<isdc::Level> lev;
     int tail;  // index of the level run by the single-workgroup tail kernel

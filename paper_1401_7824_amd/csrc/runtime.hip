@@ -51,6 +51,8 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
         if (pr->M < 2 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "Gauss-Lobatto needs 2 <= M <= 9");
     } else if (pr->node_kind == ISDC_NODES_RADAU_RIGHT) {
         if (pr->M < 1 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "right Gauss-Radau needs 1 <= M <= 9");
+    } else if (pr->node_kind == ISDC_NODES_LEGENDRE) {
+        if (pr->M < 1 || pr->M > ISDC_MAX_M) fail(ISDC_E_INVAL, "Gauss-Legendre needs 1 <= M <= 9");
     } else {
         fail(ISDC_E_INVAL, "unknown node_kind");
     }
@@ -167,6 +169,8 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
         const size_t rows = (size_t)pb.n * ((pb.n + 255) / 256);  // residual-norm blocks of the finest level
         nparts = std::max(nparts, std::max(rows, (size_t)kCResBlocks * M));
     }
+    void* endq = pr.node_kind == ISDC_NODES_LEGENDRE ? take(N * sizeof(double)) : nullptr;
+    if (p) p->END = (double*)endq;
     void* part = take(nparts * sizeof(double));
     void* sc = take(16 * sizeof(double));
     if (p) {
@@ -406,6 +410,14 @@ void cquad(isdc_plan* p, const double* const* nodes, const double* const* fe, hi
 // inverted once per node), after cquad of the same node values.  W = I + w L:
 // Dirichlet plans invert it with red-black V(1,1) cycles of the second-order
 // solver (c = -w); periodic plans with the compact Jacobi cycle at c = 0.
+// One cycle of the W solve W x = y (from zero if `zero`).
+void wsolve_cycle(isdc_plan* p, bool zero, const double* y, double* x, hipStream_t s) {
+    if (p->periodic)
+        cvcycle_rec<double>(p, p->wmg, 0, 0.0, zero, y, x, (double*)p->lev[0].e2, s);
+    else
+        vcycle_rec<double>(p, p->wmg, 0, -p->w, zero, y, x, (double*)p->lev[0].e2, s);
+}
+
 double cresidual(isdc_plan* p, hipStream_t s) {
     CResArgs ra;
     std::memset(&ra, 0, sizeof(ra));
@@ -414,13 +426,7 @@ double cresidual(isdc_plan* p, hipStream_t s) {
     const int ncyc = p->x_valid ? kWWarmCycles : kWColdCycles;
     for (int m = 0; m < p->M; ++m) {
         if (!p->Yq[m]) continue;
-        for (int k = 0; k < ncyc; ++k) {
-            const bool zero = !p->x_valid && k == 0;
-            if (p->periodic)
-                cvcycle_rec<double>(p, p->wmg, 0, 0.0, zero, p->Yq[m], p->X[m], (double*)p->lev[0].e2, s);
-            else
-                vcycle_rec<double>(p, p->wmg, 0, -p->w, zero, p->Yq[m], p->X[m], (double*)p->lev[0].e2, s);
-        }
+        for (int k = 0; k < ncyc; ++k) wsolve_cycle(p, !p->x_valid && k == 0, p->Yq[m], p->X[m], s);
         ra.um[ra.count] = p->cur[m + 1];
         ra.xm[ra.count] = p->X[m];
         ++ra.count;
@@ -551,11 +557,54 @@ double sweep_any(isdc_plan* p, hipStream_t s) {
     return p->par.precision == ISDC_PREC_MIXED ? sweep_impl<float>(p, s) : sweep_impl<double>(p, s);
 }
 
+// Gauss-Legendre steps end between the last node and T_{n+1}: the result is
+// u_0 + dt sum_j b_j f(u_j) (Sec. 1), formed by the quadrature kernel with the
+// weights b as its only row; the compact stencil keeps W f~, so W^{-1} is
+// applied first (cold W cycles, as for the residual of a step's first sweep).
+void end_quadrature(isdc_plan* p, double* d_out, hipStream_t s) {
+    const double* add = p->END;
+    if (p->compact) {
+        CQuadArgs a;
+        std::memset(&a, 0, sizeof(a));
+        for (int j = 0; j <= p->M; ++j) {
+            a.u[j] = p->cur[j];
+            a.feu[j] = p->fe_arrays ? p->curfe[j] : nullptr;
+        }
+        a.sf[0] = p->END;
+        for (int j = 0; j < p->M; ++j) a.dtS[j] = p->dt * p->b[j];
+        a.nu_6h2 = p->prob.nu / (6.0 * p->h * p->h);
+        a.n = p->n;
+        a.fe = p->prob.fe_kind;
+        a.M = p->M;
+        HIPCHK(launch_cquad(a, p->M, p->periodic, s));
+        double* x = (double*)p->lev[0].e;
+        for (int k = 0; k < kWColdCycles; ++k) wsolve_cycle(p, k == 0, p->END, x, s);
+        add = x;
+    } else {
+        QuadArgs qa;
+        std::memset(&qa, 0, sizeof(qa));
+        for (int j = 0; j <= p->M; ++j) qa.u[j] = p->cur[j];
+        qa.sf[0] = p->END;
+        for (int j = 0; j < p->M; ++j) qa.dtS[j] = p->dt * p->b[j];
+        qa.nu_h2 = p->prob.nu / (p->h * p->h);
+        qa.M = p->M;
+        qa.n = p->n;
+        qa.fe = p->prob.fe_kind;
+        int nb = 0;  // the kernel's residual output is not used here
+        HIPCHK(launch_quad_residual(p->d, qa, p->partial, &nb, s));
+    }
+    HIPCHK(launch_node_update<double>(p->N, ISDC_GUESS_PREV_SWEEP, p->u0, p->u0, add, d_out, s));
+}
+
 void end_impl(isdc_plan* p, double* d_out, hipStream_t s) {
     if (!p->begun) fail(ISDC_E_INVAL, "isdc_end before isdc_begin");
     if (!d_out) fail(ISDC_E_INVAL, "d_u_out is NULL");
-    const double* src = p->cur[p->M];
-    if (src != d_out) HIPCHK(hipMemcpyAsync(d_out, src, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (p->end_quad) {
+        end_quadrature(p, d_out, s);
+    } else {
+        const double* src = p->cur[p->M];
+        if (src != d_out) HIPCHK(hipMemcpyAsync(d_out, src, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     p->begun = false;
 }
 
@@ -575,7 +624,8 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->periodic = prob->bc == ISDC_BC_PERIODIC;
     p->h = p->periodic ? 2.0 / prob->n : 1.0 / (prob->n + 1);
     p->M = par->M;
-    tables(par->node_kind, par->M, p->tau, p->Q, p->S);
+    tables(par->node_kind, par->M, p->tau, p->Q, p->S, p->b);
+    p->end_quad = par->node_kind == ISDC_NODES_LEGENDRE;
     double prev = 0.0;
     for (int m = 0; m < p->M; ++m) {
         p->dtau[m] = p->tau[m] - prev;
@@ -638,6 +688,13 @@ int isdc_default_params(isdc_params* p) {
 int isdc_tables(int32_t node_kind, int32_t M, double* h_tau, double* h_Q, double* h_S) {
     return guarded([&] {
         if (!tables(node_kind, M, h_tau, h_Q, h_S)) fail(ISDC_E_INVAL, "invalid node_kind or M");
+    });
+}
+
+int isdc_end_weights(int32_t node_kind, int32_t M, double* h_b) {
+    return guarded([&] {
+        if (!h_b) fail(ISDC_E_INVAL, "h_b is NULL");
+        if (!tables(node_kind, M, nullptr, nullptr, nullptr, h_b)) fail(ISDC_E_INVAL, "invalid node_kind or M");
     });
 }
 

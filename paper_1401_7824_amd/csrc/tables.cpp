@@ -4,6 +4,9 @@
 // unit step, the cumulative matrix Q (integrals of the Lagrange polynomials
 // from 0 to each node) and the node-to-node matrix S of eq. (2).
 //
+// Gauss-Legendre nodes are all interior, so the end value of a step needs the
+// rule's quadrature weights b_j = integral over [0, 1] of l_j as well.
+//
 // Method (independent of any other implementation in this repository):
 //   * nodes by Newton's method on Legendre polynomials evaluated with the
 //     three-term recurrence, in long double, from Chebyshev-type starting
@@ -67,6 +70,14 @@ ld radau_g(int M, ld x, ld* dg) {
     return p1 - p0;
 }
 
+// g(x) = P_M(x).
+ld gauss_g(int M, ld x, ld* dg) {
+    ld p, dp;
+    legendre(M, x, &p, &dp);
+    *dg = dp;
+    return p;
+}
+
 }  // namespace
 
 static bool nodes_ld(int kind, int M, std::vector<ld>& tau) {
@@ -85,6 +96,10 @@ static bool nodes_ld(int kind, int M, std::vector<ld>& tau) {
         // starting values are the Chebyshev-Radau points cos(2 pi i / (2M - 1))
         for (int i = M - 1; i >= 1; --i) x.push_back(newton(std::cos(2.0L * pi * i / (2 * M - 1)), radau_g, M));
         x.push_back(1.0L);
+    } else if (kind == ISDC_NODES_LEGENDRE) {
+        if (M < 1 || M > ISDC_MAX_M) return false;
+        // roots of P_M from the asymptotic starting values cos(pi (i - 1/4) / (M + 1/2))
+        for (int i = 1; i <= M; ++i) x.push_back(newton(std::cos(pi * (i - 0.25L) / (M + 0.5L)), gauss_g, M));
     } else {
         return false;
     }
@@ -94,11 +109,11 @@ static bool nodes_ld(int kind, int M, std::vector<ld>& tau) {
     tau.resize(x.size());
     for (size_t i = 0; i < x.size(); ++i) tau[i] = (1.0L + x[i]) / 2.0L;
     if (kind == ISDC_NODES_LOBATTO) tau.front() = 0.0L;
-    tau.back() = 1.0L;
+    if (kind != ISDC_NODES_LEGENDRE) tau.back() = 1.0L;
     return true;
 }
 
-bool tables(int kind, int M, double* tau_out, double* Q_out, double* S_out) {
+bool tables(int kind, int M, double* tau_out, double* Q_out, double* S_out, double* b_out) {
     std::vector<ld> tau;
     if (!nodes_ld(kind, M, tau)) return false;
     std::vector<ld> Q((size_t)M * M);
@@ -120,6 +135,11 @@ bool tables(int kind, int M, double* tau_out, double* Q_out, double* S_out) {
             ld acc = 0.0L;
             for (int k = M - 1; k >= 0; --k) acc = acc * tau[m] + coef[k] / (k + 1);
             Q[(size_t)m * M + j] = acc * tau[m];
+        }
+        if (b_out) {  // integral over the whole step [0, 1]
+            ld acc = 0.0L;
+            for (int k = M - 1; k >= 0; --k) acc += coef[k] / (k + 1);
+            b_out[j] = (double)acc;
         }
     }
     for (int m = 0; m < M; ++m) {

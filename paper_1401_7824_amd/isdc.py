@@ -71,6 +71,14 @@ def tables(node_kind: int, M: int):
     return list(tau), [list(Q[i * M:(i + 1) * M]) for i in range(M)], [list(S[i * M:(i + 1) * M]) for i in range(M)]
 
 
+def end_weights(node_kind: int, M: int):
+    """Whole-step weights b_j (integral of l_j over [0, 1]) from the library, as a list."""
+    lib = A.load()
+    b = (C.c_double * M)()
+    A.check(lib.isdc_end_weights(node_kind, M, b))
+    return list(b)
+
+
 def workspace_bytes(problem: A.Problem, params: A.Params) -> int:
     lib = A.load()
     out = C.c_size_t()

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-NODES_LOBATTO, NODES_RADAU_RIGHT = 0, 1
+NODES_LOBATTO, NODES_RADAU_RIGHT, NODES_LEGENDRE = 0, 1, 2
 FE_ZERO, FE_CUBIC, FE_BURGERS = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 

@@ -38,15 +38,17 @@ def test_struct_sizes_match():
     assert [x.value for x in s] == [C.sizeof(A.Problem), C.sizeof(A.Params), C.sizeof(A.Stats)]
 
 
-@pytest.mark.parametrize("kind,Ms", [(A.NODES_LOBATTO, range(2, 10)), (A.NODES_RADAU_RIGHT, range(1, 10))])
+@pytest.mark.parametrize("kind,Ms", [(A.NODES_LOBATTO, range(2, 10)), (A.NODES_RADAU_RIGHT, range(1, 10)),
+                                     (A.NODES_LEGENDRE, range(1, 10))])
 def test_tables_match_oracle(kind, Ms):
-    from paper_1401_7824_amd.isdc import tables
+    from paper_1401_7824_amd.isdc import tables, end_weights
     for M in Ms:
         tau, Q, S = (np.array(v) for v in tables(kind, M))
         tol = 1e-15 if M <= 7 else 2e-15
         np.testing.assert_allclose(tau, O.nodes(kind, M), atol=1e-16, rtol=0)
         np.testing.assert_allclose(Q, O.qmatrix(kind, M), atol=tol, rtol=0)
         np.testing.assert_allclose(S, O.smatrix(kind, M), atol=tol, rtol=0)
+        np.testing.assert_allclose(np.array(end_weights(kind, M)), O.end_weights(kind, M), atol=tol, rtol=0)
 
 
 def test_tables_reject_bad_arguments():
@@ -57,6 +59,11 @@ def test_tables_reject_bad_arguments():
     assert lib.isdc_tables(A.NODES_LOBATTO, 10, buf, buf, buf) == A.E_INVAL
     assert lib.isdc_tables(7, 3, buf, buf, buf) == A.E_INVAL
     assert b"node_kind" in lib.isdc_last_error()
+    assert lib.isdc_tables(A.NODES_LEGENDRE, 0, buf, buf, buf) == A.E_INVAL
+    assert lib.isdc_tables(A.NODES_LEGENDRE, 10, buf, buf, buf) == A.E_INVAL
+    assert lib.isdc_end_weights(A.NODES_LEGENDRE, 10, buf) == A.E_INVAL
+    assert lib.isdc_end_weights(A.NODES_LEGENDRE, 3, None) == A.E_INVAL
+    assert lib.isdc_end_weights(A.NODES_LEGENDRE, 3, buf) == A.OK
 
 
 def _params(**kw):
