@@ -25,6 +25,8 @@ Module map (each function cites the passage it follows):
 * ``periodic`` -- periodic grids on [-1, 1)^d, the periodic compact stencil,
   its Fourier solves and multigrid, and the WENO5 advection of viscous
   Burgers (Sec. 4.1).
+* ``mlsdc`` -- two-level MLSDC with ISDC sweeps: a spatially coarsened
+  level tied to the fine one by an FAS term (Sec. 5).
 * ``sdc`` -- the semi-implicit SDC sweep of eq. (4) (and of eq. (5) for the
   compact stencil) with exact, classical (solve to tolerance) and inexact
   (L V-cycles) inner solves, the SDC residual of Sec. 3, and the time step.

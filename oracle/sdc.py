@@ -230,8 +230,13 @@ def _inner_solve(rhs, guess, c, h, cfg):
     return guess + e.astype(np.float64), ncyc
 
 
-def sdc_sweep(state: SDCState) -> float:
-    """One sweep of eq. (4) over all substeps; returns the new SDC residual."""
+def sdc_sweep(state: SDCState, fas: list | None = None) -> float:
+    """One sweep of eq. (4) over all substeps; returns the new SDC residual.
+
+    ``fas`` (multi-level use, see mlsdc.py): per node m = 1..M (index 0
+    unused) a term tau_m added to the collocation equations of this level,
+    U_m = u_0 + dt sum_j q_{m,j} f(U_j) + tau_m; the node-to-node form of the
+    sweep then carries tau_{m+1} - tau_m (tau_0 = 0) next to S_m^{m+1} F."""
     cfg = state.cfg
     dt, h, M = state.dt, state.h, cfg.M
     tau_ext = np.concatenate([[0.0], state.tau])
@@ -241,7 +246,10 @@ def sdc_sweep(state: SDCState) -> float:
         acc = np.zeros_like(state.u0)
         for j in range(1, M + 1):
             acc = acc + state.S[m, j - 1] * state.F[j]
-        SF.append(dt * acc)
+        sf = dt * acc
+        if fas is not None:
+            sf = sf + fas[m + 1] - (fas[m] if m > 0 else 0.0)
+        SF.append(sf)
     Uold = [u for u in state.U]
     Unew = [None] * (M + 1)
     Fnew = [None] * (M + 1)
