@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "heat3d", "heat1d", "burgers2d", "batch", "serve", "table1",
+    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "rd2d_mlsdc", "heat3d", "heat1d", "burgers2d", "batch", "serve", "table1",
                              "table1b", "kernels"])
     ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
@@ -72,7 +72,7 @@ def coarser(cfg, m):
 def make_plan(cfg):
     from paper_1401_7824_amd import Plan
     return Plan(cfg["dim"], cfg["n"], cfg["nu"], cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"],
-                precision=cfg["precision"], sdc_tol=cfg["sdc_tol"], **mg_params(cfg))
+                precision=cfg["precision"], sdc_tol=cfg["sdc_tol"], levels=cfg.get("levels", 1), **mg_params(cfg))
 
 
 def time_steps(plan, u, dt, steps, warmup, torch):
@@ -244,6 +244,7 @@ def cpu_baseline(cfg, sweeps_per_step):
     import numpy as np
     import oracle as O  # noqa: F401  (test infrastructure: the CPU baseline only)
     from oracle.sdc import SDCConfig, sdc_begin, sdc_sweep
+    from oracle.mlsdc import MLSDCStats, mlsdc_iteration
     from paper_1401_7824_amd import workloads as W
     c = dict(cfg)
     scale = 1.0
@@ -258,9 +259,13 @@ def cpu_baseline(cfg, sweeps_per_step):
     h = grid_h(c)
     t0 = time.perf_counter()
     st = sdc_begin(u0, c["dt"], h, sc)
+    ml = MLSDCStats() if c.get("levels", 1) == 2 else None
     nsw = 0
     while True:
-        sdc_sweep(st)
+        if ml is not None:
+            mlsdc_iteration(st, ml)  # one two-level iteration counts as one sweep
+        else:
+            sdc_sweep(st)
         nsw += 1
         el = time.perf_counter() - t0
         if el > 10.0 or nsw >= sweeps_per_step:
@@ -686,8 +691,11 @@ def main():
                                f"dt={cfg['dt']} L=2 "
                                + ("compact 4th-order stencil with W, Jacobi "
                                   f"V({cfg.get('nu_pre')},{cfg.get('nu_post')})" if cfg.get("stencil", 0) == 1
-                                  else "RBGS V(1,1)") + f" tol={cfg['sdc_tol']}",
+                                  else "RBGS V(1,1)") + f" tol={cfg['sdc_tol']}"
+                               + (" two-level MLSDC (511^2 coarse level, FAS, cubic interpolation)"
+                                  if cfg.get("levels", 1) == 2 else ""),
                    "sweeps_per_step": sweeps, "vcycles_per_step": vcyc,
+                   "coarse_vcycles_per_step": sum(s.coarse_vcycles for s in stats) / len(stats),
                    "host_wall_s": round(wall, 4)},
         "roofline": roof,
         "vcycle": vc,

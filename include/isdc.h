@@ -125,6 +125,10 @@ typedef struct {
     int32_t nu_post;     /* post-smoothing steps (0..8), nu_pre + nu_post >= 1             */
     int32_t precision;   /* ISDC_PREC_*                                                    */
     int32_t guess;       /* ISDC_GUESS_*                                                   */
+    int32_t levels;      /* 1: ISDC (default); 2: two-level MLSDC with ISDC sweeps (Sec. 5):  */
+                         /* each iteration is a fine sweep, one sweep on the (n-1)/2 grid   */
+                         /* with the FAS term, and the coarse correction interpolated back  */
+                         /* (second-order stencil, Dirichlet, n >= 3, not in batches)       */
 } isdc_params;
 
 typedef struct {
@@ -133,6 +137,7 @@ typedef struct {
     int64_t vcycles;                   /* V-cycles over all implicit solves of the step   */
     double residual;                   /* last SDC residual                               */
     double residual_hist[ISDC_HIST];   /* residual after sweep 1, 2, ... (first 128)      */
+    int64_t coarse_vcycles;            /* V-cycles of the coarse MLSDC level (levels = 2) */
 } isdc_stats;
 
 typedef struct isdc_plan isdc_plan;
@@ -150,7 +155,7 @@ const char* isdc_last_error(void);
 
 /* Fill *p with the defaults: Lobatto, M = 3, L = 2, inner_tol = 1e-10,
  * early_exit = 0, sdc_tol = 1e-10, max_sweeps = 100, RB-GS V(1,1), FP64,
- * warm start from the previous sweep.  Host only. */
+ * warm start from the previous sweep, one level.  Host only. */
 int isdc_default_params(isdc_params* p);
 
 /* Collocation tables (Sec. 2, eq. (1)-(2)), host only, float64:
@@ -193,9 +198,9 @@ int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats*
 /* The pieces of isdc_step, for callers that drive sweeps themselves:
  * isdc_begin sets the initial iterate u_j^0 = u_0 at every node and computes
  * S*F(u^0).  d_u0 must stay valid and unchanged until isdc_end.
- * isdc_sweep makes one sweep of eq. (4) and writes the new SDC residual to
- * *h_residual (synchronises `stream`).  isdc_end copies u_M to d_u_out (which
- * may be d_u0). */
+ * isdc_sweep makes one sweep of eq. (4) (with levels = 2: one MLSDC
+ * iteration) and writes the new SDC residual to *h_residual (synchronises
+ * `stream`).  isdc_end copies u_M to d_u_out (which may be d_u0). */
 int isdc_begin(isdc_plan* plan, const double* d_u0, double dt, void* stream);
 int isdc_sweep(isdc_plan* plan, void* stream, double* h_residual);
 int isdc_end(isdc_plan* plan, double* d_u_out, void* stream);

@@ -37,12 +37,12 @@ class Params(C.Structure):
     _fields_ = [("node_kind", C.c_int32), ("M", C.c_int32), ("vcycles", C.c_int32),
                 ("inner_tol", C.c_double), ("early_exit", C.c_int32), ("sdc_tol", C.c_double),
                 ("max_sweeps", C.c_int32), ("smoother", C.c_int32), ("nu_pre", C.c_int32),
-                ("nu_post", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32)]
+                ("nu_post", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32), ("levels", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("hist_len", C.c_int32), ("vcycles", C.c_int64),
-                ("residual", C.c_double), ("residual_hist", C.c_double * HIST)]
+                ("residual", C.c_double), ("residual_hist", C.c_double * HIST), ("coarse_vcycles", C.c_int64)]
 
 
 # (name, restype, argtypes) for every function declared in include/isdc.h

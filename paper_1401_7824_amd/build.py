@@ -17,7 +17,8 @@ INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libisdc.so")
 
-HIP_SOURCES = ["mg_kernels.hip", "mg_tiles.hip", "sdc_kernels.hip", "compact.hip", "runtime.hip", "batch.hip"]
+HIP_SOURCES = ["mg_kernels.hip", "mg_tiles.hip", "sdc_kernels.hip", "compact.hip", "mlsdc.hip", "runtime.hip",
+               "batch.hip"]
 CXX_SOURCES = ["tables.cpp"]
 
 ARCH = "gfx950"

@@ -364,6 +364,7 @@ void check_batch_params(const isdc_batch* b, const isdc_problem* pb, const isdc_
         fail(ISDC_E_UNSUPPORTED, "batches run red-black Gauss-Seidel V(1,1) cycles only");
     if (pr->guess != ISDC_GUESS_PREV_SWEEP) fail(ISDC_E_UNSUPPORTED, "batches warm-start from the previous sweep only");
     if (pr->early_exit) fail(ISDC_E_UNSUPPORTED, "batches run exactly L cycles per solve");
+    if (pr->levels != 1) fail(ISDC_E_UNSUPPORTED, "batches run single-level ISDC only");
 }
 
 void build_desc(isdc_batch* b, int slot) {

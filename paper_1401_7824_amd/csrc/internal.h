@@ -145,6 +145,13 @@ template <typename T>
 hipError_t launch_node_update(size_t N, int guess, const double* up_old, const double* um_new,
                               const T* e, double* u_out, hipStream_t s);
 
+// ---------------------------------------------------------------- two-level MLSDC (mlsdc.hip)
+// coarse[I] = fine[2I+1] per axis (fine n = 2^k - 1 points, coarse (n-1)/2).
+hipError_t launch_inject(int d, int n, const double* fine, double* coarse, hipStream_t s);
+// u += cubic interpolation of (coarse_new - coarse_old) onto the fine grid of n points.
+hipError_t launch_cubic_correct(int d, int n, const double* coarse_new, const double* coarse_old, double* u,
+                                hipStream_t s);
+
 // ---------------------------------------------------------------- compact stencil (2D, compact.hip)
 // B_H = I + w L_H - c A_H on a level of spacing H: centre b0, the 4 edge
 // neighbours bf, the 4 corners bc; omega of the weighted-Jacobi smoother.

@@ -94,6 +94,13 @@ struct isdc_plan {
     double* FE0 = nullptr;
     double* FEU[2][ISDC_MAX_M + 1];  // f^E(U[w][j]) (NULL where U[w][j] is)
 
+    // two-level MLSDC (levels = 2): coarse node values R U_j (index 0: R u_0),
+    // the coarse sweep's new values, and the injected S F of the fine level
+    int levels = 1;
+    double* Rf[ISDC_MAX_M + 1];
+    double* Uc[ISDC_MAX_M + 1];
+    double* SFc[ISDC_MAX_M];
+
     // step state
     const double* u0 = nullptr;
     double dt = 0.0;

@@ -74,6 +74,12 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
         if (pr->guess != ISDC_GUESS_PREV_SWEEP)
             fail(ISDC_E_UNSUPPORTED, "the compact stencil warm-starts from the previous sweep only");
     }
+    if (pr->levels != 1 && pr->levels != 2) fail(ISDC_E_INVAL, "levels must be 1 or 2");
+    if (pr->levels == 2) {
+        if (pb->stencil != ISDC_STENCIL_2ND || pb->bc != ISDC_BC_DIRICHLET)
+            fail(ISDC_E_UNSUPPORTED, "two-level MLSDC runs the second-order stencil with Dirichlet boundaries");
+        if (pb->n < 3) fail(ISDC_E_INVAL, "two-level MLSDC needs n >= 3 to coarsen");
+    }
     if (pb->bc == ISDC_BC_PERIODIC && pb->stencil != ISDC_STENCIL_COMPACT4)
         fail(ISDC_E_UNSUPPORTED, "periodic boundaries are implemented with the compact stencil only");
     if (pb->fe_kind == ISDC_FE_BURGERS && pb->bc != ISDC_BC_PERIODIC)
@@ -153,6 +159,16 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
         h *= 2.0;
         ++l;
     }
+    if (pr.levels == 2 && l == 0) {
+        // the fine grid is small enough for the tail: the coarse MLSDC level
+        // still needs arrays of its own, solved by the tail as well
+        n = (n - 1) / 2;
+        h *= 2.0;
+        Level C{n, h, pow_d((size_t)n, d), nullptr, nullptr, nullptr};
+        C.r = take(C.N * sizeof(double));
+        C.e = take(C.N * sizeof(double));
+        if (p) p->lev.push_back(C);
+    }
     const bool compact = pb.stencil == ISDC_STENCIL_COMPACT4;
     if (compact)
         for (int m = 0; m < M; ++m) {
@@ -168,6 +184,22 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
     if (compact) {
         const size_t rows = (size_t)pb.n * ((pb.n + 255) / 256);  // residual-norm blocks of the finest level
         nparts = std::max(nparts, std::max(rows, (size_t)kCResBlocks * M));
+    }
+    if (pr.levels == 2) {  // coarse MLSDC level: R U_j, the coarse sweep's values, injected S F
+        const size_t Nc = pow_d((size_t)((pb.n - 1) / 2), d);
+        const bool lob = pr.node_kind == ISDC_NODES_LOBATTO;  // node 1 is u_0 on both levels
+        for (int j = 0; j <= M; ++j) {
+            void* r = (j == 1 && lob) ? nullptr : take(Nc * sizeof(double));
+            void* u = (j == 0 || (j == 1 && lob)) ? nullptr : take(Nc * sizeof(double));
+            if (p) {
+                p->Rf[j] = r ? (double*)r : p->Rf[0];
+                p->Uc[j] = u ? (double*)u : p->Rf[0];
+            }
+        }
+        for (int m = 0; m < M; ++m) {
+            void* sfc = (m == 0 && lob) ? nullptr : take(Nc * sizeof(double));
+            if (p) p->SFc[m] = (double*)sfc;
+        }
     }
     void* endq = pr.node_kind == ISDC_NODES_LEGENDRE ? take(N * sizeof(double)) : nullptr;
     if (p) p->END = (double*)endq;
@@ -229,7 +261,7 @@ template <typename T>
 bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s,
                 const Fuse& fuse = Fuse()) {
     const Level& L = p->lev[l];
-    if (l == p->tail) {
+    if (l >= p->tail) {  // (beyond the tail only the coarse MLSDC level, solved the same way)
         HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
         return false;
     }
@@ -472,8 +504,10 @@ int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
     return k;
 }
 
+// The node loop of one sweep (eq. (4) / eq. (5)); afterwards cur[] holds the
+// new iterate.  The quadrature of the new values is left to the caller.
 template <typename T>
-double sweep_impl(isdc_plan* p, hipStream_t s) {
+void sweep_nodes(isdc_plan* p, hipStream_t s) {
     const int M = p->M;
     double* const* W = p->U[p->wbuf];
     const double* nw[ISDC_MAX_M + 1];
@@ -517,6 +551,73 @@ double sweep_impl(isdc_plan* p, hipStream_t s) {
         p->curfe[j] = nfe[j];
     }
     p->wbuf ^= 1;
+}
+
+// The implicit solve of one coarse MLSDC substep: r in lev[1].r, the
+// correction in lev[1].e; same modes as inner_solve.
+template <typename T>
+int coarse_solve(isdc_plan* p, double c, hipStream_t s) {
+    const Level& L1 = p->lev[1];
+    T* r1 = (T*)L1.r;
+    T* e1 = (T*)L1.e;
+    T* t1 = (T*)L1.e2;  // unused when level 1 is the single-workgroup tail
+    const isdc_params& pr = p->par;
+    const bool classical = pr.vcycles == 0;
+    const bool check = classical || pr.early_exit;
+    const int limit = classical ? 100 : pr.vcycles;
+    int k = 0;
+    if (!check) {
+        for (; k < limit; ++k) vcycle_rec<T>(p, p->mg, 1, c, k == 0, r1, e1, t1, s);
+        if (k == 0) HIPCHK(launch_fill<T>(e1, L1.N, T(0), s));
+    } else {
+        HIPCHK(launch_fill<T>(e1, L1.N, T(0), s));
+        for (; k < limit; ++k) {
+            if (resnorm<T>(p, 1, c, r1, e1, s) <= pr.inner_tol) break;
+            vcycle_rec<T>(p, p->mg, 1, c, false, r1, e1, t1, s);
+        }
+    }
+    return k;
+}
+
+// One two-level MLSDC iteration (Sec. 5): the fine sweep, injection of the
+// node values and of S F to the (n-1)/2 grid, one coarse sweep, the coarse
+// correction added back by cubic interpolation.  The coarse sweep's FAS term
+// is not formed on its own: with tau_m = R(dt Q_m F_h) - dt Q_m F_2h(R U) the
+// node-to-node sum of the coarse sweep, S_m F_2h(R U) + tau_{m+1} - tau_m,
+// equals R(S_m F_h) exactly, and that is what the fine quadrature already
+// wrote; the sweep's other terms use coarse values and the coarse operator.
+template <typename T>
+void mlsdc_iteration(isdc_plan* p, hipStream_t s) {
+    const int M = p->M, d = p->d, n = p->n;
+    sweep_nodes<T>(p, s);
+    quad_residual(p, p->cur, s);  // S F of the new fine iterate (its residual is not used)
+    for (int j = 0; j <= M; ++j)
+        if (j == 0 || p->Rf[j] != p->Rf[0]) HIPCHK(launch_inject(d, n, p->cur[j], p->Rf[j], s));
+    for (int m = 0; m < M; ++m)
+        if (p->SFc[m]) HIPCHK(launch_inject(d, n, p->SF[m], p->SFc[m], s));
+    const Level& L1 = p->lev[1];
+    const double nu_h2c = p->prob.nu / (L1.h * L1.h);
+    for (int m = 0; m < M; ++m) {
+        if (p->dtau[m] == 0.0) continue;  // Lobatto: coarse node 1 is R u_0
+        const double dtm = p->dt * p->dtau[m];
+        const double* um_new = m == 0 ? p->Rf[0] : p->Uc[m];
+        RhsArgs ra{um_new, p->Rf[m], p->Rf[m + 1], p->SFc[m], dtm, dtm * p->prob.nu, nu_h2c, L1.n,
+                   p->prob.fe_kind, ISDC_GUESS_PREV_SWEEP};
+        HIPCHK(launch_euler_rhs<T>(d, ra, (T*)L1.r, s));
+        p->stats.coarse_vcycles += coarse_solve<T>(p, dtm * p->prob.nu, s);
+        HIPCHK(launch_node_update<T>(L1.N, ISDC_GUESS_PREV_SWEEP, p->Rf[m + 1], p->Rf[m + 1], (const T*)L1.e,
+                                     p->Uc[m + 1], s));
+    }
+    for (int j = 1; j <= M; ++j)
+        if (p->cur[j] != p->u0) HIPCHK(launch_cubic_correct(d, n, p->Uc[j], p->Rf[j], (double*)p->cur[j], s));
+}
+
+template <typename T>
+double sweep_impl(isdc_plan* p, hipStream_t s) {
+    if (p->levels == 2)
+        mlsdc_iteration<T>(p, s);
+    else
+        sweep_nodes<T>(p, s);
     double res;
     if (p->compact) {
         cquad(p, p->cur, p->curfe, s);
@@ -626,6 +727,10 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->M = par->M;
     tables(par->node_kind, par->M, p->tau, p->Q, p->S, p->b);
     p->end_quad = par->node_kind == ISDC_NODES_LEGENDRE;
+    p->levels = par->levels;
+    std::memset(p->Rf, 0, sizeof(p->Rf));
+    std::memset(p->Uc, 0, sizeof(p->Uc));
+    std::memset(p->SFc, 0, sizeof(p->SFc));
     double prev = 0.0;
     for (int m = 0; m < p->M; ++m) {
         p->dtau[m] = p->tau[m] - prev;
@@ -682,6 +787,7 @@ int isdc_default_params(isdc_params* p) {
         p->nu_post = 1;
         p->precision = ISDC_PREC_FP64;
         p->guess = ISDC_GUESS_PREV_SWEEP;
+        p->levels = 1;
     });
 }
 

@@ -20,11 +20,13 @@ class StepStats:
     vcycles: int
     residual: float
     residual_hist: list = field(default_factory=list)
+    coarse_vcycles: int = 0
 
     @classmethod
     def from_c(cls, st: A.Stats, rc: int) -> "StepStats":
         return cls(status=A.STATUS_NAMES.get(rc, str(rc)), sweeps=st.sweeps, vcycles=st.vcycles,
-                   residual=st.residual, residual_hist=[st.residual_hist[i] for i in range(st.hist_len)])
+                   residual=st.residual, residual_hist=[st.residual_hist[i] for i in range(st.hist_len)],
+                   coarse_vcycles=st.coarse_vcycles)
 
 
 def _stream_handle(stream):

@@ -112,6 +112,9 @@ WORKLOADS = {
     "rd2d_compact": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
                          precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2, stencil=1, smoother=1,
                          nu_pre=2, nu_post=2),
+    # the rd2d problem with two-level MLSDC (ISDC sweeps on 1023^2 and 511^2, FAS, cubic interpolation)
+    "rd2d_mlsdc": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
+                       precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2, levels=2),
     # 2D viscous Burgers of Sec. 4.1 on [-1, 1)^2, periodic, 128^2 points (h = 1/64),
     # Gaussian sigma = 0.1, nu = 1 (diffusive CFL 4.1), WENO5 advection, compact stencil
     "burgers2d": dict(dim=2, n=128, nu=1.0, fe_kind=FE_BURGERS, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,

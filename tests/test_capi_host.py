@@ -103,6 +103,7 @@ def test_workspace_bytes_scale_with_problem():
     dict(nu=float("nan")), dict(fe=5), dict(M=1), dict(M=10), dict(node_kind=3), dict(vcycles=-1),
     dict(sdc_tol=-1.0), dict(sdc_tol=float("inf")), dict(max_sweeps=0), dict(smoother=2), dict(nu_pre=0, nu_post=0),
     dict(nu_pre=9), dict(precision=2), dict(guess=3), dict(early_exit=2), dict(inner_tol=float("nan")),
+    dict(levels=0), dict(levels=3), dict(levels=2, n=1),
 ])
 def test_validation_rejects(bad):
     kw = dict(dim=2, n=63, nu=1.0, fe=A.FE_ZERO)
@@ -133,6 +134,19 @@ def test_periodic_and_burgers_validation():
     assert _pbytes(3, 64, SC, BP)[0] == A.E_UNSUPPORTED  # compact stencil is 2D
     assert _pbytes(2, 63, SC, BD, A.FE_BURGERS)[0] == A.E_UNSUPPORTED  # Burgers needs periodic
     assert _pbytes(2, 63, S2, BD, A.FE_BURGERS)[0] == A.E_UNSUPPORTED
+
+
+def test_mlsdc_validation_and_workspace():
+    # two-level MLSDC: second-order stencil, Dirichlet; coarse arrays of ((n-1)/2)^d points
+    assert _pbytes(2, 64, A.STENCIL_COMPACT4, A.BC_PERIODIC, levels=2)[0] == A.E_UNSUPPORTED
+    assert _pbytes(2, 63, A.STENCIL_COMPACT4, A.BC_DIRICHLET, levels=2)[0] == A.E_UNSUPPORTED
+    rc1, b1 = _bytes(2, 255, M=3, node_kind=A.NODES_RADAU_RIGHT)
+    rc2, b2 = _bytes(2, 255, M=3, node_kind=A.NODES_RADAU_RIGHT, levels=2)
+    assert rc1 == 0 and rc2 == 0
+    # R U_0..3, U_c 1..3 and S F_c 0..2: 10 coarse arrays of 127^2 doubles, 256-byte aligned
+    assert b2 - b1 == 10 * ((127 * 127 * 8 + 255) // 256 * 256)
+    rc, b = _bytes(2, 7, levels=2)  # the fine grid fits the tail: the coarse level gets arrays too
+    assert rc == 0 and b > _bytes(2, 7)[1]
 
 
 def test_burgers_workspace_holds_fe_arrays():
