@@ -657,6 +657,7 @@ def main():
         return
     cfg = dict(W.WORKLOADS[args.workload])
     plan = make_plan(cfg)
+    shapes = plan.autotune()  # tile shape per level (timed once, then cached), outside the timed steps
     u = torch.from_numpy(W.workload_u0(cfg)).cuda()
     accuracy = None
     if cfg["fe_kind"] == W.FE_ZERO and cfg.get("bc", 0) == 0:
@@ -696,7 +697,7 @@ def main():
                                   if cfg.get("levels", 1) == 2 else ""),
                    "sweeps_per_step": sweeps, "vcycles_per_step": vcyc,
                    "coarse_vcycles_per_step": sum(s.coarse_vcycles for s in stats) / len(stats),
-                   "host_wall_s": round(wall, 4)},
+                   "host_wall_s": round(wall, 4), "tile_shapes": shapes},
         "roofline": roof,
         "vcycle": vc,
         "kernels": kp,

@@ -239,6 +239,25 @@ int isdc_vcycle(isdc_plan* plan, double c, int32_t precision, const void* d_rhs,
 int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t precision,
                const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
 
+/* Tile shapes of the multigrid kernels, one per level above the coarse tail
+ * (level 0 = finest).  Shape 0 is the default tile (1D 1024, 2D 64x16, 3D
+ * 32x8x4 points per workgroup), shapes 1 and 2 are smaller (1D 512 / 256,
+ * 2D 32x16 / 32x8, 3D 16x8x4 / 16x4x4).  Every shape computes the same values
+ * (the V-cycle of Sec. 3 is unchanged); only the launch shape differs.
+ * isdc_autotune times the red-black kernels of every level with each shape
+ * (three rounds of `reps` launches on `stream`, the fastest round of each
+ * shape compared) and keeps the fastest; levels where the shape changes
+ * nothing (Jacobi smoothing, compact stencil, 3D levels of 127^3 and up,
+ * which run z-marching kernels) keep shape 0.  It synchronises `stream`,
+ * overwrites the plan's multigrid buffers, and is refused during a step.
+ * The shapes, or a saved list, are read and written with the two calls
+ * below; nlevels is the number of levels above the tail (*h_nlevels), and
+ * h_shapes holds up to max_levels entries (caller-owned, may be NULL). */
+int isdc_autotune(isdc_plan* plan, int32_t reps, void* stream, int32_t* h_shapes, int32_t max_levels,
+                  int32_t* h_nlevels);
+int isdc_set_tile_shapes(isdc_plan* plan, const int32_t* h_shapes, int32_t nlevels);
+int isdc_get_tile_shapes(const isdc_plan* plan, int32_t* h_shapes, int32_t max_levels, int32_t* h_nlevels);
+
 /* Time one of the plan's kernels as the step launches it: `reps` launches on
  * `stream`, back to back between one pair of HIP events (so the average
  * includes the short gap between consecutive launches but no per-launch

@@ -66,6 +66,9 @@ SIGNATURES = [
     ("isdc_vcycle", C.c_int, [_VP, C.c_double, C.c_int32, _VP, _VP, C.c_int32, _VP, _DP]),
     ("isdc_mg_op", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _DP]),
     ("isdc_time_kernel", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, _VP, _DP, _DP]),
+    ("isdc_autotune", C.c_int, [_VP, C.c_int32, _VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
+    ("isdc_set_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32]),
+    ("isdc_get_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     ("isdc_batch_workspace_bytes", C.c_int, [C.c_int32, _SZP]),
     ("isdc_batch_create", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.c_size_t, C.POINTER(_VP)]),
     ("isdc_batch_destroy", None, [_VP]),

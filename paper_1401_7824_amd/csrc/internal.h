@@ -71,9 +71,15 @@ int tail_max_n(int d);
 // Tiled kernels (mg_tiles.hip).  One complete red-black Gauss-Seidel step
 // from e_in to e_out (e_out != e_in; zero: e_in is identically zero and is
 // not read).
+// `shape` selects the tile shape of the tiled kernels (0 .. kTileShapes - 1;
+// 0 = the default tile); every shape computes the same values.
+constexpr int kTileShapes = 3;
+// Whether the tile shape of a level with n points per axis changes which
+// kernels run (3D levels of 127^3 and up use the z-marching kernels).
+bool tile_shape_applies(int d, int n);
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
-                            hipStream_t s);
+                            hipStream_t s, int shape = 0);
 // rc = full weighting of (r - A e); rc has (n-1)/2 points per axis.
 template <typename T>
 hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, const T* e, T* rc, hipStream_t s);
@@ -81,12 +87,13 @@ hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, con
 // (r - A e_out).  d = 1, 2 only.
 template <typename T>
 hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
-                                     T* rc, hipStream_t s);
+                                     T* rc, hipStream_t s, int shape = 0);
 // e_in + P ec followed by one red-black step.  mode 0: result to e_out;
 // mode 1: u_out = g + result (float64); mode 2: u_out = result.
 template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
-                                    T* e_out, const double* g, double* u_out, int mode, hipStream_t s);
+                                    T* e_out, const double* g, double* u_out, int mode, hipStream_t s,
+                                    int shape = 0);
 
 // partial[b] = max |rhs - A u| over the points of block b; returns the block
 // count in *nblocks (<= kReduceBlocks).

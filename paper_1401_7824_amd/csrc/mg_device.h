@@ -16,11 +16,11 @@ namespace {
 // Red update on the tile plus a halo of 1, then black on the tile, in LDS.
 // se: box with halo 2 (origin tile - 2), sr: box with halo 1 (origin tile - 1).
 // A colour's update reads only the other colour, so each is one lds_pass.
-template <typename T, int D>
+template <typename T, int D, class TL = Tile<D>>
 __device__ __forceinline__ void rbgs_in_lds(T* se, const T* sr, int n, int x0, int y0, int z0, T a, T invdiag) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
+    using B2 = HaloBoxT<D, 2, TL>;
+    using B1 = HaloBoxT<D, 1, TL>;
+    using B0 = HaloBoxT<D, 0, TL>;
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
     lds_pass<T, B1>(se, [&](int k, int lx, int ly, int lz, T& v) {
         const int x = x0 - 1 + lx, y = y0 - hy + ly, z = z0 - hz + lz;
@@ -41,12 +41,12 @@ __device__ __forceinline__ void rbgs_in_lds(T* se, const T* sr, int n, int x0, i
     __syncthreads();
 }
 
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, class TL = Tile<D>>
 __device__ __forceinline__ void rbgs_tile_body(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out,
                                                int n, int x0, int y0, int z0, T a, T invdiag) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
+    using B2 = HaloBoxT<D, 2, TL>;
+    using B1 = HaloBoxT<D, 1, TL>;
+    using B0 = HaloBoxT<D, 0, TL>;
     __shared__ T se[B2::N];
     __shared__ T sr[B1::N];
     const int hy = D >= 2 ? 1 : 0, hz = D == 3 ? 1 : 0;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void rbgs_tile_body(const T* __restrict__ r, const T*
         lr.store(sr);
     }
     __syncthreads();
-    rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
+    rbgs_in_lds<T, D, TL>(se, sr, n, x0, y0, z0, a, invdiag);
     for_box<B0>([&](int, int lx, int ly, int lz) {
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (inside<D>(x, y, z, n))
@@ -118,11 +118,10 @@ __device__ __forceinline__ void restrict_tile_body(const T* __restrict__ r, cons
 // iterate and its full-weighting restriction to rc.  The tile's new iterate
 // is computed on the tile plus a halo of 1 (red on a halo of 2), so the
 // residual is available on every fine point under the tile's coarse points.
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, class TL = Tile<D>>
 __device__ __forceinline__ void rbgs_restrict_body(const T* __restrict__ r, const T* __restrict__ e_in,
                                                    T* __restrict__ e_out, T* __restrict__ rc, int n, int x0, int y0,
                                                    int z0, T a, T diag, T invdiag) {
-    using TL = Tile<D>;
     using EB = Box<D, TL::X + 7, TL::Y + 7, TL::Z + 7>;  // old iterate, origin tile - 3
     using RB = Box<D, TL::X + 5, TL::Y + 5, TL::Z + 5>;  // rhs (later residual), origin tile - 2
     using BB = Box<D, TL::X + 3, TL::Y + 3, TL::Z + 3>;  // black region, origin tile - 1
@@ -194,15 +193,15 @@ __device__ __forceinline__ void rbgs_restrict_body(const T* __restrict__ r, cons
     });
 }
 
-template <typename T, int D, int MODE>
+template <typename T, int D, int MODE, class TL = Tile<D>>
 __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const T* __restrict__ e_in,
                                                   const T* __restrict__ ec, T* __restrict__ e_out, int n, int x0, int y0,
                                                   int z0, T a, T invdiag, const double* __restrict__ g,
                                                   double* __restrict__ u_out) {
-    using B2 = HaloBox<D, 2>;
-    using B1 = HaloBox<D, 1>;
-    using B0 = HaloBox<D, 0>;
-    using CB = Box<D, Tile<D>::X / 2 + 4, Tile<D>::Y / 2 + 4, Tile<D>::Z / 2 + 4>;
+    using B2 = HaloBoxT<D, 2, TL>;
+    using B1 = HaloBoxT<D, 1, TL>;
+    using B0 = HaloBoxT<D, 0, TL>;
+    using CB = Box<D, TL::X / 2 + 4, TL::Y / 2 + 4, TL::Z / 2 + 4>;
     __shared__ T se[B2::N];
     __shared__ T sr[B1::N];
     __shared__ T sc[CB::N];
@@ -252,7 +251,7 @@ __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const
         return k;
     });
     __syncthreads();
-    rbgs_in_lds<T, D>(se, sr, n, x0, y0, z0, a, invdiag);
+    rbgs_in_lds<T, D, TL>(se, sr, n, x0, y0, z0, a, invdiag);
     for_box<B0>([&](int, int lx, int ly, int lz) {
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (!inside<D>(x, y, z, n)) return;

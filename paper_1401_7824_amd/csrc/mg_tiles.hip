@@ -27,13 +27,14 @@ namespace isdc {
 
 namespace {
 
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
             T a, T invdiag) {
+    using TL = TileS<D, S>;
     int x0, y0, z0;
-    tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    rbgs_tile_body<T, D, ZERO>(r, e_in, e_out, n, x0, y0, z0, a, invdiag);
+    tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
+    rbgs_tile_body<T, D, ZERO, TL>(r, e_in, e_out, n, x0, y0, z0, a, invdiag);
 }
 
 template <typename T, int D>
@@ -45,22 +46,24 @@ k_restrict_tile(const T* __restrict__ r, const T* __restrict__ e, T* __restrict_
     restrict_tile_body<T, D>(r, e, rc, n, X0, Y0, Z0, a, diag);
 }
 
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_restrict_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
                      int n, int ntx, int nty, T a, T diag, T invdiag) {
+    using TL = TileS<D, S>;
     int x0, y0, z0;
-    tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    rbgs_restrict_body<T, D, ZERO>(r, e_in, e_out, rc, n, x0, y0, z0, a, diag, invdiag);
+    tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
+    rbgs_restrict_body<T, D, ZERO, TL>(r, e_in, e_out, rc, n, x0, y0, z0, a, diag, invdiag);
 }
 
-template <typename T, int D, int MODE>
+template <typename T, int D, int MODE, int S>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
                     int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
+    using TL = TileS<D, S>;
     int x0, y0, z0;
-    tile_origin(ntx, nty, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    prolong_rbgs_body<T, D, MODE>(r, e_in, ec, e_out, n, x0, y0, z0, a, invdiag, g, u_out);
+    tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
+    prolong_rbgs_body<T, D, MODE, TL>(r, e_in, ec, e_out, n, x0, y0, z0, a, invdiag, g, u_out);
 }
 
 // 3D red-black step (optionally after the prolongation, with the node
@@ -91,9 +94,24 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, 
         default: return hipErrorInvalidValue;                \
     }
 
+// dimension and tile shape (0 .. kShapes-1) as compile-time constants D, S
+#define ISDC_DISPATCH_DS(d, shape, ...)                                            \
+    switch ((d) * 4 + (shape)) {                                                   \
+        case 4: { constexpr int D = 1, S = 0; __VA_ARGS__; } break;                \
+        case 5: { constexpr int D = 1, S = 1; __VA_ARGS__; } break;                \
+        case 6: { constexpr int D = 1, S = 2; __VA_ARGS__; } break;                \
+        case 8: { constexpr int D = 2, S = 0; __VA_ARGS__; } break;                \
+        case 9: { constexpr int D = 2, S = 1; __VA_ARGS__; } break;                \
+        case 10: { constexpr int D = 2, S = 2; __VA_ARGS__; } break;               \
+        case 12: { constexpr int D = 3, S = 0; __VA_ARGS__; } break;               \
+        case 13: { constexpr int D = 3, S = 1; __VA_ARGS__; } break;               \
+        case 14: { constexpr int D = 3, S = 2; __VA_ARGS__; } break;               \
+        default: return hipErrorInvalidValue;                                      \
+    }
+
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
-                            hipStream_t s) {
+                            hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
         const int mz = march_depth(n);
         int ntx, nty, nb;
@@ -104,13 +122,14 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
             hipLaunchKernelGGL((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         return hipGetLastError();
     }
-    ISDC_DISPATCH_D(d, {
+    ISDC_DISPATCH_DS(d, shape, {
+        using TL = TileS<D, S>;
         int ntx, nty, nb;
-        tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
+        tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (zero)
-            hipLaunchKernelGGL((k_rbgs_tile<T, D, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            hipLaunchKernelGGL((k_rbgs_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
         else
-            hipLaunchKernelGGL((k_rbgs_tile<T, D, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            hipLaunchKernelGGL((k_rbgs_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
     });
     return hipGetLastError();
 }
@@ -128,16 +147,17 @@ hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, con
 
 template <typename T>
 hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
-                                     T* rc, hipStream_t s) {
+                                     T* rc, hipStream_t s, int shape) {
     if (d == 3) return hipErrorInvalidValue;  // 3D uses the separate kernels (LDS budget)
-    ISDC_DISPATCH_D(d, {
+    ISDC_DISPATCH_DS(d, shape, {
         if constexpr (D < 3) {
+            using TL = TileS<D, S>;
             int ntx, nty, nb;
-            tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
+            tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
             if (zero)
-                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
             else
-                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
         }
     });
     return hipGetLastError();
@@ -145,7 +165,7 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
 
 template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
-                                    T* e_out, const double* g, double* u_out, int mode, hipStream_t s) {
+                                    T* e_out, const double* g, double* u_out, int mode, hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
         const int mz = march_depth(n);
         int ntx, nty, nb;
@@ -158,18 +178,23 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
             hipLaunchKernelGGL((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         return hipGetLastError();
     }
-    ISDC_DISPATCH_D(d, {
+    ISDC_DISPATCH_DS(d, shape, {
+        using TL = TileS<D, S>;
         int ntx, nty, nb;
-        tile_counts<D>(n, Tile<D>::X, Tile<D>::Y, Tile<D>::Z, ntx, nty, nb);
+        tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (mode == 0)
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 0>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else if (mode == 1)
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 1>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 2>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
     });
     return hipGetLastError();
 }
+
+static_assert(kShapes == kTileShapes, "tile shape count of the kernels and of the launchers");
+
+bool tile_shape_applies(int d, int n) { return !(d == 3 && march_depth(n) > 0); }
 
 int tail_max_n(int d) {
     return d == 1 ? TailLayout<1>::nmax : (d == 2 ? TailLayout<2>::nmax : TailLayout<3>::nmax);
@@ -196,12 +221,12 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
 }
 
 #define ISDC_INST_T(T)                                                                                          \
-    template hipError_t launch_rbgs_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_rbgs_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, hipStream_t, int); \
     template hipError_t launch_restrict_tile<T>(int, int, const Coef<T>&, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_rbgs_restrict_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, T*,    \
-                                                     hipStream_t);                                                 \
+                                                     hipStream_t, int);                                            \
     template hipError_t launch_prolong_rbgs_tile<T>(int, int, const Coef<T>&, const T*, const T*, const T*, T*,  \
-                                                    const double*, double*, int, hipStream_t);                  \
+                                                    const double*, double*, int, hipStream_t, int);             \
     template hipError_t launch_tail<T>(const MGConfig&, int, double, double, bool, const T*, T*, hipStream_t);
 
 ISDC_INST_T(float)

@@ -52,6 +52,7 @@ struct Level {
     void* r;
     void* e;
     void* e2;  // ping-pong partner of the out-of-place smoothers
+    int shape = 0;  // tile shape of the tiled kernels on this level (isdc_autotune)
 };
 
 void validate(const isdc_problem* pb, const isdc_params* pr);

@@ -242,10 +242,10 @@ struct Fuse {
 
 template <typename T>
 void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs,
-                  T*& cur, T*& other, hipStream_t s) {
+                  T*& cur, T*& other, hipStream_t s, int shape) {
     for (int k = 0; k < nsteps; ++k) {
         if (mg.smoother == ISDC_SMOOTH_RBGS)
-            HIPCHK(launch_rbgs_tile<T>(p->d, n, co, zero, rhs, cur, other, s));
+            HIPCHK(launch_rbgs_tile<T>(p->d, n, co, zero, rhs, cur, other, s, shape));
         else
             HIPCHK(launch_smooth<T>(mg, n, co, zero, rhs, cur, other, s));
         std::swap(cur, other);
@@ -272,12 +272,12 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
     const Level& C = p->lev[l + 1];
     if (rbgs && mg.nu_pre >= 1 && p->d <= 2) {
         // pre-smoothing steps; the last one fused with residual + restriction
-        smooth_steps<T>(p, mg, mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s);
-        HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s));
+        smooth_steps<T>(p, mg, mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s, L.shape);
+        HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s, L.shape));
         std::swap(cur, other);
         zero = false;
     } else {
-        smooth_steps<T>(p, mg, mg.nu_pre, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_pre, L.n, co, zero, rhs, cur, other, s, L.shape);
         if (zero) {  // no pre-smoothing and a zero iterate
             HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
             zero = false;
@@ -290,13 +290,14 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
         // prolongation + correction fused with the first post-smoothing step
         const bool last = mg.nu_post == 1;
         const int mode = (last && fuse.mode) ? fuse.mode : 0;
-        HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, mode, s));
+        HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, mode, s,
+                                           L.shape));
         if (mode) return true;
         std::swap(cur, other);
-        smooth_steps<T>(p, mg, mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s, L.shape);
     } else {
         HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
-        smooth_steps<T>(p, mg, mg.nu_post, L.n, co, zero, rhs, cur, other, s);
+        smooth_steps<T>(p, mg, mg.nu_post, L.n, co, zero, rhs, cur, other, s, L.shape);
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
     return fused;
@@ -1104,13 +1105,13 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
         const double N = (double)L.N, Nc = (double)C.N;
         if (kernel == ISDC_KERNEL_SMOOTH_RESTRICT) {
             if (d == 3) fail(ISDC_E_UNSUPPORTED, "the fused smoothing + restriction kernel is 1D/2D only");
-            launch = [=]() { HIPCHK(launch_rbgs_restrict_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, (T*)C.r, s)); };
+            launch = [=]() { HIPCHK(launch_rbgs_restrict_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, (T*)C.r, s, L.shape)); };
             b = (3.0 * N + Nc) * w;
         } else if (kernel == ISDC_KERNEL_PROLONG_SMOOTH) {
-            launch = [=]() { HIPCHK(launch_prolong_rbgs_tile<T>(d, L.n, co, (const T*)L.r, (const T*)L.e2, (const T*)C.e, (T*)L.e, nullptr, nullptr, 0, s)); };
+            launch = [=]() { HIPCHK(launch_prolong_rbgs_tile<T>(d, L.n, co, (const T*)L.r, (const T*)L.e2, (const T*)C.e, (T*)L.e, nullptr, nullptr, 0, s, L.shape)); };
             b = (3.0 * N + Nc) * w;
         } else {
-            launch = [=]() { HIPCHK(launch_rbgs_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, s)); };
+            launch = [=]() { HIPCHK(launch_rbgs_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, s, L.shape)); };
             b = 3.0 * N * w;
         }
     } else if (kernel == ISDC_KERNEL_TAIL) {
@@ -1149,6 +1150,108 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
 }
 
 }  // namespace
+
+namespace {
+
+bool level_shaped(const isdc_plan* p, int l) {
+    return !p->compact && p->mg.smoother == ISDC_SMOOTH_RBGS && l < p->tail &&
+           tile_shape_applies(p->d, p->lev[l].n);
+}
+
+// The tiled kernels one V-cycle runs on level l (pre- and post-smoothing,
+// the fused restriction and prolongation), on the plan's own buffers.
+template <typename T>
+void level_tile_kernels(isdc_plan* p, int l, hipStream_t s) {
+    const Level& L = p->lev[l];
+    const Level& C = p->lev[l + 1];
+    const MGConfig& mg = p->mg;
+    const Coef<T> co = make_coef<T>(1e-3, L.h, p->d, mg.omega);
+    const T* r = (const T*)L.r;
+    T* a = (T*)L.e;
+    T* b = (T*)L.e2;
+    int plain = mg.nu_pre + (mg.nu_post > 0 ? mg.nu_post - 1 : 0);
+    if (p->d <= 2 && mg.nu_pre >= 1) {
+        HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, false, r, a, b, (T*)C.r, s, L.shape));
+        --plain;
+    }
+    if (mg.nu_post >= 1)
+        HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, r, b, (const T*)C.e, a, nullptr, nullptr, 0, s, L.shape));
+    for (int k = 0; k < plain; ++k) HIPCHK(launch_rbgs_tile<T>(p->d, L.n, co, false, r, a, b, s, L.shape));
+}
+
+// Pick each level's tile shape by timing its kernels with every shape:
+// three interleaved rounds of `reps` launches per shape, the fastest round
+// of each shape compared.
+template <typename T>
+void autotune_impl(isdc_plan* p, int reps, hipStream_t s) {
+    hipEvent_t ev[2];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int l = 0; l < p->tail; ++l) {
+        if (!level_shaped(p, l)) continue;
+        double best[kTileShapes];
+        for (double& b : best) b = 1e30;
+        for (int round = 0; round < 3; ++round)
+            for (int sh = 0; sh < kTileShapes; ++sh) {
+                p->lev[l].shape = sh;
+                level_tile_kernels<T>(p, l, s);  // warm-up
+                HIPCHK(hipEventRecord(ev[0], s));
+                for (int k = 0; k < reps; ++k) level_tile_kernels<T>(p, l, s);
+                HIPCHK(hipEventRecord(ev[1], s));
+                HIPCHK(hipStreamSynchronize(s));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                best[sh] = std::min(best[sh], (double)ms);
+            }
+        int pick = 0;
+        for (int sh = 1; sh < kTileShapes; ++sh)
+            if (best[sh] < best[pick]) pick = sh;
+        p->lev[l].shape = pick;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+void get_shapes(const isdc_plan* p, int32_t* h_shapes, int32_t max_levels, int32_t* h_nlevels) {
+    if (h_nlevels) *h_nlevels = p->tail;
+    if (h_shapes)
+        for (int l = 0; l < p->tail && l < max_levels; ++l) h_shapes[l] = p->lev[l].shape;
+}
+
+}  // namespace
+
+extern "C" int isdc_autotune(isdc_plan* plan, int32_t reps, void* stream, int32_t* h_shapes, int32_t max_levels,
+                             int32_t* h_nlevels) {
+    return guarded([&] {
+        check_plan(plan);
+        if (plan->begun) fail(ISDC_E_INVAL, "isdc_autotune during a step (its timing reuses the plan's buffers)");
+        if (reps < 1 || reps > 10000) fail(ISDC_E_INVAL, "reps must be in 1..10000");
+        if (max_levels < 0) fail(ISDC_E_INVAL, "max_levels must be >= 0");
+        if (plan->par.precision == ISDC_PREC_MIXED)
+            autotune_impl<float>(plan, reps, (hipStream_t)stream);
+        else
+            autotune_impl<double>(plan, reps, (hipStream_t)stream);
+        get_shapes(plan, h_shapes, max_levels, h_nlevels);
+    });
+}
+
+extern "C" int isdc_set_tile_shapes(isdc_plan* plan, const int32_t* h_shapes, int32_t nlevels) {
+    return guarded([&] {
+        check_plan(plan);
+        if (!h_shapes && nlevels > 0) fail(ISDC_E_INVAL, "h_shapes is NULL");
+        if (nlevels != plan->tail) fail(ISDC_E_INVAL, "nlevels must equal the number of levels above the tail");
+        for (int l = 0; l < nlevels; ++l)
+            if (h_shapes[l] < 0 || h_shapes[l] >= kTileShapes) fail(ISDC_E_INVAL, "tile shape out of range");
+        for (int l = 0; l < nlevels; ++l) plan->lev[l].shape = h_shapes[l];
+    });
+}
+
+extern "C" int isdc_get_tile_shapes(const isdc_plan* plan, int32_t* h_shapes, int32_t max_levels,
+                                    int32_t* h_nlevels) {
+    return guarded([&] {
+        check_plan(plan);
+        if (max_levels < 0) fail(ISDC_E_INVAL, "max_levels must be >= 0");
+        get_shapes(plan, h_shapes, max_levels, h_nlevels);
+    });
+}
 
 extern "C" int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision,
                                 int32_t reps, void* stream, double* h_avg_us, double* h_bytes) {

@@ -18,6 +18,20 @@ template <> struct Tile<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
 template <> struct Tile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
 template <> struct Tile<3> { static constexpr int X = 32, Y = 8, Z = 4; };
 
+// Shapes of the multigrid tile kernels: shape 0 is Tile<D>, shapes 1 and 2
+// are smaller tiles (more workgroups, shorter per-workgroup latency chains,
+// more halo per point).  A plan picks one per level (isdc_autotune).  Every
+// extent is even, so a tile's coarse points start at its origin / 2.
+constexpr int kShapes = 3;
+template <int D, int S> struct TileS;
+template <int D> struct TileS<D, 0> : Tile<D> {};
+template <> struct TileS<1, 1> { static constexpr int X = 512, Y = 1, Z = 1; };
+template <> struct TileS<1, 2> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <> struct TileS<2, 1> { static constexpr int X = 32, Y = 16, Z = 1; };
+template <> struct TileS<2, 2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <> struct TileS<3, 1> { static constexpr int X = 16, Y = 8, Z = 4; };
+template <> struct TileS<3, 2> { static constexpr int X = 16, Y = 4, Z = 4; };
+
 // Coarse tile of the restriction kernel.
 template <int D> struct CTile;
 template <> struct CTile<1> { static constexpr int X = 512, Y = 1, Z = 1; };
@@ -41,8 +55,10 @@ struct Box {
     }
 };
 
+template <int D, int H, class TL>
+using HaloBoxT = Box<D, TL::X + 2 * H, TL::Y + 2 * H, TL::Z + 2 * H>;
 template <int D, int H>
-using HaloBox = Box<D, Tile<D>::X + 2 * H, Tile<D>::Y + 2 * H, Tile<D>::Z + 2 * H>;
+using HaloBox = HaloBoxT<D, H, Tile<D>>;
 
 template <int D>
 __device__ __forceinline__ bool inside(int x, int y, int z, int n) {

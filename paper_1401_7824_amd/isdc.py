@@ -98,6 +98,7 @@ class Plan:
         self.params = make_params(**params)
         self.dim, self.n = dim, n
         self.periodic = bc == A.BC_PERIODIC
+        self.stencil = stencil
         self.N = n ** dim
         self.shape = (n,) * dim
         nbytes = workspace_bytes(self.problem, self.params)
@@ -179,6 +180,38 @@ class Plan:
         res = C.c_double()
         A.check(self.lib.isdc_mg_op(self._h, op, level, c, prec, *ptrs, _stream_handle(stream), C.byref(res)))
         return res.value
+
+    @property
+    def tile_shapes(self) -> list:
+        """Tile shape of the multigrid kernels per level above the coarse tail."""
+        buf = (C.c_int32 * 32)()
+        nl = C.c_int32()
+        A.check(self.lib.isdc_get_tile_shapes(self._h, buf, 32, C.byref(nl)))
+        return list(buf[:nl.value])
+
+    @tile_shapes.setter
+    def tile_shapes(self, shapes):
+        arr = (C.c_int32 * max(1, len(shapes)))(*shapes)
+        A.check(self.lib.isdc_set_tile_shapes(self._h, arr, len(shapes)))
+
+    def autotune(self, reps: int = 50, cache: bool = True, stream=None) -> list:
+        """Pick the tile shape of every level by timing (isdc_autotune), or
+        take the choice stored for this device and plan shape in the tuning
+        cache (tuning.py); returns the shapes."""
+        from . import tuning
+        key = tuning.key(self) if cache else None
+        if key is not None:
+            saved = tuning.lookup(key)
+            if saved is not None and len(saved) == len(self.tile_shapes):
+                self.tile_shapes = saved
+                return saved
+        buf = (C.c_int32 * 32)()
+        nl = C.c_int32()
+        A.check(self.lib.isdc_autotune(self._h, reps, _stream_handle(stream), buf, 32, C.byref(nl)))
+        shapes = list(buf[:nl.value])
+        if key is not None:
+            tuning.store(key, shapes)
+        return shapes
 
     def time_kernel(self, kernel: int, level: int, c: float, precision: int, reps: int = 100, stream=None):
         """(average microseconds per launch, algorithmic bytes per launch) of one library kernel."""

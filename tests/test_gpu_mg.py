@@ -182,3 +182,56 @@ def test_time_kernel_reports_durations_and_bytes():
         p.time_kernel(P.KERNEL_QUAD, 0, c, 0, reps=2)  # no step in progress
     with pytest.raises(Exception):
         p.time_kernel(P.KERNEL_SMOOTH, 3, c, 0, reps=2)  # level 3 is the coarse tail
+
+
+# ---- tile shapes: every shape computes the same V-cycle ----
+
+SHAPE_SIZES = {1: 8191, 2: 511, 3: 63}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_vcycle_parity_every_tile_shape(d, shape, dtype):
+    n = SHAPE_SIZES[d]
+    announce("vcycle shape", d, n, shape, dtype)
+    p = _plan(d, n, RBGS, nu_pre=2, nu_post=2)
+    nl = len(p.tile_shapes)
+    assert nl >= 2
+    p.tile_shapes = [shape] * nl
+    assert p.tile_shapes == [shape] * nl
+    h = 1.0 / (n + 1)
+    c = 64.0 * h * h
+    nd = _np_dtype(dtype)
+    rhs = random_field((n,) * d, 17).astype(nd)
+    u0 = random_field((n,) * d, 18).astype(nd)
+    u = dev(u0, dtype)
+    p.vcycle(c, dev(rhs, dtype), u, ncycles=2)
+    ref = u0
+    for _ in range(2):
+        ref = O.vcycle(ref, rhs, c, h, RBGS, 2, 2)
+    assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5)
+
+
+def test_autotune_picks_valid_shapes_and_keeps_results(tmp_path, monkeypatch):
+    from paper_1401_7824_amd import ISDCError
+    announce("autotune")
+    monkeypatch.setenv("ISDC_TUNE_CACHE", str(tmp_path / "tiles.json"))
+    n = 511
+    p = _plan(2, n, RBGS)
+    shapes = p.autotune(reps=5)
+    assert len(shapes) == len(p.tile_shapes) and all(0 <= s < 3 for s in shapes)
+    assert p.tile_shapes == shapes
+    q = _plan(2, n, RBGS)
+    assert q.autotune(reps=5) == shapes  # from the cache
+    h = 1.0 / (n + 1)
+    c = 64.0 * h * h
+    rhs = random_field((n, n), 19)
+    u = dev(np.zeros((n, n)))
+    p.vcycle(c, dev(rhs), u, ncycles=2)
+    ref = O.vcycle(O.vcycle(np.zeros((n, n)), rhs, c, h, RBGS, 1, 1), rhs, c, h, RBGS, 1, 1)
+    assert rel_l2(host(u), ref) < 1e-12
+    with pytest.raises(ISDCError):
+        p.tile_shapes = [3] * len(shapes)
+    with pytest.raises(ISDCError):
+        p.tile_shapes = [0] * (len(shapes) + 1)
