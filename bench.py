@@ -97,23 +97,23 @@ def time_steps(plan, u, dt, steps, warmup, torch):
 
 
 KERNEL_NAMES = {
-    "smooth_restrict": "k_rbgs_restrict_tile<{T},{d},false>",
-    "prolong_smooth": "k_prolong_rbgs_tile<{T},{d},0>",
+    "smooth_restrict": "k_rbgs_restrict_tile<{T},{d},false,{S}>",
+    "prolong_smooth": "k_prolong_rbgs_tile<{T},{d},0,{S}>",
     "tail": "k_tail<{T},{d}>",
     "quad": "k_quad_residual_tile<{d},{M}>",
 }
 
 
-def kernel_name(name, cfg, T):
+def kernel_name(name, cfg, T, shape=0):
     """rocprof name of the kernel bench.py times for `name` on the finest level
-    (3D levels of 127^3 and up run the z-marching form)."""
+    (tile shape `shape`; 3D levels of 127^3 and up run the z-marching form)."""
     if cfg.get("stencil", 0) == 1:
         per = "true" if cfg.get("bc", 0) == 1 else "false"
         return {"smooth": f"k_cjacobi<{T},false,{per}>", "tail": f"k_ctail<{T},{per}>",
                 "explicit": "k_weno_burgers"}[name]
     if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
         return f"k_march_rbgs<{T},true,0,false>"
-    return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"])
+    return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"], S=shape)
 
 
 def accuracy_vs_collocation(cfg, torch):
@@ -190,7 +190,8 @@ def kernel_probe(plan, cfg, reps, torch):
         if name not in ("tail", "explicit") and cfg["n"] <= tail_n(cfg):
             continue  # the whole V-cycle is the single-workgroup coarse solve
         us, b = plan.time_kernel(k, 0, c, prec, reps)
-        out[name] = dict(kernel=kernel_name(name, cfg, T), avg_us=round(us, 3),
+        shape = (plan.tile_shapes or [0])[0]
+        out[name] = dict(kernel=kernel_name(name, cfg, T, shape), avg_us=round(us, 3),
                          alg_bytes=b, gbps=round(b / (us * 1e-6) / 1e9, 1))
     return out
 
@@ -439,10 +440,18 @@ def run_kernels(args, torch):
         kinds = [("smooth", P.KERNEL_SMOOTH), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH)]
         if d < 3:
             kinds.insert(0, ("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT))
+        nl = len(p.tile_shapes)
+        shapes = range(3) if (d < 3 or n < 127) else [0]  # 3D levels of 127^3 and up are z-marched
         for name, k in kinds:
-            us, b = p.time_kernel(k, 0, c, prec, args.probe_reps)
+            best = None
+            for sh in shapes:  # every tile shape on the finest level; the fastest is reported
+                p.tile_shapes = [sh] * nl
+                us, b = p.time_kernel(k, 0, c, prec, args.probe_reps)
+                if best is None or us < best[0]:
+                    best = (us, b, sh)
+            us, b, sh = best
             row[name] = {"us": round(us, 2), "alg_bytes": int(b), "gbps": round(b / (us * 1e-6) / 1e9, 1),
-                         "frac": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                         "frac": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "shape": sh}
         dt = torch.float64 if prec == 0 else torch.float32
         src = torch.empty((n,) * d, dtype=dt, device="cuda")
         dst = torch.empty_like(src)
@@ -458,7 +467,8 @@ def run_kernels(args, torch):
         row["copy"] = {"us": round(us, 2), "gbps": round(2 * src.numel() * src.element_size() / (us * 1e-6) / 1e9, 1)}
         rows.append(row)
         print(f"[kernels] {d}D n={n} {row['dtype']}: " + ", ".join(
-            f"{k} {v['gbps']} GB/s" for k, v in row.items() if isinstance(v, dict)), file=sys.stderr, flush=True)
+            f"{k} {v['gbps']} GB/s" + (f" (shape {v['shape']})" if "shape" in v else "")
+            for k, v in row.items() if isinstance(v, dict)), file=sys.stderr, flush=True)
         del p, src, dst
         torch.cuda.empty_cache()
     big = [r for r in rows if r["dim"] == 2 and r["n"] == 8191 and r["dtype"] == "f64"][0]
@@ -470,7 +480,8 @@ def run_kernels(args, torch):
         "config": {"workload": "kernels: fine-level multigrid kernels, 2D 1023^2..8191^2 and 3D 255^3..511^3, "
                                "f64 and f32; value = fused smoothing + restriction at 8191^2 f64"},
         "roofline": {"bound": "hbm", "achieved": best["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": best["frac"], "traffic": None, "kernel": "k_rbgs_restrict_tile<double,2,false> (8191^2)",
+                     "frac": best["frac"], "traffic": None,
+                     "kernel": f"k_rbgs_restrict_tile<double,2,false,{best['shape']}> (8191^2)",
                      "avg_launch_us": best["us"], "alg_bytes_per_launch": best["alg_bytes"]},
         "rows": rows,
     }

@@ -2,7 +2,7 @@
 
     python -m paper_1401_7824_amd.profiling trace RUN_kernel_trace.csv
     python -m paper_1401_7824_amd.profiling counters FETCH.csv WRITE.csv \\
-        --workload rd2d --kernel 'k_rbgs_restrict_tile<double, 2, false>' --workgroups 1024 \\
+        --workload rd2d --kernel 'k_rbgs_restrict_tile<double, 2, false, 0>' --workgroups 1024 \\
         --alg-bytes 27205664 [--update profiles/traffic.json]
 
 `trace` prints the median duration per (kernel, workgroup count) -- the
