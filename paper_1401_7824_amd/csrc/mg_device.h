@@ -306,6 +306,18 @@ __device__ __forceinline__ void slots(int n, int s0, F&& f) {
     }
 }
 
+// Whether this thread's whole wave has no point of an n^D level in any
+// slot (the test is uniform per wave, so an idle wave skips the phase's
+// instructions and only meets the barrier that follows it).
+template <int D>
+__device__ __forceinline__ bool wave_idle(int n) {
+    using L = TailLayout<D>;
+    const int w0 = threadIdx.x & ~63;  // first thread of the wave
+    if (D == 1) return w0 >= n;
+    if (D == 2) return w0 / L::X >= n;  // the wave's row (X = 64)
+    return (w0 / (L::X * L::Y)) >= n || ((w0 / L::X) % L::Y) >= n;  // its z plane, its first y row
+}
+
 // Run a phase in chunks of slots: compute all values of a chunk, then store
 // them (the callers only ever read locations no chunk of the phase writes).
 template <int D> constexpr int chunk_of() { return D == 3 ? 1 : 4; }
@@ -313,6 +325,7 @@ template <typename T, int D, typename Compute>
 __device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
     constexpr int P = TailLayout<D>::P;
     constexpr int CH = chunk_of<D>();
+    if (wave_idle<D>(n)) return;
 #pragma unroll 1
     for (int s0 = 0; s0 < P; s0 += CH) {
         T v[CH];
@@ -338,6 +351,13 @@ __device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
 template <typename T, int D, typename Compute>
 __device__ __forceinline__ void phase_colour(int n, int colour, T* out, Compute&& compute) {
     constexpr int CP = D == 1 ? 1 : 2;
+    {
+        // a wave whose first point row (plane) lies beyond the level has no
+        // point in either of its slots (the second slot lies further out)
+        const int w0 = threadIdx.x & ~63;
+        const bool idle = D == 1 ? 2 * w0 >= n : (D == 2 ? (w0 >> 5) >= n : (w0 >> 7) >= n);
+        if (idle) return;
+    }
     T v[CP];
     int idx[CP];
     bool wr[CP];
@@ -364,18 +384,26 @@ __device__ __forceinline__ void phase_colour(int n, int colour, T* out, Compute&
         if (wr[q]) out[idx[q]] = v[q];
 }
 
+// Sum of the in-level neighbours of point i (zero ghosts).  Every load is
+// unconditional (a neighbour outside the level reads the point itself and is
+// then replaced by zero), so the loads of one point issue together instead of
+// one conditional block, and one LDS wait, each; adding the zeros leaves the
+// sum bit-for-bit what skipping the terms gives.
 template <typename T, int D>
 __device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int i) {
+    const T xm = e[x > 0 ? i - 1 : i], xp = e[x < n - 1 ? i + 1 : i];
     T s = T(0);
-    if (x > 0) s += e[i - 1];
-    if (x < n - 1) s += e[i + 1];
+    s += x > 0 ? xm : T(0);
+    s += x < n - 1 ? xp : T(0);
     if (D >= 2) {
-        if (y > 0) s += e[i - n];
-        if (y < n - 1) s += e[i + n];
+        const T ym = e[y > 0 ? i - n : i], yp = e[y < n - 1 ? i + n : i];
+        s += y > 0 ? ym : T(0);
+        s += y < n - 1 ? yp : T(0);
     }
     if (D == 3) {
-        if (z > 0) s += e[i - n * n];
-        if (z < n - 1) s += e[i + n * n];
+        const T zm = e[z > 0 ? i - n * n : i], zp = e[z < n - 1 ? i + n * n : i];
+        s += z > 0 ? zm : T(0);
+        s += z < n - 1 ? zp : T(0);
     }
     return s;
 }
@@ -385,11 +413,12 @@ __device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int 
 // with zeros outside the coarse grid.
 template <typename T, int D>
 __device__ __forceinline__ T interp_at(const T* ec, int nc, int x, int y, int z) {
-    auto tap = [&](int X, int Y, int Z) -> T {
-        if ((unsigned)X >= (unsigned)nc) return T(0);
-        if (D >= 2 && (unsigned)Y >= (unsigned)nc) return T(0);
-        if (D == 3 && (unsigned)Z >= (unsigned)nc) return T(0);
-        return ec[D == 1 ? X : (Z * nc + Y) * nc + X];
+    auto tap = [&](int X, int Y, int Z) -> T {  // unconditional load, then zero outside
+        bool in = (unsigned)X < (unsigned)nc;
+        if (D >= 2) in = in && (unsigned)Y < (unsigned)nc;
+        if (D == 3) in = in && (unsigned)Z < (unsigned)nc;
+        const T v = ec[in ? (D == 1 ? X : (Z * nc + Y) * nc + X) : 0];
+        return in ? v : T(0);
     };
     const int xa = (x & 1) ? (x - 1) / 2 : x / 2 - 1;
     auto row = [&](int Y, int Z) -> T {
@@ -450,6 +479,137 @@ __device__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invd
     }
 }
 
+// Order the LDS accesses of one wave: the compiler keeps every access on its
+// side of the fence, and the hardware executes one wave's LDS instructions in
+// order, so what a lane stores before it is what any lane loads after it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Coordinates of point k of an n^D level.
+template <int D>
+__device__ __forceinline__ void point_of(int k, int n, int& x, int& y, int& z) {
+    x = k % n;
+    y = D >= 2 ? (k / n) % n : 0;
+    z = D == 3 ? k / (n * n) : 0;
+}
+
+// The V-cycle on the tail's levels l0 .. nlev-1, all of at most 64 points, by
+// the first wave alone: one lane per point and wave_sync() between phases
+// instead of workgroup barriers.  The arithmetic is that of the workgroup
+// phases of tail_body (same expressions, same order), only the thread that
+// computes each point differs.
+template <typename T, int D>
+__device__ __forceinline__ void tail_wave_levels(T* le, T* lr, T* lt, const T (*lc)[16], int n_t, int l0, int nlev,
+                                                 int smoother,
+                                 int nu1, int nu2, T w) {
+    const int lane = threadIdx.x;
+    auto nn = [&](int l) { return ((n_t + 1) >> l) - 1; };
+    auto off = [&](int l) {
+        int o = 0;
+        for (int j = 0; j < l; ++j) o += npts<D>(nn(j));
+        return o;
+    };
+    const T wts[3] = {T(0.25), T(0.5), T(0.25)};
+    // one smoothing step on level (e, r) of n points per axis
+    auto smooth = [&](T* e, const T* r, int n, T a, T diag, T invdiag) {
+        const int N = npts<D>(n);
+        int x = 0, y = 0, z = 0;
+        if (lane < N) point_of<D>(lane, n, x, y, z);
+        if (smoother == ISDC_SMOOTH_RBGS) {
+            for (int colour = 0; colour < 2; ++colour) {
+                if (lane < N && ((x + y + z) & 1) == colour) {
+                    const T v = (r[lane] + a * nb_lds<T, D>(e, n, x, y, z, lane)) * invdiag;
+                    e[lane] = v;
+                }
+                wave_sync();
+            }
+        } else {
+            if (lane < N) {
+                const T c = e[lane];
+                lt[lane] = c + w * ((r[lane] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, lane))) * invdiag);
+            }
+            wave_sync();
+            if (lane < N) e[lane] = lt[lane];
+            wave_sync();
+        }
+    };
+    int l = l0;
+    for (; l < nlev; ++l) {
+        const int n = nn(l);
+        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
+        T* e = le + off(l);
+        T* r = lr + off(l);
+        if (n == 1) {
+            if (lane == 0) e[0] = r[0] / diag;
+            wave_sync();
+            break;
+        }
+        for (int k = 0; k < nu1; ++k) smooth(e, r, n, a, diag, invdiag);
+        const int N = npts<D>(n);
+        if (lane < N) {
+            int x, y, z;
+            point_of<D>(lane, n, x, y, z);
+            lt[lane] = r[lane] - (diag * e[lane] - a * nb_lds<T, D>(e, n, x, y, z, lane));
+        }
+        wave_sync();
+        const int nc = (n - 1) / 2;
+        T* rc = lr + off(l + 1);
+        T* ec = le + off(l + 1);
+        if (lane < npts<D>(nc)) {
+            int X, Y, Z;
+            point_of<D>(lane, nc, X, Y, Z);
+            T acc = T(0);
+#pragma unroll
+            for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz)
+#pragma unroll
+                for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
+                    const int fy = D >= 2 ? 2 * Y + oy : 0, fz = D == 3 ? 2 * Z + oz : 0;
+                    const int base = (D == 1 ? 0 : (fz * n + fy) * n) + 2 * X;
+                    T row = wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2];
+                    acc += (D >= 2 ? wts[oy] : T(1)) * (D == 3 ? wts[oz] : T(1)) * row;
+                }
+            rc[lane] = acc;
+            ec[lane] = T(0);
+        }
+        wave_sync();
+    }
+    for (l = nlev - 2; l >= l0; --l) {
+        const int n = nn(l);
+        const int nc = nn(l + 1);
+        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
+        T* e = le + off(l);
+        T* r = lr + off(l);
+        const T* ec = le + off(l + 1);
+        const int N = npts<D>(n);
+        int x = 0, y = 0, z = 0;
+        if (lane < N) point_of<D>(lane, n, x, y, z);
+        int k0 = 0;
+        if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
+            if (lane < N && ((x + y + z) & 1) == 0) {
+                const T v = (r[lane] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, lane)) * invdiag;
+                e[lane] = v;
+            }
+            wave_sync();
+            if (lane < N && ((x + y + z) & 1) == 1) {
+                const T v = (r[lane] + a * nb_lds<T, D>(e, n, x, y, z, lane)) * invdiag;
+                e[lane] = v;
+            }
+            wave_sync();
+            k0 = 1;
+        } else {
+            if (lane < N) {
+                const T v = e[lane] + interp_at<T, D>(ec, nc, x, y, z);
+                e[lane] = v;
+            }
+            wave_sync();
+        }
+        for (int k = k0; k < nu2; ++k) smooth(e, r, n, a, diag, invdiag);
+    }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t,
                                           const TailCoefs& tc, int smoother, int nu1, int nu2, double omega,
@@ -495,7 +655,10 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
     }
     __syncthreads();
     const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int l = 0; l < nlev; ++l) {
+    // levels from lw on have at most 64 points: the first wave runs them alone
+    int lw = 0;
+    while (lw < nlev && npts<D>(nn(lw)) > 64) ++lw;
+    for (int l = 0; l < lw; ++l) {
         const int n = nn(l);
         const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
         T* e = le + off(l);
@@ -533,7 +696,11 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
         });
         __syncthreads();
     }
-    for (int l = nlev - 2; l >= 0; --l) {
+    if (lw < nlev) {
+        if (threadIdx.x < 64) tail_wave_levels<T, D>(le, lr, lt, lc, n_t, lw, nlev, smoother, nu1, nu2, T(omega));
+        __syncthreads();
+    }
+    for (int l = lw - 1; l >= 0; --l) {
         const int n = nn(l);
         const int nc = nn(l + 1);
         const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
