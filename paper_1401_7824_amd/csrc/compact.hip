@@ -223,6 +223,34 @@ __global__ void __launch_bounds__(kB) k_cres(CResArgs a, double* __restrict__ pa
     if (threadIdx.x == 0) partial[(size_t)k * gridDim.x + blockIdx.x] = v;
 }
 
+// ---------------------------------------------------------------- W^{-1} by Chebyshev iteration
+// W = I + (h^2/12) L_h on the finest grid: W x = x + (edges - 4 x) / 12, whose
+// Jacobi-scaled spectrum D^{-1} W lies in [1/2, 3/2] (D = 2/3) for both
+// boundary conditions.  One step of the Chebyshev iteration on that interval
+// (centre 1, half-width 1/2):
+//   r = D^{-1} (y - W x),  d = cd d + cr r  (first step: d = r),  x_out = x + d.
+// KIND 0: first step from x = 0 (x_in not read); 1: first step from x_in;
+// 2: a later step.
+template <bool PER, int KIND>
+__global__ void __launch_bounds__(kB)
+k_wcheb(const double* __restrict__ y, const double* __restrict__ x_in, double* __restrict__ x_out,
+        double* __restrict__ d, int n, double cd, double cr) {
+    const int x = blockIdx.x * kB + threadIdx.x, yy = blockIdx.y;
+    if (x >= n) return;
+    const size_t i = (size_t)yy * n + x;
+    double wx = 0.0;
+    if (KIND != 0) {
+        const double c = x_in[i];
+        const double edges = at<PER>(x_in, n, x - 1, yy) + at<PER>(x_in, n, x + 1, yy) + at<PER>(x_in, n, x, yy - 1) +
+                             at<PER>(x_in, n, x, yy + 1);
+        wx = c + (edges - 4.0 * c) / 12.0;
+    }
+    const double r = (y[i] - wx) * 1.5;
+    const double dn = KIND == 2 ? cd * d[i] + cr * r : r;
+    d[i] = dn;
+    x_out[i] = (KIND != 0 ? x_in[i] : 0.0) + dn;
+}
+
 // ---------------------------------------------------------------- WENO5 advection
 // f^E(u) = -sum over axes of (F_{i+1/2} - F_{i-1/2}) / h for the flux u^2/2
 // (periodic).  F_{i+1/2} is the fifth-order WENO reconstruction (Jiang-Shu
@@ -525,6 +553,19 @@ hipError_t launch_cres(const CResArgs& a, double* partial, int* nblocks, hipStre
     const int per = kCResBlocks;
     *nblocks = per * a.count;
     hipLaunchKernelGGL(k_cres, dim3(per, a.count), dim3(kB), 0, s, a, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_wcheb(int n, bool per, int kind, const double* y, const double* x_in, double* x_out, double* d,
+                        double cd, double cr, hipStream_t s) {
+#define ISDC_WCHEB(P, K) \
+    hipLaunchKernelGGL((k_wcheb<P, K>), grid2(n), dim3(kB), 0, s, y, x_in, x_out, d, n, cd, cr)
+    if (per) {
+        if (kind == 0) ISDC_WCHEB(true, 0); else if (kind == 1) ISDC_WCHEB(true, 1); else ISDC_WCHEB(true, 2);
+    } else {
+        if (kind == 0) ISDC_WCHEB(false, 0); else if (kind == 1) ISDC_WCHEB(false, 1); else ISDC_WCHEB(false, 2);
+    }
+#undef ISDC_WCHEB
     return hipGetLastError();
 }
 

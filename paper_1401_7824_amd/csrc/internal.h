@@ -231,6 +231,11 @@ hipError_t launch_cquad(const CQuadArgs& a, int M, bool per, hipStream_t s);
 hipError_t launch_cres(const CResArgs& a, double* partial, int* nblocks, hipStream_t s);
 // out = the periodic WENO5 Burgers advection -div(u^2/2) of u (n^2, spacing h).
 hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hipStream_t s);
+// One Chebyshev step for W x = y on the finest 2D grid (W = I + (h^2/12) L_h):
+// kind 0 = first step from zero, 1 = first step from x_in, 2 = later step with
+// coefficients cd, cr; x_out and x_in must differ, d is updated in place.
+hipError_t launch_wcheb(int n, bool per, int kind, const double* y, const double* x_in, double* x_out, double* d,
+                        double cd, double cr, hipStream_t s);
 // One V-cycle of B (weighted Jacobi V(nu_pre, nu_post)) on a level of at
 // most 63^2 (Dirichlet) or 32^2 (periodic) points in one workgroup.
 template <typename T>

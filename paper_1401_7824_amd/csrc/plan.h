@@ -82,11 +82,10 @@ struct isdc_plan {
     double* scalars;
 
     // compact stencil (eq. (5)): B = W - c A_h, weighted Jacobi; W inverted
-    // for the residual by red-black V-cycles (wmg) of I + w L
+    // for the residual by Chebyshev iteration
     bool compact = false;
     bool periodic = false;         // [-1, 1)^2 with n = 2^k points per axis, h = 2 / n
     double w = 0.0;                // h^2 / 12
-    isdc::MGConfig wmg;
     double* Yq[ISDC_MAX_M];        // dt Q_m F~ per node m+1 (NULL: node with Q row 0)
     double* X[ISDC_MAX_M];         // W^{-1} Yq[m], warm start of the next sweep's solve
     bool x_valid = false;

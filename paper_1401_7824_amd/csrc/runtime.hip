@@ -337,10 +337,14 @@ void quad_residual(isdc_plan* p, const double* const* nodes, hipStream_t s) {
 
 // ---------------------------------------------------------------- compact stencil (eq. (5))
 
-// W^{-1} for the residual: red-black V(1,1) cycles on I + w L, from zero after
-// the first sweep of a step, then warm-started from the previous sweep's value.
-constexpr int kWColdCycles = 14;
-constexpr int kWWarmCycles = 6;
+// W^{-1} for the residual (Sec. 3): Chebyshev iteration on W = I + (h^2/12) L_h,
+// whose Jacobi-scaled spectrum lies in [1/2, 3/2], so the error falls by at
+// least (sqrt(3) - 1) / (sqrt(3) + 1) = 0.268 per step: 28 steps from zero
+// (below 1e-15 relative) after the first sweep of a step, then 12 steps
+// warm-started from the previous sweep's value (the change of W^{-1} Y between
+// sweeps shrinks with the SDC residual).
+constexpr int kWColdSteps = 28;
+constexpr int kWWarmSteps = 12;
 
 // One V-cycle of B_H = I + w L_H - c A_H with weighted-Jacobi smoothing on
 // level l; same contract as vcycle_rec (result in e; tmp: scratch of the level).
@@ -443,12 +447,26 @@ void cquad(isdc_plan* p, const double* const* nodes, const double* const* fe, hi
 // inverted once per node), after cquad of the same node values.  W = I + w L:
 // Dirichlet plans invert it with red-black V(1,1) cycles of the second-order
 // solver (c = -w); periodic plans with the compact Jacobi cycle at c = 0.
-// One cycle of the W solve W x = y (from zero if `zero`).
-void wsolve_cycle(isdc_plan* p, bool zero, const double* y, double* x, hipStream_t s) {
-    if (p->periodic)
-        cvcycle_rec<double>(p, p->wmg, 0, 0.0, zero, y, x, (double*)p->lev[0].e2, s);
-    else
-        vcycle_rec<double>(p, p->wmg, 0, -p->w, zero, y, x, (double*)p->lev[0].e2, s);
+// `steps` Chebyshev steps for W x = y from x = 0 (zero) or from x; tmp and d
+// are scratch arrays of the finest level.  Even step counts end in x.
+void wsolve(isdc_plan* p, bool zero, int steps, const double* y, double* x, double* tmp, double* d,
+            hipStream_t s) {
+    double* cur = x;
+    double* other = tmp;
+    double rho = 0.5;  // 1 / sigma, sigma = centre / half-width = 2
+    for (int k = 0; k < steps; ++k) {
+        double cd = 0.0, cr = 0.0;
+        int kind = k == 0 ? (zero ? 0 : 1) : 2;
+        if (k > 0) {
+            const double rn = 1.0 / (4.0 - rho);  // 1 / (2 sigma - rho)
+            cd = rn * rho;
+            cr = 4.0 * rn;  // 2 rho_k / half-width
+            rho = rn;
+        }
+        HIPCHK(launch_wcheb(p->n, p->periodic, kind, y, cur, other, d, cd, cr, s));
+        std::swap(cur, other);
+    }
+    if (cur != x) HIPCHK(launch_copy<double>(cur, x, p->N, s));
 }
 
 double cresidual(isdc_plan* p, hipStream_t s) {
@@ -456,10 +474,10 @@ double cresidual(isdc_plan* p, hipStream_t s) {
     std::memset(&ra, 0, sizeof(ra));
     ra.u0 = p->u0;
     ra.N = p->N;
-    const int ncyc = p->x_valid ? kWWarmCycles : kWColdCycles;
+    const int steps = p->x_valid ? kWWarmSteps : kWColdSteps;
     for (int m = 0; m < p->M; ++m) {
         if (!p->Yq[m]) continue;
-        for (int k = 0; k < ncyc; ++k) wsolve_cycle(p, !p->x_valid && k == 0, p->Yq[m], p->X[m], s);
+        wsolve(p, !p->x_valid, steps, p->Yq[m], p->X[m], (double*)p->lev[0].e2, (double*)p->lev[0].e, s);
         ra.um[ra.count] = p->cur[m + 1];
         ra.xm[ra.count] = p->X[m];
         ++ra.count;
@@ -662,7 +680,7 @@ double sweep_any(isdc_plan* p, hipStream_t s) {
 // Gauss-Legendre steps end between the last node and T_{n+1}: the result is
 // u_0 + dt sum_j b_j f(u_j) (Sec. 1), formed by the quadrature kernel with the
 // weights b as its only row; the compact stencil keeps W f~, so W^{-1} is
-// applied first (cold W cycles, as for the residual of a step's first sweep).
+// applied first (cold W steps, as for the residual of a step's first sweep).
 void end_quadrature(isdc_plan* p, double* d_out, hipStream_t s) {
     const double* add = p->END;
     if (p->compact) {
@@ -680,7 +698,7 @@ void end_quadrature(isdc_plan* p, double* d_out, hipStream_t s) {
         a.M = p->M;
         HIPCHK(launch_cquad(a, p->M, p->periodic, s));
         double* x = (double*)p->lev[0].e;
-        for (int k = 0; k < kWColdCycles; ++k) wsolve_cycle(p, k == 0, p->END, x, s);
+        wsolve(p, true, kWColdSteps, p->END, x, (double*)p->lev[0].e2, (double*)p->lev[0].r, s);
         add = x;
     } else {
         QuadArgs qa;
@@ -741,10 +759,6 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->w = p->h * p->h / 12.0;
     p->mg = MGConfig{p->d, par->smoother, par->nu_pre, par->nu_post,
                      p->compact ? 1.0 : 2.0 * p->d / (2.0 * p->d + 1.0)};
-    // W solves of the residual: red-black V(1,1) of the second-order solver
-    // (Dirichlet), or the compact weighted-Jacobi V(2,2) cycle at c = 0 (periodic)
-    p->wmg = p->periodic ? MGConfig{p->d, ISDC_SMOOTH_JACOBI, 2, 2, 1.0}
-                         : MGConfig{p->d, ISDC_SMOOTH_RBGS, 1, 1, 2.0 * p->d / (2.0 * p->d + 1.0)};
     p->fe_arrays = prob->fe_kind == ISDC_FE_BURGERS;
     p->FE0 = nullptr;
     std::memset(p->FEU, 0, sizeof(p->FEU));
