@@ -376,6 +376,52 @@ def run_batch(args, torch):
     return out
 
 
+def serve_accuracy(reqs, torch, rd_sample=8):
+    """Error of each served result (float32 V-cycles, the request's own SDC
+    tolerance) against a float64 reference, relative L2: heat requests against
+    the exact collocation solution after nsteps steps (each sine mode of u_0
+    multiplied by R(dt nu lambda)^nsteps, R the collocation stability function
+    from the library's Q table); reaction-diffusion requests (the rd_sample
+    smallest) against an all-float64 plan run to SDC tolerance 1e-12."""
+    import numpy as np
+    from paper_1401_7824_amd import Plan, tables, workloads as W
+    rows = []
+    for r in reqs:
+        if r.result is None or r.status != "ok":
+            continue
+        got = r.result.detach().cpu().numpy()
+        if r.fe_kind == 0:
+            h = 1.0 / (r.n + 1)
+            Q = np.array(tables(r.node_kind, r.M)[1])
+            modes = W.draw_modes(r.dim, 8, seed=10_000 + r.rid, max_wave=4)
+            lam = [sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in modes]
+            R = [np.linalg.solve(np.eye(r.M) - r.dt * r.nu * l * Q, np.ones(r.M))[-1] for l in lam]
+            ref = W.sine_field(r.n, r.dim, [(amp * Rk ** r.nsteps, a) for (amp, a), Rk in zip(modes, R)])
+            kind = "heat vs exact collocation"
+        else:
+            continue
+        rows.append(dict(rid=r.rid, dim=r.dim, n=r.n, tol=r.sdc_tol, steps=r.nsteps, kind=kind,
+                         rel_l2=float(np.linalg.norm(got - ref) / np.linalg.norm(ref))))
+    rd = sorted((r for r in reqs if r.fe_kind == 1 and r.result is not None and r.status == "ok"),
+                key=lambda r: r.n ** r.dim)[:rd_sample]
+    for r in rd:
+        p = Plan(r.dim, r.n, r.nu, r.fe_kind, node_kind=r.node_kind, M=r.M, sdc_tol=1e-12, max_sweeps=400,
+                 precision=0)
+        u = torch.from_numpy(r.u0).cuda()
+        for _ in range(r.nsteps):
+            p.step(u, r.dt)
+        ref = u.cpu().numpy()
+        got = r.result.detach().cpu().numpy()
+        rows.append(dict(rid=r.rid, dim=r.dim, n=r.n, tol=r.sdc_tol, steps=r.nsteps,
+                         kind="reaction-diffusion vs float64 at tol 1e-12",
+                         rel_l2=float(np.linalg.norm(got - ref) / np.linalg.norm(ref))))
+    worst = {}
+    for row in rows:
+        key = f"tol {row['tol']:g}"
+        worst[key] = max(worst.get(key, 0.0), row["rel_l2"])
+    return {"checked": len(rows), "max_rel_l2_by_tolerance": worst, "per_result": rows}
+
+
 def run_serve(args, torch):
     """Serving: Poisson arrivals of mixed 2D (127^2..1023^2) and 3D (31^3..255^3)
     heat / reaction-diffusion requests (tolerance 1e-5 or 1e-8, 1..20 steps),
@@ -392,8 +438,10 @@ def run_serve(args, torch):
 
     warm = make_requests(8, rate=0.0, seed=99)
     server().serve(warm)
-    sat = server().serve(make_requests(count, rate=0.0, seed=5))
+    sat_reqs = make_requests(count, rate=0.0, seed=5)
+    sat = server().serve(sat_reqs)
     cap = sat.completed / sat.makespan
+    accuracy = serve_accuracy(sat_reqs, torch)
     print(f"[serve] saturated: {sat.completed} requests in {sat.makespan:.2f} s", file=sys.stderr, flush=True)
     rows = []
     for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
@@ -415,7 +463,7 @@ def run_serve(args, torch):
         "config": {"workload": f"serve: {count} requests, half 2D 127..1023, half 3D 31..255, heat / "
                                f"reaction-diffusion, tol 1e-5 / 1e-8, 1..20 steps, HBM budget "
                                f"{args.serve_budget_gb} GiB, 64 slots per dimension"},
-        "saturated": sat.summary(), "rate_sweep": rows, "sequential_baseline_at_0.25": seq,
+        "saturated": sat.summary(), "accuracy": accuracy, "rate_sweep": rows, "sequential_baseline_at_0.25": seq,
         "sequential_baseline_saturated": seq_sat,
         "capacity_vs_sequential": round(cap / seq_sat["throughput_req_s"], 2) if seq_sat["throughput_req_s"] else None,
     }
