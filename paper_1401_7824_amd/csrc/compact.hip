@@ -316,18 +316,21 @@ __device__ __forceinline__ T capply_lds(const T* e, int n, int x, int y, int i, 
         edges = e[y * n + xm] + e[y * n + xp] + e[ym * n + x] + e[yp * n + x];
         corners = e[ym * n + xm] + e[ym * n + xp] + e[yp * n + xm] + e[yp * n + xp];
     } else {
-        if (x > 0) edges += e[i - 1];
-        if (x < n - 1) edges += e[i + 1];
-        if (y > 0) edges += e[i - n];
-        if (y < n - 1) edges += e[i + n];
-        if (y > 0) {
-            if (x > 0) corners += e[i - n - 1];
-            if (x < n - 1) corners += e[i - n + 1];
-        }
-        if (y < n - 1) {
-            if (x > 0) corners += e[i + n - 1];
-            if (x < n - 1) corners += e[i + n + 1];
-        }
+        // unconditional loads (an outside neighbour reads the point itself),
+        // then zeros in place of the outside terms: the same sums as skipping them
+        const bool xl = x > 0, xr = x < n - 1, yd = y > 0, yu = y < n - 1;
+        const T vxl = e[xl ? i - 1 : i], vxr = e[xr ? i + 1 : i];
+        const T vyd = e[yd ? i - n : i], vyu = e[yu ? i + n : i];
+        const T vdl = e[yd && xl ? i - n - 1 : i], vdr = e[yd && xr ? i - n + 1 : i];
+        const T vul = e[yu && xl ? i + n - 1 : i], vur = e[yu && xr ? i + n + 1 : i];
+        edges += xl ? vxl : T(0);
+        edges += xr ? vxr : T(0);
+        edges += yd ? vyd : T(0);
+        edges += yu ? vyu : T(0);
+        corners += yd && xl ? vdl : T(0);
+        corners += yd && xr ? vdr : T(0);
+        corners += yu && xl ? vul : T(0);
+        corners += yu && xr ? vur : T(0);
     }
     return b0 * e[i] + bf * edges + bc * corners;
 }
@@ -370,20 +373,31 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
     __syncthreads();
     const T w = T(omega);
     const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    auto jacobi = [&](T* e, const T* r, int n, T b0, T bf, T bc) {
+    // nsteps Jacobi steps ping-ponging between e and lt (one phase each), the
+    // result copied back to e after an odd count
+    auto jacobi = [&](T* e, const T* r, int n, T b0, T bf, T bc, int nsteps) {
         const T inv = T(1) / b0;
-        phase<T, 2>(n, lt, [&](bool ok, int x, int y, int, int i, T& v) {
-            if (!ok) return false;
-            v = e[i] + w * (r[i] - capply_lds<PER>(e, n, x, y, i, b0, bf, bc)) * inv;
-            return true;
-        });
-        __syncthreads();
-        phase<T, 2>(n, e, [&](bool ok, int, int, int, int i, T& v) {
-            if (!ok) return false;
-            v = lt[i];
-            return true;
-        });
-        __syncthreads();
+        T* src = e;
+        T* dst = lt;
+        for (int k = 0; k < nsteps; ++k) {
+            phase<T, 2>(n, dst, [&](bool ok, int x, int y, int, int i, T& v) {
+                if (!ok) return false;
+                v = src[i] + w * (r[i] - capply_lds<PER>(src, n, x, y, i, b0, bf, bc)) * inv;
+                return true;
+            });
+            __syncthreads();
+            T* t = src;
+            src = dst;
+            dst = t;
+        }
+        if (src != e) {
+            phase<T, 2>(n, e, [&](bool ok, int, int, int, int i, T& v) {
+                if (!ok) return false;
+                v = src[i];
+                return true;
+            });
+            __syncthreads();
+        }
     };
     for (int l = 0; l < nlev; ++l) {
         const int n = nn(l);
@@ -397,7 +411,7 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
             __syncthreads();
             break;
         }
-        for (int k = 0; k < nu1; ++k) jacobi(e, r, n, b0, bf, bc);
+        jacobi(e, r, n, b0, bf, bc, nu1);
         phase<T, 2>(n, lt, [&](bool ok, int x, int y, int, int i, T& v) {
             if (!ok) return false;
             v = r[i] - capply_lds<PER>(e, n, x, y, i, b0, bf, bc);
@@ -452,7 +466,7 @@ k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc
             return true;
         });
         __syncthreads();
-        for (int k = 0; k < nu2; ++k) jacobi(e, r, n, b0, bf, bc);
+        jacobi(e, r, n, b0, bf, bc, nu2);
     }
     {
         constexpr int I = (L::big + kTail - 1) / kTail;

@@ -451,28 +451,41 @@ __device__ __forceinline__ T nb_corrected(const T* e, const T* ec, int n, int nc
     return s;
 }
 
+// nsteps smoothing steps on a level.  Red-black works in place (a colour reads
+// only the other colour); Jacobi ping-pongs between e and tmp, one phase per
+// step, and copies the result back to e after an odd count.
 template <typename T, int D>
-__device__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invdiag, T w, int smoother) {
+__device__ __forceinline__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invdiag, T w, int smoother,
+                                            int nsteps) {
     if (smoother == ISDC_SMOOTH_RBGS) {
-        for (int colour = 0; colour < 2; ++colour) {
-            // a colour reads only the other colour: no barrier between compute and store
-            phase_colour<T, D>(n, colour, e, [&](int x, int y, int z, int i, T& v) {
-                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-        }
-    } else {
-        phase<T, D>(n, tmp, [&](bool ok, int x, int y, int z, int i, T& v) {
+        for (int k = 0; k < nsteps; ++k)
+            for (int colour = 0; colour < 2; ++colour) {
+                phase_colour<T, D>(n, colour, e, [&](int x, int y, int z, int i, T& v) {
+                    v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
+                    return true;
+                });
+                __syncthreads();
+            }
+        return;
+    }
+    T* src = e;
+    T* dst = tmp;
+    for (int k = 0; k < nsteps; ++k) {
+        phase<T, D>(n, dst, [&](bool ok, int x, int y, int z, int i, T& v) {
             if (!ok) return false;
-            const T c = e[i];
-            v = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, i))) * invdiag);
+            const T c = src[i];
+            v = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(src, n, x, y, z, i))) * invdiag);
             return true;
         });
         __syncthreads();
-        phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
+        T* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != e) {
+        phase<T, D>(n, e, [&](bool ok, int, int, int, int i, T& v) {
             if (!ok) return false;
-            v = tmp[i];
+            v = src[i];
             return true;
         });
         __syncthreads();
@@ -668,7 +681,7 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
             __syncthreads();
             break;
         }
-        for (int k = 0; k < nu1; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
+        tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother, nu1);
         phase<T, D>(n, lt, [&](bool ok, int x, int y, int z, int i, T& v) {
             if (!ok) return false;
             v = r[i] - (diag * e[i] - a * nb_lds<T, D>(e, n, x, y, z, i));
@@ -730,7 +743,7 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __rest
             });
             __syncthreads();
         }
-        for (int k = k0; k < nu2; ++k) tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother);
+        tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother, nu2 - k0);
     }
     {
         constexpr int I = (L::big + kTail - 1) / kTail;
