@@ -104,6 +104,14 @@ KERNEL_NAMES = {
 }
 
 
+# 2D levels run the row-mapped tile kernels
+ROW_KERNEL_NAMES = {
+    "smooth": "k_rows_rbgs<{T},false,{S}>",
+    "smooth_restrict": "k_rows_rbgs_restrict<{T},false,{S}>",
+    "prolong_smooth": "k_rows_prolong_rbgs<{T},0,{S}>",
+}
+
+
 def kernel_name(name, cfg, T, shape=0):
     """rocprof name of the kernel bench.py times for `name` on the finest level
     (tile shape `shape`; 3D levels of 127^3 and up run the z-marching form)."""
@@ -113,6 +121,8 @@ def kernel_name(name, cfg, T, shape=0):
                 "explicit": "k_weno_burgers"}[name]
     if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
         return f"k_march_rbgs<{T},true,0,false>"
+    if cfg["dim"] == 2 and name in ROW_KERNEL_NAMES:
+        return ROW_KERNEL_NAMES[name].format(T=T, S=shape)
     return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"], S=shape)
 
 
@@ -489,7 +499,7 @@ def run_kernels(args, torch):
         if d < 3:
             kinds.insert(0, ("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT))
         nl = len(p.tile_shapes)
-        shapes = range(3) if (d < 3 or n < 127) else [0]  # 3D levels of 127^3 and up are z-marched
+        shapes = range(3)  # tile shapes (3D levels of 127^3 and up: column depths of the z-march)
         for name, k in kinds:
             best = None
             for sh in shapes:  # every tile shape on the finest level; the fastest is reported

@@ -244,11 +244,13 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * 32x8x4 points per workgroup), shapes 1 and 2 are smaller (1D 512 / 256,
  * 2D 32x16 / 32x8, 3D 16x8x4 / 16x4x4).  Every shape computes the same values
  * (the V-cycle of Sec. 3 is unchanged); only the launch shape differs.
+ * On 3D levels of 127^3 and up, which run z-marching kernels, the shape picks
+ * the depth of a workgroup's column of planes instead: 16, 32 or 8 planes
+ * (4, 8 or 2 on 127^3).
  * isdc_autotune times the red-black kernels of every level with each shape
  * (three rounds of `reps` launches on `stream`, the fastest round of each
  * shape compared) and keeps the fastest; levels where the shape changes
- * nothing (Jacobi smoothing, compact stencil, 3D levels of 127^3 and up,
- * which run z-marching kernels) keep shape 0.  It synchronises `stream`,
+ * nothing (Jacobi smoothing, compact stencil) keep shape 0.  It synchronises `stream`,
  * overwrites the plan's multigrid buffers, and is refused during a step.
  * The shapes, or a saved list, are read and written with the two calls
  * below; nlevels is the number of levels above the tail (*h_nlevels), and

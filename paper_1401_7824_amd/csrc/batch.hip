@@ -27,12 +27,14 @@
 #include "mg_device.h"
 #include "mg_march.h"
 #include "plan.h"
+#include "rows2d.h"
 #include "sdc_device.h"
 
 namespace isdc {
 namespace {
 
 constexpr int kMaxLev = 16;
+using BRow = RowShape<0>::RT;  // the row tile of 2D levels
 constexpr int kChunkPts = 4 * kThreads;  // points per workgroup of the pointwise kernels
 
 struct SlotDesc {
@@ -122,9 +124,15 @@ __global__ void __launch_bounds__(kThreads) kb_rbgs_restrict(BArgs a) {
     const SlotDesc& s = a.desc[i];
     const int l = a.level, p = a.p;
     int x0, y0, z0;
-    tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
-    rbgs_restrict_body<T, D, ZERO>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], (T*)s.lr[l + 1], s.ln[l], x0,
-                                   y0, z0, T(s.la[p][l]), T(s.ldiag[p][l]), T(s.linv[p][l]));
+    if constexpr (D == 2) {
+        tile_xyz<D>(t, s.ln[l], BRow::TX, BRow::TY, 1, x0, y0, z0);
+        rows_rbgs_restrict_body<T, ZERO, BRow>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], (T*)s.lr[l + 1],
+                                               s.ln[l], x0, y0, T(s.la[p][l]), T(s.ldiag[p][l]), T(s.linv[p][l]));
+    } else {
+        tile_xyz<D>(t, s.ln[l], Tile<D>::X, Tile<D>::Y, Tile<D>::Z, x0, y0, z0);
+        rbgs_restrict_body<T, D, ZERO>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], (T*)s.lr[l + 1], s.ln[l],
+                                       x0, y0, z0, T(s.la[p][l]), T(s.ldiag[p][l]), T(s.linv[p][l]));
+    }
 }
 
 template <typename T, int D, bool ZERO>
@@ -135,7 +143,11 @@ __global__ void __launch_bounds__(kThreads) kb_rbgs(BArgs a) {
     const int l = a.level, p = a.p;
     int x0, y0, z0;
     const int mz = D == 3 ? march_depth(s.ln[l]) : 0;
-    if (D == 3 && mz > 0) {
+    if constexpr (D == 2) {
+        tile_xyz<D>(t, s.ln[l], BRow::TX, BRow::TY, 1, x0, y0, z0);
+        rows_rbgs_body<T, ZERO, BRow>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], s.ln[l], x0, y0,
+                                      T(s.la[p][l]), T(s.linv[p][l]));
+    } else if (D == 3 && mz > 0) {
         tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
         march_rbgs_body<T, false, 0, ZERO>((const T*)s.lr[l], (const T*)s.le[l], nullptr, (T*)s.le2[l], s.ln[l], x0, y0,
                                            z0, mz, T(s.la[p][l]), T(s.linv[p][l]), nullptr, nullptr);
@@ -180,7 +192,11 @@ __global__ void __launch_bounds__(kThreads) kb_prolong_rbgs(BArgs a) {
     const double* g = MODE == 1 ? s.U[par ^ 1][m + 1] : nullptr;
     double* u_out = MODE == 1 ? s.U[par][m + 1] : nullptr;
     const int mz = D == 3 ? march_depth(s.ln[l]) : 0;
-    if (D == 3 && mz > 0) {
+    if constexpr (D == 2) {
+        tile_xyz<D>(t, s.ln[l], BRow::TX, BRow::TY, 1, x0, y0, z0);
+        rows_prolong_rbgs_body<T, MODE, BRow>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1],
+                                              (T*)s.le[l], s.ln[l], x0, y0, T(s.la[p][l]), T(s.linv[p][l]), g, u_out);
+    } else if (D == 3 && mz > 0) {
         tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
         march_rbgs_body<T, true, MODE, false>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1],
                                               (T*)s.le[l], s.ln[l], x0, y0, z0, mz, T(s.la[p][l]), T(s.linv[p][l]), g,
@@ -341,8 +357,10 @@ int tiles_fine(int d, int n) {
                             : ntiles_of<3>(n, Tile<3>::X, Tile<3>::Y, Tile<3>::Z));
 }
 
-// Workgroups of the smoothing kernels on an n^d level (3D: marched columns).
+// Workgroups of the smoothing kernels on an n^d level (3D: marched columns,
+// 2D: row-mapped tiles).
 int tiles_smooth(int d, int n) {
+    if (d == 2) return ntiles_of<2>(n, BRow::TX, BRow::TY, 1);
     return (d == 3 && march_depth(n) > 0) ? ntiles_of<3>(n, MTile::X, MTile::Y, march_depth(n)) : tiles_fine(d, n);
 }
 

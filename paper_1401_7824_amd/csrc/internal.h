@@ -71,12 +71,10 @@ int tail_max_n(int d);
 // Tiled kernels (mg_tiles.hip).  One complete red-black Gauss-Seidel step
 // from e_in to e_out (e_out != e_in; zero: e_in is identically zero and is
 // not read).
-// `shape` selects the tile shape of the tiled kernels (0 .. kTileShapes - 1;
-// 0 = the default tile); every shape computes the same values.
+// `shape` selects the tile shape of the tiled kernels, or the column depth of
+// the z-marching kernels on 3D levels of 127^3 and up (0 .. kTileShapes - 1;
+// 0 = the default); every shape computes the same values.
 constexpr int kTileShapes = 3;
-// Whether the tile shape of a level with n points per axis changes which
-// kernels run (3D levels of 127^3 and up use the z-marching kernels).
-bool tile_shape_applies(int d, int n);
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                             hipStream_t s, int shape = 0);

@@ -33,7 +33,15 @@ struct MTile { static constexpr int X = 32, Y = 16; };
 // Planes per marched column on an n^3 level, or 0 where the one-pass 3D tile
 // kernels are used instead: a column costs a chain of Z + 4 dependent steps,
 // which only pays where the level is large enough to fill the chip anyway.
-__host__ __device__ constexpr int march_depth(int n) { return n >= 255 ? 16 : (n >= 127 ? 4 : 0); }
+// The tile shape of a marched level picks the depth: shape 0 the default,
+// 1 twice as deep (fewer workgroups, less z overlap), 2 half as deep (more
+// workgroups, shorter chains).  Every depth is even, so a column starts on an
+// even plane, which the coarse-plane bookkeeping of the prolongation assumes.
+__host__ __device__ constexpr int march_depth(int n, int shape = 0) {
+    const int base = n >= 255 ? 16 : (n >= 127 ? 4 : 0);
+    return shape == 1 ? 2 * base : (shape == 2 ? base / 2 : base);
+}
+static_assert(march_depth(127, 2) % 2 == 0 && march_depth(255, 2) % 2 == 0, "column depths are even");
 
 template <typename T, bool PRO, int MODE, bool ZERO>
 __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T* __restrict__ e_in,

@@ -12,7 +12,10 @@
 //                       red-black step; optionally writes g + e to a float64
 //                       node array instead of e (the node update of eq. (4));
 //   k_march_rbgs        the 3D form of the two red-black kernels above:
-//                       columns of planes marched in z instead of 3D tiles.
+//                       columns of planes marched in z instead of 3D tiles;
+//   k_rows_*            the 2D forms of the red-black, fused red-black +
+//                       restriction and prolongation + red-black kernels on
+//                       row-mapped tiles (rows2d.h).
 //
 // Workgroups are numbered so that each of the 8 XCDs (the hardware hands
 // workgroup b to XCD b mod 8) receives a contiguous band of tiles, keeping the
@@ -22,6 +25,7 @@
 #include "internal.h"
 #include "mg_device.h"
 #include "mg_march.h"
+#include "rows2d.h"
 
 namespace isdc {
 
@@ -77,6 +81,38 @@ k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __res
     march_rbgs_body<T, PRO, MODE, ZERO>(r, e_in, ec, e_out, n, x0, y0, z0, mz, a, invdiag, g, u_out);
 }
 
+// 2D row-mapped tiles (shape S selects the row tile).
+template <typename T, bool ZERO, int S>
+__global__ void __launch_bounds__(kThreads)
+k_rows_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty, T a,
+            T invdiag) {
+    using RT = typename RowShape<S>::RT;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
+    rows_rbgs_body<T, ZERO, RT>(r, e_in, e_out, n, x0, y0, a, invdiag);
+}
+
+template <typename T, bool ZERO, int S>
+__global__ void __launch_bounds__(kThreads)
+k_rows_rbgs_restrict(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
+                     int n, int ntx, int nty, T a, T diag, T invdiag) {
+    using RT = typename RowShape<S>::RT;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
+    rows_rbgs_restrict_body<T, ZERO, RT>(r, e_in, e_out, rc, n, x0, y0, a, diag, invdiag);
+}
+
+template <typename T, int MODE, int S>
+__global__ void __launch_bounds__(kThreads)
+k_rows_prolong_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec,
+                    T* __restrict__ e_out, int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g,
+                    double* __restrict__ u_out) {
+    using RT = typename RowShape<S>::RT;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
+    rows_prolong_rbgs_body<T, MODE, RT>(r, e_in, ec, e_out, n, x0, y0, a, invdiag, g, u_out);
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
@@ -109,17 +145,39 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, 
         default: return hipErrorInvalidValue;                                      \
     }
 
+// 2D row shape as the compile-time constant S
+#define ISDC_DISPATCH_ROWS(shape, ...)                                  \
+    switch (shape) {                                                    \
+        case 0: { constexpr int S = 0; __VA_ARGS__; } break;            \
+        case 1: { constexpr int S = 1; __VA_ARGS__; } break;            \
+        case 2: { constexpr int S = 2; __VA_ARGS__; } break;            \
+        default: return hipErrorInvalidValue;                           \
+    }
+
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                             hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
-        const int mz = march_depth(n);
+        if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
+        const int mz = march_depth(n, shape);
         int ntx, nty, nb;
         tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
         if (zero)
             hipLaunchKernelGGL((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         else
             hipLaunchKernelGGL((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+        return hipGetLastError();
+    }
+    if (d == 2) {
+        ISDC_DISPATCH_ROWS(shape, {
+            using RT = typename RowShape<S>::RT;
+            int ntx, nty, nb;
+            tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
+            if (zero)
+                hipLaunchKernelGGL((k_rows_rbgs<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            else
+                hipLaunchKernelGGL((k_rows_rbgs<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+        });
         return hipGetLastError();
     }
     ISDC_DISPATCH_DS(d, shape, {
@@ -149,6 +207,18 @@ template <typename T>
 hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                                      T* rc, hipStream_t s, int shape) {
     if (d == 3) return hipErrorInvalidValue;  // 3D uses the separate kernels (LDS budget)
+    if (d == 2) {
+        ISDC_DISPATCH_ROWS(shape, {
+            using RT = typename RowShape<S>::RT;
+            int ntx, nty, nb;
+            tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
+            if (zero)
+                hipLaunchKernelGGL((k_rows_rbgs_restrict<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+            else
+                hipLaunchKernelGGL((k_rows_rbgs_restrict<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+        });
+        return hipGetLastError();
+    }
     ISDC_DISPATCH_DS(d, shape, {
         if constexpr (D < 3) {
             using TL = TileS<D, S>;
@@ -167,7 +237,8 @@ template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
                                     T* e_out, const double* g, double* u_out, int mode, hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
-        const int mz = march_depth(n);
+        if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
+        const int mz = march_depth(n, shape);
         int ntx, nty, nb;
         tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
         if (mode == 0)
@@ -176,6 +247,20 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
             hipLaunchKernelGGL((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else
             hipLaunchKernelGGL((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+        return hipGetLastError();
+    }
+    if (d == 2) {
+        ISDC_DISPATCH_ROWS(shape, {
+            using RT = typename RowShape<S>::RT;
+            int ntx, nty, nb;
+            tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
+            if (mode == 0)
+                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            else if (mode == 1)
+                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            else
+                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+        });
         return hipGetLastError();
     }
     ISDC_DISPATCH_DS(d, shape, {
@@ -193,8 +278,6 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
 }
 
 static_assert(kShapes == kTileShapes, "tile shape count of the kernels and of the launchers");
-
-bool tile_shape_applies(int d, int n) { return !(d == 3 && march_depth(n) > 0); }
 
 int tail_max_n(int d) {
     return d == 1 ? TailLayout<1>::nmax : (d == 2 ? TailLayout<2>::nmax : TailLayout<3>::nmax);

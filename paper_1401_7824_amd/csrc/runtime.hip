@@ -1168,8 +1168,7 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
 namespace {
 
 bool level_shaped(const isdc_plan* p, int l) {
-    return !p->compact && p->mg.smoother == ISDC_SMOOTH_RBGS && l < p->tail &&
-           tile_shape_applies(p->d, p->lev[l].n);
+    return !p->compact && p->mg.smoother == ISDC_SMOOTH_RBGS && l < p->tail;
 }
 
 // The tiled kernels one V-cycle runs on level l (pre- and post-smoothing,

@@ -10,6 +10,8 @@ from __future__ import annotations
 import json
 import os
 
+VERSION = 2  # 2: the shape of a z-marched 3D level selects its column depth
+
 
 def path() -> str:
     return os.environ.get("ISDC_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "isdc",
@@ -21,8 +23,9 @@ def key(plan) -> str:
     props = torch.cuda.get_device_properties(plan.device)
     arch = getattr(props, "gcnArchName", props.name).split(":")[0]
     p = plan.params
-    return (f"{arch}:d{plan.dim}:n{plan.n}:stencil{plan.stencil}:prec{p.precision}:smoother{p.smoother}"
-            f":nu{p.nu_pre}{p.nu_post}")
+    # VERSION changes whenever what a shape number selects changes
+    return (f"v{VERSION}:{arch}:d{plan.dim}:n{plan.n}:stencil{plan.stencil}:prec{p.precision}"
+            f":smoother{p.smoother}:nu{p.nu_pre}{p.nu_post}")
 
 
 def _load() -> dict:

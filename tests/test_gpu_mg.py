@@ -213,6 +213,28 @@ def test_vcycle_parity_every_tile_shape(d, shape, dtype):
     assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_vcycle_parity_every_march_depth(dtype):
+    # 3D levels of 127^3 and up are z-marched; the shape picks the column
+    # depth (2, 4 or 8 planes at 127^3, the 63^3 level below uses tiles)
+    n, d = 127, 3
+    h = 1.0 / (n + 1)
+    c = 64.0 * h * h
+    nd = _np_dtype(dtype)
+    rhs = random_field((n,) * d, 27).astype(nd)
+    u0 = random_field((n,) * d, 28).astype(nd)
+    ref = u0
+    for _ in range(2):
+        ref = O.vcycle(ref, rhs, c, h, RBGS, 2, 2)
+    for shape in (0, 1, 2):
+        announce("vcycle march depth", n, shape, dtype)
+        p = _plan(d, n, RBGS, nu_pre=2, nu_post=2)
+        p.tile_shapes = [shape] * len(p.tile_shapes)
+        u = dev(u0, dtype)
+        p.vcycle(c, dev(rhs, dtype), u, ncycles=2)
+        assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5), shape
+
+
 def test_autotune_picks_valid_shapes_and_keeps_results(tmp_path, monkeypatch):
     from paper_1401_7824_amd import ISDCError
     announce("autotune")

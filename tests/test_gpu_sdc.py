@@ -74,6 +74,31 @@ def test_sweep_iterates_match_oracle(name, d, n, nu, fe, dt, par):
     np.testing.assert_array_equal(host(u0d), u0)  # u_0 is read only
 
 
+def test_sweep_iterates_match_oracle_every_march_depth():
+    # 127^3 runs the z-marched kernels, including the fused node update of a
+    # solve's last cycle; every column depth gives the oracle's iterates
+    d, n, nu, dt, M = 3, 127, 0.3, 2e-3, 3
+    par = dict(node_kind=RAD, M=M)
+    u0 = 2.0 * W.sine_field(n, d, W.draw_modes(d, 8, seed=113))
+    st = sdc_begin(u0, dt, 1.0 / (n + 1), _cfg(nu, O.FE_CUBIC, **par))
+    plans = []
+    for shape in (0, 1, 2):
+        p = _plan(d, n, nu, O.FE_CUBIC, **par)
+        p.tile_shapes = [shape] * len(p.tile_shapes)
+        p.begin(dev(u0), dt)
+        plans.append(p)
+    for k in range(2):
+        res_cpu = sdc_sweep(st)
+        for shape, p in enumerate(plans):
+            announce("sweeps march depth", n, shape, k)
+            res_gpu = p.sweep()
+            assert abs(res_gpu - res_cpu) <= 1e-6 * res_cpu, (shape, k)
+            for j in range(1, M + 1):
+                assert rel_l2(host(p.node_values(j)), st.U[j]) < 1e-12, (shape, k, j)
+    for p in plans:
+        p.end(dev(np.zeros_like(u0)))
+
+
 STEP_CASES = [
     ("heat1d-config", 1, 127, 1.0, O.FE_ZERO, 0.01, dict(node_kind=LOB, M=3, sdc_tol=1e-10)),
     ("rd2d-lob5", 2, 255, 0.1, O.FE_CUBIC, 1e-3, dict(node_kind=LOB, M=5, sdc_tol=1e-10)),
