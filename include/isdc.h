@@ -240,9 +240,9 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
                const void* d_a, const void* d_b, void* d_out, void* stream, double* h_scalar);
 
 /* Tile shapes of the multigrid kernels, one per level above the coarse tail
- * (level 0 = finest).  Shape 0 is the default tile (1D 1024, 2D 64x16, 3D
+ * (level 0 = finest).  Shape 0 is the default tile (1D 1024, 2D 56x16, 3D
  * 32x8x4 points per workgroup), shapes 1 and 2 are smaller (1D 512 / 256,
- * 2D 32x16 / 32x8, 3D 16x8x4 / 16x4x4).  Every shape computes the same values
+ * 2D 56x8 / 24x8, 3D 16x8x4 / 16x4x4).  Every shape computes the same values
  * (the V-cycle of Sec. 3 is unchanged); only the launch shape differs.
  * On 3D levels of 127^3 and up, which run z-marching kernels, the shape picks
  * the depth of a workgroup's column of planes instead: 16, 32 or 8 planes

@@ -26,6 +26,7 @@
 #include "mg_device.h"
 #include "mg_march.h"
 #include "rows2d.h"
+#include "tail2d.h"
 
 namespace isdc {
 
@@ -117,7 +118,10 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
        double omega, int zero_guess) {
-    tail_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
+    if constexpr (D == 2)
+        tail2_body<T>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
+    else
+        tail_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
 }
 
 }  // namespace
@@ -130,15 +134,13 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, 
         default: return hipErrorInvalidValue;                \
     }
 
-// dimension and tile shape (0 .. kShapes-1) as compile-time constants D, S
+// dimension (1 or 3; 2D levels run the row kernels) and tile shape
+// (0 .. kShapes-1) as compile-time constants D, S
 #define ISDC_DISPATCH_DS(d, shape, ...)                                            \
     switch ((d) * 4 + (shape)) {                                                   \
         case 4: { constexpr int D = 1, S = 0; __VA_ARGS__; } break;                \
         case 5: { constexpr int D = 1, S = 1; __VA_ARGS__; } break;                \
         case 6: { constexpr int D = 1, S = 2; __VA_ARGS__; } break;                \
-        case 8: { constexpr int D = 2, S = 0; __VA_ARGS__; } break;                \
-        case 9: { constexpr int D = 2, S = 1; __VA_ARGS__; } break;                \
-        case 10: { constexpr int D = 2, S = 2; __VA_ARGS__; } break;               \
         case 12: { constexpr int D = 3, S = 0; __VA_ARGS__; } break;               \
         case 13: { constexpr int D = 3, S = 1; __VA_ARGS__; } break;               \
         case 14: { constexpr int D = 3, S = 2; __VA_ARGS__; } break;               \
@@ -286,7 +288,7 @@ int tail_max_n(int d) {
 template <typename T>
 hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero_guess, const T* rhs, T* e,
                        hipStream_t s) {
-    if (n > tail_max_n(cfg.d)) return hipErrorInvalidValue;
+    if (n < 1 || n > tail_max_n(cfg.d) || ((n + 1) & n) != 0) return hipErrorInvalidValue;  // n = 2^k - 1
     TailCoefs tc;
     double hl = h;
     for (int l = 0, m = n; l < 16; ++l, m = (m - 1) / 2, hl *= 2.0) {

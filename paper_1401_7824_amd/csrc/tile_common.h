@@ -18,17 +18,16 @@ template <> struct Tile<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
 template <> struct Tile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
 template <> struct Tile<3> { static constexpr int X = 32, Y = 8, Z = 4; };
 
-// Shapes of the multigrid tile kernels: shape 0 is Tile<D>, shapes 1 and 2
-// are smaller tiles (more workgroups, shorter per-workgroup latency chains,
-// more halo per point).  A plan picks one per level (isdc_autotune).  Every
-// extent is even, so a tile's coarse points start at its origin / 2.
+// Shapes of the 1D and 3D multigrid tile kernels (2D levels use the row
+// tiles of rows2d.h): shape 0 is Tile<D>, shapes 1 and 2 are smaller tiles
+// (more workgroups, shorter per-workgroup latency chains, more halo per
+// point).  A plan picks one per level (isdc_autotune).  Every extent is even,
+// so a tile's coarse points start at its origin / 2.
 constexpr int kShapes = 3;
 template <int D, int S> struct TileS;
 template <int D> struct TileS<D, 0> : Tile<D> {};
 template <> struct TileS<1, 1> { static constexpr int X = 512, Y = 1, Z = 1; };
 template <> struct TileS<1, 2> { static constexpr int X = 256, Y = 1, Z = 1; };
-template <> struct TileS<2, 1> { static constexpr int X = 32, Y = 16, Z = 1; };
-template <> struct TileS<2, 2> { static constexpr int X = 32, Y = 8, Z = 1; };
 template <> struct TileS<3, 1> { static constexpr int X = 16, Y = 8, Z = 4; };
 template <> struct TileS<3, 2> { static constexpr int X = 16, Y = 4, Z = 4; };
 
