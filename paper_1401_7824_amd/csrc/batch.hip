@@ -28,7 +28,7 @@
 #include "mg_march.h"
 #include "plan.h"
 #include "rows2d.h"
-#include "tail2d.h"
+#include "tailc.h"
 #include "sdc_device.h"
 
 namespace isdc {
@@ -179,10 +179,7 @@ __global__ void __launch_bounds__(kTail) kb_tail(BArgs a) {
     const int l = s.nlev;
     // the tail starts from zero below the finest level and in the first cycle
     const int zero = (a.flag == 0 || l > 0) ? 1 : 0;
-    if constexpr (D == 2)
-        tail2_body<T>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_RBGS, 1, 1, 0.0, zero);
-    else
-        tail_body<T, D>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_RBGS, 1, 1, 0.0, zero);
+    tailc_body<T, D>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_RBGS, 1, 1, 0.0, zero);
 }
 
 template <typename T, int D, int MODE>

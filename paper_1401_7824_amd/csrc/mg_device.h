@@ -1,8 +1,9 @@
-// Device bodies of the tiled multigrid kernels and of the coarse tail (see
-// mg_tiles.hip for what each computes).  A body works on one tile whose
-// origin the caller supplies, so the same code serves the single-instance
-// kernels (tile from the workgroup index) and the batched kernels (instance
-// and tile from a table).
+// Device bodies of the tiled multigrid kernels of 1D and 3D levels (see
+// mg_tiles.hip for what each computes; 2D levels use rows2d.h) and helpers of
+// the single-workgroup levels.  A body works on one tile whose origin the
+// caller supplies, so the same code serves the single-instance kernels (tile
+// from the workgroup index) and the batched kernels (instance and tile from a
+// table).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -263,13 +264,14 @@ __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const
     });
 }
 
-// ---------------------------------------------------------------- coarse tail
-// All levels n_t, (n_t-1)/2, ..., 1 in one workgroup with every level's
-// iterate, right-hand side and a residual scratch in LDS.  Threads form a
+// ---------------------------------------------------------------- single-workgroup levels
+// Helpers of the compact-stencil coarse tail (compact.hip): all levels n_t,
+// (n_t-1)/2, ..., 1 in one workgroup with every level in LDS.  Threads form a
 // fixed (X, Y, Z) block; thread (tx, ty, tz) owns at most P points of a level
 // (its "slots", strided along the last used axis), so no index needs a
 // division.  Each phase first computes all of a thread's values and only then
-// stores them, letting the LDS reads of all slots overlap.
+// stores them, letting the LDS reads of all slots overlap.  (The
+// second-order tail has compile-time level sizes: tailc.h.)
 
 constexpr int kTail = 1024;
 // X * Y * Z = kTail; slots run along the last used axis, so a slot beyond the
@@ -343,71 +345,6 @@ __device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
     }
 }
 
-// One colour ((x + y + z) & 1 == colour) of an n^D level: thread t takes the
-// colour's points t and t + kTail (1D: t only), packed two per pair of x
-// positions, so every lane of a wave has a point where a plain phase would
-// leave every other lane idle.  compute(x, y, z, i, v) returns whether to
-// store v at i; as in phase, all values are computed before any is stored.
-template <typename T, int D, typename Compute>
-__device__ __forceinline__ void phase_colour(int n, int colour, T* out, Compute&& compute) {
-    constexpr int CP = D == 1 ? 1 : 2;
-    {
-        // a wave whose first point row (plane) lies beyond the level has no
-        // point in either of its slots (the second slot lies further out)
-        const int w0 = threadIdx.x & ~63;
-        const bool idle = D == 1 ? 2 * w0 >= n : (D == 2 ? (w0 >> 5) >= n : (w0 >> 7) >= n);
-        if (idle) return;
-    }
-    T v[CP];
-    int idx[CP];
-    bool wr[CP];
-#pragma unroll
-    for (int q = 0; q < CP; ++q) {
-        const int k = threadIdx.x + kTail * q;
-        int x, y = 0, z = 0;
-        if (D == 1) {
-            x = 2 * k + colour;
-        } else if (D == 2) {
-            y = k >> 5;
-            x = 2 * (k & 31) + ((y + colour) & 1);
-        } else {
-            y = (k >> 3) & 15;
-            z = k >> 7;
-            x = 2 * (k & 7) + ((y + z + colour) & 1);
-        }
-        const bool ok = x < n && (D < 2 || y < n) && (D < 3 || z < n);
-        idx[q] = D == 1 ? x : (z * n + y) * n + x;
-        wr[q] = ok && compute(x, y, z, idx[q], v[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < CP; ++q)
-        if (wr[q]) out[idx[q]] = v[q];
-}
-
-// Sum of the in-level neighbours of point i (zero ghosts).  Every load is
-// unconditional (a neighbour outside the level reads the point itself and is
-// then replaced by zero), so the loads of one point issue together instead of
-// one conditional block, and one LDS wait, each; adding the zeros leaves the
-// sum bit-for-bit what skipping the terms gives.
-template <typename T, int D>
-__device__ __forceinline__ T nb_lds(const T* e, int n, int x, int y, int z, int i) {
-    const T xm = e[x > 0 ? i - 1 : i], xp = e[x < n - 1 ? i + 1 : i];
-    T s = T(0);
-    s += x > 0 ? xm : T(0);
-    s += x < n - 1 ? xp : T(0);
-    if (D >= 2) {
-        const T ym = e[y > 0 ? i - n : i], yp = e[y < n - 1 ? i + n : i];
-        s += y > 0 ? ym : T(0);
-        s += y < n - 1 ? yp : T(0);
-    }
-    if (D == 3) {
-        const T zm = e[z > 0 ? i - n * n : i], zp = e[z < n - 1 ? i + n * n : i];
-        s += z > 0 ? zm : T(0);
-        s += z < n - 1 ? zp : T(0);
-    }
-    return s;
-}
-
 // Linear interpolation of the coarse iterate ec (nc points per axis) at fine
 // point (x, y, z): per axis, odd -> (i-1)/2, even -> mean of i/2-1 and i/2,
 // with zeros outside the coarse grid.
@@ -434,64 +371,6 @@ __device__ __forceinline__ T interp_at(const T* ec, int nc, int x, int y, int z)
     return T(0.5) * plane(z / 2 - 1) + T(0.5) * plane(z / 2);
 }
 
-// Neighbour sum of the corrected iterate e + P ec, in the order of nb_lds.
-template <typename T, int D>
-__device__ __forceinline__ T nb_corrected(const T* e, const T* ec, int n, int nc, int x, int y, int z, int i) {
-    T s = T(0);
-    if (x > 0) s += e[i - 1] + interp_at<T, D>(ec, nc, x - 1, y, z);
-    if (x < n - 1) s += e[i + 1] + interp_at<T, D>(ec, nc, x + 1, y, z);
-    if (D >= 2) {
-        if (y > 0) s += e[i - n] + interp_at<T, D>(ec, nc, x, y - 1, z);
-        if (y < n - 1) s += e[i + n] + interp_at<T, D>(ec, nc, x, y + 1, z);
-    }
-    if (D == 3) {
-        if (z > 0) s += e[i - n * n] + interp_at<T, D>(ec, nc, x, y, z - 1);
-        if (z < n - 1) s += e[i + n * n] + interp_at<T, D>(ec, nc, x, y, z + 1);
-    }
-    return s;
-}
-
-// nsteps smoothing steps on a level.  Red-black works in place (a colour reads
-// only the other colour); Jacobi ping-pongs between e and tmp, one phase per
-// step, and copies the result back to e after an odd count.
-template <typename T, int D>
-__device__ __forceinline__ void tail_smooth(T* e, const T* r, T* tmp, int n, T a, T diag, T invdiag, T w, int smoother,
-                                            int nsteps) {
-    if (smoother == ISDC_SMOOTH_RBGS) {
-        for (int k = 0; k < nsteps; ++k)
-            for (int colour = 0; colour < 2; ++colour) {
-                phase_colour<T, D>(n, colour, e, [&](int x, int y, int z, int i, T& v) {
-                    v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
-                    return true;
-                });
-                __syncthreads();
-            }
-        return;
-    }
-    T* src = e;
-    T* dst = tmp;
-    for (int k = 0; k < nsteps; ++k) {
-        phase<T, D>(n, dst, [&](bool ok, int x, int y, int z, int i, T& v) {
-            if (!ok) return false;
-            const T c = src[i];
-            v = c + w * ((r[i] - (diag * c - a * nb_lds<T, D>(src, n, x, y, z, i))) * invdiag);
-            return true;
-        });
-        __syncthreads();
-        T* t = src;
-        src = dst;
-        dst = t;
-    }
-    if (src != e) {
-        phase<T, D>(n, e, [&](bool ok, int, int, int, int i, T& v) {
-            if (!ok) return false;
-            v = src[i];
-            return true;
-        });
-        __syncthreads();
-    }
-}
-
 // Order the LDS accesses of one wave: the compiler keeps every access on its
 // side of the fence, and the hardware executes one wave's LDS instructions in
 // order, so what a lane stores before it is what any lane loads after it.
@@ -499,261 +378,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Coordinates of point k of an n^D level.
-template <int D>
-__device__ __forceinline__ void point_of(int k, int n, int& x, int& y, int& z) {
-    x = k % n;
-    y = D >= 2 ? (k / n) % n : 0;
-    z = D == 3 ? k / (n * n) : 0;
-}
-
-// The V-cycle on the tail's levels l0 .. nlev-1, all of at most 64 points, by
-// the first wave alone: one lane per point and wave_sync() between phases
-// instead of workgroup barriers.  The arithmetic is that of the workgroup
-// phases of tail_body (same expressions, same order), only the thread that
-// computes each point differs.
-template <typename T, int D>
-__device__ __forceinline__ void tail_wave_levels(T* le, T* lr, T* lt, const T (*lc)[16], int n_t, int l0, int nlev,
-                                                 int smoother,
-                                 int nu1, int nu2, T w) {
-    const int lane = threadIdx.x;
-    auto nn = [&](int l) { return ((n_t + 1) >> l) - 1; };
-    auto off = [&](int l) {
-        int o = 0;
-        for (int j = 0; j < l; ++j) o += npts<D>(nn(j));
-        return o;
-    };
-    const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    // one smoothing step on level (e, r) of n points per axis
-    auto smooth = [&](T* e, const T* r, int n, T a, T diag, T invdiag) {
-        const int N = npts<D>(n);
-        int x = 0, y = 0, z = 0;
-        if (lane < N) point_of<D>(lane, n, x, y, z);
-        if (smoother == ISDC_SMOOTH_RBGS) {
-            for (int colour = 0; colour < 2; ++colour) {
-                if (lane < N && ((x + y + z) & 1) == colour) {
-                    const T v = (r[lane] + a * nb_lds<T, D>(e, n, x, y, z, lane)) * invdiag;
-                    e[lane] = v;
-                }
-                wave_sync();
-            }
-        } else {
-            if (lane < N) {
-                const T c = e[lane];
-                lt[lane] = c + w * ((r[lane] - (diag * c - a * nb_lds<T, D>(e, n, x, y, z, lane))) * invdiag);
-            }
-            wave_sync();
-            if (lane < N) e[lane] = lt[lane];
-            wave_sync();
-        }
-    };
-    int l = l0;
-    for (; l < nlev; ++l) {
-        const int n = nn(l);
-        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        if (n == 1) {
-            if (lane == 0) e[0] = r[0] / diag;
-            wave_sync();
-            break;
-        }
-        for (int k = 0; k < nu1; ++k) smooth(e, r, n, a, diag, invdiag);
-        const int N = npts<D>(n);
-        if (lane < N) {
-            int x, y, z;
-            point_of<D>(lane, n, x, y, z);
-            lt[lane] = r[lane] - (diag * e[lane] - a * nb_lds<T, D>(e, n, x, y, z, lane));
-        }
-        wave_sync();
-        const int nc = (n - 1) / 2;
-        T* rc = lr + off(l + 1);
-        T* ec = le + off(l + 1);
-        if (lane < npts<D>(nc)) {
-            int X, Y, Z;
-            point_of<D>(lane, nc, X, Y, Z);
-            T acc = T(0);
-#pragma unroll
-            for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz)
-#pragma unroll
-                for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
-                    const int fy = D >= 2 ? 2 * Y + oy : 0, fz = D == 3 ? 2 * Z + oz : 0;
-                    const int base = (D == 1 ? 0 : (fz * n + fy) * n) + 2 * X;
-                    T row = wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2];
-                    acc += (D >= 2 ? wts[oy] : T(1)) * (D == 3 ? wts[oz] : T(1)) * row;
-                }
-            rc[lane] = acc;
-            ec[lane] = T(0);
-        }
-        wave_sync();
-    }
-    for (l = nlev - 2; l >= l0; --l) {
-        const int n = nn(l);
-        const int nc = nn(l + 1);
-        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        const T* ec = le + off(l + 1);
-        const int N = npts<D>(n);
-        int x = 0, y = 0, z = 0;
-        if (lane < N) point_of<D>(lane, n, x, y, z);
-        int k0 = 0;
-        if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
-            if (lane < N && ((x + y + z) & 1) == 0) {
-                const T v = (r[lane] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, lane)) * invdiag;
-                e[lane] = v;
-            }
-            wave_sync();
-            if (lane < N && ((x + y + z) & 1) == 1) {
-                const T v = (r[lane] + a * nb_lds<T, D>(e, n, x, y, z, lane)) * invdiag;
-                e[lane] = v;
-            }
-            wave_sync();
-            k0 = 1;
-        } else {
-            if (lane < N) {
-                const T v = e[lane] + interp_at<T, D>(ec, nc, x, y, z);
-                e[lane] = v;
-            }
-            wave_sync();
-        }
-        for (int k = k0; k < nu2; ++k) smooth(e, r, n, a, diag, invdiag);
-    }
-}
-
-template <typename T, int D>
-__device__ __forceinline__ void tail_body(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t,
-                                          const TailCoefs& tc, int smoother, int nu1, int nu2, double omega,
-                                          int zero_guess) {
-    using L = TailLayout<D>;
-    __shared__ T le[L::total];
-    __shared__ T lr[L::total];
-    __shared__ T lt[L::big];
-    __shared__ T lc[3][16];  // per-level a, diag, 1/diag
-    // level l has nn(l) = (n_t + 1) / 2^l - 1 points per axis and starts at
-    // off(l) in the level arrays (uniform scalars, recomputed where needed)
-    auto nn = [&](int l) { return ((n_t + 1) >> l) - 1; };
-    auto off = [&](int l) {
-        int o = 0;
-        for (int j = 0; j < l; ++j) o += npts<D>(nn(j));
-        return o;
-    };
-    int nlev = 1;
-    while (nn(nlev - 1) > 1) ++nlev;
-    {
-        // every load of the finest level is issued before any is waited on
-        constexpr int I = (L::big + kTail - 1) / kTail;
-        const int N0 = npts<D>(n_t);
-        T vr[I], ve[I];
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            vr[it] = i < N0 ? rhs_g[i] : T(0);
-            ve[it] = (i < N0 && !zero_guess) ? e_g[i] : T(0);
-        }
-        if (threadIdx.x < 48) {
-            const int q = threadIdx.x >> 4, l = threadIdx.x & 15;
-            lc[q][l] = T(q == 0 ? tc.a[l] : (q == 1 ? tc.diag[l] : tc.invdiag[l]));
-        }
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            if (i < N0) {
-                lr[i] = vr[it];
-                le[i] = ve[it];
-            }
-        }
-    }
-    __syncthreads();
-    const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    // levels from lw on have at most 64 points: the first wave runs them alone
-    int lw = 0;
-    while (lw < nlev && npts<D>(nn(lw)) > 64) ++lw;
-    for (int l = 0; l < lw; ++l) {
-        const int n = nn(l);
-        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        if (n == 1) {
-            if (threadIdx.x == 0) e[0] = r[0] / diag;
-            __syncthreads();
-            break;
-        }
-        tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother, nu1);
-        phase<T, D>(n, lt, [&](bool ok, int x, int y, int z, int i, T& v) {
-            if (!ok) return false;
-            v = r[i] - (diag * e[i] - a * nb_lds<T, D>(e, n, x, y, z, i));
-            return true;
-        });
-        __syncthreads();
-        const int nc = (n - 1) / 2;
-        T* rc = lr + off(l + 1);
-        T* ec = le + off(l + 1);
-        phase<T, D>(nc, rc, [&](bool ok, int X, int Y, int Z, int I, T& v) {
-            if (!ok) return false;
-            T acc = T(0);
-#pragma unroll
-            for (int oz = 0; oz < (D == 3 ? 3 : 1); ++oz)
-#pragma unroll
-                for (int oy = 0; oy < (D >= 2 ? 3 : 1); ++oy) {
-                    const int fy = D >= 2 ? 2 * Y + oy : 0, fz = D == 3 ? 2 * Z + oz : 0;
-                    const int base = (D == 1 ? 0 : (fz * n + fy) * n) + 2 * X;
-                    T row = wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2];
-                    acc += (D >= 2 ? wts[oy] : T(1)) * (D == 3 ? wts[oz] : T(1)) * row;
-                }
-            v = acc;
-            ec[I] = T(0);
-            return true;
-        });
-        __syncthreads();
-    }
-    if (lw < nlev) {
-        if (threadIdx.x < 64) tail_wave_levels<T, D>(le, lr, lt, lc, n_t, lw, nlev, smoother, nu1, nu2, T(omega));
-        __syncthreads();
-    }
-    for (int l = lw - 1; l >= 0; --l) {
-        const int n = nn(l);
-        const int nc = nn(l + 1);
-        const T a = lc[0][l], diag = lc[1][l], invdiag = lc[2][l];
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        const T* ec = le + off(l + 1);
-        int k0 = 0;
-        if (D <= 2 && smoother == ISDC_SMOOTH_RBGS && nu2 >= 1) {
-            // first red pass on the corrected iterate e + P ec without storing the
-            // correction: red reads only black values, black overwrites black
-            phase_colour<T, D>(n, 0, e, [&](int x, int y, int z, int i, T& v) {
-                v = (r[i] + a * nb_corrected<T, D>(e, ec, n, nc, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-            phase_colour<T, D>(n, 1, e, [&](int x, int y, int z, int i, T& v) {
-                v = (r[i] + a * nb_lds<T, D>(e, n, x, y, z, i)) * invdiag;
-                return true;
-            });
-            __syncthreads();
-            k0 = 1;
-        } else {
-            phase<T, D>(n, e, [&](bool ok, int x, int y, int z, int i, T& v) {
-                if (!ok) return false;
-                v = e[i] + interp_at<T, D>(ec, nc, x, y, z);
-                return true;
-            });
-            __syncthreads();
-        }
-        tail_smooth<T, D>(e, r, lt, n, a, diag, invdiag, T(omega), smoother, nu2 - k0);
-    }
-    {
-        constexpr int I = (L::big + kTail - 1) / kTail;
-        const int N0 = npts<D>(n_t);
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            if (i < N0) e_g[i] = le[i];
-        }
-    }
 }
 
 }  // namespace

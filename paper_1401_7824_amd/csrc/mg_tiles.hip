@@ -26,7 +26,7 @@
 #include "mg_device.h"
 #include "mg_march.h"
 #include "rows2d.h"
-#include "tail2d.h"
+#include "tailc.h"
 
 namespace isdc {
 
@@ -118,10 +118,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
        double omega, int zero_guess) {
-    if constexpr (D == 2)
-        tail2_body<T>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
-    else
-        tail_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
+    tailc_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
 }
 
 }  // namespace
@@ -282,7 +279,7 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
 static_assert(kShapes == kTileShapes, "tile shape count of the kernels and of the launchers");
 
 int tail_max_n(int d) {
-    return d == 1 ? TailLayout<1>::nmax : (d == 2 ? TailLayout<2>::nmax : TailLayout<3>::nmax);
+    return d == 1 ? kTailMax<1> : (d == 2 ? kTailMax<2> : kTailMax<3>);
 }
 
 template <typename T>
