@@ -30,6 +30,7 @@
 // between neighbouring threads.
 #include <hip/hip_runtime.h>
 
+#include "ctail.h"
 #include "internal.h"
 #include "mg_device.h"
 #include "sdc_device.h"
@@ -304,179 +305,13 @@ __global__ void __launch_bounds__(kB) k_weno_burgers(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- compact tail
-// One V-cycle of B on levels n_t, ..., 1 in one workgroup, every level in LDS
-// (same layout and phases as the second-order tail), weighted Jacobi.
-
-template <bool PER, typename T>
-__device__ __forceinline__ T capply_lds(const T* e, int n, int x, int y, int i, T b0, T bf, T bc) {
-    T edges = T(0), corners = T(0);
-    if (PER) {
-        const int xm = x == 0 ? n - 1 : x - 1, xp = x == n - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? n - 1 : y - 1, yp = y == n - 1 ? 0 : y + 1;
-        edges = e[y * n + xm] + e[y * n + xp] + e[ym * n + x] + e[yp * n + x];
-        corners = e[ym * n + xm] + e[ym * n + xp] + e[yp * n + xm] + e[yp * n + xp];
-    } else {
-        // unconditional loads (an outside neighbour reads the point itself),
-        // then zeros in place of the outside terms: the same sums as skipping them
-        const bool xl = x > 0, xr = x < n - 1, yd = y > 0, yu = y < n - 1;
-        const T vxl = e[xl ? i - 1 : i], vxr = e[xr ? i + 1 : i];
-        const T vyd = e[yd ? i - n : i], vyu = e[yu ? i + n : i];
-        const T vdl = e[yd && xl ? i - n - 1 : i], vdr = e[yd && xr ? i - n + 1 : i];
-        const T vul = e[yu && xl ? i + n - 1 : i], vur = e[yu && xr ? i + n + 1 : i];
-        edges += xl ? vxl : T(0);
-        edges += xr ? vxr : T(0);
-        edges += yd ? vyd : T(0);
-        edges += yu ? vyu : T(0);
-        corners += yd && xl ? vdl : T(0);
-        corners += yd && xr ? vdr : T(0);
-        corners += yu && xl ? vul : T(0);
-        corners += yu && xr ? vur : T(0);
-    }
-    return b0 * e[i] + bf * edges + bc * corners;
-}
+// One V-cycle of B on levels n_t, ..., 1 in one workgroup (ctail.h).
 
 template <typename T, bool PER>
 __global__ void __launch_bounds__(kTail)
 k_ctail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, CTailCoefs tc, int nu1, int nu2, double omega,
         int zero_guess) {
-    using L = TailLayout<2>;
-    __shared__ T le[L::total];
-    __shared__ T lr[L::total];
-    __shared__ T lt[L::big];
-    auto nn = [&](int l) { return PER ? n_t >> l : ((n_t + 1) >> l) - 1; };
-    auto off = [&](int l) {
-        int o = 0;
-        for (int j = 0; j < l; ++j) o += nn(j) * nn(j);
-        return o;
-    };
-    int nlev = 1;
-    while (nn(nlev - 1) > 1) ++nlev;
-    {
-        constexpr int I = (L::big + kTail - 1) / kTail;
-        const int N0 = n_t * n_t;
-        T vr[I], ve[I];
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            vr[it] = i < N0 ? rhs_g[i] : T(0);
-            ve[it] = (i < N0 && !zero_guess) ? e_g[i] : T(0);
-        }
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            if (i < N0) {
-                lr[i] = vr[it];
-                le[i] = ve[it];
-            }
-        }
-    }
-    __syncthreads();
-    const T w = T(omega);
-    const T wts[3] = {T(0.25), T(0.5), T(0.25)};
-    // nsteps Jacobi steps ping-ponging between e and lt (one phase each), the
-    // result copied back to e after an odd count
-    auto jacobi = [&](T* e, const T* r, int n, T b0, T bf, T bc, int nsteps) {
-        const T inv = T(1) / b0;
-        T* src = e;
-        T* dst = lt;
-        for (int k = 0; k < nsteps; ++k) {
-            phase<T, 2>(n, dst, [&](bool ok, int x, int y, int, int i, T& v) {
-                if (!ok) return false;
-                v = src[i] + w * (r[i] - capply_lds<PER>(src, n, x, y, i, b0, bf, bc)) * inv;
-                return true;
-            });
-            __syncthreads();
-            T* t = src;
-            src = dst;
-            dst = t;
-        }
-        if (src != e) {
-            phase<T, 2>(n, e, [&](bool ok, int, int, int, int i, T& v) {
-                if (!ok) return false;
-                v = src[i];
-                return true;
-            });
-            __syncthreads();
-        }
-    };
-    for (int l = 0; l < nlev; ++l) {
-        const int n = nn(l);
-        const T b0 = T(tc.b0[l]), bf = T(tc.bf[l]), bc = T(tc.bc[l]);
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        if (n == 1) {
-            // Dirichlet: every neighbour is a zero ghost; periodic: every
-            // neighbour is the point itself and B = I
-            if (threadIdx.x == 0) e[0] = PER ? r[0] : r[0] / b0;
-            __syncthreads();
-            break;
-        }
-        jacobi(e, r, n, b0, bf, bc, nu1);
-        phase<T, 2>(n, lt, [&](bool ok, int x, int y, int, int i, T& v) {
-            if (!ok) return false;
-            v = r[i] - capply_lds<PER>(e, n, x, y, i, b0, bf, bc);
-            return true;
-        });
-        __syncthreads();
-        const int nc = PER ? n / 2 : (n - 1) / 2;
-        T* rc = lr + off(l + 1);
-        T* ec = le + off(l + 1);
-        phase<T, 2>(nc, rc, [&](bool ok, int X, int Y, int, int I, T& v) {
-            if (!ok) return false;
-            T acc = T(0);
-#pragma unroll
-            for (int oy = 0; oy < 3; ++oy) {
-                if (PER) {
-                    int fy = 2 * Y + oy - 1;
-                    fy = fy < 0 ? fy + n : fy;
-                    const int fx0 = 2 * X == 0 ? n - 1 : 2 * X - 1;
-                    acc += wts[oy] * (wts[0] * lt[fy * n + fx0] + wts[1] * lt[fy * n + 2 * X] +
-                                      wts[2] * lt[fy * n + 2 * X + 1]);
-                } else {
-                    const int base = (2 * Y + oy) * n + 2 * X;
-                    acc += wts[oy] * (wts[0] * lt[base] + wts[1] * lt[base + 1] + wts[2] * lt[base + 2]);
-                }
-            }
-            v = acc;
-            ec[I] = T(0);
-            return true;
-        });
-        __syncthreads();
-    }
-    for (int l = nlev - 2; l >= 0; --l) {
-        const int n = nn(l);
-        const int nc = nn(l + 1);
-        const T b0 = T(tc.b0[l]), bf = T(tc.bf[l]), bc = T(tc.bc[l]);
-        T* e = le + off(l);
-        T* r = lr + off(l);
-        const T* ec = le + off(l + 1);
-        phase<T, 2>(n, e, [&](bool ok, int x, int y, int, int i, T& v) {
-            if (!ok) return false;
-            if (PER) {
-                const int X0 = x >> 1, Y0 = y >> 1;
-                const int X1 = (x & 1) ? (X0 + 1 == nc ? 0 : X0 + 1) : X0;
-                const int Y1 = (y & 1) ? (Y0 + 1 == nc ? 0 : Y0 + 1) : Y0;
-                const T wx = (x & 1) ? T(0.5) : T(1), wy = (y & 1) ? T(0.5) : T(1);
-                const T wx1 = (x & 1) ? T(0.5) : T(0), wy1 = (y & 1) ? T(0.5) : T(0);
-                v = e[i] + (wy * (wx * ec[Y0 * nc + X0] + wx1 * ec[Y0 * nc + X1]) +
-                            wy1 * (wx * ec[Y1 * nc + X0] + wx1 * ec[Y1 * nc + X1]));
-            } else {
-                v = e[i] + interp_at<T, 2>(ec, nc, x, y, 0);
-            }
-            return true;
-        });
-        __syncthreads();
-        jacobi(e, r, n, b0, bf, bc, nu2);
-    }
-    {
-        constexpr int I = (L::big + kTail - 1) / kTail;
-        const int N0 = n_t * n_t;
-#pragma unroll
-        for (int it = 0; it < I; ++it) {
-            const int i = threadIdx.x + it * kTail;
-            if (i < N0) e_g[i] = le[i];
-        }
-    }
+    ctail_body<T, PER>(rhs_g, e_g, n_t, tc, nu1, nu2, omega, zero_guess);
 }
 
 dim3 grid2(int n) { return dim3((n + kB - 1) / kB, n); }
@@ -591,7 +426,10 @@ hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hi
 template <typename T>
 hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h, bool zero, const T* rhs, T* e,
                         bool per, hipStream_t s) {
-    if (n > (per ? kCTailMaxPeriodic : TailLayout<2>::nmax)) return hipErrorInvalidValue;
+    // Dirichlet n = 2^k - 1 <= 63, periodic n = 2^k <= 32
+    const bool ok = per ? (n >= 1 && n <= kCTailMaxPeriodic && (n & (n - 1)) == 0)
+                        : (n >= 1 && n <= kCTailMaxDirichlet && ((n + 1) & n) == 0);
+    if (!ok) return hipErrorInvalidValue;
     CTailCoefs tc;
     double H = h;
     for (int l = 0; l < 16; ++l) {

@@ -1,6 +1,6 @@
 // Device bodies of the tiled multigrid kernels of 1D and 3D levels (see
-// mg_tiles.hip for what each computes; 2D levels use rows2d.h) and helpers of
-// the single-workgroup levels.  A body works on one tile whose origin the
+// mg_tiles.hip for what each computes; 2D levels use rows2d.h) and the
+// wave-level ordering of the single-workgroup tails.  A body works on one tile whose origin the
 // caller supplies, so the same code serves the single-instance kernels (tile
 // from the workgroup index) and the batched kernels (instance and tile from a
 // table).
@@ -265,111 +265,8 @@ __device__ __forceinline__ void prolong_rbgs_body(const T* __restrict__ r, const
 }
 
 // ---------------------------------------------------------------- single-workgroup levels
-// Helpers of the compact-stencil coarse tail (compact.hip): all levels n_t,
-// (n_t-1)/2, ..., 1 in one workgroup with every level in LDS.  Threads form a
-// fixed (X, Y, Z) block; thread (tx, ty, tz) owns at most P points of a level
-// (its "slots", strided along the last used axis), so no index needs a
-// division.  Each phase first computes all of a thread's values and only then
-// stores them, letting the LDS reads of all slots overlap.  (The
-// second-order tail has compile-time level sizes: tailc.h.)
-
+// Threads of the single-workgroup coarse-tail kernels (tailc.h, ctail.h).
 constexpr int kTail = 1024;
-// X * Y * Z = kTail; slots run along the last used axis, so a slot beyond the
-// level is skipped by whole waves (the slot coordinate is uniform per wave).
-template <int D> struct TailLayout;
-template <> struct TailLayout<1> { static constexpr int X = 1024, Y = 1, Z = 1, P = 2, nmax = 2047, total = 4096, big = 2047; };
-template <> struct TailLayout<2> { static constexpr int X = 64, Y = 16, Z = 1, P = 4, nmax = 63, total = 5216, big = 3969; };
-template <> struct TailLayout<3> { static constexpr int X = 16, Y = 16, Z = 4, P = 4, nmax = 15, total = 3752, big = 3375; };
-
-template <int D>
-__device__ __forceinline__ int npts(int n) {
-    return D == 1 ? n : (D == 2 ? n * n : n * n * n);
-}
-
-// Call f(q, ok, x, y, z, i) for slots s0 + q, q < CH, of this thread on an
-// n^D level (ok: the point lies in the level).
-template <int D, int CH, typename F>
-__device__ __forceinline__ void slots(int n, int s0, F&& f) {
-    using L = TailLayout<D>;
-    const int tx = threadIdx.x % L::X;
-    const int ty = (threadIdx.x / L::X) % L::Y;
-    const int tz = threadIdx.x / (L::X * L::Y);
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int s = s0 + q;
-        const int x = D == 1 ? tx + L::X * s : tx;
-        const int y = D == 2 ? ty + L::Y * s : (D == 3 ? ty : 0);
-        const int z = D == 3 ? tz + L::Z * s : 0;
-        // slot coordinate beyond the level: the same for the whole wave
-        const int sc = D == 1 ? L::X * s : (D == 2 ? L::Y * s : s);
-        if (sc >= n) break;
-        const bool ok = x < n && (D < 2 || y < n) && (D < 3 || z < n);
-        f(q, ok, x, y, z, D == 1 ? x : (z * n + y) * n + x);
-    }
-}
-
-// Whether this thread's whole wave has no point of an n^D level in any
-// slot (the test is uniform per wave, so an idle wave skips the phase's
-// instructions and only meets the barrier that follows it).
-template <int D>
-__device__ __forceinline__ bool wave_idle(int n) {
-    using L = TailLayout<D>;
-    const int w0 = threadIdx.x & ~63;  // first thread of the wave
-    if (D == 1) return w0 >= n;
-    if (D == 2) return w0 / L::X >= n;  // the wave's row (X = 64)
-    return (w0 / (L::X * L::Y)) >= n || ((w0 / L::X) % L::Y) >= n;  // its z plane, its first y row
-}
-
-// Run a phase in chunks of slots: compute all values of a chunk, then store
-// them (the callers only ever read locations no chunk of the phase writes).
-template <int D> constexpr int chunk_of() { return D == 3 ? 1 : 4; }
-template <typename T, int D, typename Compute>
-__device__ __forceinline__ void phase(int n, T* out, Compute&& compute) {
-    constexpr int P = TailLayout<D>::P;
-    constexpr int CH = chunk_of<D>();
-    if (wave_idle<D>(n)) return;
-#pragma unroll 1
-    for (int s0 = 0; s0 < P; s0 += CH) {
-        T v[CH];
-        int idx[CH];
-        bool wr[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q) wr[q] = false;
-        slots<D, CH>(n, s0, [&](int q, bool ok, int x, int y, int z, int i) {
-            idx[q] = i;
-            wr[q] = compute(ok, x, y, z, i, v[q]);
-        });
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-            if (wr[q]) out[idx[q]] = v[q];
-    }
-}
-
-// Linear interpolation of the coarse iterate ec (nc points per axis) at fine
-// point (x, y, z): per axis, odd -> (i-1)/2, even -> mean of i/2-1 and i/2,
-// with zeros outside the coarse grid.
-template <typename T, int D>
-__device__ __forceinline__ T interp_at(const T* ec, int nc, int x, int y, int z) {
-    auto tap = [&](int X, int Y, int Z) -> T {  // unconditional load, then zero outside
-        bool in = (unsigned)X < (unsigned)nc;
-        if (D >= 2) in = in && (unsigned)Y < (unsigned)nc;
-        if (D == 3) in = in && (unsigned)Z < (unsigned)nc;
-        const T v = ec[in ? (D == 1 ? X : (Z * nc + Y) * nc + X) : 0];
-        return in ? v : T(0);
-    };
-    const int xa = (x & 1) ? (x - 1) / 2 : x / 2 - 1;
-    auto row = [&](int Y, int Z) -> T {
-        return (x & 1) ? tap(xa, Y, Z) : T(0.5) * tap(xa, Y, Z) + T(0.5) * tap(xa + 1, Y, Z);
-    };
-    auto plane = [&](int Z) -> T {
-        if (D < 2) return row(0, Z);
-        if (y & 1) return row((y - 1) / 2, Z);
-        return T(0.5) * row(y / 2 - 1, Z) + T(0.5) * row(y / 2, Z);
-    };
-    if (D < 3) return plane(0);
-    if (z & 1) return plane((z - 1) / 2);
-    return T(0.5) * plane(z / 2 - 1) + T(0.5) * plane(z / 2);
-}
 
 // Order the LDS accesses of one wave: the compiler keeps every access on its
 // side of the fence, and the hardware executes one wave's LDS instructions in

@@ -2,7 +2,7 @@
 
     python -m paper_1401_7824_amd.profiling trace RUN_kernel_trace.csv
     python -m paper_1401_7824_amd.profiling counters FETCH.csv WRITE.csv \\
-        --workload rd2d --kernel 'k_rbgs_restrict_tile<double, 2, false, 0>' --workgroups 1024 \\
+        --workload rd2d --kernel 'k_rows_rbgs_restrict<double, false, 0>' --workgroups 1216 \\
         --alg-bytes 27205664 [--update profiles/traffic.json]
 
 `trace` prints the median duration per (kernel, workgroup count) -- the
@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources of the multigrid kernels; counter figures taken before a change to
 # any of them are stale
 TRAFFIC_SOURCES = ("paper_1401_7824_amd/csrc/mg_tiles.hip", "paper_1401_7824_amd/csrc/mg_device.h",
-                   "paper_1401_7824_amd/csrc/mg_march.h", "paper_1401_7824_amd/csrc/tile_common.h")
+                   "paper_1401_7824_amd/csrc/mg_march.h", "paper_1401_7824_amd/csrc/tile_common.h",
+                   "paper_1401_7824_amd/csrc/rows2d.h", "paper_1401_7824_amd/csrc/tailc.h")
 COPY_KIB = 512 * 1024
 
 
