@@ -34,6 +34,7 @@
 #include "internal.h"
 #include "mg_device.h"
 #include "sdc_device.h"
+#include "tile_common.h"
 
 namespace isdc {
 
@@ -81,6 +82,104 @@ k_cjacobi(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e
     } else {
         const T uc = e_in[i];
         e_out[i] = uc + k.omega * (r[i] - apply_b<PER>(e_in, n, x, y, uc, k)) * k.inv_b0;
+    }
+}
+
+// K weighted-Jacobi steps in one launch on row-mapped tiles: a tile of
+// (64 - 2K) x 16 points stages the iterate on the tile plus a halo of K in
+// LDS (64 columns from x0 - K, one column per lane) and the right-hand side
+// of its own points in registers, then runs step s on the tile plus a halo of
+// K - s, ping-ponging between two LDS buffers; the last step leaves the tile.
+// Each point is updated with the expression of k_cjacobi, so the result is
+// that of K single-step launches.  Dirichlet: points outside the grid are
+// zero and never updated; periodic: the staged box wraps, and points past
+// the end of a ragged last tile repeat points of the first (same values),
+// only the tile's own points are stored.
+constexpr int kJL = 64;   // LDS columns (lanes per row)
+constexpr int kJTY = 16;  // tile rows
+template <int K> struct JTile {
+    static constexpr int TX = kJL - 2 * K, TY = kJTY;
+    static constexpr int ROWS = TY + 2 * K;
+    static constexpr int RP = kThreads / kJL;  // rows per block step
+    static constexpr int IP = (ROWS + RP - 1) / RP;
+    static constexpr int N = IP * kThreads;
+};
+
+template <typename T, bool PER, int K, bool ZERO>
+__global__ void __launch_bounds__(kThreads)
+k_cjacobi_k(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
+            CCoef<T> k) {
+    using J = JTile<K>;
+    constexpr int L = kJL;
+    __shared__ T sa[J::N];
+    __shared__ T sb[J::N];
+    int x0, y0, z0;
+    tile_origin(ntx, nty, J::TX, J::TY, 1, x0, y0, z0);
+    const int c = threadIdx.x % L, j = threadIdx.x / L;
+    // LDS column c is x = x0 - K + c, row q is y = y0 - K + q
+    const int x = x0 - K + c;
+    const int xg = PER ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x;
+    const bool xin = PER ? (c < J::TX + 2 * K) : (c < J::TX + 2 * K && x >= 0 && x < n);
+    T vr[J::IP];
+#pragma unroll
+    for (int i = 0; i < J::IP; ++i) {
+        const int q = j + i * J::RP;
+        const int y = y0 - K + q;
+        const int yg = PER ? (y < 0 ? y + n : (y >= n ? y - n : y)) : y;
+        const bool in = xin && q < J::ROWS && (PER || (y >= 0 && y < n));
+        T ve = T(0), rv = T(0);
+        if (in) {
+            const size_t gi = (size_t)yg * n + xg;
+            if (!ZERO) ve = e_in[gi];
+            rv = r[gi];
+        }
+        vr[i] = rv;
+        sa[threadIdx.x + i * kThreads] = ve;
+        sb[threadIdx.x + i * kThreads] = ve;
+    }
+    __syncthreads();
+    // step s (1..K) updates the tile plus a halo of K - s: LDS columns and
+    // rows s .. TX + 2K - 1 - s, inside the grid (Dirichlet)
+    T* src = sa;
+    T* dst = sb;
+    const T w = k.omega, inv = k.inv_b0;
+#pragma unroll
+    for (int st = 1; st <= K; ++st) {
+        const bool cok = c >= st && c <= J::TX + 2 * K - 1 - st && xin;
+        T v[J::IP];
+        bool wr[J::IP];
+#pragma unroll
+        for (int i = 0; i < J::IP; ++i) {
+            const int q = j + i * J::RP;
+            const int y = y0 - K + q;
+            wr[i] = cok && q >= st && q <= J::TY + 2 * K - 1 - st && (PER || (y >= 0 && y < n));
+            if (wr[i]) {
+                const int a = threadIdx.x + i * kThreads;
+                if (ZERO && st == 1) {
+                    v[i] = w * vr[i] * inv;
+                } else {
+                    const T uc = src[a];
+                    const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
+                    const T corners = src[a - L - 1] + src[a - L + 1] + src[a + L - 1] + src[a + L + 1];
+                    v[i] = uc + w * (vr[i] - (k.b0 * uc + k.bf * edges + k.bc * corners)) * inv;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < J::IP; ++i)
+            if (wr[i]) dst[threadIdx.x + i * kThreads] = v[i];
+        __syncthreads();
+        T* t = src;
+        src = dst;
+        dst = t;
+    }
+    // the tile: columns / rows K .. K + T - 1, inside the grid
+    if (c < K || c >= K + J::TX || x >= n || x < 0) return;
+#pragma unroll
+    for (int i = 0; i < J::IP; ++i) {
+        const int q = j + i * J::RP;
+        const int y = y0 - K + q;
+        if (q >= K && q < K + J::TY && y < n) e_out[(size_t)y * n + x] = src[threadIdx.x + i * kThreads];
     }
 }
 
@@ -232,6 +331,7 @@ __global__ void __launch_bounds__(kB) k_cres(CResArgs a, double* __restrict__ pa
 //   r = D^{-1} (y - W x),  d = cd d + cr r  (first step: d = r),  x_out = x + d.
 // KIND 0: first step from x = 0 (x_in not read); 1: first step from x_in;
 // 2: a later step.
+constexpr double kTwelfth = 1.0 / 12.0;
 template <bool PER, int KIND>
 __global__ void __launch_bounds__(kB)
 k_wcheb(const double* __restrict__ y, const double* __restrict__ x_in, double* __restrict__ x_out,
@@ -244,12 +344,106 @@ k_wcheb(const double* __restrict__ y, const double* __restrict__ x_in, double* _
         const double c = x_in[i];
         const double edges = at<PER>(x_in, n, x - 1, yy) + at<PER>(x_in, n, x + 1, yy) + at<PER>(x_in, n, x, yy - 1) +
                              at<PER>(x_in, n, x, yy + 1);
-        wx = c + (edges - 4.0 * c) / 12.0;
+        wx = c + (edges - 4.0 * c) * kTwelfth;
     }
     const double r = (y[i] - wx) * 1.5;
     const double dn = KIND == 2 ? cd * d[i] + cr * r : r;
     d[i] = dn;
     x_out[i] = (KIND != 0 ? x_in[i] : 0.0) + dn;
+}
+
+// kWS consecutive Chebyshev steps in one launch on the row-mapped tiles of
+// the Jacobi kernel above: x on the tile plus a halo of kWS in LDS (two
+// buffers), y and d of the thread's points in registers; step s runs on the
+// tile plus a halo of kWS - s with its own coefficients (cd[s], cr[s]).  Every
+// point is updated with the expression of k_wcheb, so the result is that of
+// kWS single steps.  KIND: the first step's kind as in k_wcheb.  d is read on
+// the halo, so it goes from d_in to d_out (x from x_in to x_out).
+constexpr int kWS = 4;
+struct WChebCoefs {
+    double cd[kWS], cr[kWS];
+};
+
+template <bool PER, int KIND>
+__global__ void __launch_bounds__(kThreads)
+k_wcheb_k(const double* __restrict__ y, const double* __restrict__ x_in, double* __restrict__ x_out,
+          const double* __restrict__ d_in, double* __restrict__ d_out, int n, int ntx, int nty, WChebCoefs co) {
+    using J = JTile<kWS>;
+    constexpr int K = kWS, L = kJL;
+    __shared__ double sa[J::N];
+    __shared__ double sb[J::N];
+    int x0, y0, z0;
+    tile_origin(ntx, nty, J::TX, J::TY, 1, x0, y0, z0);
+    const int c = threadIdx.x % L, j = threadIdx.x / L;
+    const int x = x0 - K + c;
+    const int xg = PER ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x;
+    const bool xin = PER ? true : (x >= 0 && x < n);
+    double vy[J::IP], vd[J::IP];
+#pragma unroll
+    for (int i = 0; i < J::IP; ++i) {
+        const int q = j + i * J::RP;
+        const int yy = y0 - K + q;
+        const int yg = PER ? (yy < 0 ? yy + n : (yy >= n ? yy - n : yy)) : yy;
+        const bool in = xin && q < J::ROWS && (PER || (yy >= 0 && yy < n));
+        double vx = 0.0, a = 0.0, b = 0.0;
+        if (in) {
+            const size_t gi = (size_t)yg * n + xg;
+            if (KIND != 0) vx = x_in[gi];
+            a = y[gi];
+            if (KIND == 2) b = d_in[gi];
+        }
+        vy[i] = a;
+        vd[i] = b;
+        sa[threadIdx.x + i * kThreads] = vx;
+        sb[threadIdx.x + i * kThreads] = vx;
+    }
+    __syncthreads();
+    double* src = sa;
+    double* dst = sb;
+#pragma unroll
+    for (int st = 1; st <= K; ++st) {
+        const bool first = st == 1;
+        const bool cok = c >= st && c <= J::TX + 2 * K - 1 - st && xin;
+        double v[J::IP];
+        bool wr[J::IP];
+#pragma unroll
+        for (int i = 0; i < J::IP; ++i) {
+            const int q = j + i * J::RP;
+            const int yy = y0 - K + q;
+            wr[i] = cok && q >= st && q <= J::TY + 2 * K - 1 - st && (PER || (yy >= 0 && yy < n));
+            if (wr[i]) {
+                const int a = threadIdx.x + i * kThreads;
+                double wx = 0.0, xc = 0.0;
+                if (!(first && KIND == 0)) {
+                    xc = src[a];
+                    const double edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
+                    wx = xc + (edges - 4.0 * xc) * kTwelfth;
+                }
+                const double r = (vy[i] - wx) * 1.5;
+                const double dn = (first && KIND != 2) ? r : co.cd[st - 1] * vd[i] + co.cr[st - 1] * r;
+                vd[i] = dn;
+                v[i] = xc + dn;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < J::IP; ++i)
+            if (wr[i]) dst[threadIdx.x + i * kThreads] = v[i];
+        __syncthreads();
+        double* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (c < K || c >= K + J::TX || x >= n || x < 0) return;
+#pragma unroll
+    for (int i = 0; i < J::IP; ++i) {
+        const int q = j + i * J::RP;
+        const int yy = y0 - K + q;
+        if (q >= K && q < K + J::TY && yy < n) {
+            const size_t gi = (size_t)yy * n + x;
+            x_out[gi] = src[threadIdx.x + i * kThreads];
+            d_out[gi] = vd[i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- WENO5 advection
@@ -349,6 +543,26 @@ hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const
 }
 
 template <typename T>
+hipError_t launch_cjacobi_steps(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out,
+                                bool per, hipStream_t s) {
+    if (nsteps == 1) return launch_cjacobi<T>(n, k, zero, r, e_in, e_out, per, s);
+#define ISDC_CJK(KV)                                                                                          \
+    {                                                                                                         \
+        int ntx, nty, nb;                                                                                     \
+        tile_counts<2>(n, JTile<KV>::TX, JTile<KV>::TY, 1, ntx, nty, nb);                                     \
+        if (per && zero) hipLaunchKernelGGL((k_cjacobi_k<T, true, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else if (per) hipLaunchKernelGGL((k_cjacobi_k<T, true, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else if (zero) hipLaunchKernelGGL((k_cjacobi_k<T, false, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else hipLaunchKernelGGL((k_cjacobi_k<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+    }
+    if (nsteps == 2) ISDC_CJK(2)
+    else if (nsteps == 3) ISDC_CJK(3)
+    else return hipErrorInvalidValue;
+#undef ISDC_CJK
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, bool per, hipStream_t s) {
     if (per)
         hipLaunchKernelGGL((k_cresfw<T, true>), grid2(n / 2), dim3(kB), 0, s, r, e, rc, n, k);
@@ -418,6 +632,28 @@ hipError_t launch_wcheb(int n, bool per, int kind, const double* y, const double
     return hipGetLastError();
 }
 
+hipError_t launch_wcheb_steps(int n, bool per, int kind, int nsteps, const double* y, const double* x_in,
+                              double* x_out, const double* d_in, double* d_out, const double* cd, const double* cr,
+                              hipStream_t s) {
+    if (nsteps != kWS) return hipErrorInvalidValue;
+    WChebCoefs co;
+    for (int k = 0; k < kWS; ++k) {
+        co.cd[k] = cd[k];
+        co.cr[k] = cr[k];
+    }
+    int ntx, nty, nb;
+    tile_counts<2>(n, JTile<kWS>::TX, JTile<kWS>::TY, 1, ntx, nty, nb);
+#define ISDC_WCHK(P, K) \
+    hipLaunchKernelGGL((k_wcheb_k<P, K>), dim3(nb), dim3(kThreads), 0, s, y, x_in, x_out, d_in, d_out, n, ntx, nty, co)
+    if (per) {
+        if (kind == 0) ISDC_WCHK(true, 0); else if (kind == 1) ISDC_WCHK(true, 1); else ISDC_WCHK(true, 2);
+    } else {
+        if (kind == 0) ISDC_WCHK(false, 0); else if (kind == 1) ISDC_WCHK(false, 1); else ISDC_WCHK(false, 2);
+    }
+#undef ISDC_WCHK
+    return hipGetLastError();
+}
+
 hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_weno_burgers, grid2(n), dim3(kB), 0, s, u, out, n, 1.0 / h);
     return hipGetLastError();
@@ -451,6 +687,8 @@ hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h,
 #define ISDC_CINST(T)                                                                                              \
     template CCoef<T> make_ccoef<T>(double, double, double, double);                                               \
     template hipError_t launch_cjacobi<T>(int, const CCoef<T>&, bool, const T*, const T*, T*, bool, hipStream_t);   \
+    template hipError_t launch_cjacobi_steps<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, bool,      \
+                                                hipStream_t);                                                      \
     template hipError_t launch_cresfw<T>(int, const CCoef<T>&, const T*, const T*, T*, bool, hipStream_t);          \
     template hipError_t launch_cprolong_p<T>(int, const T*, T*, hipStream_t);                                       \
     template hipError_t launch_cresnorm<T>(int, const CCoef<T>&, const T*, const T*, double*, int*, bool, hipStream_t); \

@@ -210,6 +210,11 @@ struct CResArgs {
 template <typename T>
 hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, bool per,
                           hipStream_t s);
+// nsteps (1..3) weighted-Jacobi steps from e_in to e_out in one launch (the
+// result of nsteps single steps); zero: e_in is zero and not read.
+template <typename T>
+hipError_t launch_cjacobi_steps(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out,
+                                bool per, hipStream_t s);
 // rc = full weighting of r - B e on the next coarser level.
 template <typename T>
 hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, bool per, hipStream_t s);
@@ -234,6 +239,14 @@ hipError_t launch_weno_burgers(int n, double h, const double* u, double* out, hi
 // coefficients cd, cr; x_out and x_in must differ, d is updated in place.
 hipError_t launch_wcheb(int n, bool per, int kind, const double* y, const double* x_in, double* x_out, double* d,
                         double cd, double cr, hipStream_t s);
+// kWChebSteps Chebyshev steps in one launch (the result of that many single
+// steps): kind as above for the first step, cd[k], cr[k] the coefficients of
+// step k (those of a first step are not used); d goes from d_in to d_out
+// (d_in != d_out), x from x_in to x_out.
+constexpr int kWChebSteps = 4;
+hipError_t launch_wcheb_steps(int n, bool per, int kind, int nsteps, const double* y, const double* x_in,
+                              double* x_out, const double* d_in, double* d_out, const double* cd, const double* cr,
+                              hipStream_t s);
 // One V-cycle of B (weighted Jacobi V(nu_pre, nu_post)) on a level of at
 // most 63^2 (Dirichlet) or 32^2 (periodic) points in one workgroup.
 template <typename T>

@@ -88,6 +88,8 @@ struct isdc_plan {
     double w = 0.0;                // h^2 / 12
     double* Yq[ISDC_MAX_M];        // dt Q_m F~ per node m+1 (NULL: node with Q row 0)
     double* X[ISDC_MAX_M];         // W^{-1} Yq[m], warm start of the next sweep's solve
+    double* WX = nullptr;          // W solve: partner of the iterate's ping-pong
+    double* WD[2] = {nullptr, nullptr};  // W solve: Chebyshev direction, double-buffered
     bool x_valid = false;
     // stencil f^E (WENO5 Burgers): f^E of u_0 and of every node array
     bool fe_arrays = false;

@@ -180,6 +180,16 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
                 p->X[m] = (double*)x;
             }
         }
+    if (compact) {
+        void* wx = take(N * sizeof(double));
+        void* wd0 = take(N * sizeof(double));
+        void* wd1 = take(N * sizeof(double));
+        if (p) {
+            p->WX = (double*)wx;
+            p->WD[0] = (double*)wd0;
+            p->WD[1] = (double*)wd1;
+        }
+    }
     size_t nparts = quad_partials(d, pb.n) > kReduceBlocks ? quad_partials(d, pb.n) : kReduceBlocks;
     if (compact) {
         const size_t rows = (size_t)pb.n * ((pb.n + 255) / 256);  // residual-norm blocks of the finest level
@@ -360,10 +370,13 @@ void cvcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, c
     const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, mg.omega);
     T* cur = e;
     T* other = tmp;
-    for (int i = 0; i < mg.nu_pre; ++i) {
-        HIPCHK(launch_cjacobi<T>(L.n, k, zero, rhs, cur, other, per, s));
+    // up to three Jacobi steps per launch
+    for (int i = 0; i < mg.nu_pre;) {
+        const int ks = std::min(3, mg.nu_pre - i);
+        HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, zero, rhs, cur, other, per, s));
         std::swap(cur, other);
         zero = false;
+        i += ks;
     }
     if (zero) {
         HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
@@ -376,9 +389,11 @@ void cvcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, c
         HIPCHK(launch_cprolong_p<T>(L.n, (const T*)C.e, cur, s));
     else
         HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
-    for (int i = 0; i < mg.nu_post; ++i) {
-        HIPCHK(launch_cjacobi<T>(L.n, k, false, rhs, cur, other, per, s));
+    for (int i = 0; i < mg.nu_post;) {
+        const int ks = std::min(3, mg.nu_post - i);
+        HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, false, rhs, cur, other, per, s));
         std::swap(cur, other);
+        i += ks;
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
 }
@@ -449,21 +464,33 @@ void cquad(isdc_plan* p, const double* const* nodes, const double* const* fe, hi
 // solver (c = -w); periodic plans with the compact Jacobi cycle at c = 0.
 // `steps` Chebyshev steps for W x = y from x = 0 (zero) or from x; tmp and d
 // are scratch arrays of the finest level.  Even step counts end in x.
-void wsolve(isdc_plan* p, bool zero, int steps, const double* y, double* x, double* tmp, double* d,
-            hipStream_t s) {
+void wsolve(isdc_plan* p, bool zero, int steps, const double* y, double* x, hipStream_t s) {
     double* cur = x;
-    double* other = tmp;
+    double* other = p->WX;
+    double* d = p->WD[0];
+    double* d2 = p->WD[1];
     double rho = 0.5;  // 1 / sigma, sigma = centre / half-width = 2
-    for (int k = 0; k < steps; ++k) {
-        double cd = 0.0, cr = 0.0;
-        int kind = k == 0 ? (zero ? 0 : 1) : 2;
-        if (k > 0) {
-            const double rn = 1.0 / (4.0 - rho);  // 1 / (2 sigma - rho)
-            cd = rn * rho;
-            cr = 4.0 * rn;  // 2 rho_k / half-width
-            rho = rn;
+    // the coefficients of every step, then launches of kWChebSteps fused steps
+    // (single steps for a remainder)
+    std::vector<double> cdv(steps, 0.0), crv(steps, 0.0);
+    for (int k = 1; k < steps; ++k) {
+        const double rn = 1.0 / (4.0 - rho);  // 1 / (2 sigma - rho)
+        cdv[k] = rn * rho;
+        crv[k] = 4.0 * rn;  // 2 rho_k / half-width
+        rho = rn;
+    }
+    for (int k = 0; k < steps;) {
+        const int kind = k == 0 ? (zero ? 0 : 1) : 2;
+        if (steps - k >= kWChebSteps) {
+            // the fused steps read d on a halo, so it is written out of place
+            HIPCHK(launch_wcheb_steps(p->n, p->periodic, kind, kWChebSteps, y, cur, other, d, d2, &cdv[k], &crv[k],
+                                      s));
+            std::swap(d, d2);
+            k += kWChebSteps;
+        } else {
+            HIPCHK(launch_wcheb(p->n, p->periodic, kind, y, cur, other, d, cdv[k], crv[k], s));
+            ++k;
         }
-        HIPCHK(launch_wcheb(p->n, p->periodic, kind, y, cur, other, d, cd, cr, s));
         std::swap(cur, other);
     }
     if (cur != x) HIPCHK(launch_copy<double>(cur, x, p->N, s));
@@ -477,7 +504,7 @@ double cresidual(isdc_plan* p, hipStream_t s) {
     const int steps = p->x_valid ? kWWarmSteps : kWColdSteps;
     for (int m = 0; m < p->M; ++m) {
         if (!p->Yq[m]) continue;
-        wsolve(p, !p->x_valid, steps, p->Yq[m], p->X[m], (double*)p->lev[0].e2, (double*)p->lev[0].e, s);
+        wsolve(p, !p->x_valid, steps, p->Yq[m], p->X[m], s);
         ra.um[ra.count] = p->cur[m + 1];
         ra.xm[ra.count] = p->X[m];
         ++ra.count;
@@ -698,7 +725,7 @@ void end_quadrature(isdc_plan* p, double* d_out, hipStream_t s) {
         a.M = p->M;
         HIPCHK(launch_cquad(a, p->M, p->periodic, s));
         double* x = (double*)p->lev[0].e;
-        wsolve(p, true, kWColdSteps, p->END, x, (double*)p->lev[0].e2, (double*)p->lev[0].r, s);
+        wsolve(p, true, kWColdSteps, p->END, x, s);
         add = x;
     } else {
         QuadArgs qa;
@@ -1093,7 +1120,10 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
             const Level& L = p->lev[level];
             const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
             const bool per = p->periodic;
-            launch = [=]() { HIPCHK(launch_cjacobi<T>(L.n, k, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, per, s)); };
+            const int ks = std::min(3, std::max(1, p->mg.nu_pre));
+            launch = [=]() {
+                HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, per, s));
+            };
             b = 3.0 * (double)L.N * w;
         } else if (kernel == ISDC_KERNEL_TAIL) {
             const Level& L = p->lev[p->tail];
