@@ -118,8 +118,8 @@ def kernel_name(name, cfg, T, shape=0):
     if cfg.get("stencil", 0) == 1:
         per = "true" if cfg.get("bc", 0) == 1 else "false"
         ks = min(3, max(1, cfg.get("nu_pre", 3)))
-        smooth = f"k_cjacobi<{T},false,{per}>" if ks == 1 else f"k_cjacobi_k<{T},{per},{ks},false>"
-        return {"smooth": smooth, "tail": f"k_ctail<{T},{per}>", "explicit": "k_weno_burgers"}[name]
+        return {"smooth": f"k_cjres<{T},{per},{ks},false>", "tail": f"k_ctail<{T},{per}>",
+                "explicit": "k_weno_burgers"}[name]
     if cfg["dim"] == 3 and cfg["n"] >= 127 and name == "prolong_smooth":
         return f"k_march_rbgs<{T},true,0,false>"
     if cfg["dim"] == 2 and name in ROW_KERNEL_NAMES:
@@ -233,12 +233,14 @@ def vcycle_probe(plan, cfg, reps, torch):
     # prolongation+smoothing; the tail reads its rhs and writes its iterate
     b, m = 0.0, n
     compact = cfg.get("stencil", 0) == 1
-    # compact: Jacobi launches of up to three fused steps, 3N each
-    njl = -(-cfg.get("nu_pre", 1) // 3) - (-cfg.get("nu_post", 1) // 3)
+    # compact: Jacobi steps + residual + restriction and prolongation + Jacobi
+    # steps (3N + Nc each, up to three steps per launch), further launches of
+    # up to three steps 3N each
+    extra = (-(-cfg.get("nu_pre", 1) // 3) - 1) + (-(-cfg.get("nu_post", 1) // 3) - 1)
     while m > tail_n(cfg):
         N, Nc = m ** d, coarser(cfg, m) ** d
-        if compact:  # Jacobi launches 3N each; residual + restriction 2N + Nc; prolongation 2N + Nc
-            b += (njl * 3 * N + 4 * N + 2 * Nc) * w
+        if compact:
+            b += (2 * (3 * N + Nc) + extra * 3 * N) * w
         else:        # smoothing + restriction 3N + Nc; prolongation + smoothing 3N + Nc
             b += 2 * (3 * N + Nc) * w
         m = coarser(cfg, m)

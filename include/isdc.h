@@ -270,10 +270,10 @@ int isdc_get_tile_shapes(const isdc_plan* plan, int32_t* h_shapes, int32_t max_l
  * written once) to *h_bytes, and synchronises `stream`.  For measurement;
  * leaves the plan's workspace arrays with unspecified contents, so call it
  * only between steps.  Compact-stencil plans time ISDC_KERNEL_SMOOTH (the
- * launch of min(3, nu_pre) fused weighted-Jacobi steps of B that the
- * V-cycle's pre-smoothing starts with; algorithmic bytes: the rhs and the
- * iterate read once, the iterate written once), ISDC_KERNEL_TAIL (the
- * compact tail) and ISDC_KERNEL_EXPLICIT only.
+ * V-cycle's launch of min(3, nu_pre) weighted-Jacobi steps of B fused with
+ * the residual's full-weighting restriction; algorithmic bytes: the rhs and
+ * the iterate read once, the iterate and the coarse rhs written once),
+ * ISDC_KERNEL_TAIL (the compact tail) and ISDC_KERNEL_EXPLICIT only.
  *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
  *                                full-weighting restriction (levels above the
  *                                coarse tail, d = 1 or 2)

@@ -215,6 +215,16 @@ hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const
 template <typename T>
 hipError_t launch_cjacobi_steps(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out,
                                 bool per, hipStream_t s);
+// nsteps (1..3) Jacobi steps from e_in to e_out fused with rc = full
+// weighting of r - B e_out on the next coarser level (zero: e_in is zero).
+template <typename T>
+hipError_t launch_cjres(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out, T* rc,
+                        bool per, hipStream_t s);
+// e_in + P ec (linear interpolation of the coarse correction) followed by
+// nsteps (1..3) Jacobi steps, into e_out.
+template <typename T>
+hipError_t launch_cpjac(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
+                        bool per, hipStream_t s);
 // rc = full weighting of r - B e on the next coarser level.
 template <typename T>
 hipError_t launch_cresfw(int n, const CCoef<T>& k, const T* r, const T* e, T* rc, bool per, hipStream_t s);

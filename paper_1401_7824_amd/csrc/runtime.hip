@@ -370,30 +370,46 @@ void cvcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, c
     const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, mg.omega);
     T* cur = e;
     T* other = tmp;
-    // up to three Jacobi steps per launch
-    for (int i = 0; i < mg.nu_pre;) {
-        const int ks = std::min(3, mg.nu_pre - i);
-        HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, zero, rhs, cur, other, per, s));
-        std::swap(cur, other);
-        zero = false;
-        i += ks;
-    }
-    if (zero) {
-        HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
-        zero = false;
-    }
     const Level& C = p->lev[l + 1];
-    HIPCHK(launch_cresfw<T>(L.n, k, rhs, cur, (T*)C.r, per, s));
-    cvcycle_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
-    if (per)
-        HIPCHK(launch_cprolong_p<T>(L.n, (const T*)C.e, cur, s));
-    else
-        HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
-    for (int i = 0; i < mg.nu_post;) {
-        const int ks = std::min(3, mg.nu_post - i);
-        HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, false, rhs, cur, other, per, s));
+    // pre-smoothing: the last (up to three) Jacobi steps fused with the
+    // residual's restriction, earlier ones three per launch
+    int pre = mg.nu_pre;
+    while (pre > 3) {
+        HIPCHK(launch_cjacobi_steps<T>(L.n, k, 3, zero, rhs, cur, other, per, s));
         std::swap(cur, other);
-        i += ks;
+        zero = false;
+        pre -= 3;
+    }
+    if (pre > 0) {
+        HIPCHK(launch_cjres<T>(L.n, k, pre, zero, rhs, cur, other, (T*)C.r, per, s));
+        std::swap(cur, other);
+        zero = false;
+    } else {
+        if (zero) {
+            HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
+            zero = false;
+        }
+        HIPCHK(launch_cresfw<T>(L.n, k, rhs, cur, (T*)C.r, per, s));
+    }
+    cvcycle_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    // post-smoothing: the prolongation fused with the first (up to three)
+    // Jacobi steps, later ones three per launch
+    int post = mg.nu_post;
+    if (post > 0) {
+        const int first = std::min(3, post);
+        HIPCHK(launch_cpjac<T>(L.n, k, first, rhs, cur, (const T*)C.e, other, per, s));
+        std::swap(cur, other);
+        post -= first;
+        while (post > 0) {
+            const int ks = std::min(3, post);
+            HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, false, rhs, cur, other, per, s));
+            std::swap(cur, other);
+            post -= ks;
+        }
+    } else if (per) {
+        HIPCHK(launch_cprolong_p<T>(L.n, (const T*)C.e, cur, s));
+    } else {
+        HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
 }
@@ -1114,17 +1130,20 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
     std::function<void()> launch;
     double b = 0.0;
     if (p->compact) {
-        // compact plans: the weighted-Jacobi step (SMOOTH) and the compact tail
+        // compact plans: the fused Jacobi + restriction launch (SMOOTH), the
+        // compact tail and the Burgers advection
         if (kernel == ISDC_KERNEL_SMOOTH) {
             if (level < 0 || level >= p->tail) fail(ISDC_E_INVAL, "level must lie above the coarse tail for this kernel");
             const Level& L = p->lev[level];
             const CCoef<T> k = make_ccoef<T>(c, p->w, L.h, p->mg.omega);
             const bool per = p->periodic;
+            // the V-cycle's fused pre-smoothing + residual + restriction launch
+            const Level& Cl = p->lev[level + 1];
             const int ks = std::min(3, std::max(1, p->mg.nu_pre));
             launch = [=]() {
-                HIPCHK(launch_cjacobi_steps<T>(L.n, k, ks, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, per, s));
+                HIPCHK(launch_cjres<T>(L.n, k, ks, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, (T*)Cl.r, per, s));
             };
-            b = 3.0 * (double)L.N * w;
+            b = (3.0 * (double)L.N + (double)Cl.N) * w;
         } else if (kernel == ISDC_KERNEL_TAIL) {
             const Level& L = p->lev[p->tail];
             launch = [=]() {
