@@ -112,6 +112,26 @@ def test_periodic_vcycle(n):
     assert abs(res - P.residual_compact_inf_p(ref, rhs, c, h)) < 1e-9 * max(res, 1e-30) + 1e-14
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nus", [(1, 1), (2, 2), (4, 5), (0, 2), (2, 0)])
+def test_periodic_vcycle_smoothing_counts(nus, dtype):
+    # the launches of a periodic level for every split of the smoothing steps
+    n, (nu1, nu2) = 256, nus
+    announce("periodic vcycle nu", nus, dtype)
+    p = _plan(n, nu_pre=nu1, nu_post=nu2)
+    h = 2.0 / n
+    c = 1e-3 * 0.37
+    nd = _np(dtype)
+    rhs = random_field((n, n), 43).astype(nd)
+    u0 = (0.1 * random_field((n, n), 44)).astype(nd)
+    u = dev(u0, dtype)
+    p.vcycle(c, dev(rhs, dtype), u, 2)
+    ref = u0
+    for _ in range(2):
+        ref = P.vcycle_compact_p(ref, rhs, c, h, nu1, nu2, 1.0)
+    assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5)
+
+
 @pytest.mark.parametrize("n", [4, 8, 128, 1024])
 def test_weno_burgers_advection(n):
     from paper_1401_7824_amd import OP_EXPLICIT

@@ -104,6 +104,28 @@ def test_compact_vcycle(n):
     assert abs(res - C.residual_compact_inf(ref, rhs, c, h)) < 1e-9 * max(res, 1e-30) + 1e-14
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nus", [(1, 1), (2, 2), (4, 5), (0, 2), (2, 0)])
+def test_compact_vcycle_smoothing_counts(nus, dtype):
+    # every split of the smoothing steps over the launches of a level: up to
+    # three steps fused with the restriction / prolongation, the rest three
+    # per launch, none at all (plain restriction / prolongation)
+    n, (nu1, nu2) = 255, nus
+    announce("compact vcycle nu", nus, dtype)
+    p = _plan(n, nu_pre=nu1, nu_post=nu2)
+    h = 1.0 / (n + 1)
+    c = 1e-3 * 0.37
+    nd = _np(dtype)
+    rhs = random_field((n, n), 41).astype(nd)
+    u0 = (0.1 * random_field((n, n), 42)).astype(nd)
+    u = dev(u0, dtype)
+    p.vcycle(c, dev(rhs, dtype), u, 2)
+    ref = u0
+    for _ in range(2):
+        ref = C.vcycle_compact(ref, rhs, c, h, nu1, nu2, 1.0)
+    assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5)
+
+
 def _cfg(nu, fe, kind, M, prec=0, **kw):
     base = dict(nu=nu, fe_kind=fe, node_kind=kind, M=M, inner="mg", smoother=1, nu1=3, nu2=3, precision=prec,
                 stencil=STENCIL_COMPACT4)
