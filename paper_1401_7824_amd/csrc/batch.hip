@@ -166,6 +166,12 @@ __global__ void __launch_bounds__(kThreads) kb_restrict(BArgs a) {
     const SlotDesc& s = a.desc[i];
     const int l = a.level, p = a.p;
     int X0, Y0, Z0;
+    if (D == 3 && march_depth(s.ln[l]) > 0) {
+        tile_xyz<D>(t, (s.ln[l] - 1) / 2, MRTile::X, MRTile::Y, march_restrict_depth(), X0, Y0, Z0);
+        march_restrict_body<T>((const T*)s.lr[l], (const T*)s.le2[l], (T*)s.lr[l + 1], s.ln[l], X0, Y0, Z0,
+                               march_restrict_depth(), T(s.la[p][l]), T(s.ldiag[p][l]));
+        return;
+    }
     tile_xyz<D>(t, (s.ln[l] - 1) / 2, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, X0, Y0, Z0);
     restrict_tile_body<T, D>((const T*)s.lr[l], (const T*)s.le2[l], (T*)s.lr[l + 1], s.ln[l], X0, Y0, Z0,
                              T(s.la[p][l]), T(s.ldiag[p][l]));
@@ -366,6 +372,8 @@ int tiles_smooth(int d, int n) {
 }
 
 int tiles_coarse(int d, int nc) {
+    if (d == 3 && march_depth(2 * nc + 1) > 0)  // the fine level is marched: so is its restriction
+        return ntiles_of<3>(nc, MRTile::X, MRTile::Y, march_restrict_depth());
     return d == 1 ? ntiles_of<1>(nc, CTile<1>::X, 1, 1)
                   : (d == 2 ? ntiles_of<2>(nc, CTile<2>::X, CTile<2>::Y, 1)
                             : ntiles_of<3>(nc, CTile<3>::X, CTile<3>::Y, CTile<3>::Z));

@@ -253,5 +253,153 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
     }
 }
 
+// Residual r - A e of a 3D level and its full weighting onto the coarse
+// level, z-marched.  A workgroup owns a coarse xy tile of MRTile::X x
+// MRTile::Y points and a column of mzc coarse planes [Z0, Z0 + mzc).  Coarse
+// plane Z takes the residual of fine planes 2Z, 2Z+1, 2Z+2 (coarse point I on
+// fine 2I+1), and fine plane f needs the iterate on planes f-1..f+1: each step
+// loads iterate planes 2Z+2, 2Z+3 (a ring of four, xy halo 1) and rhs planes
+// 2Z+1, 2Z+2 (in registers, on the threads that compute the residual there),
+// computes residual planes 2Z+1, 2Z+2 (a ring of three; 2Z is left from the
+// step before) and writes coarse plane Z.  Each array is read about once
+// instead of the 2-3 times of a 3D tile with a halo.  The residual and the
+// weighted sums are the expressions of restrict_tile_body, term for term.
+struct MRTile { static constexpr int X = 16, Y = 8; };
+__host__ __device__ constexpr int march_restrict_depth() { return 8; }
+
+template <typename T>
+__device__ __forceinline__ void march_restrict_body(const T* __restrict__ r, const T* __restrict__ e,
+                                                    T* __restrict__ rc, int n, int X0, int Y0, int Z0, int mzc, T a,
+                                                    T diag) {
+    using RB = Box<2, 2 * MRTile::X + 1, 2 * MRTile::Y + 1, 1>;  // residual plane, fine origin (2X0, 2Y0)
+    using EB = Box<2, 2 * MRTile::X + 3, 2 * MRTile::Y + 3, 1>;  // iterate plane, origin (2X0-1, 2Y0-1)
+    constexpr int IE = (EB::N + kThreads - 1) / kThreads;
+    constexpr int IR = (RB::N + kThreads - 1) / kThreads;
+    __shared__ T sE[4][EB::N];
+    __shared__ T sRes[3][RB::N];
+    const size_t nn = (size_t)n * n;
+    const int nc = (n - 1) / 2;
+    const int Z1 = min(Z0 + mzc, nc);
+    const int fx = 2 * X0, fy = 2 * Y0;
+
+    auto load_e = [&](T (&dst)[IE], int p) {
+#pragma unroll
+        for (int it = 0; it < IE; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            int lx, ly, lz;
+            EB::split(k, lx, ly, lz);
+            const int x = fx - 1 + lx, y = fy - 1 + ly;
+            T v = T(0);
+            if (k < EB::N && (unsigned)p < (unsigned)n && inside<2>(x, y, 0, n)) v = e[p * nn + (size_t)y * n + x];
+            dst[it] = v;
+        }
+    };
+    auto load_r = [&](T (&dst)[IR], int p) {
+#pragma unroll
+        for (int it = 0; it < IR; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            int lx, ly, lz;
+            RB::split(k, lx, ly, lz);
+            const int x = fx + lx, y = fy + ly;
+            T v = T(0);
+            if (k < RB::N && (unsigned)p < (unsigned)n && inside<2>(x, y, 0, n)) v = r[p * nn + (size_t)y * n + x];
+            dst[it] = v;
+        }
+    };
+    auto store_e = [&](const T (&src)[IE], int p) {
+        T* d = sE[p & 3];
+#pragma unroll
+        for (int it = 0; it < IE; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            if (k < EB::N) d[k] = src[it];
+        }
+    };
+    // residual of fine plane f (iterate planes f-1..f+1 in the ring) from the
+    // thread's rhs values rr; points outside the grid keep 0
+    auto residual = [&](const T (&rr)[IR], int f) {
+        const T* em = sE[(f + 3) & 3];
+        const T* e0 = sE[f & 3];
+        const T* ep = sE[(f + 1) & 3];
+        T* out = sRes[f % 3];
+#pragma unroll
+        for (int it = 0; it < IR; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            int lx, ly, lz;
+            RB::split(k, lx, ly, lz);
+            if (k >= RB::N) break;
+            T v = T(0);
+            if (inside<2>(fx + lx, fy + ly, 0, n)) {
+                const int i = (ly + 1) * EB::X + (lx + 1);
+                const T nb = e0[i - 1] + e0[i + 1] + e0[i - EB::X] + e0[i + EB::X] + em[i] + ep[i];
+                v = rr[it] - (diag * e0[i] - a * nb);
+            }
+            out[k] = v;
+        }
+    };
+
+    T ea[IE], eb[IE], ra[IR], rb[IR];
+    // prologue: residual plane 2 Z0 from iterate planes 2Z0-1 .. 2Z0+1
+    {
+        const int f = 2 * Z0;
+        load_e(ea, f - 1);
+        load_e(eb, f);
+        T ec[IE];
+        load_e(ec, f + 1);
+        load_r(ra, f);
+        store_e(ea, f - 1);
+        store_e(eb, f);
+        store_e(ec, f + 1);
+        __syncthreads();
+        residual(ra, f);
+        __syncthreads();  // the first step overwrites plane f - 1
+    }
+    // loads of the first step: iterate planes 2Z0+2, 2Z0+3, rhs 2Z0+1, 2Z0+2
+    load_e(ea, 2 * Z0 + 2);
+    load_e(eb, 2 * Z0 + 3);
+    load_r(ra, 2 * Z0 + 1);
+    load_r(rb, 2 * Z0 + 2);
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    for (int Z = Z0; Z < Z1; ++Z) {
+        const int f = 2 * Z;
+        store_e(ea, f + 2);
+        store_e(eb, f + 3);
+        T rr1[IR], rr2[IR];
+#pragma unroll
+        for (int it = 0; it < IR; ++it) {
+            rr1[it] = ra[it];
+            rr2[it] = rb[it];
+        }
+        if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
+            load_e(ea, f + 4);
+            load_e(eb, f + 5);
+            load_r(ra, f + 3);
+            load_r(rb, f + 4);
+        }
+        __syncthreads();
+        residual(rr1, f + 1);
+        residual(rr2, f + 2);
+        __syncthreads();
+        // coarse plane Z from residual planes f, f+1, f+2
+        for (int c = threadIdx.x; c < MRTile::X * MRTile::Y; c += kThreads) {
+            const int cx = c % MRTile::X, cy = c / MRTile::X;
+            const int X = X0 + cx, Y = Y0 + cy;
+            if (X >= nc || Y >= nc) continue;
+            T acc = T(0);
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) {
+                const T* s = sRes[(f + oz) % 3];
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    const int base = (2 * cy + oy) * RB::X + 2 * cx;
+                    T row = w[0] * s[base] + w[1] * s[base + 1] + w[2] * s[base + 2];
+                    T wyz = w[oy] * w[oz];
+                    acc += wyz * row;
+                }
+            }
+            rc[((size_t)Z * nc + Y) * nc + X] = acc;
+        }
+    }
+}
+
 }  // namespace
 }  // namespace isdc

@@ -13,6 +13,8 @@
 //                       node array instead of e (the node update of eq. (4));
 //   k_march_rbgs        the 3D form of the two red-black kernels above:
 //                       columns of planes marched in z instead of 3D tiles;
+//   k_march_restrict    the 3D restriction of those levels, marched over
+//                       coarse planes;
 //   k_rows_*            the 2D forms of the red-black, fused red-black +
 //                       restriction and prolongation + red-black kernels on
 //                       row-mapped tiles (rows2d.h).
@@ -83,6 +85,17 @@ k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __res
 }
 
 // 2D row-mapped tiles (shape S selects the row tile).
+// 3D residual + full weighting, z-marched over coarse planes (levels of
+// 127^3 and up).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_march_restrict(const T* __restrict__ r, const T* __restrict__ e, T* __restrict__ rc, int n, int ntx, int nty,
+                 int mzc, T a, T diag) {
+    int X0, Y0, Z0;
+    tile_origin(ntx, nty, MRTile::X, MRTile::Y, mzc, X0, Y0, Z0);
+    march_restrict_body<T>(r, e, rc, n, X0, Y0, Z0, mzc, a, diag);
+}
+
 template <typename T, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty, T a,
@@ -194,6 +207,14 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
 template <typename T>
 hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, const T* e, T* rc, hipStream_t s) {
     const int nc = (n - 1) / 2;
+    if (d == 3 && march_depth(n) > 0) {
+        const int mzc = march_restrict_depth();
+        int ntx, nty, nb;
+        tile_counts<3>(nc, MRTile::X, MRTile::Y, mzc, ntx, nty, nb);
+        hipLaunchKernelGGL((k_march_restrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, mzc, co.a,
+                           co.diag);
+        return hipGetLastError();
+    }
     ISDC_DISPATCH_D(d, {
         int ntx, nty, nb;
         tile_counts<D>(nc, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, ntx, nty, nb);
