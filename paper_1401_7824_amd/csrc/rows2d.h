@@ -186,33 +186,37 @@ __device__ __forceinline__ void rows_rbgs_body(const T* __restrict__ r, const T*
 // One red-black step from e_in to e_out fused with rc = full weighting of
 // (r - A e_out): the new iterate is computed on the tile plus a halo of 1
 // (red on a halo of 2), so the residual is known on every fine point under
-// the tile's coarse points.
+// the tile's coarse points.  In two parts: rr_load fills registers, rr_run
+// stores them to LDS and does the rest.
+template <typename T, class RT>
+struct RRStage {
+    T ve[RT::IP], vr[RT::IP];
+};
+
 template <typename T, bool ZERO, class RT>
-__device__ __forceinline__ void rows_rbgs_restrict_body(const T* __restrict__ r, const T* __restrict__ e_in,
-                                                        T* __restrict__ e_out, T* __restrict__ rc, int n, int x0,
-                                                        int y0, T a, T diag, T invdiag) {
-    constexpr int L = RT::LPR;
-    __shared__ T se[RT::N];
-    __shared__ T sr[RT::N];
+__device__ __forceinline__ void rr_load(RRStage<T, RT>& st, const T* __restrict__ r, const T* __restrict__ e_in,
+                                        int n, int x0, int y0) {
     // the residual is needed on x0 .. x0+TX (one past the tile), so every
     // region below it reaches one point further on the high side
-    const Region R3 = region(3, 1, 1, x0, y0, n, RT::TX, RT::TY);
+    if (ZERO) {
+#pragma unroll
+        for (int i = 0; i < RT::IP; ++i) st.ve[i] = T(0);
+    } else {
+        rows_load<RT>(st.ve, e_in, n, x0, y0, region(3, 1, 1, x0, y0, n, RT::TX, RT::TY));
+    }
+    rows_load<RT>(st.vr, r, n, x0, y0, region(2, 1, 1, x0, y0, n, RT::TX, RT::TY));
+}
+
+template <typename T, class RT>
+__device__ __forceinline__ void rr_run(const RRStage<T, RT>& st, T* se, T* sr, T* __restrict__ e_out,
+                                       T* __restrict__ rc, int n, int x0, int y0, T a, T diag, T invdiag) {
+    constexpr int L = RT::LPR;
     const Region R2 = region(2, 1, 1, x0, y0, n, RT::TX, RT::TY);
     const Region R1 = region(1, 1, 1, x0, y0, n, RT::TX, RT::TY);
     const Region RS = region(0, 1, 1, x0, y0, n, RT::TX, RT::TY);  // x0 .. x0+TX, y0 .. y0+TY
     const Region T0 = region(0, 0, 0, x0, y0, n, RT::TX, RT::TY);
-    {
-        T ve[RT::IP], vr[RT::IP];
-        if (ZERO) {
-#pragma unroll
-            for (int i = 0; i < RT::IP; ++i) ve[i] = T(0);
-        } else {
-            rows_load<RT>(ve, e_in, n, x0, y0, R3);
-        }
-        rows_load<RT>(vr, r, n, x0, y0, R2);
-        rows_store_lds<RT>(se, ve);
-        rows_store_lds<RT>(sr, vr);
-    }
+    rows_store_lds<RT>(se, st.ve);
+    rows_store_lds<RT>(sr, st.vr);
     __syncthreads();
     rows_colour<RT>(se, sr, 0, x0, y0, R2, a, invdiag);
     __syncthreads();
@@ -256,6 +260,17 @@ __device__ __forceinline__ void rows_rbgs_restrict_body(const T* __restrict__ r,
         acc += w0 * r2;
         at_byte(rc, ((unsigned)Y * (unsigned)nc + (unsigned)X) * (unsigned)sizeof(T)) = acc;
     }
+}
+
+template <typename T, bool ZERO, class RT>
+__device__ __forceinline__ void rows_rbgs_restrict_body(const T* __restrict__ r, const T* __restrict__ e_in,
+                                                        T* __restrict__ e_out, T* __restrict__ rc, int n, int x0,
+                                                        int y0, T a, T diag, T invdiag) {
+    __shared__ T se[RT::N];
+    __shared__ T sr[RT::N];
+    RRStage<T, RT> st;
+    rr_load<T, ZERO, RT>(st, r, e_in, n, x0, y0);
+    rr_run<T, RT>(st, se, sr, e_out, rc, n, x0, y0, a, diag, invdiag);
 }
 
 // e_in + P ec (linear interpolation) on the tile plus a halo of 2, then one
