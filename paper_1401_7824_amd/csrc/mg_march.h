@@ -8,11 +8,12 @@
 // updated on the tile plus an xy halo of 1, then the black points of plane k
 // on the tile; plane k is then final and goes to memory.  Red reads only old
 // black values and black only new red values, so this is exactly one
-// red-black step (red = even index sum, first).  Red on planes z0-1 and z0 is
-// recomputed from the old iterate, so neighbouring columns never exchange
-// data.  Every step first stores the planes loaded during the previous step
-// into LDS and issues the loads for the next step, so global reads stay in
-// flight while the step's LDS work runs.
+// red-black step (red = even index sum, first).  Red on the planes just
+// outside the column (z0 - 1 and z0 + mz) is recomputed from the old iterate,
+// so neighbouring columns never exchange data.  Every step first stores the plane loaded during the previous step
+// into LDS and issues the loads for the next step (the next plane of the
+// iterate; the rhs at the next red and black points, which go to registers),
+// so global reads stay in flight while the step's LDS work runs.
 //
 // PRO: the iterate entering the ring is e_in + P e_c (trilinear
 // interpolation of the coarse correction; coarse planes pass through one LDS
@@ -23,12 +24,38 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "tile_common.h"
 
 namespace isdc {
 namespace {
 
-struct MTile { static constexpr int X = 32, Y = 16; };
+// Plane layout of the march (row-mapped, as the 2D row tiles): LPR = 64
+// columns x0-2 .. x0+61 by ROWS = Y + 4 rows y0-2 .. y0+Y+1, stride LPR, for
+// an xy tile of X = 60 by Y = 16 points.  A plain pass (loads, LDS stores,
+// the prolongation) gives thread t column t % LPR and rows t / LPR + RP i; a
+// colour pass gives it colour lane t % H of rows t / H + RC i, and a row's
+// H points of one colour sit one every other column, so every lane has a
+// point of the colour and its column parity is fixed per plane.  LDS
+// addresses are per-thread constants plus compile-time offsets, global ones a
+// per-thread 32-bit byte offset from a uniform plane base.
+struct MTile {
+    static constexpr int X = 60, Y = 16;
+    static constexpr int LPR = 64, ROWS = Y + 4;
+    static constexpr int PN = LPR * ROWS;               // values per LDS plane
+    static constexpr int RP = kThreads / LPR;           // rows per plain step
+    static constexpr int IP = ROWS / RP;                // plain steps over a plane
+    static constexpr int H = LPR / 2;                   // colour lanes per row
+    static constexpr int RC = kThreads / H;             // rows per colour step
+    static constexpr int IRED = (Y + 2 + RC - 1) / RC;  // red: rows 1 .. Y+2 (halo 1)
+    static constexpr int IBLK = Y / RC;                 // black: rows 2 .. Y+1 (the tile)
+    static constexpr int CROWS = Y / 2 + 4;             // coarse rows y0/2-2 .. (one spare)
+    static constexpr int ICP = (CROWS + RP - 1) / RP;   // plain steps over the coarse plane
+    static_assert(X + 4 == LPR && ROWS % RP == 0 && Y % RC == 0, "whole plain and colour steps");
+    static_assert(RP % 2 == 0 && RC % 2 == 0 && X % 2 == 0, "even row steps keep a thread's row parity");
+    static_assert(X / 2 + 4 <= LPR && ICP * RP >= CROWS, "the coarse plane fits the layout");
+};
 
 // Planes per marched column on an n^3 level, or 0 where the one-pass 3D tile
 // kernels are used instead: a column costs a chain of Z + 4 dependent steps,
@@ -48,94 +75,128 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
                                                 const T* __restrict__ ec, T* __restrict__ e_out, int n, int x0, int y0,
                                                 int z0, int mz, T a, T invdiag, const double* __restrict__ g,
                                                 double* __restrict__ u_out) {
-    using EP = Box<2, MTile::X + 4, MTile::Y + 4, 1>;          // iterate plane, origin (x0-2, y0-2)
-    using RP = Box<2, MTile::X + 2, MTile::Y + 2, 1>;          // rhs plane, origin (x0-1, y0-1)
-    using IP = Box<2, MTile::X, MTile::Y, 1>;                  // the tile
-    using CP = Box<2, MTile::X / 2 + 4, MTile::Y / 2 + 4, 1>;  // coarse plane, origin (x0/2-2, y0/2-2)
-    constexpr int NE = 5, NR = 3;                              // ring lengths (see the hazards below)
-    constexpr int IE = (EP::N + kThreads - 1) / kThreads;
-    constexpr int IR = (RP::N + kThreads - 1) / kThreads;
-    constexpr int II = (IP::N + kThreads - 1) / kThreads;
-    constexpr int IC = (CP::N + kThreads - 1) / kThreads;
-    __shared__ T sE[NE][EP::N];
-    __shared__ T sR[NR][RP::N];
-    __shared__ T sC[PRO ? CP::N : 1];
+    using M = MTile;
+    using TO = typename std::conditional<MODE == 0, T, double>::type;
+    constexpr int L = M::LPR;
+    constexpr int NE = 5;  // iterate ring (see the hazards below)
+    __shared__ T sE[NE * M::PN];
+    __shared__ T sC[PRO ? M::CROWS * L : 1];
 
     const size_t nn = (size_t)n * n;
     const int nc = (n - 1) / 2;
     const int z1 = min(z0 + mz, n);  // planes [z0, z1) are written
-    const int cxo = x0 / 2 - 2, cyo = y0 / 2 - 2;
-    auto ring = [](int p, int len) { return ((p % len) + len) % len; };
+    // the domain 0 <= x, y < n in layout columns / rows (x = x0 - 2 + c, y = y0 - 2 + row)
+    const int clo = max(0, 2 - x0), chi = min(L - 1, n + 1 - x0);
+    const int rlo = max(0, 2 - y0), rhi = min(M::ROWS - 1, n + 1 - y0);
+    const int rclo = max(1, clo), rchi = min(M::X + 2, chi), rrlo = max(1, rlo), rrhi = min(M::Y + 2, rhi);
+    const int bclo = max(2, clo), bchi = min(M::X + 1, chi), brlo = max(2, rlo), brhi = min(M::Y + 1, rhi);
+    const unsigned rowb = (unsigned)n * (unsigned)sizeof(T);
+    const unsigned rowo = (unsigned)n * (unsigned)sizeof(TO);
 
-    T eraw[IE], rraw[IR], craw[IC], icur[IE];
-    double graw[II];
+    // plain mapping: column pc, rows pj + RP i
+    const int pc = threadIdx.x % L, pj = threadIdx.x / L;
+    const bool pcok = pc >= clo && pc <= chi;
+    const unsigned poff = (unsigned)(y0 - 2 + pj) * rowb + (unsigned)(x0 - 2 + pc) * (unsigned)sizeof(T);
+    // colour mapping: lane cl of rows cr + RC i; on plane p a row's points of
+    // one colour have column parity cpar0 ^ (p & 1) (red rows start at row 1,
+    // black rows at row 2: both give the same parity)
+    const int cl = threadIdx.x % M::H, cr = threadIdx.x / M::H;
+    const int cpar0 = (x0 + y0 + cr + 1) & 1;
+
+    T eraw[M::IP], icur[M::IP];
+    T rred[M::IRED], rblk[M::IBLK];          // rhs of this step's red and black points
+    T rred_n[M::IRED], rblk_n[M::IBLK];      // ... and of the next step's
+    double gb[M::IBLK][2], gb_n[M::IBLK][2];  // g at the black point and its red neighbour (MODE 1)
+    T craw[M::ICP];
 
     auto load_e = [&](int p) {
+        const bool pok = !ZERO && (unsigned)p < (unsigned)n;
+        const T* b = pok ? e_in + (size_t)p * nn : e_in;
 #pragma unroll
-        for (int it = 0; it < IE; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            int lx, ly, lz;
-            EP::split(k, lx, ly, lz);
-            const int x = x0 - 2 + lx, y = y0 - 2 + ly;
+        for (int i = 0; i < M::IP; ++i) {
+            const int row = pj + i * M::RP;
             T v = T(0);
-            if (!ZERO && k < EP::N && (unsigned)p < (unsigned)n && inside<2>(x, y, 0, n)) v = e_in[p * nn + (size_t)y * n + x];
-            eraw[it] = v;
+            if (pok && pcok && row >= rlo && row <= rhi) v = at_byte(b, poff + (unsigned)(i * M::RP) * rowb);
+            eraw[i] = v;
         }
     };
-    auto load_r = [&](int p) {
+    // rhs at the red points of plane q (tile plus an xy halo of 1)
+    auto load_rred = [&](int q) {
+        const bool qok = q >= z0 - 1 && q >= 0 && q < n;
+        const T* b = qok ? r + (size_t)q * nn : r;
+        const int c = 2 * cl + (cpar0 ^ (q & 1));
+        const bool cok = qok && c >= rclo && c <= rchi;
+        const unsigned off = (unsigned)(y0 - 1 + cr) * rowb + (unsigned)(x0 - 2 + c) * (unsigned)sizeof(T);
 #pragma unroll
-        for (int it = 0; it < IR; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            int lx, ly, lz;
-            RP::split(k, lx, ly, lz);
-            const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+        for (int i = 0; i < M::IRED; ++i) {
+            const int row = 1 + cr + i * M::RC;
             T v = T(0);
-            if (k < RP::N && (unsigned)p < (unsigned)n && inside<2>(x, y, 0, n)) v = r[p * nn + (size_t)y * n + x];
-            rraw[it] = v;
+            if (cok && row >= rrlo && row <= rrhi) v = at_byte(b, off + (unsigned)(i * M::RC) * rowb);
+            rred_n[i] = v;
         }
     };
+    // rhs at the black points of plane k (the tile), and g there and at the
+    // red point beside each (MODE 1)
+    auto load_rblk = [&](int k) {
+        const bool kok = k >= z0 && k < z1;
+        const T* b = kok ? r + (size_t)k * nn : r;
+        const int par = cpar0 ^ (k & 1);
+        const int cb = 2 * cl + par, cw = 2 * cl + (par ^ 1);
+        const bool bok = kok && cb >= bclo && cb <= bchi, wok = kok && cw >= bclo && cw <= bchi;
+        const unsigned off = (unsigned)(y0 + cr) * rowb + (unsigned)(x0 - 2 + cb) * (unsigned)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < M::IBLK; ++i) {
+            const int row = 2 + cr + i * M::RC;
+            const bool rok = row >= brlo && row <= brhi;
+            T v = T(0);
+            if (bok && rok) v = at_byte(b, off + (unsigned)(i * M::RC) * rowb);
+            rblk_n[i] = v;
+            if (MODE == 1) {
+                const double* gp = kok ? g + (size_t)k * nn : g;
+                const unsigned rowg = (unsigned)n * 8u;
+                const unsigned og = (unsigned)(y0 + cr + i * M::RC) * rowg;
+                gb_n[i][0] = (bok && rok) ? at_byte(gp, og + (unsigned)(x0 - 2 + cb) * 8u) : 0.0;
+                gb_n[i][1] = (wok && rok) ? at_byte(gp, og + (unsigned)(x0 - 2 + cw) * 8u) : 0.0;
+            }
+        }
+    };
+    // coarse plane Z, columns x0/2-2 .., rows y0/2-2 .. (zero outside 0 .. nc-1)
     auto load_c = [&](int Z) {
+        const int X = x0 / 2 - 2 + pc;
+        const bool ok = (unsigned)Z < (unsigned)nc && pc < M::X / 2 + 4 && X >= 0 && X < nc;
+        const T* b = ok ? ec + (size_t)Z * nc * nc : ec;
+        const unsigned rowc = (unsigned)nc * (unsigned)sizeof(T);
+        const unsigned off = (unsigned)(y0 / 2 - 2 + pj) * rowc + (unsigned)X * (unsigned)sizeof(T);
 #pragma unroll
-        for (int it = 0; it < IC; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            int lx, ly, lz;
-            CP::split(k, lx, ly, lz);
-            const int X = cxo + lx, Y = cyo + ly;
+        for (int i = 0; i < M::ICP; ++i) {
+            const int Y = y0 / 2 - 2 + pj + i * M::RP;
             T v = T(0);
-            if (k < CP::N && (unsigned)Z < (unsigned)nc && inside<2>(X, Y, 0, nc))
-                v = ec[(size_t)Z * nc * nc + (size_t)Y * nc + X];
-            craw[it] = v;
+            if (ok && Y >= 0 && Y < nc) v = at_byte(b, off + (unsigned)(i * M::RP) * rowc);
+            craw[i] = v;
         }
     };
     auto store_c = [&]() {
 #pragma unroll
-        for (int it = 0; it < IC; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            if (k < CP::N) sC[k] = craw[it];
-        }
+        for (int i = 0; i < M::ICP; ++i)
+            if (pj + i * M::RP < M::CROWS) sC[threadIdx.x + i * kThreads] = craw[i];
     };
-    // bilinear interpolation of the coarse plane in sC at this thread's
-    // iterate-plane points (odd index: one coarse point, even: mean of two)
+    // bilinear interpolation of the coarse plane in sC at this thread's plain
+    // points (odd index: one coarse point, even: the mean of two; x0, y0 and
+    // RP are even, so the parities are pc's and pj's)
+    const T wx0 = (pc & 1) ? T(1) : T(0.5), wx1 = (pc & 1) ? T(0) : T(0.5);
+    const T wy0 = (pj & 1) ? T(1) : T(0.5), wy1 = (pj & 1) ? T(0) : T(0.5);
+    const int cb0 = ((pj + 1) >> 1) * L + ((pc + 1) >> 1);
     auto interp_c = [&](T* out) {
 #pragma unroll
-        for (int it = 0; it < IE; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            int lx, ly, lz;
-            EP::split(k, lx, ly, lz);
-            const int x = x0 - 2 + lx, y = y0 - 2 + ly;
+        for (int i = 0; i < M::IP; ++i) {
+            const int row = pj + i * M::RP;
             T acc = T(0);
-            if (k < EP::N && inside<2>(x, y, 0, n)) {
-                int ix0, iy0;
-                T wx1 = T(0), wy1 = T(0), wx0 = T(1), wy0 = T(1);
-                if (x & 1) { ix0 = (x - 1) / 2 - cxo; }
-                else { ix0 = x / 2 - 1 - cxo; wx0 = wx1 = T(0.5); }
-                if (y & 1) { iy0 = (y - 1) / 2 - cyo; }
-                else { iy0 = y / 2 - 1 - cyo; wy0 = wy1 = T(0.5); }
-                const int b00 = iy0 * CP::X + ix0;
-                acc = wy0 * (wx0 * sC[b00] + wx1 * sC[b00 + 1]);
-                acc += wy1 * (wx0 * sC[b00 + CP::X] + wx1 * sC[b00 + CP::X + 1]);
+            if (pcok && row >= rlo && row <= rhi) {
+                const int b = cb0 + i * (M::RP / 2) * L;
+                acc = wy0 * (wx0 * sC[b] + wx1 * sC[b + 1]);
+                acc += wy1 * (wx0 * sC[b + L] + wx1 * sC[b + L + 1]);
             }
-            out[it] = acc;
+            out[i] = acc;
         }
     };
 
@@ -152,104 +213,123 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
         __syncthreads();
     }
     load_e(z0 - 2);
-    load_r(z0 - 3);
+#pragma unroll
+    for (int i = 0; i < M::IRED; ++i) rred_n[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < M::IBLK; ++i) {
+        rblk_n[i] = T(0);
+        gb_n[i][0] = gb_n[i][1] = 0.0;
+    }
 
-    // Step k stores plane k+2 of the iterate and k+1 of the rhs, then
-    // updates red on k+1 and black on k.  Ring hazards: the store of plane
-    // k+2 may overlap black(k-1) of slower threads, which reads k-2..k, so the
-    // iterate ring needs 5 planes; the rhs store of k+1 may overlap their
-    // read of rhs plane k-1, so that ring needs 3.
+    // Step k stores plane k+2 of the iterate, then updates red on k+1 and
+    // black on k.  Ring hazard: the store of plane k+2 may overlap black(k-1)
+    // of slower threads, which reads planes k-2 .. k, so the ring has 5 slots.
+    // sk: the slot of plane k.
+    int sk = ((z0 - 4) % NE + NE) % NE;
+    auto slot = [&](int m) {  // slot of plane k + m, -1 <= m <= 2
+        int v = sk + m;
+        if (v >= NE) v -= NE;
+        if (v < 0) v += NE;
+        return v;
+    };
     for (int k = z0 - 4; k < z1; ++k) {
+#pragma unroll
+        for (int i = 0; i < M::IRED; ++i) rred[i] = rred_n[i];
+#pragma unroll
+        for (int i = 0; i < M::IBLK; ++i) {
+            rblk[i] = rblk_n[i];
+            gb[i][0] = gb_n[i][0];
+            gb[i][1] = gb_n[i][1];
+        }
         const int pe = k + 2;  // iterate plane entering the ring
-        T* se = sE[ring(pe, NE)];
         {
-            T inew[IE];
+            T* se = sE + slot(2) * M::PN;
+            T inew[M::IP];
             if (PRO && !(pe & 1)) interp_c(inew);  // coarse plane pe/2 (stored one step earlier)
 #pragma unroll
-            for (int it = 0; it < IE; ++it) {
-                const int k2 = threadIdx.x + it * kThreads;
-                if (k2 >= EP::N) break;
-                T v = eraw[it];
+            for (int i = 0; i < M::IP; ++i) {
+                T v = eraw[i];
                 if (PRO) {
                     // odd plane: the coarse plane below; even: mean of the two around it
-                    const T corr = (pe & 1) ? icur[it] : T(0.5) * icur[it] + T(0.5) * inew[it];
+                    const T corr = (pe & 1) ? icur[i] : T(0.5) * icur[i] + T(0.5) * inew[i];
                     if ((unsigned)pe < (unsigned)n) v += corr;
                 }
-                se[k2] = v;
+                se[threadIdx.x + i * kThreads] = v;
             }
             if (PRO && !(pe & 1)) {
 #pragma unroll
-                for (int it = 0; it < IE; ++it) icur[it] = inew[it];
-            }
-        }
-        {
-            T* sr = sR[ring(k + 1, NR)];
-#pragma unroll
-            for (int it = 0; it < IR; ++it) {
-                const int k2 = threadIdx.x + it * kThreads;
-                if (k2 < RP::N) sr[k2] = rraw[it];
+                for (int i = 0; i < M::IP; ++i) icur[i] = inew[i];
             }
         }
         if (PRO && !((k + 3) & 1)) store_c();  // coarse plane (k+3)/2 for the next step
-        // loads for the next step (and g of this step's output plane)
+        // loads for the next step
         load_e(k + 3);
-        load_r(k + 2);
+        load_rred(k + 2);
+        load_rblk(k + 1);
         if (PRO && !((k + 4) & 1)) load_c((k + 4) / 2);
-        if (MODE == 1 && k >= z0) {
-#pragma unroll
-            for (int it = 0; it < II; ++it) {
-                const int k2 = threadIdx.x + it * kThreads;
-                int lx, ly, lz;
-                IP::split(k2, lx, ly, lz);
-                const int x = x0 + lx, y = y0 + ly;
-                graw[it] = (k2 < IP::N && inside<2>(x, y, 0, n)) ? g[k * nn + (size_t)y * n + x] : 0.0;
-            }
-        }
         __syncthreads();
-        // red on plane q = k+1, tile plus an xy halo of 1 (ghost planes
-        // q < 0 and q >= n stay zero)
+        // red on plane q = k+1, tile plus an xy halo of 1 (ghost planes q < 0
+        // and q >= n stay zero)
         const int q = k + 1;
         if (q >= z0 - 1 && q >= 0 && q < n) {
-            T* em = sE[ring(q - 1, NE)];
-            T* e0 = sE[ring(q, NE)];
-            T* ep = sE[ring(q + 1, NE)];
-            const T* sr = sR[ring(q, NR)];
-            lds_pass<T, RP>(e0, [&](int kk, int lx, int ly, int, T& v) {
-                const int x = x0 - 1 + lx, y = y0 - 1 + ly;
-                if (!inside<2>(x, y, 0, n) || ((x + y + q) & 1)) return -1;
-                const int i = (ly + 1) * EP::X + (lx + 1);
-                const T nb = e0[i - 1] + e0[i + 1] + e0[i - EP::X] + e0[i + EP::X] + em[i] + ep[i];
-                v = (sr[kk] + a * nb) * invdiag;
-                return i;
-            });
-        }
-        __syncthreads();
-        // black on plane k, tile only; plane k is then final
-        if (k >= z0) {
-            T* em = sE[ring(k - 1, NE)];
-            T* e0 = sE[ring(k, NE)];
-            T* ep = sE[ring(k + 1, NE)];
-            const T* sr = sR[ring(k, NR)];
+            const T* em = sE + slot(0) * M::PN;
+            T* e0 = sE + slot(1) * M::PN;
+            const T* ep = sE + slot(2) * M::PN;
+            const int c = 2 * cl + (cpar0 ^ (q & 1));
+            if (c >= rclo && c <= rchi) {
+                T v[M::IRED];
+                bool w[M::IRED];
 #pragma unroll
-            for (int it = 0; it < II; ++it) {
-                const int k2 = threadIdx.x + it * kThreads;
-                int lx, ly, lz;
-                IP::split(k2, lx, ly, lz);
-                const int x = x0 + lx, y = y0 + ly;
-                if (k2 >= IP::N || !inside<2>(x, y, 0, n)) continue;
-                const int i = (ly + 2) * EP::X + (lx + 2);
-                T v = e0[i];
-                if ((x + y + k) & 1) {
-                    const int kr = (ly + 1) * RP::X + (lx + 1);
-                    const T nb = e0[i - 1] + e0[i + 1] + e0[i - EP::X] + e0[i + EP::X] + em[i] + ep[i];
-                    v = (sr[kr] + a * nb) * invdiag;
+                for (int i = 0; i < M::IRED; ++i) {
+                    const int row = 1 + cr + i * M::RC;
+                    w[i] = row >= rrlo && row <= rrhi;
+                    if (w[i]) {
+                        const int kk = row * L + c;
+                        const T nb = e0[kk - 1] + e0[kk + 1] + e0[kk - L] + e0[kk + L] + em[kk] + ep[kk];
+                        v[i] = (rred[i] + a * nb) * invdiag;
+                    }
                 }
-                const size_t gi = k * nn + (size_t)y * n + x;
-                if (MODE == 0) e_out[gi] = v;
-                else if (MODE == 1) u_out[gi] = graw[it] + (double)v;
-                else u_out[gi] = (double)v;
+#pragma unroll
+                for (int i = 0; i < M::IRED; ++i)
+                    if (w[i]) e0[(1 + cr + i * M::RC) * L + c] = v[i];
             }
         }
+        __syncthreads();
+        // black on plane k (the tile), written out with the red point beside
+        // each: plane k is then final
+        if (k >= z0) {
+            const T* em = sE + slot(-1) * M::PN;
+            const T* e0 = sE + slot(0) * M::PN;
+            const T* ep = sE + slot(1) * M::PN;
+            const int par = cpar0 ^ (k & 1);
+            const int cb = 2 * cl + par, cw = 2 * cl + (par ^ 1);
+            const bool bok = cb >= bclo && cb <= bchi, wok = cw >= bclo && cw <= bchi;
+            TO* ob = MODE == 0 ? (TO*)e_out + (size_t)k * nn : (TO*)u_out + (size_t)k * nn;
+            const unsigned ooff = (unsigned)(y0 + cr) * rowo;
+#pragma unroll
+            for (int i = 0; i < M::IBLK; ++i) {
+                const int row = 2 + cr + i * M::RC;
+                if (row < brlo || row > brhi) continue;
+                const unsigned orow = ooff + (unsigned)(i * M::RC) * rowo;
+                if (bok) {
+                    const int kk = row * L + cb;
+                    const T nb = e0[kk - 1] + e0[kk + 1] + e0[kk - L] + e0[kk + L] + em[kk] + ep[kk];
+                    const T v = (rblk[i] + a * nb) * invdiag;
+                    TO& o = at_byte(ob, orow + (unsigned)(x0 - 2 + cb) * (unsigned)sizeof(TO));
+                    if (MODE == 0) o = (TO)v;
+                    else if (MODE == 1) o = (TO)(gb[i][0] + (double)v);
+                    else o = (TO)v;
+                }
+                if (wok) {
+                    const T v = e0[row * L + cw];
+                    TO& o = at_byte(ob, orow + (unsigned)(x0 - 2 + cw) * (unsigned)sizeof(TO));
+                    if (MODE == 0) o = (TO)v;
+                    else if (MODE == 1) o = (TO)(gb[i][1] + (double)v);
+                    else o = (TO)v;
+                }
+            }
+        }
+        sk = sk == NE - 1 ? 0 : sk + 1;
     }
 }
 

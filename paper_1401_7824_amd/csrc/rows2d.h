@@ -66,15 +66,6 @@ __device__ __forceinline__ Region region(int h, int xr, int yr, int x0, int y0, 
     return g;
 }
 
-template <typename T>
-__device__ __forceinline__ const T& at_byte(const T* p, unsigned off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
-}
-template <typename T>
-__device__ __forceinline__ T& at_byte(T* p, unsigned off) {
-    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off);
-}
-
 // Plain-pass loads of g over region gr into v (zero elsewhere).
 template <class RT, typename T>
 __device__ __forceinline__ void rows_load(T (&v)[RT::IP], const T* __restrict__ g, int n, int x0, int y0,

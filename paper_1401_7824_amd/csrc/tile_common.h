@@ -59,6 +59,17 @@ using HaloBoxT = Box<D, TL::X + 2 * H, TL::Y + 2 * H, TL::Z + 2 * H>;
 template <int D, int H>
 using HaloBox = HaloBoxT<D, H, Tile<D>>;
 
+// The element at byte offset off from p (a 32-bit per-thread offset from a
+// uniform base: the saddr + voffset form of global loads and stores).
+template <typename T>
+__device__ __forceinline__ const T& at_byte(const T* p, unsigned off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+}
+template <typename T>
+__device__ __forceinline__ T& at_byte(T* p, unsigned off) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off);
+}
+
 template <int D>
 __device__ __forceinline__ bool inside(int x, int y, int z, int n) {
     bool ok = (unsigned)x < (unsigned)n;
