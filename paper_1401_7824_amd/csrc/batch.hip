@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kThreads) kb_rbgs(BArgs a) {
         rows_rbgs_body<T, ZERO, BRow>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], s.ln[l], x0, y0,
                                       T(s.la[p][l]), T(s.linv[p][l]));
     } else if (D == 3 && mz > 0) {
-        tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
+        tile_xyz<D>(t, s.ln[l], MTile<T>::X, MTile<T>::Y, mz, x0, y0, z0);
         march_rbgs_body<T, false, 0, ZERO>((const T*)s.lr[l], (const T*)s.le[l], nullptr, (T*)s.le2[l], s.ln[l], x0, y0,
                                            z0, mz, T(s.la[p][l]), T(s.linv[p][l]), nullptr, nullptr);
     } else {
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kThreads) kb_prolong_rbgs(BArgs a) {
         rows_prolong_rbgs_body<T, MODE, BRow>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1],
                                               (T*)s.le[l], s.ln[l], x0, y0, T(s.la[p][l]), T(s.linv[p][l]), g, u_out);
     } else if (D == 3 && mz > 0) {
-        tile_xyz<D>(t, s.ln[l], MTile::X, MTile::Y, mz, x0, y0, z0);
+        tile_xyz<D>(t, s.ln[l], MTile<T>::X, MTile<T>::Y, mz, x0, y0, z0);
         march_rbgs_body<T, true, MODE, false>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1],
                                               (T*)s.le[l], s.ln[l], x0, y0, z0, mz, T(s.la[p][l]), T(s.linv[p][l]), g,
                                               u_out);
@@ -366,9 +366,12 @@ int tiles_fine(int d, int n) {
 
 // Workgroups of the smoothing kernels on an n^d level (3D: marched columns,
 // 2D: row-mapped tiles).
-int tiles_smooth(int d, int n) {
+int tiles_smooth(int d, int n, bool fp64) {
     if (d == 2) return ntiles_of<2>(n, BRow::TX, BRow::TY, 1);
-    return (d == 3 && march_depth(n) > 0) ? ntiles_of<3>(n, MTile::X, MTile::Y, march_depth(n)) : tiles_fine(d, n);
+    if (d == 3 && march_depth(n) > 0)
+        return fp64 ? ntiles_of<3>(n, MTile<double>::X, MTile<double>::Y, march_depth(n))
+                    : ntiles_of<3>(n, MTile<float>::X, MTile<float>::Y, march_depth(n));
+    return tiles_fine(d, n);
 }
 
 int tiles_coarse(int d, int nc) {
@@ -538,7 +541,7 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
             mtail[p].add(i, 1);
             if (sd.nlev == 0) mupd[p].add(i, ceil_div(sd.N, kChunkPts));
             for (int l = 0; l < sd.nlev; ++l) {
-                mlev[p][l].add(i, tiles_smooth(D, sd.ln[l]));
+                mlev[p][l].add(i, tiles_smooth(D, sd.ln[l], b->prec == ISDC_PREC_FP64));
                 mres[p][l].add(i, tiles_coarse(D, (sd.ln[l] - 1) / 2));
             }
         }

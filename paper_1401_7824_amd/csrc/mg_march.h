@@ -2,7 +2,7 @@
 //
 // A 3D tile with a halo of 2 in every direction stages 3-5 times its own
 // points; marching removes the z part of that overhead.  A workgroup owns an
-// xy tile of MTile::X x MTile::Y points and a column of mz planes
+// xy tile of MTile<T>::X x MTile<T>::Y points and a column of mz planes
 // [z0, z0 + mz).  Planes of the iterate enter a ring of LDS planes (xy halo 2)
 // as the march reaches them.  At step k the red points of plane k+1 are
 // updated on the tile plus an xy halo of 1, then the black points of plane k
@@ -33,15 +33,17 @@ namespace {
 
 // Plane layout of the march (row-mapped, as the 2D row tiles): LPR = 64
 // columns x0-2 .. x0+61 by ROWS = Y + 4 rows y0-2 .. y0+Y+1, stride LPR, for
-// an xy tile of X = 60 by Y = 16 points.  A plain pass (loads, LDS stores,
+// an xy tile of X = 60 by Y points (16 in float32, 8 in float64, so that a
+// workgroup's ring of planes stays near 30 KB of LDS).  A plain pass (loads, LDS stores,
 // the prolongation) gives thread t column t % LPR and rows t / LPR + RP i; a
 // colour pass gives it colour lane t % H of rows t / H + RC i, and a row's
 // H points of one colour sit one every other column, so every lane has a
 // point of the colour and its column parity is fixed per plane.  LDS
 // addresses are per-thread constants plus compile-time offsets, global ones a
 // per-thread 32-bit byte offset from a uniform plane base.
-struct MTile {
-    static constexpr int X = 60, Y = 16;
+template <int Y_>
+struct MTileT {
+    static constexpr int X = 60, Y = Y_;
     static constexpr int LPR = 64, ROWS = Y + 4;
     static constexpr int PN = LPR * ROWS;               // values per LDS plane
     static constexpr int RP = kThreads / LPR;           // rows per plain step
@@ -56,6 +58,8 @@ struct MTile {
     static_assert(RP % 2 == 0 && RC % 2 == 0 && X % 2 == 0, "even row steps keep a thread's row parity");
     static_assert(X / 2 + 4 <= LPR && ICP * RP >= CROWS, "the coarse plane fits the layout");
 };
+template <typename T>
+using MTile = MTileT<sizeof(T) == 8 ? 8 : 16>;
 
 // Planes per marched column on an n^3 level, or 0 where the one-pass 3D tile
 // kernels are used instead: a column costs a chain of Z + 4 dependent steps,
@@ -75,7 +79,7 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
                                                 const T* __restrict__ ec, T* __restrict__ e_out, int n, int x0, int y0,
                                                 int z0, int mz, T a, T invdiag, const double* __restrict__ g,
                                                 double* __restrict__ u_out) {
-    using M = MTile;
+    using M = MTile<T>;
     using TO = typename std::conditional<MODE == 0, T, double>::type;
     constexpr int L = M::LPR;
     constexpr int NE = 5;  // iterate ring (see the hazards below)

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kThreads)
 k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
              int n, int ntx, int nty, int mz, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
     int x0, y0, z0;
-    tile_origin(ntx, nty, MTile::X, MTile::Y, mz, x0, y0, z0);
+    tile_origin(ntx, nty, MTile<T>::X, MTile<T>::Y, mz, x0, y0, z0);
     march_rbgs_body<T, PRO, MODE, ZERO>(r, e_in, ec, e_out, n, x0, y0, z0, mz, a, invdiag, g, u_out);
 }
 
@@ -173,7 +173,7 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
         if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
         const int mz = march_depth(n, shape);
         int ntx, nty, nb;
-        tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
+        tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (zero)
             hipLaunchKernelGGL((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         else
@@ -260,7 +260,7 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
         if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
         const int mz = march_depth(n, shape);
         int ntx, nty, nb;
-        tile_counts<3>(n, MTile::X, MTile::Y, mz, ntx, nty, nb);
+        tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (mode == 0)
             hipLaunchKernelGGL((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else if (mode == 1)

@@ -66,6 +66,33 @@ def test_batch_slots_equal_single_instance_runs(d, prec):
         assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_marched_3d_slots_equal_single_instance_runs(prec):
+    # 127^3 levels run the z-marched kernels (float32 and float64 plane
+    # layouts differ in tile height); slots still equal the plan's bits
+    from paper_1401_7824_amd import Batch
+    announce("batch marched 3d", prec)
+    d, n = 3, 127
+    inst = []
+    for i, (nu, fe, dt) in enumerate([(0.3, O.FE_CUBIC, 2e-3), (1.0, O.FE_ZERO, 1e-3)]):
+        u0 = 2.0 * W.sine_field(n, d, W.draw_modes(d, 6, seed=900 + i, max_wave=4))
+        inst.append(dict(nu=nu, fe=fe, dt=dt, u0=u0,
+                         par=dict(node_kind=LOB, M=3, precision=prec, sdc_tol=1e-10 if prec == 0 else 1e-9)))
+    b = Batch(2, d, precision=prec, vcycles=2)
+    us = []
+    for i, x in enumerate(inst):
+        u = dev(x["u0"])
+        b.set(i, u, x["dt"], 1, x["nu"], x["fe"], **x["par"])
+        us.append(u)
+    b.run()
+    for i, x in enumerate(inst):
+        state, status, steps, st = b.info(i)
+        ref, rstats = _alone(d, n, x["nu"], x["fe"], x["u0"], x["dt"], 1, **x["par"])
+        assert status == "ok" and steps == 1, (i, status)
+        assert np.array_equal(host(us[i]), ref), f"slot {i} differs from the single-instance run"
+        assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
+
+
 def test_continuous_batching_join_and_leave():
     # slots join while others are mid-step and a finished slot is reused;
     # every result equals its run alone
