@@ -244,9 +244,10 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * 32x8x4 points per workgroup), shapes 1 and 2 are smaller (1D 512 / 256,
  * 2D 56x8 / 24x8, 3D 16x8x4 / 16x4x4).  Every shape computes the same values
  * (the V-cycle of Sec. 3 is unchanged); only the launch shape differs.
- * On 3D levels of 127^3 and up, which run z-marching kernels, the shape picks
- * the depth of a workgroup's column of planes instead: 16, 32 or 8 planes
- * (4, 8 or 2 on 127^3).
+ * On 3D levels of 127^3 and up, which run z-marching kernels (xy tiles of
+ * 60x16 points in float32, 60x8 in float64), the shape picks the depth of a
+ * workgroup's column of planes instead: 16, 32 or 8 planes (4, 8 or 2 on
+ * 127^3).
  * isdc_autotune times the red-black kernels of every level with each shape
  * (three rounds of `reps` launches on `stream`, the fastest round of each
  * shape compared) and keeps the fastest; levels where the shape changes
