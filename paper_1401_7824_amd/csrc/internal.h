@@ -144,6 +144,12 @@ struct RhsArgs {
 // r = rhs - (I - c L_h) g for the right-hand side of eq. (4) and the guess g.
 template <typename T>
 hipError_t launch_euler_rhs(int d, const RhsArgs& ra, T* r, hipStream_t s);
+// launch_euler_rhs (guess ISDC_GUESS_PREV_SWEEP) followed by the zero-start
+// launch_rbgs_restrict_tile on a 2D level, in one launch: r, e_out and rc
+// receive the same values.
+template <typename T>
+hipError_t launch_rhs_rbgs_restrict_tile(int d, int n, const RhsArgs& ra, const Coef<T>& co, T* r, T* e_out, T* rc,
+                                         hipStream_t s, int shape = 0);
 
 // u_out = g + e with g = u_{m+1}^k (PREV_SWEEP), 0 (ZERO) or u_m^{k+1} (PREV_NODE).
 template <typename T>

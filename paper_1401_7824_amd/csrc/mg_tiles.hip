@@ -17,7 +17,9 @@
 //                       coarse planes;
 //   k_rows_*            the 2D forms of the red-black, fused red-black +
 //                       restriction and prolongation + red-black kernels on
-//                       row-mapped tiles (rows2d.h).
+//                       row-mapped tiles (rows2d.h), and the first launch of
+//                       a solve with the right-hand side of eq. (4) formed in
+//                       it (k_rows_rhs_rbgs_restrict).
 //
 // Workgroups are numbered so that each of the 8 XCDs (the hardware hands
 // workgroup b to XCD b mod 8) receives a contiguous band of tiles, keeping the
@@ -28,6 +30,7 @@
 #include "mg_device.h"
 #include "mg_march.h"
 #include "rows2d.h"
+#include "sdc_device.h"
 #include "tailc.h"
 
 namespace isdc {
@@ -114,6 +117,19 @@ k_rows_rbgs_restrict(const T* __restrict__ r, const T* __restrict__ e_in, T* __r
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
     rows_rbgs_restrict_body<T, ZERO, RT>(r, e_in, e_out, rc, n, x0, y0, a, diag, invdiag);
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(kThreads)
+k_rows_rhs_rbgs_restrict(RhsArgs ra, T* __restrict__ r, T* __restrict__ e_out, T* __restrict__ rc, int n, int ntx,
+                         int nty, T a, T diag, T invdiag) {
+    using RT = typename RowShape<S>::RT;
+    int x0, y0, z0;
+    tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
+    const int fe = ra.fe;
+    rows_rhs_rbgs_restrict_body<T, RT>(ra.um_new, ra.um_old, ra.up_old, ra.sf, ra.dtm,
+                                       [fe](double u) { return fexp(u, fe); }, r, e_out, rc, n, x0, y0, a, diag,
+                                       invdiag);
 }
 
 template <typename T, int MODE, int S>
@@ -254,6 +270,19 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
 }
 
 template <typename T>
+hipError_t launch_rhs_rbgs_restrict_tile(int d, int n, const RhsArgs& ra, const Coef<T>& co, T* r, T* e_out, T* rc,
+                                         hipStream_t s, int shape) {
+    if (d != 2 || ra.guess != ISDC_GUESS_PREV_SWEEP || ra.n != n) return hipErrorInvalidValue;
+    ISDC_DISPATCH_ROWS(shape, {
+        using RT = typename RowShape<S>::RT;
+        int ntx, nty, nb;
+        tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
+        hipLaunchKernelGGL((k_rows_rhs_rbgs_restrict<T, S>), dim3(nb), dim3(kThreads), 0, s, ra, r, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r, const T* e_in, const T* ec,
                                     T* e_out, const double* g, double* u_out, int mode, hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
@@ -330,6 +359,8 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
                                                      hipStream_t, int);                                            \
     template hipError_t launch_prolong_rbgs_tile<T>(int, int, const Coef<T>&, const T*, const T*, const T*, T*,  \
                                                     const double*, double*, int, hipStream_t, int);             \
+    template hipError_t launch_rhs_rbgs_restrict_tile<T>(int, int, const RhsArgs&, const Coef<T>&, T*, T*, T*,   \
+                                                         hipStream_t, int);                                     \
     template hipError_t launch_tail<T>(const MGConfig&, int, double, double, bool, const T*, T*, hipStream_t);
 
 ISDC_INST_T(float)

@@ -264,6 +264,43 @@ __device__ __forceinline__ void rows_rbgs_restrict_body(const T* __restrict__ r,
     rr_run<T, RT>(st, se, sr, e_out, rc, n, x0, y0, a, diag, invdiag);
 }
 
+// The first launch of a substep's solve from e = 0 with the right-hand side
+// of eq. (4) formed in it (guess g = u_{m+1}^k, where the L_h terms cancel):
+// r = u_m^{k+1} + dt_m [f^E(u_m^{k+1}) - f^E(u_m^k)] + S F - u_{m+1}^k on the
+// region the step reads, the tile's part written to r_out for the later
+// kernels, then rr_run as rows_rbgs_restrict_body (ZERO).  The values of a
+// separate rhs pass followed by rows_rbgs_restrict_body<T, true, RT>.
+template <typename T, class RT, typename FE>
+__device__ __forceinline__ void rows_rhs_rbgs_restrict_body(const double* __restrict__ um_new,
+                                                            const double* __restrict__ um_old,
+                                                            const double* __restrict__ up_old,
+                                                            const double* __restrict__ sf, double dtm, FE fexp,
+                                                            T* __restrict__ r_out, T* __restrict__ e_out,
+                                                            T* __restrict__ rc, int n, int x0, int y0, T a, T diag,
+                                                            T invdiag) {
+    __shared__ T se[RT::N];
+    __shared__ T sr[RT::N];
+    RRStage<T, RT> st;
+#pragma unroll
+    for (int i = 0; i < RT::IP; ++i) st.ve[i] = T(0);
+    {
+        const Region R2 = region(2, 1, 1, x0, y0, n, RT::TX, RT::TY);
+        double un[RT::IP], uo[RT::IP], upo[RT::IP], sfv[RT::IP];
+        rows_load<RT>(un, um_new, n, x0, y0, R2);
+        rows_load<RT>(uo, um_old, n, x0, y0, R2);
+        rows_load<RT>(upo, up_old, n, x0, y0, R2);
+        rows_load<RT>(sfv, sf, n, x0, y0, R2);
+#pragma unroll
+        for (int i = 0; i < RT::IP; ++i) {
+            const double base = un[i] + dtm * (fexp(un[i]) - fexp(uo[i])) + sfv[i];
+            st.vr[i] = T(base - upo[i]);  // zero outside the region: every input loads as zero there
+        }
+    }
+    rows_store<RT>(r_out, n, x0, y0, region(0, 0, 0, x0, y0, n, RT::TX, RT::TY),
+                   [&](int, int i) { return st.vr[i]; });
+    rr_run<T, RT>(st, se, sr, e_out, rc, n, x0, y0, a, diag, invdiag);
+}
+
 // e_in + P ec (linear interpolation) on the tile plus a halo of 2, then one
 // red-black step.  MODE 0: result to e_out; 1: u_out = g + result (float64);
 // 2: u_out = result.

@@ -269,7 +269,7 @@ void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int n, const Coe
 // level's size.  Returns true if the fused update was done.
 template <typename T>
 bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp, hipStream_t s,
-                const Fuse& fuse = Fuse()) {
+                const Fuse& fuse = Fuse(), const RhsArgs* fra = nullptr) {
     const Level& L = p->lev[l];
     if (l >= p->tail) {  // (beyond the tail only the coarse MLSDC level, solved the same way)
         HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
@@ -283,7 +283,10 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
     if (rbgs && mg.nu_pre >= 1 && p->d <= 2) {
         // pre-smoothing steps; the last one fused with residual + restriction
         smooth_steps<T>(p, mg, mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s, L.shape);
-        HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s, L.shape));
+        if (fra && zero && mg.nu_pre == 1 && p->d == 2)  // rhs formed in the first launch (writes rhs)
+            HIPCHK(launch_rhs_rbgs_restrict_tile<T>(p->d, L.n, *fra, co, (T*)rhs, other, (T*)C.r, s, L.shape));
+        else
+            HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s, L.shape));
         std::swap(cur, other);
         zero = false;
     } else {
@@ -537,7 +540,7 @@ double cresidual(isdc_plan* p, hipStream_t s) {
 // inner residual <= inner_tol), then u_out = g + e.  The update is fused into
 // the last V-cycle's final kernel when possible.
 template <typename T>
-int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
+int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s, const RhsArgs* fra = nullptr) {
     const Level& L0 = p->lev[0];
     T* r0 = (T*)L0.r;
     T* e0 = (T*)L0.e;
@@ -549,7 +552,9 @@ int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
     int k = 0;
     bool fused = false;
     if (!check) {
-        for (; k < limit; ++k) fused = vcycle_rec<T>(p, p->mg, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse());
+        for (; k < limit; ++k)
+            fused = vcycle_rec<T>(p, p->mg, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse(),
+                                  k == 0 ? fra : nullptr);
     } else {
         HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
         for (; k < limit; ++k) {
@@ -564,6 +569,16 @@ int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s) {
         HIPCHK(launch_node_update<T>(p->N, guess, upd.g, upd.g, e0, upd.u_out, s));
     }
     return k;
+}
+
+// True if a substep's right-hand side can be formed in the first launch of its
+// solve (launch_rhs_rbgs_restrict_tile): 2D red-black V(1,1)-type cycles with
+// one pre-smoothing step, a fixed number of cycles from e = 0 and the
+// previous-sweep guess, for which the rhs is pointwise.
+bool rhs_fusable(const isdc_plan* p) {
+    return p->d == 2 && !p->compact && !p->periodic && p->par.guess == ISDC_GUESS_PREV_SWEEP &&
+           p->mg.smoother == ISDC_SMOOTH_RBGS && p->mg.nu_pre == 1 && p->par.vcycles >= 1 && !p->par.early_exit &&
+           p->tail >= 1 && (p->prob.fe_kind == ISDC_FE_ZERO || p->prob.fe_kind == ISDC_FE_CUBIC);
 }
 
 // The node loop of one sweep (eq. (4) / eq. (5)); afterwards cur[] holds the
@@ -597,7 +612,8 @@ void sweep_nodes(isdc_plan* p, hipStream_t s) {
         }
         RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
                    p->prob.fe_kind, p->par.guess};
-        HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
+        const bool fuse_rhs = rhs_fusable(p);
+        if (!fuse_rhs) HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
         Fuse upd;
         upd.u_out = (double*)nw[m + 1];
         if (p->par.guess == ISDC_GUESS_ZERO) {
@@ -606,7 +622,7 @@ void sweep_nodes(isdc_plan* p, hipStream_t s) {
             upd.mode = 1;
             upd.g = p->par.guess == ISDC_GUESS_PREV_NODE ? nw[m] : p->cur[m + 1];
         }
-        p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, upd, s);
+        p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, upd, s, fuse_rhs ? &ra : nullptr);
     }
     for (int j = 0; j <= M; ++j) {
         p->cur[j] = nw[j];
