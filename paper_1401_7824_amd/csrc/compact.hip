@@ -515,7 +515,9 @@ __global__ void __launch_bounds__(kB) k_crhs(CRhsArgs a, T* __restrict__ out) {
         }
         const size_t j = (size_t)yy * n + xx;
         const double un = a.um_new[j];
-        const double dfe = a.fe_new ? a.fe_new[j] - a.fe_old[j] : fe_of(un, a.fe) - fe_of(a.um_old[j], a.fe);
+        // u_m^k only enters through f^E: not read for f^E = 0
+        const double dfe = a.fe_new ? a.fe_new[j] - a.fe_old[j]
+                                    : fe_of(un, a.fe) - fe_of(a.fe == ISDC_FE_ZERO ? 0.0 : a.um_old[j], a.fe);
         return un - a.up_old[j] + a.dtm * dfe;
     };
     const double bc = base(x, y);

@@ -127,7 +127,7 @@ k_rows_rhs_rbgs_restrict(RhsArgs ra, T* __restrict__ r, T* __restrict__ e_out, T
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
     const int fe = ra.fe;
-    rows_rhs_rbgs_restrict_body<T, RT>(ra.um_new, ra.um_old, ra.up_old, ra.sf, ra.dtm,
+    rows_rhs_rbgs_restrict_body<T, RT>(ra.um_new, ra.um_old, ra.up_old, ra.sf, ra.dtm, fe != ISDC_FE_ZERO,
                                        [fe](double u) { return fexp(u, fe); }, r, e_out, rc, n, x0, y0, a, diag,
                                        invdiag);
 }

@@ -274,7 +274,8 @@ template <typename T, class RT, typename FE>
 __device__ __forceinline__ void rows_rhs_rbgs_restrict_body(const double* __restrict__ um_new,
                                                             const double* __restrict__ um_old,
                                                             const double* __restrict__ up_old,
-                                                            const double* __restrict__ sf, double dtm, FE fexp,
+                                                            const double* __restrict__ sf, double dtm, bool read_old,
+                                                            FE fexp,
                                                             T* __restrict__ r_out, T* __restrict__ e_out,
                                                             T* __restrict__ rc, int n, int x0, int y0, T a, T diag,
                                                             T invdiag) {
@@ -287,7 +288,12 @@ __device__ __forceinline__ void rows_rhs_rbgs_restrict_body(const double* __rest
         const Region R2 = region(2, 1, 1, x0, y0, n, RT::TX, RT::TY);
         double un[RT::IP], uo[RT::IP], upo[RT::IP], sfv[RT::IP];
         rows_load<RT>(un, um_new, n, x0, y0, R2);
-        rows_load<RT>(uo, um_old, n, x0, y0, R2);
+        if (read_old) {  // u_m^k only enters through f^E
+            rows_load<RT>(uo, um_old, n, x0, y0, R2);
+        } else {
+#pragma unroll
+            for (int i = 0; i < RT::IP; ++i) uo[i] = 0.0;
+        }
         rows_load<RT>(upo, up_old, n, x0, y0, R2);
         rows_load<RT>(sfv, sf, n, x0, y0, R2);
 #pragma unroll

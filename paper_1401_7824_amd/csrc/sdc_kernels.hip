@@ -27,7 +27,8 @@ __global__ void __launch_bounds__(kBlock) k_euler_rhs(RhsArgs ra, T* __restrict_
     const int n = ra.n;
     const size_t N = (D == 1) ? (size_t)n : (D == 2 ? (size_t)n * n : (size_t)n * n * n);
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-        const double umn = ra.um_new[i], umo = ra.um_old[i], upo = ra.up_old[i];
+        // f^E = 0 (heat): u_m^k only enters through f^E, so it is not read
+        const double umn = ra.um_new[i], umo = ra.fe == ISDC_FE_ZERO ? 0.0 : ra.um_old[i], upo = ra.up_old[i];
         double base = umn + ra.dtm * (fexp(umn, ra.fe) - fexp(umo, ra.fe)) + ra.sf[i];
         double v;
         if (GUESS == ISDC_GUESS_PREV_SWEEP) {
