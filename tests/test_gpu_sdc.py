@@ -99,6 +99,27 @@ def test_sweep_iterates_match_oracle_every_march_depth():
         p.end(dev(np.zeros_like(u0)))
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_rhs_formed_in_first_launch_equals_separate_pass(prec):
+    # A fixed number of red-black V(1,1) cycles in 2D forms the substep's
+    # right-hand side inside the first launch of each solve; early-exit mode
+    # with inner_tol = 0 runs the same L cycles through the separate rhs
+    # pass, a zero fill and the unfused node update.  The results are equal
+    # bit for bit.
+    d, n, nu, dt = 2, 255, 0.1, 1e-3
+    announce("rhs fusion", n, prec)
+    u0 = 2.0 * W.sine_field(n, d, W.draw_modes(d, 8, seed=131))
+    out = []
+    for early in (0, 1):
+        p = _plan(d, n, nu, O.FE_CUBIC, node_kind=LOB, M=5, vcycles=2, early_exit=early, inner_tol=0.0,
+                  precision=prec, sdc_tol=1e-10 if prec == FP64 else 1e-9)
+        u = dev(u0)
+        st = p.step(u, dt)
+        out.append((host(u), st.sweeps, st.vcycles))
+    assert out[0][1:] == out[1][1:]
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+
+
 STEP_CASES = [
     ("heat1d-config", 1, 127, 1.0, O.FE_ZERO, 0.01, dict(node_kind=LOB, M=3, sdc_tol=1e-10)),
     ("rd2d-lob5", 2, 255, 0.1, O.FE_CUBIC, 1e-3, dict(node_kind=LOB, M=5, sdc_tol=1e-10)),
