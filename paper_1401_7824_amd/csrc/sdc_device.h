@@ -64,7 +64,7 @@ __device__ __forceinline__ void split(size_t i, int n, int& x, int& y, int& z) {
 
 // Tiled form of the quadrature + residual kernel: one tile of points per
 // workgroup, each node array staged in LDS (tile plus a halo of 1) in turn,
-// the next one's loads in flight while the current one is used.
+// the next two's loads in flight while the current one is used.
 // Per point: f_j = nu L_h u_j + f^E(u_j); sf_m = sum_j dt s_{m,j} f_j;
 // acc_m = u_0 + sum_j dt q_{m,j} f_j - u_m, and the tile's max |acc_m| goes
 // to partial[workgroup].
@@ -96,15 +96,19 @@ __device__ __forceinline__ double quad_residual_body(const QuadArgs& qa, int x0,
             acc[m][s] = u0;
         }
     }
-    // node j + 1's box is loaded into registers while node j is worked on
-    Staged<double, D, B1> next;
-    next.load(qa.u[1], n, x0 - 1, y0 - hy, z0 - hz, false);
+    // the boxes of nodes j + 1 and j + 2 are loaded into registers while
+    // node j is worked on (the node loop is unrolled, so each node's
+    // registers are fixed and no load in flight is copied)
+    constexpr int PD = M > 1 ? 2 : 1;
+    Staged<double, D, B1> box[M];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) box[j].load(qa.u[j + 1], n, x0 - 1, y0 - hy, z0 - hz, false);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if (j > 0) __syncthreads();
-        next.store(su);
+        box[j].store(su);
         __syncthreads();
-        if (j + 1 < M) next.load(qa.u[j + 2], n, x0 - 1, y0 - hy, z0 - hz, false);
+        if (j + PD < M) box[j + PD].load(qa.u[j + PD + 1], n, x0 - 1, y0 - hy, z0 - hz, false);
 #pragma unroll
         for (int s = 0; s < P; ++s) {
             const double c = su[li[s]];
