@@ -104,6 +104,10 @@ class SDCStats:
     residual: float = float("inf")
     residual_hist: list = field(default_factory=list)
     status: str = "ok"           # "ok" | "not_converged" | "diverged"
+    # smallest |res / inner_tol - 1| over every inner stopping test made (classical
+    # mode and early exit); it tells the tests when a V-cycle count was decided at
+    # the edge of the inner tolerance, where another rounding order may decide otherwise
+    inner_margin: float = float("inf")
 
 
 @dataclass
@@ -187,7 +191,7 @@ def sdc_begin(u0: np.ndarray, dt: float, h: float, cfg: SDCConfig) -> SDCState:
                     S=smatrix(cfg.node_kind, M), stats=SDCStats())
 
 
-def _inner_solve(rhs, guess, c, h, cfg):
+def _inner_solve(rhs, guess, c, h, cfg, stats=None):
     """Solve (I - c L_h) u = rhs (compact: (W - c A_h) u = rhs); returns (u, V-cycles)."""
     compact = cfg.stencil == STENCIL_COMPACT4
     op = _Compact(cfg.bc)
@@ -218,8 +222,12 @@ def _inner_solve(rhs, guess, c, h, cfg):
     check = classical or cfg.early_exit
     ncyc = 0
     while ncyc < limit:
-        if check and inner_res() <= cfg.inner_tol:
-            break
+        if check:
+            res = inner_res()
+            if stats is not None and cfg.inner_tol > 0:
+                stats.inner_margin = min(stats.inner_margin, abs(res / cfg.inner_tol - 1.0))
+            if res <= cfg.inner_tol:
+                break
         if cfg.precision == PREC_FP64:
             u = cycle(u, rhs)
         else:
@@ -277,7 +285,7 @@ def sdc_sweep(state: SDCState, fas: list | None = None) -> float:
                 g = um_new
             else:
                 raise ValueError("unknown guess mode")
-            u, ncyc = _inner_solve(rhs, g, c, h, cfg)
+            u, ncyc = _inner_solve(rhs, g, c, h, cfg, state.stats)
             state.stats.vcycles += ncyc
         Unew[m + 1] = u
         Fnew[m + 1] = _f(u, cfg, h)

@@ -4,7 +4,9 @@ Burgers advection and the periodic Burgers sweep (Sec. 4.1, eq. (5)).
 Targets that do not reuse the oracle's own formulas: stencils as loops with
 modular indices, Fourier-mode eigenvalues in closed form, O(h^4) consistency,
 dense solves, the linear fifth-order upwind flux that WENO5 reduces to when
-its smoothness weights are switched off, discrete conservation, a
+its smoothness weights are switched off, the smoothness indicators and
+candidate values recomputed from their integral and cell-average
+definitions, the ENO property at a jump, discrete conservation, a
 high-accuracy ODE integration (scipy DOP853) of the same semi-discrete
 system, and the modal collocation solution of the periodic heat problem.
 """
@@ -140,6 +142,79 @@ def test_weno5_reduces_to_linear_upwind_flux():
             ref[i, j] = ((2 * fp(-2) - 13 * fp(-1) + 47 * fp(0) + 27 * fp(1) - 3 * fp(2)) / 60.0
                          + (-3 * fm(-1) + 27 * fm(0) + 47 * fm(1) - 13 * fm(2) + 2 * fm(3)) / 60.0)
     assert np.max(np.abs(F - ref)) < 1e-12
+
+
+def _jiang_shu_candidates(vals):
+    """Independent evaluation of the Jiang-Shu WENO5 ingredients on one face,
+    from their definitions rather than from the closed-form coefficients:
+    for each candidate stencil k (cells i-2+k .. i+k, unit cells, cell i =
+    [-1/2, 1/2]) the quadratic p_k whose cell averages equal the given values,
+    its value at the face x = 1/2, and the smoothness indicator
+    beta_k = sum_{l=1,2} integral over cell i of (d^l p_k / dx^l)^2
+    (the h^(2l-1) factors are 1 on unit cells)."""
+    from numpy.polynomial import polynomial as Pn
+    q, beta = [], []
+    for k in range(3):
+        cells = [j - 2 + k for j in range(3)]
+        # cell average of x^p over [j - 1/2, j + 1/2] is ((j+1/2)^(p+1) - (j-1/2)^(p+1)) / (p+1)
+        A = np.array([[((j + 0.5) ** (p + 1) - (j - 0.5) ** (p + 1)) / (p + 1) for p in range(3)] for j in cells])
+        coef = np.linalg.solve(A, np.asarray(vals[k:k + 3], dtype=np.float64))
+        q.append(Pn.polyval(0.5, coef))
+        b = 0.0
+        for l in (1, 2):
+            d = Pn.polyder(coef, l)
+            sq = Pn.polyint(Pn.polymul(d, d))
+            b += Pn.polyval(0.5, sq) - Pn.polyval(-0.5, sq)
+        beta.append(b)
+    return np.array(q), np.array(beta)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weno5_indicators_and_weights_follow_jiang_shu(seed):
+    # smoothness indicators and candidate values from their integral and
+    # cell-average definitions; the nonlinear weights d_k / (eps + beta_k)^2
+    # with eps = 1e-6 (Jiang and Shu).  Values scaled so that beta ~ eps,
+    # where the result depends on eps and on every indicator term.
+    rng = np.random.default_rng(100 + seed)
+    scale = 10.0 ** rng.uniform(-4, 0)
+    vals = scale * rng.standard_normal(5)
+    q, beta = _jiang_shu_candidates(vals)
+    dlin = np.array([0.1, 0.6, 0.3])
+    alpha = dlin / (1e-6 + beta) ** 2
+    ref = float(np.dot(alpha, q) / alpha.sum())
+    got = P._weno5_left(*vals)
+    assert abs(got - ref) <= 1e-12 * max(1.0, np.max(np.abs(vals)))
+
+
+def test_weno5_eno_property_at_a_jump():
+    # data with a jump between the face's two cells: the stencils that cross
+    # it carry weights of order eps^2 / beta^2, so the reconstruction equals
+    # the smooth stencil's value to about 1e-11 (a larger eps would leak
+    # O(1e-4) of the crossing stencils into it)
+    for left, right in ((0.0, 1.0), (2.0, -1.0), (0.5, 0.5 + 3.0)):
+        vals = [left, left, left, right, right]
+        got = P._weno5_left(*vals)
+        assert abs(got - left) < 1e-10 * max(1.0, abs(right - left))
+    # a jump one cell further right: only the rightmost stencil crosses it
+    vals = [0.0, 0.0, 0.0, 0.0, 1.0]
+    q, beta = _jiang_shu_candidates(vals)
+    assert beta[0] == 0.0 and beta[1] == 0.0 and beta[2] > 1.0
+    assert abs(P._weno5_left(*vals)) < 1e-10
+
+
+def test_weno5_eps_enters_where_indicators_vanish():
+    # beta_1 = 0 (b = c = d) while beta_0 and beta_2 are of order eps: the
+    # result moves with eps at O(1) of the candidate spread
+    vals = np.array([1.0e-3, 0.0, 0.0, 0.0, -2.0e-3])
+    q, beta = _jiang_shu_candidates(vals)
+    assert beta[1] == 0.0 and 1e-7 < beta[0] < 1e-5 and 1e-7 < beta[2] < 1e-5
+    dlin = np.array([0.1, 0.6, 0.3])
+    for eps in (1e-6, 1e-5):
+        alpha = dlin / (eps + beta) ** 2
+        ref = float(np.dot(alpha, q) / alpha.sum())
+        assert abs(P._weno5_left(*vals, eps=eps) - ref) < 1e-15
+    assert abs(P._weno5_left(*vals) - P._weno5_left(*vals, eps=1e-5)) > 1e-6 * np.ptp(q)
+    assert P.WENO_EPS == 1e-6
 
 
 def test_weno5_conservative_and_consistent():

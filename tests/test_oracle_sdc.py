@@ -175,6 +175,31 @@ def test_mixed_precision_cubic_reaches_newton_collocation():
     assert _rel(u, ref) < 1e-8
 
 
+@pytest.mark.parametrize("fe_kind,nu,dt", [(O.FE_ZERO, 1.0, 1e-3), (O.FE_CUBIC, 0.3, 0.01)])
+def test_mixed_sweep_equals_fp64_sweep_within_float32_rounding(fe_kind, nu, dt):
+    # one float32-V-cycle sweep from the same iterate as an all-float64 sweep:
+    # the two differ only by the float32 rounding of the correction (the
+    # right-hand side r rounded, the cycles' float32 arithmetic), so per node
+    # |U_mixed - U_64| is a few float32 ulps of the correction |U_64 - U_old|
+    # and not zero (the float32 cycles are really float32)
+    import copy
+    u0, h = _smooth_u0(31, 2, 29)
+    u0 = 3.0 * u0
+    base = SDCConfig(nu=nu, fe_kind=fe_kind, node_kind=LOB, M=5, vcycles=2)
+    st = sdc_begin(u0, dt, h, base)
+    sdc_sweep(st)  # a state whose next corrections are neither zero nor the whole solution
+    s64, smx = copy.deepcopy(st), copy.deepcopy(st)
+    smx.cfg = SDCConfig(nu=nu, fe_kind=fe_kind, node_kind=LOB, M=5, vcycles=2, precision=PREC_MIXED)
+    sdc_sweep(s64)
+    sdc_sweep(smx)
+    for m in range(2, 6):
+        corr = np.max(np.abs(s64.U[m] - st.U[m]))
+        diff = np.max(np.abs(smx.U[m] - s64.U[m]))
+        assert corr > 1e-6
+        assert diff < 3e-6 * corr, (m, diff / corr)
+        assert diff > 1e-12 * corr, (m, diff / corr)
+
+
 # ---- residual definition ----
 
 def test_residual_zero_at_collocation_and_sees_perturbation():
