@@ -118,7 +118,7 @@ typedef struct {
                          /* cycle until the inner residual <= inner_tol (at most 100)      */
     double inner_tol;    /* max-norm inner residual tolerance (classical / early exit)     */
     int32_t early_exit;  /* 1: stop a solve before L cycles once inner_tol is met          */
-    double sdc_tol;      /* stop once the max-norm SDC residual < sdc_tol (Sec. 3)         */
+    double sdc_tol;      /* > 0: stop once the max-norm SDC residual < sdc_tol (Sec. 3)    */
     int32_t max_sweeps;  /* 1..100000                                                      */
     int32_t smoother;    /* ISDC_SMOOTH_*                                                  */
     int32_t nu_pre;      /* pre-smoothing steps  (0..8)                                    */

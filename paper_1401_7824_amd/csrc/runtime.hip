@@ -59,7 +59,8 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
     if (pr->vcycles < 0 || pr->vcycles > 64) fail(ISDC_E_INVAL, "vcycles must be in 0..64");
     if (!std::isfinite(pr->inner_tol) || pr->inner_tol < 0) fail(ISDC_E_INVAL, "inner_tol must be finite, >= 0");
     if (pr->early_exit != 0 && pr->early_exit != 1) fail(ISDC_E_INVAL, "early_exit must be 0 or 1");
-    if (!std::isfinite(pr->sdc_tol) || pr->sdc_tol < 0) fail(ISDC_E_INVAL, "sdc_tol must be finite, >= 0");
+    // the sweeps stop once the residual is strictly below sdc_tol (Sec. 3), which a zero tolerance never allows
+    if (!std::isfinite(pr->sdc_tol) || pr->sdc_tol <= 0) fail(ISDC_E_INVAL, "sdc_tol must be finite and > 0");
     if (pr->max_sweeps < 1 || pr->max_sweeps > 100000) fail(ISDC_E_INVAL, "max_sweeps must be in 1..100000");
     if (pr->smoother != ISDC_SMOOTH_RBGS && pr->smoother != ISDC_SMOOTH_JACOBI) fail(ISDC_E_INVAL, "unknown smoother");
     if (pr->nu_pre < 0 || pr->nu_pre > 8 || pr->nu_post < 0 || pr->nu_post > 8 || pr->nu_pre + pr->nu_post < 1)

@@ -101,7 +101,7 @@ def test_workspace_bytes_scale_with_problem():
 @pytest.mark.parametrize("bad", [
     dict(dim=0), dict(dim=4), dict(n=0), dict(n=10), dict(n=16383, dim=2), dict(n=2047, dim=3), dict(nu=-1.0),
     dict(nu=float("nan")), dict(fe=5), dict(M=1), dict(M=10), dict(node_kind=3), dict(vcycles=-1),
-    dict(sdc_tol=-1.0), dict(sdc_tol=float("inf")), dict(max_sweeps=0), dict(smoother=2), dict(nu_pre=0, nu_post=0),
+    dict(sdc_tol=-1.0), dict(sdc_tol=0.0), dict(sdc_tol=float("inf")), dict(max_sweeps=0), dict(smoother=2), dict(nu_pre=0, nu_post=0),
     dict(nu_pre=9), dict(precision=2), dict(guess=3), dict(early_exit=2), dict(inner_tol=float("nan")),
     dict(levels=0), dict(levels=3), dict(levels=2, n=1),
 ])
