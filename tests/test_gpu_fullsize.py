@@ -44,11 +44,20 @@ def test_rd2d_full_size_sweeps_match_oracle():
     for j in (2, cfg["M"]):
         assert rel_l2(host(p.node_values(j)), st.U[j]) < 1e-12
     p.end(torch.empty_like(u0d))
-    # the whole step converges below the tolerance
+    # the whole step: the oracle continues its sweeps to the tolerance, and
+    # the GPU step from u_0 gives the same counts and the same result
+    res_hist = [rc]
+    while rc >= cfg["sdc_tol"] and st.stats.sweeps < 100:
+        rc = sdc_sweep(st)
+        res_hist.append(rc)
+    assert rc < cfg["sdc_tol"]
     u = dev(u0)
     s = p.step(u, cfg["dt"])
     assert s.status == "ok" and s.residual < cfg["sdc_tol"]
+    if all(abs(r / cfg["sdc_tol"] - 1.0) > 1e-6 for r in res_hist):
+        assert s.sweeps == st.stats.sweeps and s.vcycles == st.stats.vcycles
     assert s.vcycles == s.sweeps * (cfg["M"] - 1) * 2
+    assert rel_l2(host(u), st.U[cfg["M"]]) < 1e-12
 
 
 def test_heat3d_full_size_mixed_matches_collocation():

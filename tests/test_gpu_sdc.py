@@ -196,7 +196,15 @@ def test_mixed_precision_reaches_collocation(case):
     # the oracle's float32 emulation of the same path lands at the same place
     ref, rst = sdc_step(u0, dt, h, _cfg(nu, fe, precision=MIXED, sdc_tol=1e-11, **par))
     assert rel_l2(host(u), ref) < 1e-9
-    assert abs(st.sweeps - rst.sweeps) <= 2
+    # the two float32 paths round differently (FMA, summation order), so their
+    # per-sweep residuals agree to a small relative amount, not bit for bit;
+    # the sweep counts must then be equal unless a residual falls within that
+    # amount of the tolerance (Sec. 3 stopping rule)
+    tol, window = 1e-11, 1e-3
+    for a, b in zip(st.residual_hist, rst.residual_hist):
+        assert abs(a - b) <= window * b, (st.residual_hist, rst.residual_hist)
+    if all(abs(r / tol - 1.0) > window for r in rst.residual_hist):
+        assert st.sweeps == rst.sweeps, (st.residual_hist, rst.residual_hist)
 
 
 def test_mixed_precision_sweep_iterates_track_oracle_float32():
@@ -230,7 +238,11 @@ def test_classical_and_early_exit_match_oracle(vcycles, early):
     ref, rst = sdc_step(u0, dt, 1.0 / (n + 1), _cfg(nu, O.FE_ZERO, **par))
     assert st.status == "ok"
     assert st.sweeps == rst.sweeps
-    assert abs(st.vcycles - rst.vcycles) <= 1
+    # counts are equal unless an inner residual of the oracle came within 1e-6
+    # of inner_tol, where the GPU's rounding order may stop a cycle earlier or later
+    assert rst.inner_margin < float("inf")
+    if rst.inner_margin > 1e-6:
+        assert st.vcycles == rst.vcycles, (st.vcycles, rst.vcycles, rst.inner_margin)
     assert rel_l2(host(u), ref) < 1e-10
 
 
