@@ -196,13 +196,19 @@ def test_mixed_precision_reaches_collocation(case):
     # the oracle's float32 emulation of the same path lands at the same place
     ref, rst = sdc_step(u0, dt, h, _cfg(nu, fe, precision=MIXED, sdc_tol=1e-11, **par))
     assert rel_l2(host(u), ref) < 1e-9
-    # the two float32 paths round differently (FMA, summation order), so their
-    # per-sweep residuals agree to a small relative amount, not bit for bit;
-    # the sweep counts must then be equal unless a residual falls within that
-    # amount of the tolerance (Sec. 3 stopping rule)
-    tol, window = 1e-11, 1e-3
+    # The two float32 paths round differently (FMA, summation order).  The
+    # max-norm residual passes each sweep's float32 rounding noise through
+    # nu L_h, so it moves by a small relative amount that the oracle itself
+    # measures: the shift between its float32 and float64 runs.  The GPU's
+    # residuals must agree with the oracle's float32 ones within a few times
+    # that shift, and the sweep counts must be equal unless an oracle residual
+    # lies within that window of the tolerance (Sec. 3 stopping rule).
+    _, r64 = sdc_step(u0, dt, h, _cfg(nu, fe, precision=FP64, sdc_tol=1e-11, **par))
+    shift = max(abs(a / b - 1.0) for a, b in zip(rst.residual_hist, r64.residual_hist))
+    tol, window = 1e-11, max(4.0 * shift, 1e-4)
+    print("[residuals] gpu", st.residual_hist, "oracle", rst.residual_hist, "window", window, flush=True)
     for a, b in zip(st.residual_hist, rst.residual_hist):
-        assert abs(a - b) <= window * b, (st.residual_hist, rst.residual_hist)
+        assert abs(a - b) <= window * b, (st.residual_hist, rst.residual_hist, window)
     if all(abs(r / tol - 1.0) > window for r in rst.residual_hist):
         assert st.sweeps == rst.sweeps, (st.residual_hist, rst.residual_hist)
 
