@@ -100,9 +100,12 @@ enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KER
 
 typedef struct {
     int32_t dim;      /* d = 1, 2 or 3                                                */
-    int32_t n;        /* points per axis: Dirichlet 2^k - 1 interior points with      */
+    int32_t n[3];     /* points per axis: Dirichlet 2^k - 1 interior points with      */
                       /* 1 <= k <= 15 (d = 1), k <= 13 (d = 2), k <= 10 (d = 3);      */
-                      /* periodic 2^k with 2 <= k <= 13                               */
+                      /* periodic 2^k with 2 <= k <= 13.  n[a] = 1 on the axes        */
+                      /* a >= dim (else ISDC_E_INVAL); the used axes must have the    */
+                      /* same count (else ISDC_E_UNSUPPORTED: the multigrid hierarchy */
+                      /* coarsens every axis together)                                */
     double nu;        /* diffusion coefficient, finite and >= 0                       */
     int32_t fe_kind;  /* ISDC_FE_*                                                    */
     int32_t stencil;  /* ISDC_STENCIL_* (COMPACT4: dim = 2, smoother JACOBI, guess     */
@@ -303,15 +306,43 @@ typedef struct isdc_batch isdc_batch;
 /* Slot states reported by isdc_batch_slot_info. */
 enum { ISDC_SLOT_FREE = 0, ISDC_SLOT_RUNNING = 1, ISDC_SLOT_FINISHED = 2 };
 
-/* Device workspace bytes of a batch with `capacity` slots (1..4096): slot
- * descriptors, states, residuals and launch maps.  Host only. */
+/* ---- Fixed instances, one full time step per call.
+ * `count` (1..4096) independent instances (Sec. 2, eq. (1)-(4): each its own
+ * u_0, f^I/f^E split, nodes and M, and L V-cycles per solve), probs[i] and
+ * pars[i] for instance i; all must share dim, precision and L >= 1, and run
+ * the batch's solver (above).  isdc_batch_bytes gives the device workspace
+ * of such a batch: the batch's own arrays followed by every instance's plan
+ * workspace.  Host only; probs and pars are copied. */
+int isdc_batch_bytes(int32_t count, const isdc_problem* probs, const isdc_params* pars, size_t* out_bytes);
+int isdc_batch_create(int32_t count, const isdc_problem* probs, const isdc_params* pars, void* d_workspace,
+                      size_t bytes, isdc_batch** out);
+
+/* One ISDC time step of every active instance (active[i] != 0; active NULL =
+ * all): d_u[i] (instance i's n^d float64 state) holds u_n on entry and
+ * u_{n+1} on return, dt[i] > 0 is its step.  All active instances sweep
+ * together (one launch per sweep phase, one 8-byte-per-instance residual
+ * read-back per sweep) until each has converged or stopped; stats[i] (stats
+ * may be NULL; entries of inactive instances are untouched) receives its
+ * counters.  Instance i's result is bitwise that of isdc_step on its own plan.
+ * Returns ISDC_OK if every active instance converged, else the status of the
+ * first one (by index) that did not (ISDC_E_NOT_CONVERGED / ISDC_E_DIVERGED),
+ * with every active d_u[i] holding that instance's last iterate.  Invalid
+ * pointers or dt are rejected before any device work.  Synchronises `stream`.
+ * Only for batches made by isdc_batch_create. */
+int isdc_batch_step(isdc_batch* batch, double* const* d_u, const double* dt, const int32_t* active, void* stream,
+                    isdc_stats* stats);
+
+/* ---- Open slots, for continuous batching (a serving loop).
+ * isdc_batch_workspace_bytes: device workspace of a slot batch with
+ * `capacity` slots (1..4096): slot descriptors, states, residuals and launch
+ * maps.  Host only. */
 int isdc_batch_workspace_bytes(int32_t capacity, size_t* out_bytes);
 
-/* Create a batch over caller-owned device workspace (256-byte aligned, at
+/* Open a slot batch over caller-owned device workspace (256-byte aligned, at
  * least isdc_batch_workspace_bytes).  dim, precision (ISDC_PREC_*) and
  * vcycles (L >= 1) are common to all slots.  Host only. */
-int isdc_batch_create(int32_t capacity, int32_t dim, int32_t precision, int32_t vcycles, void* d_workspace,
-                      size_t bytes, isdc_batch** out);
+int isdc_batch_open(int32_t capacity, int32_t dim, int32_t precision, int32_t vcycles, void* d_workspace,
+                    size_t bytes, isdc_batch** out);
 
 /* Destroy a batch (NULL is ignored); frees its slot plans and pinned host
  * staging, not the caller's workspaces. */

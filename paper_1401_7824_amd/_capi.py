@@ -29,8 +29,14 @@ HIST = 128
 
 
 class Problem(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("fe_kind", C.c_int32),
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("nu", C.c_double), ("fe_kind", C.c_int32),
                 ("stencil", C.c_int32), ("bc", C.c_int32)]
+
+
+def problem(dim, n, nu, fe_kind=FE_ZERO, stencil=STENCIL_2ND, bc=BC_DIRICHLET) -> Problem:
+    """isdc_problem of a grid with n points on each of the dim axes (n[a] = 1 beyond)."""
+    axes = (C.c_int32 * 3)(*[n if a < dim else 1 for a in range(3)])
+    return Problem(dim=dim, n=axes, nu=nu, fe_kind=fe_kind, stencil=stencil, bc=bc)
 
 
 class Params(C.Structure):
@@ -69,8 +75,12 @@ SIGNATURES = [
     ("isdc_autotune", C.c_int, [_VP, C.c_int32, _VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     ("isdc_set_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32]),
     ("isdc_get_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
+    ("isdc_batch_bytes", C.c_int, [C.c_int32, C.POINTER(Problem), C.POINTER(Params), _SZP]),
+    ("isdc_batch_create", C.c_int, [C.c_int32, C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t,
+                                    C.POINTER(_VP)]),
+    ("isdc_batch_step", C.c_int, [_VP, C.POINTER(_VP), _DP, C.POINTER(C.c_int32), _VP, C.POINTER(Stats)]),
     ("isdc_batch_workspace_bytes", C.c_int, [C.c_int32, _SZP]),
-    ("isdc_batch_create", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.c_size_t, C.POINTER(_VP)]),
+    ("isdc_batch_open", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.c_size_t, C.POINTER(_VP)]),
     ("isdc_batch_destroy", None, [_VP]),
     ("isdc_batch_set", C.c_int, [_VP, C.c_int32, C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, _VP,
                                  C.c_double, C.c_int32]),

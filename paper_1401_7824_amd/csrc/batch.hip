@@ -321,6 +321,13 @@ struct isdc_batch {
     int* h_maps;
     std::vector<bool> desc_dirty;
     std::vector<isdc::Slot> slots;
+    // instances fixed at creation (isdc_batch_create): problem, parameters and
+    // plan workspace per slot, carved from the caller's one workspace
+    bool fixed = false;
+    std::vector<isdc_problem> fprob;
+    std::vector<isdc_params> fpar;
+    std::vector<char*> fws;
+    std::vector<size_t> fbytes;
 };
 
 namespace isdc {
@@ -349,6 +356,7 @@ size_t batch_layout(int cap, char* base, isdc_batch* b) {
 }
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
 
 template <int D>
 int ntiles_of(int n, int TX, int TY, int TZ) {
@@ -395,6 +403,32 @@ void check_batch_params(const isdc_batch* b, const isdc_problem* pb, const isdc_
     if (pr->guess != ISDC_GUESS_PREV_SWEEP) fail(ISDC_E_UNSUPPORTED, "batches warm-start from the previous sweep only");
     if (pr->early_exit) fail(ISDC_E_UNSUPPORTED, "batches run exactly L cycles per solve");
     if (pr->levels != 1) fail(ISDC_E_UNSUPPORTED, "batches run single-level ISDC only");
+}
+
+// isdc_batch_create's workspace: the batch arrays, then each instance's plan
+// workspace (validated and checked against the batch rules).
+size_t fixed_layout(int count, const isdc_problem* probs, const isdc_params* pars, char* base, isdc_batch* b) {
+    size_t off = batch_layout(count, nullptr, nullptr);
+    if (b) {
+        b->fws.assign(count, nullptr);
+        b->fbytes.assign(count, 0);
+    }
+    isdc_batch shape{};
+    shape.d = probs[0].dim;
+    shape.prec = pars[0].precision;
+    shape.L = pars[0].vcycles;
+    for (int i = 0; i < count; ++i) {
+        validate(&probs[i], &pars[i]);
+        if (shape.L < 1) fail(ISDC_E_UNSUPPORTED, "batches run a fixed number L >= 1 of V-cycles per solve");
+        check_batch_params(&shape, &probs[i], &pars[i]);
+        const size_t need = layout(probs[i], pars[i], nullptr, nullptr);
+        if (b) {
+            b->fws[i] = base + off;
+            b->fbytes[i] = need;
+        }
+        off = align_up(off + need);
+    }
+    return off;
 }
 
 void build_desc(isdc_batch* b, int slot) {
@@ -679,8 +713,8 @@ int isdc_batch_workspace_bytes(int32_t capacity, size_t* out_bytes) {
     });
 }
 
-int isdc_batch_create(int32_t capacity, int32_t dim, int32_t precision, int32_t vcycles, void* d_workspace,
-                      size_t bytes, isdc_batch** out) {
+int isdc_batch_open(int32_t capacity, int32_t dim, int32_t precision, int32_t vcycles, void* d_workspace,
+                    size_t bytes, isdc_batch** out) {
     return guarded([&] {
         if (capacity < 1 || capacity > 4096) fail(ISDC_E_INVAL, "capacity must be in 1..4096");
         if (dim < 1 || dim > 3) fail(ISDC_E_INVAL, "dim must be 1, 2 or 3");
@@ -705,6 +739,83 @@ int isdc_batch_create(int32_t capacity, int32_t dim, int32_t precision, int32_t 
         b->desc_dirty.assign(capacity, false);
         *out = b;
     });
+}
+
+int isdc_batch_bytes(int32_t count, const isdc_problem* probs, const isdc_params* pars, size_t* out_bytes) {
+    return guarded([&] {
+        if (count < 1 || count > 4096) fail(ISDC_E_INVAL, "count must be in 1..4096");
+        if (!probs || !pars) fail(ISDC_E_INVAL, "NULL problems or params");
+        if (!out_bytes) fail(ISDC_E_INVAL, "out_bytes is NULL");
+        *out_bytes = fixed_layout(count, probs, pars, nullptr, nullptr);
+    });
+}
+
+int isdc_batch_create(int32_t count, const isdc_problem* probs, const isdc_params* pars, void* d_workspace,
+                      size_t bytes, isdc_batch** out) {
+    return guarded([&] {
+        if (count < 1 || count > 4096) fail(ISDC_E_INVAL, "count must be in 1..4096");
+        if (!probs || !pars) fail(ISDC_E_INVAL, "NULL problems or params");
+        if (!out) fail(ISDC_E_INVAL, "out is NULL");
+        *out = nullptr;
+        const size_t need = fixed_layout(count, probs, pars, nullptr, nullptr);
+        if (!d_workspace || ((uintptr_t)d_workspace) % kAlign) fail(ISDC_E_WORKSPACE, "workspace NULL or misaligned");
+        if (bytes < need) fail(ISDC_E_WORKSPACE, "batch workspace too small: need " + std::to_string(need));
+        isdc_batch* b = nullptr;
+        const int rc = isdc_batch_open(count, probs[0].dim, pars[0].precision, pars[0].vcycles, d_workspace,
+                                       batch_layout(count, nullptr, nullptr), &b);
+        if (rc != ISDC_OK) fail(rc, last_error());
+        b->fixed = true;
+        b->fprob.assign(probs, probs + count);
+        b->fpar.assign(pars, pars + count);
+        fixed_layout(count, probs, pars, (char*)d_workspace, b);
+        *out = b;
+    });
+}
+
+int isdc_batch_step(isdc_batch* b, double* const* d_u, const double* dt, const int32_t* active, void* stream,
+                    isdc_stats* stats) {
+    int status = ISDC_OK;
+    int first_bad = -1;
+    const int rc = guarded([&] {
+        as_batch(b);
+        if (!b->fixed) fail(ISDC_E_INVAL, "isdc_batch_step needs a batch made by isdc_batch_create");
+        if (!d_u || !dt) fail(ISDC_E_INVAL, "NULL d_u or dt");
+        for (int i = 0; i < b->cap; ++i)
+            if (b->slots[i].state == SLOT_RUNNING) fail(ISDC_E_INVAL, "slots are running (isdc_batch_set use)");
+        // validate every active instance before any device work
+        int nact = 0;
+        for (int i = 0; i < b->cap; ++i) {
+            if (active && !active[i]) continue;
+            if (!d_u[i]) fail(ISDC_E_INVAL, "d_u[" + std::to_string(i) + "] is NULL");
+            if (!std::isfinite(dt[i]) || dt[i] <= 0) fail(ISDC_E_INVAL, "dt[" + std::to_string(i) + "] must be finite and > 0");
+            ++nact;
+        }
+        for (int i = 0; i < b->cap; ++i) {
+            if (active && !active[i]) continue;
+            const int r = isdc_batch_set(b, i, &b->fprob[i], &b->fpar[i], b->fws[i], b->fbytes[i], d_u[i], dt[i], 1);
+            if (r != ISDC_OK) fail(r, last_error());
+        }
+        int running = nact;
+        while (running > 0) {
+            const int r = isdc_batch_advance(b, stream, &running);
+            if (r != ISDC_OK) fail(r, last_error());
+        }
+        for (int i = 0; i < b->cap; ++i) {
+            if (active && !active[i]) continue;
+            Slot& sl = b->slots[i];
+            if (stats) stats[i] = sl.last;
+            if (sl.status != ISDC_OK && status == ISDC_OK) {
+                status = sl.status;
+                first_bad = i;
+            }
+            sl.state = SLOT_FREE;  // the plan stays for the next step; the slot is ready to be set again
+        }
+    });
+    if (rc != ISDC_OK) return rc;
+    if (status != ISDC_OK)
+        last_error() = std::string(status == ISDC_E_DIVERGED ? "non-finite SDC residual" : "SDC residual not below sdc_tol after max_sweeps") +
+                       " in instance " + std::to_string(first_bad);
+    return status;
 }
 
 void isdc_batch_destroy(isdc_batch* b) {

@@ -38,10 +38,14 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
     if (!pb || !pr) fail(ISDC_E_INVAL, "NULL problem or params");
     if (pb->dim < 1 || pb->dim > 3) fail(ISDC_E_INVAL, "dim must be 1, 2 or 3");
     if (pb->bc != ISDC_BC_DIRICHLET && pb->bc != ISDC_BC_PERIODIC) fail(ISDC_E_INVAL, "unknown bc");
+    for (int a = pb->dim; a < 3; ++a)
+        if (pb->n[a] != 1) fail(ISDC_E_INVAL, "n[a] must be 1 on the axes a >= dim");
+    for (int a = 1; a < pb->dim; ++a)
+        if (pb->n[a] != pb->n[0]) fail(ISDC_E_UNSUPPORTED, "grids must have the same number of points on every axis");
     if (pb->bc == ISDC_BC_PERIODIC) {
-        if (pb->n < 4 || pb->n > 8192 || (pb->n & (pb->n - 1)) != 0)
+        if (pb->n[0] < 4 || pb->n[0] > 8192 || (pb->n[0] & (pb->n[0] - 1)) != 0)
             fail(ISDC_E_INVAL, "periodic grids need n = 2^k points with 2 <= k <= 13");
-    } else if (!valid_n(pb->dim, pb->n)) {
+    } else if (!valid_n(pb->dim, pb->n[0])) {
         fail(ISDC_E_INVAL, "n must be 2^k - 1 within the size limit for dim");
     }
     if (!std::isfinite(pb->nu) || pb->nu < 0) fail(ISDC_E_INVAL, "nu must be finite and >= 0");
@@ -79,7 +83,7 @@ void isdc::validate(const isdc_problem* pb, const isdc_params* pr) {
     if (pr->levels == 2) {
         if (pb->stencil != ISDC_STENCIL_2ND || pb->bc != ISDC_BC_DIRICHLET)
             fail(ISDC_E_UNSUPPORTED, "two-level MLSDC runs the second-order stencil with Dirichlet boundaries");
-        if (pb->n < 3) fail(ISDC_E_INVAL, "two-level MLSDC needs n >= 3 to coarsen");
+        if (pb->n[0] < 3) fail(ISDC_E_INVAL, "two-level MLSDC needs n >= 3 to coarsen");
     }
     if (pb->bc == ISDC_BC_PERIODIC && pb->stencil != ISDC_STENCIL_COMPACT4)
         fail(ISDC_E_UNSUPPORTED, "periodic boundaries are implemented with the compact stencil only");
@@ -108,7 +112,7 @@ int level_count(bool periodic, int n0) {
 // Lay the plan's arrays out from `base` (nullptr: sizing only); returns the byte count.
 size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p) {
     const int d = pb.dim, M = pr.M;
-    const size_t N = pow_d((size_t)pb.n, d);
+    const size_t N = pow_d((size_t)pb.n[0], d);
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
         void* ptr = base ? (void*)(base + off) : nullptr;
@@ -141,8 +145,8 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
     }
     // multigrid hierarchy: 8 bytes per entry so either precision fits
     const int tmax = periodic ? kCTailMaxPeriodic : tail_max_n(d);
-    int n = pb.n;
-    double h = periodic ? 2.0 / pb.n : 1.0 / (pb.n + 1);
+    int n = pb.n[0];
+    double h = periodic ? 2.0 / pb.n[0] : 1.0 / (pb.n[0] + 1);
     int l = 0;
     if (p) p->lev.clear();
     while (true) {
@@ -191,13 +195,13 @@ size_t isdc::layout(const isdc_problem& pb, const isdc_params& pr, char* base, i
             p->WD[1] = (double*)wd1;
         }
     }
-    size_t nparts = quad_partials(d, pb.n) > kReduceBlocks ? quad_partials(d, pb.n) : kReduceBlocks;
+    size_t nparts = quad_partials(d, pb.n[0]) > kReduceBlocks ? quad_partials(d, pb.n[0]) : kReduceBlocks;
     if (compact) {
-        const size_t rows = (size_t)pb.n * ((pb.n + 255) / 256);  // residual-norm blocks of the finest level
+        const size_t rows = (size_t)pb.n[0] * ((pb.n[0] + 255) / 256);  // residual-norm blocks of the finest level
         nparts = std::max(nparts, std::max(rows, (size_t)kCResBlocks * M));
     }
     if (pr.levels == 2) {  // coarse MLSDC level: R U_j, the coarse sweep's values, injected S F
-        const size_t Nc = pow_d((size_t)((pb.n - 1) / 2), d);
+        const size_t Nc = pow_d((size_t)((pb.n[0] - 1) / 2), d);
         const bool lob = pr.node_kind == ISDC_NODES_LOBATTO;  // node 1 is u_0 on both levels
         for (int j = 0; j <= M; ++j) {
             void* r = (j == 1 && lob) ? nullptr : take(Nc * sizeof(double));
@@ -792,6 +796,37 @@ void check_plan(const isdc_plan* p) {
     if (!p) fail(ISDC_E_INVAL, "plan is NULL");
 }
 
+// One time step (Sec. 2-3): sweeps until the SDC residual is below sdc_tol,
+// it is not finite, or max_sweeps is reached; returns the step's status.
+int step_loop(isdc_plan* plan, double* d_u, double dt, hipStream_t s, isdc_stats* out) {
+    if (!d_u) fail(ISDC_E_INVAL, "d_u is NULL");
+    begin_impl(plan, d_u, dt, s);
+    int status = ISDC_E_NOT_CONVERGED;
+    for (int k = 0; k < plan->par.max_sweeps; ++k) {
+        double res = sweep_any(plan, s);
+        if (!std::isfinite(res)) {
+            status = ISDC_E_DIVERGED;
+            break;
+        }
+        if (res < plan->par.sdc_tol) {
+            status = ISDC_OK;
+            break;
+        }
+    }
+    end_impl(plan, d_u, s);
+    if (out) *out = plan->stats;
+    return status;
+}
+
+int step_status(const isdc_plan* plan, int status) {
+    if (status == ISDC_E_NOT_CONVERGED)
+        isdc::last_error() = "SDC residual " + std::to_string(plan->stats.residual) + " not below sdc_tol after max_sweeps";
+    else if (status == ISDC_E_DIVERGED)
+        isdc::last_error() = "non-finite SDC residual";
+    return status;
+}
+
+
 }  // namespace
 
 
@@ -799,10 +834,10 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     p->prob = *prob;
     p->par = *par;
     p->d = prob->dim;
-    p->n = prob->n;
-    p->N = pow_d((size_t)prob->n, prob->dim);
+    p->n = prob->n[0];
+    p->N = pow_d((size_t)prob->n[0], prob->dim);
     p->periodic = prob->bc == ISDC_BC_PERIODIC;
-    p->h = p->periodic ? 2.0 / prob->n : 1.0 / (prob->n + 1);
+    p->h = p->periodic ? 2.0 / prob->n[0] : 1.0 / (prob->n[0] + 1);
     p->M = par->M;
     tables(par->node_kind, par->M, p->tau, p->Q, p->S, p->b);
     p->end_quad = par->node_kind == ISDC_NODES_LEGENDRE;
@@ -935,30 +970,9 @@ int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats*
     int status = ISDC_OK;
     int rc = guarded([&] {
         check_plan(plan);
-        if (!d_u) fail(ISDC_E_INVAL, "d_u is NULL");
-        hipStream_t s = (hipStream_t)stream;
-        begin_impl(plan, d_u, dt, s);
-        status = ISDC_E_NOT_CONVERGED;
-        for (int k = 0; k < plan->par.max_sweeps; ++k) {
-            double res = sweep_any(plan, s);
-            if (!std::isfinite(res)) {
-                status = ISDC_E_DIVERGED;
-                break;
-            }
-            if (res < plan->par.sdc_tol) {
-                status = ISDC_OK;
-                break;
-            }
-        }
-        end_impl(plan, d_u, s);
-        if (out) *out = plan->stats;
+        status = step_loop(plan, d_u, dt, (hipStream_t)stream, out);
     });
-    if (rc != ISDC_OK) return rc;
-    if (status == ISDC_E_NOT_CONVERGED)
-        isdc::last_error() = "SDC residual " + std::to_string(plan->stats.residual) + " not below sdc_tol after max_sweeps";
-    else if (status == ISDC_E_DIVERGED)
-        isdc::last_error() = "non-finite SDC residual";
-    return status;
+    return rc != ISDC_OK ? rc : step_status(plan, status);
 }
 
 int isdc_node_values(isdc_plan* plan, int32_t j, double* d_out, void* stream) {

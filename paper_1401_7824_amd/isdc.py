@@ -49,7 +49,7 @@ def _dev_ptr(t: torch.Tensor, dtype=None, numel=None):
 
 
 def make_problem(dim, n, nu, fe_kind=A.FE_ZERO, stencil=A.STENCIL_2ND, bc=A.BC_DIRICHLET) -> A.Problem:
-    return A.Problem(dim=dim, n=n, nu=nu, fe_kind=fe_kind, stencil=stencil, bc=bc)
+    return A.problem(dim, n, nu, fe_kind, stencil, bc)
 
 
 def make_params(**kw) -> A.Params:
@@ -236,8 +236,8 @@ class Batch:
         A.check(self.lib.isdc_batch_workspace_bytes(capacity, C.byref(nbytes)))
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
         h = C.c_void_p()
-        A.check(self.lib.isdc_batch_create(capacity, dim, precision, vcycles, C.c_void_p(self.workspace.data_ptr()),
-                                           nbytes.value, C.byref(h)))
+        A.check(self.lib.isdc_batch_open(capacity, dim, precision, vcycles, C.c_void_p(self.workspace.data_ptr()),
+                                         nbytes.value, C.byref(h)))
         self._h = h
         self._keep = [None] * capacity
 
@@ -297,3 +297,69 @@ class Batch:
             if k >= max_advances:
                 raise RuntimeError("batch did not finish")
         return k + 1
+
+
+class FixedBatch:
+    """`count` fixed instances stepped together (isdc_batch_create /
+    isdc_batch_step): instance i is (dims, n_i, nu_i, f^E_i, params_i); one
+    torch workspace holds the batch arrays and every instance's plan."""
+
+    def __init__(self, dim: int, instances, device=None):
+        """instances: list of dicts with keys n, nu, fe_kind (optional) and the
+        isdc_params fields (node_kind, M, vcycles, precision, sdc_tol, ...)."""
+        self.lib = A.load()
+        self.dim = dim
+        self.count = len(instances)
+        probs = (A.Problem * self.count)()
+        pars = (A.Params * self.count)()
+        self.n = []
+        for i, inst in enumerate(instances):
+            inst = dict(inst)
+            n = inst.pop("n")
+            nu = inst.pop("nu")
+            fe = inst.pop("fe_kind", A.FE_ZERO)
+            probs[i] = make_problem(dim, n, nu, fe)
+            pars[i] = make_params(**inst)
+            self.n.append(n)
+        self._probs, self._pars = probs, pars
+        nbytes = C.c_size_t()
+        A.check(self.lib.isdc_batch_bytes(self.count, probs, pars, C.byref(nbytes)))
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        A.check(self.lib.isdc_batch_create(self.count, probs, pars, C.c_void_p(self.workspace.data_ptr()),
+                                           nbytes.value, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.isdc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, us, dts, active=None, stream=None):
+        """One time step of every active instance in place on us[i] (float64,
+        shape (n_i,)*dim) with step dts[i]; returns (status, [StepStats or None])."""
+        if len(us) != self.count or len(dts) != self.count:
+            raise ValueError(f"need {self.count} states and step sizes")
+        ptrs = (C.c_void_p * self.count)()
+        for i, u in enumerate(us):
+            on = active is None or active[i]
+            ptrs[i] = _dev_ptr(u, torch.float64, self.n[i] ** self.dim).value if on else None
+        dt = (C.c_double * self.count)(*dts)
+        flags = [1] * self.count if active is None else [1 if a else 0 for a in active]
+        act = (C.c_int32 * self.count)(*flags)
+        stats = (A.Stats * self.count)()
+        rc = self.lib.isdc_batch_step(self._h, ptrs, dt, act, _stream_handle(stream), stats)
+        A.check(rc, allow=(A.E_NOT_CONVERGED, A.E_DIVERGED))
+        out = []
+        for i in range(self.count):
+            on = active is None or active[i]
+            out.append(StepStats.from_c(stats[i], A.OK) if on else None)
+        return A.STATUS_NAMES.get(rc, rc), out

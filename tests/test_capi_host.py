@@ -74,7 +74,7 @@ def _params(**kw):
 def _bytes(dim, n, nu=1.0, fe=A.FE_ZERO, **kw):
     lib = A.load()
     out = C.c_size_t()
-    rc = lib.isdc_workspace_bytes(C.byref(A.Problem(dim, n, nu, fe)), C.byref(_params(**kw)), C.byref(out))
+    rc = lib.isdc_workspace_bytes(C.byref(A.problem(dim, n, nu, fe)), C.byref(_params(**kw)), C.byref(out))
     return rc, out.value
 
 
@@ -114,10 +114,22 @@ def test_validation_rejects(bad):
     assert A.load().isdc_last_error() != b""
 
 
+def test_axis_counts():
+    # n[a] = 1 beyond dim; unequal counts on the used axes are a valid grid this build does not run
+    lib = A.load()
+    out = C.c_size_t()
+    par = _params()
+    for dim, n, rc in [(2, (63, 63, 1), 0), (3, (31, 31, 31), 0), (1, (127, 1, 1), 0),
+                       (2, (63, 63, 3), A.E_INVAL), (1, (127, 127, 1), A.E_INVAL),
+                       (2, (63, 31, 1), A.E_UNSUPPORTED), (3, (31, 31, 15), A.E_UNSUPPORTED)]:
+        prob = A.Problem(dim=dim, n=(C.c_int32 * 3)(*n), nu=1.0, fe_kind=A.FE_ZERO)
+        assert lib.isdc_workspace_bytes(C.byref(prob), C.byref(par), C.byref(out)) == rc, (dim, n)
+
+
 def _pbytes(dim, n, stencil, bc, fe=A.FE_ZERO, **kw):
     lib = A.load()
     out = C.c_size_t()
-    prob = A.Problem(dim=dim, n=n, nu=1.0, fe_kind=fe, stencil=stencil, bc=bc)
+    prob = A.problem(dim, n, 1.0, fe, stencil, bc)
     par = _params(**dict(dict(smoother=A.SMOOTH_JACOBI), **kw))
     return lib.isdc_workspace_bytes(C.byref(prob), C.byref(par), C.byref(out)), out.value
 
@@ -159,7 +171,7 @@ def test_burgers_workspace_holds_fe_arrays():
 
 def test_create_checks_workspace_without_touching_it():
     lib = A.load()
-    prob = A.Problem(2, 63, 1.0, A.FE_ZERO)
+    prob = A.problem(2, 63, 1.0, A.FE_ZERO)
     par = _params()
     need = C.c_size_t()
     assert lib.isdc_workspace_bytes(C.byref(prob), C.byref(par), C.byref(need)) == 0
@@ -194,3 +206,47 @@ def test_null_plan_rejected():
     r = C.c_double()
     assert lib.isdc_sweep(None, None, C.byref(r)) == A.E_INVAL
     assert lib.isdc_get_stats(None, C.byref(A.Stats())) == A.E_INVAL
+
+
+def test_fixed_batch_validation_host_only():
+    # isdc_batch_bytes / isdc_batch_create check every instance before any
+    # device work; isdc_batch_step rejects NULL states and bad steps first
+    lib = A.load()
+    from paper_1401_7824_amd.isdc import make_params
+    probs = (A.Problem * 3)(A.problem(2, 63, 1.0), A.problem(2, 127, 0.5, A.FE_CUBIC), A.problem(2, 31, 0.1))
+    pars = (A.Params * 3)(make_params(precision=1), make_params(precision=1, M=5), make_params(precision=1))
+    out = C.c_size_t()
+    assert lib.isdc_batch_bytes(3, probs, pars, C.byref(out)) == 0
+    base = C.c_size_t()
+    assert lib.isdc_batch_workspace_bytes(3, C.byref(base)) == 0
+    plans = sum((_bytes(2, n, nu, fe, **kw)[1] + 255) // 256 * 256 for n, nu, fe, kw in
+                [(63, 1.0, A.FE_ZERO, dict(precision=1)), (127, 0.5, A.FE_CUBIC, dict(precision=1, M=5)),
+                 (31, 0.1, A.FE_ZERO, dict(precision=1))])
+    assert out.value == base.value + plans
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 40)  # never dereferenced
+    assert lib.isdc_batch_create(3, probs, pars, fake, out.value - 1, C.byref(h)) == A.E_WORKSPACE
+    assert lib.isdc_batch_create(3, probs, pars, fake, out.value, C.byref(h)) == 0 and h.value
+    us = (C.c_void_p * 3)(fake.value, None, fake.value)
+    dts = (C.c_double * 3)(1e-3, 1e-3, 1e-3)
+    assert lib.isdc_batch_step(h, us, dts, None, None, None) == A.E_INVAL          # d_u[1] NULL, all active
+    bad = (C.c_double * 3)(1e-3, 1e-3, -1.0)
+    act = (C.c_int32 * 3)(1, 0, 1)
+    assert lib.isdc_batch_step(h, us, bad, act, None, None) == A.E_INVAL           # dt[2] <= 0
+    assert b"dt[2]" in lib.isdc_last_error()
+    lib.isdc_batch_destroy(h)
+    # a slot batch (isdc_batch_open) has no fixed instances to step
+    sb = C.c_void_p()
+    assert lib.isdc_batch_open(3, 2, 1, 2, fake, base.value, C.byref(sb)) == 0
+    assert lib.isdc_batch_step(sb, us, dts, act, None, None) == A.E_INVAL
+    lib.isdc_batch_destroy(sb)
+    # instances must share dim, precision and L, and run the batch's solver
+    mixed = (A.Params * 2)(make_params(precision=1), make_params(precision=0))
+    two = (A.Problem * 2)(A.problem(2, 63, 1.0), A.problem(2, 63, 1.0))
+    assert lib.isdc_batch_bytes(2, two, mixed, C.byref(out)) == A.E_INVAL
+    jac = (A.Params * 2)(make_params(), make_params(smoother=A.SMOOTH_JACOBI, nu_pre=2, nu_post=2))
+    assert lib.isdc_batch_bytes(2, two, jac, C.byref(out)) == A.E_UNSUPPORTED
+    dims = (A.Problem * 2)(A.problem(2, 63, 1.0), A.problem(3, 15, 1.0))
+    assert lib.isdc_batch_bytes(2, dims, (A.Params * 2)(make_params(), make_params()), C.byref(out)) == A.E_INVAL
+    assert lib.isdc_batch_bytes(0, two, mixed, C.byref(out)) == A.E_INVAL
+

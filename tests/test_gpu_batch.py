@@ -187,3 +187,33 @@ def test_batch_rejects_unsupported_parameters():
         b.set(0, u, 1e-3, 1, 1.0, precision=1)  # batch is FP64
     with pytest.raises(ISDCError):
         b.set(5, u, 1e-3, 1, 1.0)  # slot out of range
+
+
+@pytest.mark.parametrize("d,prec", [(2, 1), (3, 0)])
+def test_fixed_batch_step_equals_isdc_step(d, prec):
+    # isdc_batch_create / isdc_batch_step: one full step of every active
+    # instance per call; instance i is bitwise isdc_step on its own plan
+    from paper_1401_7824_amd import FixedBatch, Plan
+    announce("fixed batch step", d, prec)
+    inst = _instances(d, prec, 5, seed=70 + d + prec)
+    fb = FixedBatch(d, [dict(n=x["n"], nu=x["nu"], fe_kind=x["fe"], vcycles=2, **x["par"]) for x in inst])
+    us = [dev(x["u0"]) for x in inst]
+    refs = [dev(x["u0"]) for x in inst]
+    plans = [Plan(d, x["n"], x["nu"], x["fe"], vcycles=2, **x["par"]) for x in inst]
+    masks = [None, [True, False, True, True, False]]
+    for call, active in enumerate(masks):
+        status, stats = fb.step(us, [x["dt"] for x in inst], active)
+        assert status == "ok"
+        for i, x in enumerate(inst):
+            if active is not None and not active[i]:
+                assert stats[i] is None
+                continue
+            st = plans[i].step(refs[i], x["dt"])
+            assert torch.equal(us[i], refs[i]), f"call {call}: instance {i} differs from isdc_step"
+            assert (stats[i].sweeps, stats[i].vcycles) == (st.sweeps, st.vcycles)
+            assert stats[i].residual_hist == st.residual_hist
+    # inactive instances kept their state: one step behind the others
+    for i in (1, 4):
+        ref = dev(inst[i]["u0"])
+        plans[i].step(ref, inst[i]["dt"])
+        assert torch.equal(us[i], ref)
