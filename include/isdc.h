@@ -198,6 +198,22 @@ void isdc_destroy(isdc_plan* plan);
  * last iterate in d_u and *out (may be NULL) filled. */
 int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats* out);
 
+/* isdc_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same time step of (prob, par) on d_u, with the plan's workspace in a static
+ * device array of the library (64 MiB, ISDC_STATIC_SCRATCH_BYTES; one copy per
+ * device, held until the process ends) instead of a caller workspace.
+ * Problems whose isdc_workspace_bytes exceed it return ISDC_E_WORKSPACE
+ * before any device work.  The first call on a device looks up the array's
+ * address and makes a host plan for that device; later calls allocate
+ * nothing.  Results equal isdc_step's on a plan of the same (prob, par).
+ * Every call on one device shares the array and that host plan, which keep
+ * the last call's contents (nothing in them needs to start at zero): calls
+ * that overlap on one device, from any thread or stream, race. */
+#define ISDC_STATIC_SCRATCH_BYTES (64u << 20)
+int isdc_step_noalloc(const isdc_problem* prob, const isdc_params* par, double* d_u, double dt, void* stream,
+                      isdc_stats* out);
+
 /* The pieces of isdc_step, for callers that drive sweeps themselves:
  * isdc_begin sets the initial iterate u_j^0 = u_0 at every node and computes
  * S*F(u^0).  d_u0 must stay valid and unchanged until isdc_end.

@@ -18,7 +18,7 @@ def __getattr__(name):
     # the torch-based binding is imported lazily so that the C-ABI checks and the
     # input generators work without touching a GPU
     if name in ("Plan", "Batch", "FixedBatch", "StepStats", "tables", "end_weights", "make_params", "make_problem",
-                "workspace_bytes"):
+                "workspace_bytes", "step_noalloc"):
         from . import isdc
         return getattr(isdc, name)
     raise AttributeError(name)

@@ -64,6 +64,7 @@ SIGNATURES = [
     ("isdc_create", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)]),
     ("isdc_destroy", None, [_VP]),
     ("isdc_step", C.c_int, [_VP, _VP, C.c_double, _VP, C.POINTER(Stats)]),
+    ("isdc_step_noalloc", C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, C.c_double, _VP, C.POINTER(Stats)]),
     ("isdc_begin", C.c_int, [_VP, _VP, C.c_double, _VP]),
     ("isdc_sweep", C.c_int, [_VP, _VP, _DP]),
     ("isdc_end", C.c_int, [_VP, _VP, _VP]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -826,6 +827,46 @@ int step_status(const isdc_plan* plan, int status) {
     return status;
 }
 
+// ---------------------------------------------------------------- static scratch
+// isdc_step_noalloc lays its plan out on this device array instead of a caller
+// workspace.  In host code `scratch` only names the symbol: its device address
+// comes from hipGetSymbolAddress, once per device, and only that address is
+// passed on.  Every device the library runs on holds its own copy until the
+// process ends.
+constexpr size_t kScratchBytes = ISDC_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct StaticDevice {
+    std::once_flag once;
+    hipError_t err = hipSuccess;
+    void* scratch_ptr = nullptr;  // this device's address of `scratch`
+    isdc_plan* plan = nullptr;    // host plan shared by the calls on this device
+    double readback[8];           // residual read-back target (ordinary host memory)
+};
+StaticDevice g_static[kMaxDevices];
+
+// Set-up on the first call on the current device: the scratch address and a
+// host plan whose level table is reserved and whose read-back target is the
+// static host buffer, so later calls allocate nothing on the device or pinned.
+StaticDevice& static_device() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(ISDC_E_UNSUPPORTED, "device index beyond the static scratch table");
+    StaticDevice& sd = g_static[dev];
+    std::call_once(sd.once, [&sd] {
+        void* ptr = nullptr;
+        sd.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (sd.err != hipSuccess) return;
+        sd.scratch_ptr = ptr;
+        sd.plan = new isdc_plan();
+        sd.plan->lev.reserve(32);
+        sd.plan->h_pinned = sd.readback;
+    });
+    if (sd.err != hipSuccess)
+        fail(ISDC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(sd.err));
+    return sd;
+}
 
 }  // namespace
 
@@ -970,6 +1011,25 @@ int isdc_step(isdc_plan* plan, double* d_u, double dt, void* stream, isdc_stats*
     int status = ISDC_OK;
     int rc = guarded([&] {
         check_plan(plan);
+        status = step_loop(plan, d_u, dt, (hipStream_t)stream, out);
+    });
+    return rc != ISDC_OK ? rc : step_status(plan, status);
+}
+
+int isdc_step_noalloc(const isdc_problem* prob, const isdc_params* par, double* d_u, double dt, void* stream,
+                      isdc_stats* out) {
+    int status = ISDC_OK;
+    isdc_plan* plan = nullptr;
+    int rc = guarded([&] {
+        validate(prob, par);
+        const size_t need = layout(*prob, *par, nullptr, nullptr);
+        if (need > kScratchBytes)
+            fail(ISDC_E_WORKSPACE, "problem needs " + std::to_string(need) + " bytes of workspace; the static scratch holds " +
+                                       std::to_string(kScratchBytes));
+        if (!d_u) fail(ISDC_E_INVAL, "d_u is NULL");
+        StaticDevice& sd = static_device();
+        plan = sd.plan;
+        init_plan(plan, prob, par, sd.scratch_ptr);
         status = step_loop(plan, d_u, dt, (hipStream_t)stream, out);
     });
     return rc != ISDC_OK ? rc : step_status(plan, status);

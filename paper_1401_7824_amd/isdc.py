@@ -88,6 +88,22 @@ def workspace_bytes(problem: A.Problem, params: A.Params) -> int:
     return out.value
 
 
+def step_noalloc(u: torch.Tensor, dt: float, nu: float, fe_kind: int = A.FE_ZERO, stencil: int = A.STENCIL_2ND,
+                 bc: int = A.BC_DIRICHLET, stream=None, **params) -> StepStats:
+    """One ISDC step in place on u (float64, shape (n,)*d) through
+    isdc_step_noalloc: the library's static device scratch instead of a
+    workspace, so nothing is allocated on the device."""
+    lib = A.load()
+    dim, n = u.dim(), u.shape[0]
+    prob = make_problem(dim, n, nu, fe_kind, stencil, bc)
+    par = make_params(**params)
+    st = A.Stats()
+    rc = lib.isdc_step_noalloc(C.byref(prob), C.byref(par), _dev_ptr(u, torch.float64, n ** dim), dt,
+                               _stream_handle(stream), C.byref(st))
+    A.check(rc, allow=(A.E_NOT_CONVERGED, A.E_DIVERGED))
+    return StepStats.from_c(st, rc)
+
+
 class Plan:
     """One ISDC problem instance: the C plan plus its torch-owned workspace."""
 

@@ -250,3 +250,17 @@ def test_fixed_batch_validation_host_only():
     assert lib.isdc_batch_bytes(2, dims, (A.Params * 2)(make_params(), make_params()), C.byref(out)) == A.E_INVAL
     assert lib.isdc_batch_bytes(0, two, mixed, C.byref(out)) == A.E_INVAL
 
+
+
+def test_step_noalloc_rejects_before_device_work():
+    lib = A.load()
+    par = _params()
+    st = A.Stats()
+    # 1023^2 with M = 5 needs more than the static scratch
+    big = A.problem(2, 1023, 1.0)
+    p5 = _params(M=5)
+    assert lib.isdc_step_noalloc(C.byref(big), C.byref(p5), C.c_void_p(1 << 40), 1e-3, None, C.byref(st)) == A.E_WORKSPACE
+    assert b"static scratch" in lib.isdc_last_error()
+    small = A.problem(2, 63, 1.0)
+    assert lib.isdc_step_noalloc(C.byref(small), C.byref(par), None, 1e-3, None, C.byref(st)) == A.E_INVAL
+    assert lib.isdc_step_noalloc(None, C.byref(par), C.c_void_p(1 << 40), 1e-3, None, C.byref(st)) == A.E_INVAL
