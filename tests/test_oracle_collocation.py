@@ -282,3 +282,20 @@ def test_legendre_pointwise_ode_order():
         expect = u0 * math.exp(dt) / np.sqrt(1 - u0 ** 2 + u0 ** 2 * math.exp(2 * dt))
         errs.append(np.max(np.abs(got - expect)))
     assert errs[1] < 1e-7 and 2 ** 7 * 0.5 < errs[0] / errs[1] < 2 ** 7 * 1.5
+
+
+def _pade_exp(k, j):
+    """(k, j) Pade approximant of exp from its textbook coefficients."""
+    f = math.factorial
+    num = [f(k + j - i) * f(k) / (f(k + j) * f(i) * f(k - i)) for i in range(k + 1)]
+    den = [(-1) ** i * f(k + j - i) * f(j) / (f(k + j) * f(i) * f(j - i)) for i in range(j + 1)]
+    return lambda z: np.polyval(num[::-1], z) / np.polyval(den[::-1], z)
+
+
+@pytest.mark.parametrize("kind,Ms", [(LOB, range(2, 10)), (RAD, range(1, 10)), (LEG, range(1, 10))])
+def test_stability_function_is_pade_for_every_m(kind, Ms):
+    # Lobatto IIIA: (M-1, M-1) Pade; Radau IIA: (M-1, M); Gauss: (M, M)
+    z = np.array([0.0, -0.01, -0.5, -1.0, -3.0, -10.0, -100.0, -655.0, 0.3])
+    for M in Ms:
+        k, j = {LOB: (M - 1, M - 1), RAD: (M - 1, M), LEG: (M, M)}[kind]
+        np.testing.assert_allclose(O.stability_function(z, kind, M), _pade_exp(k, j)(z), rtol=1e-13, atol=1e-15)
