@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
-"""ISDC throughput on one MI355X: steps/s of the 2D reaction-diffusion workload.
+"""ISDC throughput on one MI355X.
 
-Workload (default): u_t = nu Lap(u) + u - u^3 on [0,1]^2, Dirichlet, 1023^2
-interior points, nu = 0.1, 16 seeded sine modes, Gauss-Lobatto M = 5,
-dt = 1e-3, FP64, L = 2 RB-GS V(1,1) cycles per implicit solve, sweeps until
-the SDC residual < 1e-10.  One "step" is one complete ISDC time step (all
-sweeps, all V-cycles, the quadrature and the residual), with the state
-resident in HBM; the timed steps continue the time integration.
+Default workload (heat3d): u_t = Lap(u) on [0,1]^3, Dirichlet, 255^3
+interior points (a working set of about 2 GB, far above the 256 MB Infinity
+Cache), 32 seeded sine modes, right Gauss-Radau M = 3, dt = 1e-3, L = 2
+red-black V(1,1) cycles per implicit solve, sweeps until the SDC residual
+< 1e-10.  `value` is the all-float64 steps/s; the float32-V-cycle variant
+runs beside it.  One "step" is one complete ISDC time step (all sweeps, all
+V-cycles, the quadrature and the residual), with the state resident in HBM;
+the timed steps continue the time integration.  The dominant kernel's
+duration is taken inside the timed steps (each of its launches records its
+own dispatch start and end into HIP events).
 
 Prints one JSON line.  Only one GPU is supported (--gpus 1).
 """
@@ -32,13 +36,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rd2d", choices=["rd2d", "rd2d_compact", "rd2d_mlsdc", "heat3d", "heat1d", "burgers2d", "batch", "serve", "table1",
-                             "table1b", "kernels"])
-    ap.add_argument("--serve-count", type=int, default=120)
-    ap.add_argument("--serve-budget-gb", type=float, default=24.0)
+    ap.add_argument("--workload", default="heat3d", choices=["rd2d", "rd2d_compact", "rd2d_mlsdc", "heat3d", "heat1d", "burgers2d", "batch", "serve", "table1",
+                             "table1b", "kernels", "compare"])
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve-latency", action="store_true",
+                    help="skip the short serving run that gives the headline line its p50/p99 latency")
     ap.add_argument("--probe-reps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (reference kernel for HBM byte counters)")
@@ -127,22 +133,53 @@ def kernel_name(name, cfg, T, shape=0):
     return KERNEL_NAMES[name].format(T=T, d=cfg["dim"], M=cfg["M"], S=shape)
 
 
+def pade_exp(k, j):
+    """Ascending coefficients of the (k, j) Pade approximant P/Q of exp(z)."""
+    from math import factorial as f
+    num = [f(k + j - i) * f(k) / (f(k + j) * f(i) * f(k - i)) for i in range(k + 1)]
+    den = [(-1) ** i * f(k + j - i) * f(j) / (f(k + j) * f(i) * f(j - i)) for i in range(j + 1)]
+    return num, den
+
+
+def collocation_stability(node_kind, M, z):
+    """R(z) of collocation with M nodes (Sec. 1) for u' = lambda u, z = dt lambda:
+    Gauss-Lobatto collocation (Lobatto IIIA) gives the (M-1, M-1) Pade
+    approximant of exp, right Gauss-Radau (Radau IIA) the (M-1, M) one,
+    Gauss-Legendre the (M, M) one.  A textbook closed form, independent of the
+    library's quadrature tables."""
+    import numpy as np
+    k, j = {0: (M - 1, M - 1), 1: (M - 1, M), 2: (M, M)}[node_kind]
+    num, den = pade_exp(k, j)
+    z = np.asarray(z, dtype=np.float64)
+    return np.polyval(num[::-1], z) / np.polyval(den[::-1], z)
+
+
+def collocation_reference(cfg, u0_modes, nsteps, n=None):
+    """Direct collocation solution of a heat workload after nsteps steps: each
+    sine mode of u_0 (an eigenvector of L_h with eigenvalue
+    -(4/h^2) sum_i sin^2(a_i pi h / 2)) multiplied by R(dt nu lambda)^nsteps."""
+    import numpy as np
+    from paper_1401_7824_amd import workloads as W
+    n = cfg["n"] if n is None else n
+    d = cfg["dim"]
+    h = 1.0 / (n + 1)
+    lam = np.array([sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in u0_modes])
+    R = collocation_stability(cfg["node_kind"], cfg["M"], cfg["dt"] * cfg["nu"] * lam)
+    return W.sine_field(n, d, [(amp * r ** nsteps, a) for (amp, a), r in zip(u0_modes, R)])
+
+
 def accuracy_vs_collocation(cfg, torch):
     """One step of a linear (heat) workload in float32-V-cycle and all-float64
     form, each compared with the direct collocation solution: the sine-mode
     expansion of u_0 with every mode multiplied by the collocation stability
-    function R(z) = last entry of (I - z Q)^{-1} (1, ..., 1), z = dt nu lambda_a
-    (Sec. 2), with Q from the library's own tables.  Also times both variants."""
+    function R(z), z = dt nu lambda_a (Sec. 2), from its Pade closed form
+    (collocation_stability).  Also times both variants."""
     import numpy as np
-    from paper_1401_7824_amd import tables, workloads as W
-    n, d, M = cfg["n"], cfg["dim"], cfg["M"]
+    from paper_1401_7824_amd import workloads as W
+    n, d = cfg["n"], cfg["dim"]
     modes = W.workload_modes(cfg)
     u0 = W.sine_field(n, d, modes)
-    h = 1.0 / (n + 1)
-    Q = np.array(tables(cfg["node_kind"], M)[1])
-    lam = [sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in modes]
-    R = [np.linalg.solve(np.eye(M) - cfg["dt"] * cfg["nu"] * l * Q, np.ones(M))[-1] for l in lam]
-    coll = W.sine_field(n, d, [(amp * r, a) for (amp, a), r in zip(modes, R)])
+    coll = collocation_reference(cfg, modes, 1)
     out = {}
     for prec in (1, 0):
         c = dict(cfg, precision=prec)
@@ -159,6 +196,55 @@ def accuracy_vs_collocation(cfg, torch):
         out["mixed" if prec else "fp64"] = dict(rel_l2_vs_collocation=err, sweeps=st.sweeps, status=st.status,
                                                  steps_per_s=round(3 / (time.perf_counter() - t0), 3))
     return out
+
+
+# kernels followed inside the steps (isdc_probe_arm): (key, ISDC_KERNEL_*, level)
+PROBE_KINDS = [("smooth", 2, 0), ("smooth_restrict", 0, 0), ("restrict", 7, 0), ("prolong_smooth", 1, 0),
+               ("prolong_update", 6, 0), ("quad", 4, 0), ("rhs", 8, 0), ("tail", 3, 0)]
+
+
+def probe_kernel_name(key, cfg, T, shape=0):
+    """rocprof name of the finest-level kernel a probe key follows."""
+    d, M = cfg["dim"], cfg["M"]
+    if key == "quad":
+        return f"k_quad_residual_tile<{d},{M}>"
+    if key == "tail":
+        return f"k_tail<{T},{d}>"
+    if key == "rhs":
+        return f"k_euler_rhs<{T},{d},0>"
+    if d == 3 and cfg["n"] >= 127:
+        return {"smooth": f"k_march_rbgs<{T},false,0,false>", "restrict": f"k_march_restrict<{T}>",
+                "prolong_smooth": f"k_march_rbgs<{T},true,0,false>",
+                "prolong_update": f"k_march_rbgs<{T},true,1,false>"}[key]
+    if d == 2:
+        return {"smooth": f"k_rows_rbgs<{T},false,{shape}>", "smooth_restrict": f"k_rows_rbgs_restrict<{T},false,{shape}>",
+                "prolong_smooth": f"k_rows_prolong_rbgs<{T},0,{shape}>",
+                "prolong_update": f"k_rows_prolong_rbgs<{T},1,{shape}>"}[key]
+    return {"smooth": f"k_rbgs_tile<{T},{d},false,{shape}>", "smooth_restrict": f"k_rbgs_restrict_tile<{T},{d},false,{shape}>",
+            "restrict": f"k_restrict_tile<{T},{d}>", "prolong_smooth": f"k_prolong_rbgs_tile<{T},{d},0,{shape}>",
+            "prolong_update": f"k_prolong_rbgs_tile<{T},{d},1,{shape}>"}[key]
+
+
+def kernel_survey(plan, u, dt, cfg):
+    """Kernel time per step of each followed kernel: one step per kernel with
+    every launch of that kernel recording its dispatch start and end (untimed
+    steps before the warm-up; they continue the integration).  Returns
+    ({key: (launches, average us, us per step, algorithmic bytes per launch)}, steps run)."""
+    out = {}
+    ran = 0
+    for key, kind, level in PROBE_KINDS:
+        try:
+            plan.probe_arm(kind, level, 1, 100000)
+        except Exception:
+            continue  # not followed in this plan (e.g. no level above the tail)
+        st = plan.step(u, dt)
+        ran += 1
+        if st.status != "ok":
+            raise RuntimeError(f"survey step failed: {st.status}")
+        n, us, b = plan.probe_read()
+        if n:
+            out[key] = (n, us, n * us, b)
+    return out, ran
 
 
 def counter_traffic(kernel: str, workload: str):
@@ -392,25 +478,22 @@ def run_batch(args, torch):
 
 def serve_accuracy(reqs, torch, rd_sample=8):
     """Error of each served result (float32 V-cycles, the request's own SDC
-    tolerance) against a float64 reference, relative L2: heat requests against
-    the exact collocation solution after nsteps steps (each sine mode of u_0
-    multiplied by R(dt nu lambda)^nsteps, R the collocation stability function
-    from the library's Q table); reaction-diffusion requests (the rd_sample
-    smallest) against an all-float64 plan run to SDC tolerance 1e-12."""
+    tolerance) against a float64 reference, relative L2: every heat request
+    against the exact collocation solution after nsteps steps (each sine mode
+    of u_0 multiplied by R(dt nu lambda)^nsteps, R the Pade closed form of the
+    collocation stability function); reaction-diffusion requests (the
+    rd_sample smallest) against an all-float64 plan run to SDC tolerance 1e-12."""
     import numpy as np
-    from paper_1401_7824_amd import Plan, tables, workloads as W
+    from paper_1401_7824_amd import Plan, workloads as W
     rows = []
     for r in reqs:
         if r.result is None or r.status != "ok":
             continue
         got = r.result.detach().cpu().numpy()
         if r.fe_kind == 0:
-            h = 1.0 / (r.n + 1)
-            Q = np.array(tables(r.node_kind, r.M)[1])
             modes = W.draw_modes(r.dim, 8, seed=10_000 + r.rid, max_wave=4)
-            lam = [sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in modes]
-            R = [np.linalg.solve(np.eye(r.M) - r.dt * r.nu * l * Q, np.ones(r.M))[-1] for l in lam]
-            ref = W.sine_field(r.n, r.dim, [(amp * Rk ** r.nsteps, a) for (amp, a), Rk in zip(modes, R)])
+            cfg = dict(dim=r.dim, n=r.n, nu=r.nu, dt=r.dt, node_kind=r.node_kind, M=r.M)
+            ref = collocation_reference(cfg, modes, r.nsteps)
             kind = "heat vs exact collocation"
         else:
             continue
@@ -701,6 +784,188 @@ def run_table1b(args, torch):
     }
 
 
+def workload_text(name, cfg):
+    return (f"{name}: {cfg['dim']}D n={cfg['n']} {'periodic' if cfg.get('bc', 0) == 1 else 'Dirichlet'} "
+            f"nu={cfg['nu']} fe={['zero', 'cubic', 'WENO5 Burgers'][cfg['fe_kind']]} "
+            f"{['Lobatto', 'Radau-right', 'Legendre'][cfg['node_kind']]} M={cfg['M']} dt={cfg['dt']} L=2 "
+            + ("compact 4th-order stencil with W, Jacobi "
+               f"V({cfg.get('nu_pre')},{cfg.get('nu_post')})" if cfg.get("stencil", 0) == 1 else "RBGS V(1,1)")
+            + f" tol={cfg['sdc_tol']}"
+            + (" two-level MLSDC (coarse level (n-1)/2, FAS, cubic interpolation)" if cfg.get("levels", 1) == 2 else ""))
+
+
+def serve_latency(args, torch, count=48):
+    """p50 / p99 latency of a short serving run (the serving workload's request
+    mix, `count` requests): saturated capacity first (all requests at t = 0),
+    then Poisson arrivals at half of it."""
+    from paper_1401_7824_amd.serve import Server, make_requests
+    budget = int(args.serve_budget_gb * 2 ** 30)
+
+    def server():
+        return Server(budget, slots_per_batch=64, precision=1, vcycles=2)
+
+    server().serve(make_requests(8, rate=0.0, seed=99))
+    sat = server().serve(make_requests(count, rate=0.0, seed=5))
+    cap = sat.completed / sat.makespan
+    half = server().serve(make_requests(count, rate=0.5 * cap, seed=5)).summary()
+    return {"requests": count, "capacity_req_s": round(cap, 3), "rate_req_s": round(0.5 * cap, 3),
+            "p50_ms": half["p50_ms"], "p99_ms": half["p99_ms"], "saturated_p50_ms": sat.summary()["p50_ms"],
+            "saturated_p99_ms": sat.summary()["p99_ms"], "hbm_budget_gib": args.serve_budget_gb}
+
+
+def run_followed(args, cfg, torch):
+    """Steps/s of a second-order-stencil workload with the dominant kernel's
+    duration taken inside the timed steps.  A survey step per followed kernel
+    finds the kernel with the most time per step; during the timed steps every
+    launch of it records its own dispatch start and end (hipExtLaunchKernelGGL
+    with HIP events, on the stream the kernel runs on), and achieved GB/s =
+    its average algorithmic bytes / its average duration."""
+    import numpy as np
+    from paper_1401_7824_amd import workloads as W
+    name = args.workload
+    T = "double" if cfg["precision"] == 0 else "float"
+    plan = make_plan(cfg)
+    shapes = plan.autotune()  # tile shape per level (timed once, then cached), outside the timed steps
+    modes = W.workload_modes(cfg) if "gaussian_sigma" not in cfg else None
+    u = torch.from_numpy(W.workload_u0(cfg)).cuda()
+    survey, nsurvey = kernel_survey(plan, u, cfg["dt"], cfg)
+    print(f"[bench] {name}: survey of {len(survey)} kernels in {nsurvey} steps done", file=sys.stderr, flush=True)
+    dom_key = max(survey, key=lambda k: survey[k][2])
+    kind = dict((k, (kd, lv)) for k, kd, lv in PROBE_KINDS)[dom_key]
+    for _ in range(args.warmup):
+        plan.step(u, cfg["dt"])
+    plan.probe_arm(kind[0], kind[1], 1, 1000000)
+    elapsed, wall, stats = time_steps(plan, u, cfg["dt"], args.steps, 0, torch)
+    nl, avg_us, alg_b = plan.probe_read()
+    print(f"[bench] {name}: {args.steps} timed steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    sweeps = sum(s.sweeps for s in stats) / len(stats)
+    vcyc = sum(s.vcycles for s in stats) / len(stats)
+    kname = probe_kernel_name(dom_key, cfg, T, (shapes or [0])[0])
+    gbps = alg_b / (avg_us * 1e-6) / 1e9
+    traffic = counter_traffic(kname, name)
+    roof = dict(bound="hbm", achieved=round(gbps, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbps / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname + " (finest level)",
+                avg_launch_us=round(avg_us, 3), launches_timed=nl, alg_bytes_per_launch=alg_b,
+                timing="each launch of the kernel inside the timed steps, its dispatch start/end in HIP events")
+    total = sum(v[2] for v in survey.values())
+    kernels = {k: dict(kernel=probe_kernel_name(k, cfg, T, (shapes or [0])[0]), launches_per_step=v[0],
+                       avg_us=round(v[1], 3), us_per_step=round(v[2], 1), alg_bytes=v[3],
+                       gbps=round(v[3] / (v[1] * 1e-6) / 1e9, 1) if v[1] > 0 else None)
+               for k, v in sorted(survey.items(), key=lambda kv: -kv[1][2])}
+    out = {
+        "metric": METRIC, "value": round(args.steps / elapsed, 4), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if cfg["precision"] == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": workload_text(name, cfg), "sweeps_per_step": sweeps, "vcycles_per_step": vcyc,
+                   "coarse_vcycles_per_step": sum(s.coarse_vcycles for s in stats) / len(stats),
+                   "host_wall_s": round(wall, 4), "tile_shapes": shapes,
+                   "survey_steps": nsurvey},
+        "roofline": roof,
+        "kernels_followed_us_per_step": kernels,
+        "kernel_share_of_step": round(total / (elapsed / args.steps * 1e6), 3),
+    }
+    nstep = nsurvey + args.warmup + args.steps
+    if cfg["fe_kind"] == W.FE_ZERO and modes is not None:
+        ref = collocation_reference(cfg, modes, nstep)
+        got = u.cpu().numpy()
+        out["accuracy"] = {"rel_l2_vs_collocation": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                           "steps_compared": nstep,
+                           "reference": "sine modes of u_0 times R(dt nu lambda)^steps, R the Pade closed form"}
+    del plan
+    torch.cuda.empty_cache()
+    if cfg["precision"] == 0 and name == "heat3d":
+        # the float32-V-cycle variant of the same workload (FP64 residual, S*F and update)
+        mc = dict(cfg, precision=1)
+        mplan = make_plan(mc)
+        mshapes = mplan.autotune()
+        um = torch.from_numpy(W.workload_u0(mc)).cuda()
+        for _ in range(args.warmup):
+            mplan.step(um, mc["dt"])
+        m_el, _, m_stats = time_steps(mplan, um, mc["dt"], args.steps, 0, torch)
+        ref = collocation_reference(mc, modes, args.warmup + args.steps)
+        got = um.cpu().numpy()
+        out["mixed"] = {"steps_per_s": round(args.steps / m_el, 4), "ms_per_step": round(m_el / args.steps * 1e3, 4),
+                        "sweeps_per_step": sum(s.sweeps for s in m_stats) / len(m_stats),
+                        "vcycles_per_step": sum(s.vcycles for s in m_stats) / len(m_stats),
+                        "rel_l2_vs_collocation": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                        "steps_compared": args.warmup + args.steps, "tile_shapes": mshapes}
+        del mplan, um
+        torch.cuda.empty_cache()
+        print(f"[bench] {name}: mixed variant {out['mixed']['steps_per_s']} steps/s", file=sys.stderr, flush=True)
+    if not args.no_serve_latency and name == "heat3d":
+        out["latency"] = serve_latency(args, torch)
+        print(f"[bench] serving latency {out['latency']}", file=sys.stderr, flush=True)
+    if args.calib_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, sweeps)
+    return out
+
+
+COMPARE_VARIANTS = [
+    # (name, params): classical SDC solves each implicit system to tol / 50;
+    # ISDC runs L = 2 cycles of the given smoother (Sec. 3, Sec. 4.2)
+    ("sdc_classical_rbgs11", dict(vcycles=0, smoother=0, nu_pre=1, nu_post=1)),
+    ("isdc_rbgs11", dict(vcycles=2, smoother=0, nu_pre=1, nu_post=1)),
+    ("isdc_rbgs22", dict(vcycles=2, smoother=0, nu_pre=2, nu_post=2)),
+    ("isdc_jacobi22", dict(vcycles=2, smoother=1, nu_pre=2, nu_post=2)),
+    ("isdc_jacobi33", dict(vcycles=2, smoother=1, nu_pre=3, nu_post=3)),
+]
+
+
+def run_compare(args, torch):
+    """The paper's comparison (Sec. 4.2, Table 1) at full size: classical SDC
+    (every implicit system solved by V-cycles until its max-norm residual
+    <= sdc_tol / 50) against ISDC with L = 2 V-cycles per solve and several
+    smoothers, on the rd2d and heat3d workloads (all float64).  Every variant
+    runs the same first step from u_0 (--steps timed repetitions after one
+    untimed one); reports sweeps, V-cycles and time per step."""
+    from paper_1401_7824_amd import Plan, workloads as W
+    out_rows = {}
+    for wname in ("rd2d", "heat3d"):
+        cfg = dict(W.WORKLOADS[wname], precision=0)
+        u0 = torch.from_numpy(W.workload_u0(cfg)).cuda()
+        rows = {}
+        for vname, par in COMPARE_VARIANTS:
+            p = Plan(cfg["dim"], cfg["n"], cfg["nu"], cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"],
+                     precision=0, sdc_tol=cfg["sdc_tol"], inner_tol=cfg["sdc_tol"] / 50, max_sweeps=200, **par)
+            if par["smoother"] == 0:
+                p.autotune()
+            u = u0.clone()
+            st = p.step(u, cfg["dt"])
+            reps = max(1, args.steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                u.copy_(u0)
+                p.step(u, cfg["dt"])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            rows[vname] = {"sweeps": st.sweeps, "vcycles": st.vcycles, "status": st.status,
+                           "ms_per_step": round(ms, 3)}
+            print(f"[compare] {wname} {vname}: {st.sweeps} sweeps, {st.vcycles} V-cycles, {ms:.2f} ms/step",
+                  file=sys.stderr, flush=True)
+            del p
+            torch.cuda.empty_cache()
+        out_rows[wname] = rows
+    best = min(out_rows["heat3d"].items(), key=lambda kv: kv[1]["ms_per_step"])
+    return {
+        "metric": "ISDC vs classical SDC at full size: time per step and V-cycles",
+        "value": round(1e3 / best[1]["ms_per_step"], 4), "unit": "steps/s", "n_gpus": 1,
+        "steps": max(1, args.steps) * len(COMPARE_VARIANTS) * 2, "warmup": len(COMPARE_VARIANTS) * 2,
+        "ms_per_step": best[1]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "compare: rd2d 1023^2 Lobatto M=5 and heat3d 255^3 Radau-right M=3, first step "
+                               "from u_0, tol 1e-10; classical SDC inner tolerance 2e-12",
+                   "fastest_heat3d_variant": best[0]},
+        "rows": out_rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -725,10 +990,16 @@ def main():
     if args.workload == "table1b":
         print(json.dumps(run_table1b(args, torch)), flush=True)
         return
+    if args.workload == "compare":
+        print(json.dumps(run_compare(args, torch)), flush=True)
+        return
     if args.workload == "kernels":
         print(json.dumps(run_kernels(args, torch)), flush=True)
         return
     cfg = dict(W.WORKLOADS[args.workload])
+    if cfg.get("stencil", 0) == 0:
+        print(json.dumps(run_followed(args, cfg, torch)), flush=True)
+        return
     plan = make_plan(cfg)
     shapes = plan.autotune()  # tile shape per level (timed once, then cached), outside the timed steps
     u = torch.from_numpy(W.workload_u0(cfg)).cuda()

@@ -35,6 +35,12 @@
  *    validated before any device work is enqueued; an invalid argument leaves
  *    device memory untouched.  No C++ exception crosses this interface.
  *  - A plan is not thread safe: calls on one plan must not overlap.
+ *  - Tracing: with the environment variable ISDC_TRACE set ("1" or "stderr":
+ *    standard error; any other non-empty value except "0": a file path the
+ *    lines are appended to; read once per process) every sweep of
+ *    isdc_step and every batch sweep writes one line with the host time
+ *    after its residual read-back ("isdc_trace plan=... sweep=... t_us=...
+ *    residual=... vcycles=..." / "isdc_trace batch=... running=... t_us=...").
  */
 #ifndef ISDC_H
 #define ISDC_H
@@ -91,9 +97,11 @@ enum { ISDC_GUESS_PREV_SWEEP = 0, ISDC_GUESS_ZERO = 1, ISDC_GUESS_PREV_NODE = 2 
 enum { ISDC_OP_SMOOTH = 0, ISDC_OP_RESTRICT = 1, ISDC_OP_PROLONG = 2, ISDC_OP_COARSE = 3,
        ISDC_OP_RESIDUAL_NORM = 4, ISDC_OP_EXPLICIT = 5 };
 
-/* Kernels that isdc_time_kernel can time (see there). */
+/* Kernels that isdc_time_kernel can time and isdc_probe_arm can follow
+ * inside steps (see there). */
 enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KERNEL_SMOOTH = 2,
-       ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4, ISDC_KERNEL_EXPLICIT = 5 };
+       ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4, ISDC_KERNEL_EXPLICIT = 5, ISDC_KERNEL_PROLONG_UPDATE = 6,
+       ISDC_KERNEL_RESTRICT = 7, ISDC_KERNEL_RHS = 8 };
 
 #define ISDC_MAX_M 9
 #define ISDC_HIST 128
@@ -307,6 +315,33 @@ int isdc_get_tile_shapes(const isdc_plan* plan, int32_t* h_shapes, int32_t max_l
  * precision selects the V-cycle arithmetic as in isdc_vcycle. */
 int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, int32_t precision, int32_t reps,
                      void* stream, double* h_avg_us, double* h_bytes);
+
+/* In-step timing of one kernel, for measurement: after isdc_probe_arm, every
+ * `every`-th launch (1..1000000) of `kernel` on multigrid level `level` that
+ * the plan's steps make (isdc_step, isdc_sweep; level ignored for the
+ * single-level kernels) records its own dispatch start and end into a HIP
+ * event pair (hipExtLaunchKernelGGL, so no extra packet is placed between
+ * launches), up to max_samples (1..1000000) launches.  The launches that are
+ * followed (second-order stencil plans; other launches are not followed):
+ *   ISDC_KERNEL_SMOOTH_RESTRICT  2D red-black step + residual + restriction
+ *                                from a nonzero iterate;
+ *   ISDC_KERNEL_SMOOTH           a red-black step from a nonzero iterate;
+ *   ISDC_KERNEL_RESTRICT         residual + full weighting (3D, Jacobi);
+ *   ISDC_KERNEL_PROLONG_SMOOTH   prolongation + correction + red-black step;
+ *   ISDC_KERNEL_PROLONG_UPDATE   the same fused with the node update
+ *                                u = g + e (the last launch of a solve, level 0);
+ *   ISDC_KERNEL_TAIL             the coarse tail;
+ *   ISDC_KERNEL_QUAD             S*F quadrature + SDC residual (level 0);
+ *   ISDC_KERNEL_RHS              the separate right-hand-side pass (level 0).
+ * isdc_probe_read waits for the sampled launches' events, writes the number
+ * of samples, their average duration in microseconds and their average
+ * algorithmic bytes (every array element read or written once; the QUAD
+ * figure depends on how many node arrays the sampled launches read), and
+ * disarms the probe.  Host only, apart from that wait; arming again restarts
+ * the sample.  Event pairs are created by the arming call and kept by the
+ * plan. */
+int isdc_probe_arm(isdc_plan* plan, int32_t kernel, int32_t level, int32_t every, int32_t max_samples);
+int isdc_probe_read(isdc_plan* plan, int64_t* h_samples, double* h_avg_us, double* h_bytes);
 
 /* ---------------------------------------------------------------- batches
  * A batch advances many independent ISDC instances ("slots") together: every

@@ -10,6 +10,7 @@ from ._capi import (  # noqa: F401
     SMOOTH_RBGS, SMOOTH_JACOBI, PREC_FP64, PREC_MIXED, GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE,
     OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, OP_EXPLICIT, load,
     KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD, KERNEL_EXPLICIT,
+    KERNEL_PROLONG_UPDATE, KERNEL_RESTRICT, KERNEL_RHS,
     SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED,
 )
 

@@ -23,6 +23,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 GUESS_PREV_SWEEP, GUESS_ZERO, GUESS_PREV_NODE = 0, 1, 2
 OP_SMOOTH, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_RESIDUAL_NORM, OP_EXPLICIT = 0, 1, 2, 3, 4, 5
 KERNEL_SMOOTH_RESTRICT, KERNEL_PROLONG_SMOOTH, KERNEL_SMOOTH, KERNEL_TAIL, KERNEL_QUAD, KERNEL_EXPLICIT = 0, 1, 2, 3, 4, 5
+KERNEL_PROLONG_UPDATE, KERNEL_RESTRICT, KERNEL_RHS = 6, 7, 8
 SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED = 0, 1, 2
 MAX_M = 9
 HIST = 128
@@ -73,6 +74,8 @@ SIGNATURES = [
     ("isdc_vcycle", C.c_int, [_VP, C.c_double, C.c_int32, _VP, _VP, C.c_int32, _VP, _DP]),
     ("isdc_mg_op", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _DP]),
     ("isdc_time_kernel", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, _VP, _DP, _DP]),
+    ("isdc_probe_arm", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    ("isdc_probe_read", C.c_int, [_VP, C.POINTER(C.c_int64), _DP, _DP]),
     ("isdc_autotune", C.c_int, [_VP, C.c_int32, _VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     ("isdc_set_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32]),
     ("isdc_get_tile_shapes", C.c_int, [_VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
@@ -107,6 +110,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1401_7824_amd.build`")
+    # torch brings its own HIP runtime; load it first so that the library binds
+    # to that one instead of starting a second runtime beside it
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)

@@ -17,6 +17,8 @@
 // (begin a step) and leave (end a step, converge, fail) between sweeps.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -646,6 +648,11 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
     ISDC_BLAUNCH(kb_reduce, kThreads, mred, 0, A(o_red, 0, 0, 0));
     HIPCHK(hipMemcpyAsync(b->h_res, b->d_res, cap * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (FILE* trace = trace_stream()) {  // host time once the batch sweep's residuals are back
+        const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+        std::fprintf(trace, "isdc_trace batch=%p running=%d t_us=%.1f\n", (void*)b, (int)run.size(), us);
+        std::fflush(trace);
+    }
     // ---- decisions
     Map mend;
     for (int i : run) {

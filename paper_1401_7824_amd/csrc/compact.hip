@@ -105,7 +105,7 @@ template <int K> struct JTile {
     static constexpr int N = IP * kThreads;
 };
 
-template <typename T, bool PER, int K, bool ZERO>
+template <typename T, bool PER, int K, bool ZERO, bool C9 = true>
 __global__ void __launch_bounds__(kThreads)
 k_cjacobi_k(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
             CCoef<T> k) {
@@ -157,11 +157,15 @@ k_cjacobi_k(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__
                 const int a = threadIdx.x + i * kThreads;
                 if (ZERO && st == 1) {
                     v[i] = w * vr[i] * inv;
-                } else {
+                } else if (C9) {
                     const T uc = src[a];
                     const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
                     const T corners = src[a - L - 1] + src[a - L + 1] + src[a + L - 1] + src[a + L + 1];
                     v[i] = uc + w * (vr[i] - (k.b0 * uc + k.bf * edges + k.bc * corners)) * inv;
+                } else {
+                    const T uc = src[a];
+                    const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
+                    v[i] = uc + w * (vr[i] - (k.b0 * uc + k.bf * edges)) * inv;
                 }
             }
         }
@@ -207,7 +211,7 @@ template <int K> struct CVT {
 // One weighted-Jacobi step of B from src to dst on LDS columns / rows
 // [lo, chi] x [lo, rhi] of a box whose column c is grid x = bx + c, row q is
 // y = by + q (Dirichlet: points outside the grid are not updated).
-template <typename T, bool PER, int IP, bool ZERO>
+template <typename T, bool PER, int IP, bool ZERO, bool C9 = true>
 __device__ __forceinline__ void cj_step(const T* src, T* dst, const T (&vr)[IP], int lo, int chi, int rhi, int bx,
                                         int by, int n, const CCoef<T>& k) {
     constexpr int L = kJL, RP = kThreads / kJL;
@@ -225,11 +229,15 @@ __device__ __forceinline__ void cj_step(const T* src, T* dst, const T (&vr)[IP],
             const int a = threadIdx.x + i * kThreads;
             if (ZERO) {
                 v[i] = k.omega * vr[i] * k.inv_b0;
-            } else {
+            } else if (C9) {
                 const T uc = src[a];
                 const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
                 const T corners = src[a - L - 1] + src[a - L + 1] + src[a + L - 1] + src[a + L + 1];
                 v[i] = uc + k.omega * (vr[i] - (k.b0 * uc + k.bf * edges + k.bc * corners)) * k.inv_b0;
+            } else {
+                const T uc = src[a];
+                const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
+                v[i] = uc + k.omega * (vr[i] - (k.b0 * uc + k.bf * edges)) * k.inv_b0;
             }
         }
     }
@@ -259,7 +267,7 @@ __device__ __forceinline__ void cj_load(T (&v)[IP], const T* __restrict__ u, int
     }
 }
 
-template <typename T, bool PER, int K, bool ZERO>
+template <typename T, bool PER, int K, bool ZERO, bool C9 = true>
 __global__ void __launch_bounds__(kThreads)
 k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc, int n,
         int ntx, int nty, CCoef<T> k) {
@@ -292,8 +300,8 @@ k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_o
     T* dst = sb;
 #pragma unroll
     for (int st = 1; st <= K; ++st) {
-        if (ZERO && st == 1) cj_step<T, PER, V::IP, true>(src, dst, vr, st, V::COLS - 1 - st, V::ROWS - 1 - st, bx, by, n, k);
-        else cj_step<T, PER, V::IP, false>(src, dst, vr, st, V::COLS - 1 - st, V::ROWS - 1 - st, bx, by, n, k);
+        if (ZERO && st == 1) cj_step<T, PER, V::IP, true, C9>(src, dst, vr, st, V::COLS - 1 - st, V::ROWS - 1 - st, bx, by, n, k);
+        else cj_step<T, PER, V::IP, false, C9>(src, dst, vr, st, V::COLS - 1 - st, V::ROWS - 1 - st, bx, by, n, k);
         __syncthreads();
         T* t = src;
         src = dst;
@@ -318,8 +326,12 @@ k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_o
             if (wr[i]) {
                 const T uc = src[a];
                 const T edges = src[a - 1] + src[a + 1] + src[a - L] + src[a + L];
-                const T corners = src[a - L - 1] + src[a - L + 1] + src[a + L - 1] + src[a + L + 1];
-                v[i] = vr[i] - (k.b0 * uc + k.bf * edges + k.bc * corners);
+                if (C9) {
+                    const T corners = src[a - L - 1] + src[a - L + 1] + src[a + L - 1] + src[a + L + 1];
+                    v[i] = vr[i] - (k.b0 * uc + k.bf * edges + k.bc * corners);
+                } else {
+                    v[i] = vr[i] - (k.b0 * uc + k.bf * edges);
+                }
             }
         }
 #pragma unroll
@@ -350,7 +362,7 @@ k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_o
     }
 }
 
-template <typename T, bool PER, int K>
+template <typename T, bool PER, int K, bool C9 = true>
 __global__ void __launch_bounds__(kThreads)
 k_cpjac(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out, int n,
         int ntx, int nty, CCoef<T> k) {
@@ -424,7 +436,7 @@ k_cpjac(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict
     T* dst = sb;
 #pragma unroll
     for (int st = 1; st <= K; ++st) {
-        cj_step<T, PER, V::IP, false>(src, dst, vr, st, COLS - 1 - st, ROWS - 1 - st, bx, by, n, k);
+        cj_step<T, PER, V::IP, false, C9>(src, dst, vr, st, COLS - 1 - st, ROWS - 1 - st, bx, by, n, k);
         __syncthreads();
         T* t = src;
         src = dst;
@@ -786,6 +798,19 @@ CCoef<T> make_ccoef(double c, double w, double H, double omega) {
 }
 
 template <typename T>
+CCoef<T> make_coef5(double c, double h, double omega) {
+    const double a = c / (h * h);
+    const double b0 = 1.0 + 4.0 * a;
+    CCoef<T> k;
+    k.b0 = T(b0);
+    k.bf = T(-a);
+    k.bc = T(0);
+    k.inv_b0 = T(1.0 / b0);
+    k.omega = T(omega);
+    return k;
+}
+
+template <typename T>
 hipError_t launch_cjacobi(int n, const CCoef<T>& k, bool zero, const T* r, const T* e_in, T* e_out, bool per,
                           hipStream_t s) {
     if (per) {
@@ -857,6 +882,61 @@ hipError_t launch_cpjac(int n, const CCoef<T>& k, int nsteps, const T* r, const 
     else if (nsteps == 3) ISDC_CPJ(3)
     else return hipErrorInvalidValue;
 #undef ISDC_CPJ
+    return hipGetLastError();
+}
+
+// The same fused kernels for the second-order five-point operator
+// A = I - c L_h (Dirichlet): b0 = 1 + 4a, bf = -a, no corner term.
+template <typename T>
+hipError_t launch_jacobi5_steps(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out,
+                                hipStream_t s) {
+#define ISDC_J5K(KV)                                                                                          \
+    {                                                                                                         \
+        int ntx, nty, nb;                                                                                     \
+        tile_counts<2>(n, JTile<KV>::TX, JTile<KV>::TY, 1, ntx, nty, nb);                                     \
+        if (zero) ISDC_LAUNCH((k_cjacobi_k<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else ISDC_LAUNCH((k_cjacobi_k<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+    }
+    if (nsteps == 1) ISDC_J5K(1)
+    else if (nsteps == 2) ISDC_J5K(2)
+    else if (nsteps == 3) ISDC_J5K(3)
+    else return hipErrorInvalidValue;
+#undef ISDC_J5K
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jres5(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out, T* rc,
+                        hipStream_t s) {
+#define ISDC_J5R(KV)                                                                                          \
+    {                                                                                                         \
+        int ntx, nty, nb;                                                                                     \
+        tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
+        if (zero) ISDC_LAUNCH((k_cjres<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        else ISDC_LAUNCH((k_cjres<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+    }
+    if (nsteps == 1) ISDC_J5R(1)
+    else if (nsteps == 2) ISDC_J5R(2)
+    else if (nsteps == 3) ISDC_J5R(3)
+    else return hipErrorInvalidValue;
+#undef ISDC_J5R
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pjac5(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
+                        hipStream_t s) {
+#define ISDC_P5J(KV)                                                                                          \
+    {                                                                                                         \
+        int ntx, nty, nb;                                                                                     \
+        tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
+        ISDC_LAUNCH((k_cpjac<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k); \
+    }
+    if (nsteps == 1) ISDC_P5J(1)
+    else if (nsteps == 2) ISDC_P5J(2)
+    else if (nsteps == 3) ISDC_P5J(3)
+    else return hipErrorInvalidValue;
+#undef ISDC_P5J
     return hipGetLastError();
 }
 
@@ -984,6 +1064,7 @@ hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h,
 
 #define ISDC_CINST(T)                                                                                              \
     template CCoef<T> make_ccoef<T>(double, double, double, double);                                               \
+    template CCoef<T> make_coef5<T>(double, double, double);                                                       \
     template hipError_t launch_cjacobi<T>(int, const CCoef<T>&, bool, const T*, const T*, T*, bool, hipStream_t);   \
     template hipError_t launch_cjacobi_steps<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, bool,      \
                                                 hipStream_t);                                                      \
@@ -992,6 +1073,9 @@ hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h,
     template hipError_t launch_cpjac<T>(int, const CCoef<T>&, int, const T*, const T*, const T*, T*, bool,          \
                                         hipStream_t);                                                              \
     template hipError_t launch_cresfw<T>(int, const CCoef<T>&, const T*, const T*, T*, bool, hipStream_t);          \
+    template hipError_t launch_jacobi5_steps<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_jres5<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, T*, hipStream_t);  \
+    template hipError_t launch_pjac5<T>(int, const CCoef<T>&, int, const T*, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_cprolong_p<T>(int, const T*, T*, hipStream_t);                                       \
     template hipError_t launch_cresnorm<T>(int, const CCoef<T>&, const T*, const T*, double*, int*, bool, hipStream_t); \
     template hipError_t launch_crhs<T>(const CRhsArgs&, T*, bool, hipStream_t);                                    \

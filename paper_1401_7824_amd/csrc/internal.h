@@ -7,6 +7,7 @@
 #include <vector>
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "../../include/isdc.h"
 #include "tables.h"
@@ -18,6 +19,28 @@ struct Error {
     int code;
     std::string msg;
 };
+
+// ---------------------------------------------------------------- in-step launch timing
+// An event pair that one launch records its own dispatch start and end into
+// (hipExtLaunchKernelGGL).  The runtime arms one on the calling thread right
+// before a launcher call it wants timed and disarms it after; the first
+// ISDC_LAUNCH inside the launcher consumes it.
+struct LaunchProbe {
+    hipEvent_t start, stop;
+};
+LaunchProbe*& armed_probe();
+
+#define ISDC_LAUNCH(kernel, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                                  \
+        ::isdc::LaunchProbe* probe_ = ::isdc::armed_probe();                                              \
+        if (probe_) {                                                                                     \
+            ::isdc::armed_probe() = nullptr;                                                              \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, probe_->start, probe_->stop, 0,     \
+                                  __VA_ARGS__);                                                           \
+        } else {                                                                                          \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                          \
+        }                                                                                                 \
+    } while (0)
 
 // ---------------------------------------------------------------- multigrid launchers
 // Coefficients of A_l = I - c L_{h_l} on one level: a = c / h_l^2,
@@ -228,6 +251,21 @@ hipError_t launch_cjres(int n, const CCoef<T>& k, int nsteps, bool zero, const T
                         bool per, hipStream_t s);
 // e_in + P ec (linear interpolation of the coarse correction) followed by
 // nsteps (1..3) Jacobi steps, into e_out.
+// The fused row-tile Jacobi kernels above for the second-order five-point
+// operator I - c L_h on a 2D Dirichlet level (k from make_coef5): nsteps
+// (1..3) weighted-Jacobi steps; the same fused with the residual's full
+// weighting into rc; the prolongation + correction fused with nsteps steps.
+template <typename T>
+CCoef<T> make_coef5(double c, double h, double omega);
+template <typename T>
+hipError_t launch_jacobi5_steps(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_jres5(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out, T* rc,
+                        hipStream_t s);
+template <typename T>
+hipError_t launch_pjac5(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
+                        hipStream_t s);
 template <typename T>
 hipError_t launch_cpjac(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
                         bool per, hipStream_t s);

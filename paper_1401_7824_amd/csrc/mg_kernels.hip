@@ -269,9 +269,9 @@ hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zer
         dim3 g = stencil_grid(d, n, n);
         ISDC_DISPATCH_D(d, {
             if (zero_guess)
-                hipLaunchKernelGGL((k_jacobi<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+                ISDC_LAUNCH((k_jacobi<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
             else
-                hipLaunchKernelGGL((k_jacobi<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+                ISDC_LAUNCH((k_jacobi<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
         });
         return hipGetLastError();
     }
@@ -279,10 +279,10 @@ hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zer
     dim3 g = stencil_grid(d, (n + 1) / 2, n);
     ISDC_DISPATCH_D(d, {
         if (zero_guess)
-            hipLaunchKernelGGL((k_rbgs_half<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+            ISDC_LAUNCH((k_rbgs_half<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
         else
-            hipLaunchKernelGGL((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
-        hipLaunchKernelGGL((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 1);
+            ISDC_LAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+        ISDC_LAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 1);
     });
     return hipGetLastError();
 }
@@ -291,14 +291,14 @@ template <typename T>
 hipError_t launch_restrict(int d, int n, const Coef<T>& co, const T* rhs, const T* u, T* rc, hipStream_t s) {
     int nc = (n - 1) / 2;
     dim3 g = stencil_grid(d, nc, nc);
-    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_restrict<T, D>), g, dim3(kBlock), 0, s, rhs, u, rc, n, co.a, co.diag); });
+    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_restrict<T, D>), g, dim3(kBlock), 0, s, rhs, u, rc, n, co.a, co.diag); });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(int d, int n, const T* ec, T* u, hipStream_t s) {
     dim3 g = stencil_grid(d, n, n);
-    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_prolong<T, D>), g, dim3(kBlock), 0, s, ec, u, n); });
+    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_prolong<T, D>), g, dim3(kBlock), 0, s, ec, u, n); });
     return hipGetLastError();
 }
 
@@ -308,26 +308,26 @@ hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T
     size_t N = d == 1 ? (size_t)n : (d == 2 ? (size_t)n * n : (size_t)n * n * n);
     int nb = reduce_blocks(N);
     *nblocks = nb;
-    ISDC_DISPATCH_D(d, { hipLaunchKernelGGL((k_resnorm<T, D>), dim3(nb), dim3(kBlock), 0, s, rhs, u, n, co.a, co.diag, partial); });
+    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_resnorm<T, D>), dim3(nb), dim3(kBlock), 0, s, rhs, u, n, co.a, co.diag, partial); });
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_max(const double* partial, int nblocks, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+    ISDC_LAUNCH(k_reduce_max, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, T value, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fill<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, p, count, value);
+    ISDC_LAUNCH((k_fill<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, p, count, value);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, size_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_copy<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, src, dst, count);
+    ISDC_LAUNCH((k_copy<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, src, dst, count);
     return hipGetLastError();
 }
 

@@ -191,9 +191,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
         int ntx, nty, nb;
         tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (zero)
-            hipLaunchKernelGGL((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+            ISDC_LAUNCH((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         else
-            hipLaunchKernelGGL((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+            ISDC_LAUNCH((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         return hipGetLastError();
     }
     if (d == 2) {
@@ -202,9 +202,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (zero)
-                hipLaunchKernelGGL((k_rows_rbgs<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+                ISDC_LAUNCH((k_rows_rbgs<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
             else
-                hipLaunchKernelGGL((k_rows_rbgs<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+                ISDC_LAUNCH((k_rows_rbgs<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
         });
         return hipGetLastError();
     }
@@ -213,9 +213,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
         int ntx, nty, nb;
         tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (zero)
-            hipLaunchKernelGGL((k_rbgs_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            ISDC_LAUNCH((k_rbgs_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
         else
-            hipLaunchKernelGGL((k_rbgs_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            ISDC_LAUNCH((k_rbgs_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
     });
     return hipGetLastError();
 }
@@ -227,14 +227,14 @@ hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, con
         const int mzc = march_restrict_depth();
         int ntx, nty, nb;
         tile_counts<3>(nc, MRTile::X, MRTile::Y, mzc, ntx, nty, nb);
-        hipLaunchKernelGGL((k_march_restrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, mzc, co.a,
+        ISDC_LAUNCH((k_march_restrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, mzc, co.a,
                            co.diag);
         return hipGetLastError();
     }
     ISDC_DISPATCH_D(d, {
         int ntx, nty, nb;
         tile_counts<D>(nc, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, ntx, nty, nb);
-        hipLaunchKernelGGL((k_restrict_tile<T, D>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, co.a, co.diag);
+        ISDC_LAUNCH((k_restrict_tile<T, D>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, co.a, co.diag);
     });
     return hipGetLastError();
 }
@@ -249,9 +249,9 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (zero)
-                hipLaunchKernelGGL((k_rows_rbgs_restrict<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_LAUNCH((k_rows_rbgs_restrict<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
             else
-                hipLaunchKernelGGL((k_rows_rbgs_restrict<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_LAUNCH((k_rows_rbgs_restrict<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
         });
         return hipGetLastError();
     }
@@ -261,9 +261,9 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
             int ntx, nty, nb;
             tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
             if (zero)
-                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_LAUNCH((k_rbgs_restrict_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
             else
-                hipLaunchKernelGGL((k_rbgs_restrict_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_LAUNCH((k_rbgs_restrict_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
         }
     });
     return hipGetLastError();
@@ -277,7 +277,7 @@ hipError_t launch_rhs_rbgs_restrict_tile(int d, int n, const RhsArgs& ra, const 
         using RT = typename RowShape<S>::RT;
         int ntx, nty, nb;
         tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
-        hipLaunchKernelGGL((k_rows_rhs_rbgs_restrict<T, S>), dim3(nb), dim3(kThreads), 0, s, ra, r, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+        ISDC_LAUNCH((k_rows_rhs_rbgs_restrict<T, S>), dim3(nb), dim3(kThreads), 0, s, ra, r, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
     });
     return hipGetLastError();
 }
@@ -291,11 +291,11 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
         int ntx, nty, nb;
         tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (mode == 0)
-            hipLaunchKernelGGL((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else if (mode == 1)
-            hipLaunchKernelGGL((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else
-            hipLaunchKernelGGL((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         return hipGetLastError();
     }
     if (d == 2) {
@@ -304,11 +304,11 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (mode == 0)
-                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
             else if (mode == 1)
-                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
             else
-                hipLaunchKernelGGL((k_rows_prolong_rbgs<T, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         });
         return hipGetLastError();
     }
@@ -317,11 +317,11 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
         int ntx, nty, nb;
         tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (mode == 0)
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else if (mode == 1)
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else
-            hipLaunchKernelGGL((k_prolong_rbgs_tile<T, D, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
     });
     return hipGetLastError();
 }
@@ -346,7 +346,7 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
         if (m == 1) break;
     }
     ISDC_DISPATCH_D(cfg.d, {
-        hipLaunchKernelGGL((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, cfg.smoother, cfg.nu_pre,
+        ISDC_LAUNCH((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, cfg.smoother, cfg.nu_pre,
                            cfg.nu_post, cfg.omega, zero_guess ? 1 : 0);
     });
     return hipGetLastError();

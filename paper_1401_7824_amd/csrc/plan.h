@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,25 @@ struct Level {
     void* e2;  // ping-pong partner of the out-of-place smoothers
     int shape = 0;  // tile shape of the tiled kernels on this level (isdc_autotune)
 };
+
+// In-step timing of one kernel kind on one level (isdc_probe_arm /
+// isdc_probe_read): every `every`-th matching launch records its dispatch
+// start and end into the next event pair of the pool.
+struct ProbeState {
+    int kind = -1;   // ISDC_KERNEL_* (-1: off)
+    int level = 0;
+    int every = 1;
+    int64_t seen = 0;       // matching launches since arming
+    size_t used = 0;        // event pairs handed out
+    size_t limit = 0;       // at most this many samples
+    double bytes = 0.0;     // algorithmic bytes of the sampled launches
+    std::vector<LaunchProbe> pool;
+};
+
+// Per-sweep host trace (environment variable ISDC_TRACE, read once): unset,
+// empty or "0" = off; "1" or "stderr" = standard error; otherwise a file path
+// the lines are appended to.  nullptr when off.
+FILE* trace_stream();
 
 void validate(const isdc_problem* pb, const isdc_params* pr);
 size_t layout(const isdc_problem& pb, const isdc_params& pr, char* base, isdc_plan* p);
@@ -112,6 +132,7 @@ struct isdc_plan {
     bool begun = false;
     isdc_stats stats;
     double* h_pinned = nullptr;
+    isdc::ProbeState probe;
 };
 
 namespace isdc {

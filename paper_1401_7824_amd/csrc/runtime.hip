@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +22,20 @@ namespace isdc {
 std::string& last_error() {
     thread_local std::string msg;
     return msg;
+}
+FILE* trace_stream() {
+    static FILE* const stream = [] () -> FILE* {
+        const char* v = std::getenv("ISDC_TRACE");
+        if (!v || !*v || std::strcmp(v, "0") == 0) return nullptr;
+        if (std::strcmp(v, "1") == 0 || std::strcmp(v, "stderr") == 0) return stderr;
+        FILE* f = std::fopen(v, "a");
+        return f ? f : stderr;
+    }();
+    return stream;
+}
+LaunchProbe*& armed_probe() {
+    thread_local LaunchProbe* probe = nullptr;
+    return probe;
 }
 }  // namespace isdc
 
@@ -239,6 +255,49 @@ void ensure_pinned(isdc_plan* p) {
     }
 }
 
+// Arms the plan's probe for the launch made in this scope if that launch is of
+// the followed kind and level and its turn in the sample (isdc_probe_arm);
+// `bytes` are its algorithmic bytes.  A probe the launcher did not consume
+// (no launch was made) is handed back.
+struct ProbeScope {
+    isdc_plan* p;
+    bool armed = false;
+    ProbeScope(isdc_plan* plan, int kind, int level, double bytes) : p(plan) {
+        ProbeState& pr = p->probe;
+        if (pr.kind != kind || pr.level != level) return;
+        if (pr.seen++ % pr.every != 0 || pr.used >= pr.limit) return;
+        armed_probe() = &pr.pool[pr.used++];
+        pr.bytes += bytes;
+        armed = true;
+        pending_bytes = bytes;
+    }
+    ~ProbeScope() {
+        if (armed && armed_probe()) {  // not consumed
+            armed_probe() = nullptr;
+            p->probe.used -= 1;
+            p->probe.bytes -= pending_bytes;
+        }
+    }
+    double pending_bytes = 0.0;
+};
+
+// Algorithmic bytes of one launch of a followed multigrid kernel on level l
+// (every array element read or written once; w = bytes per V-cycle value).
+double mg_bytes(const isdc_plan* p, int kind, int l) {
+    const double w = p->par.precision == ISDC_PREC_MIXED ? 4.0 : 8.0;
+    const double N = (double)p->lev[l].N;
+    const double Nc = l + 1 < (int)p->lev.size() ? (double)p->lev[l + 1].N : 0.0;
+    switch (kind) {
+        case ISDC_KERNEL_SMOOTH_RESTRICT: return (3.0 * N + Nc) * w;  // rhs, e in; e, coarse rhs out
+        case ISDC_KERNEL_SMOOTH: return 3.0 * N * w;                  // rhs, e in; e out
+        case ISDC_KERNEL_RESTRICT: return (2.0 * N + Nc) * w;         // rhs, e in; coarse rhs out
+        case ISDC_KERNEL_PROLONG_SMOOTH: return (3.0 * N + Nc) * w;   // rhs, e, coarse e in; e out
+        case ISDC_KERNEL_PROLONG_UPDATE: return (2.0 * N + Nc) * w + 16.0 * N;  // + float64 g in, u out
+        case ISDC_KERNEL_TAIL: return 2.0 * N * w;
+        default: return 0.0;
+    }
+}
+
 double read_scalar(isdc_plan* p, const double* d_src, hipStream_t s) {
     ensure_pinned(p);
     HIPCHK(hipMemcpyAsync(p->h_pinned, d_src, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -257,16 +316,79 @@ struct Fuse {
 };
 
 template <typename T>
-void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int n, const Coef<T>& co, bool& zero, const T* rhs,
+void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int l, const Coef<T>& co, bool& zero, const T* rhs,
                   T*& cur, T*& other, hipStream_t s, int shape) {
+    const int n = p->lev[l].n;
     for (int k = 0; k < nsteps; ++k) {
-        if (mg.smoother == ISDC_SMOOTH_RBGS)
+        if (mg.smoother == ISDC_SMOOTH_RBGS) {
+            ProbeScope probe(p, zero ? -2 : ISDC_KERNEL_SMOOTH, l, mg_bytes(p, ISDC_KERNEL_SMOOTH, l));
             HIPCHK(launch_rbgs_tile<T>(p->d, n, co, zero, rhs, cur, other, s, shape));
-        else
+        } else
             HIPCHK(launch_smooth<T>(mg, n, co, zero, rhs, cur, other, s));
         std::swap(cur, other);
         zero = false;
     }
+}
+
+// One V-cycle on a 2D Dirichlet level l with weighted-Jacobi smoothing of the
+// second-order operator, on the fused row-tile kernels: the last (up to
+// three) pre-smoothing steps with the residual's restriction in one launch,
+// the prolongation with the first (up to three) post-smoothing steps in
+// another; further steps three per launch.  Result in e (tmp: scratch of the
+// level's size).
+template <typename T>
+void jvcycle5_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp,
+                  hipStream_t s) {
+    const Level& L = p->lev[l];
+    if (l >= p->tail) {
+        ProbeScope probe(p, l == p->tail ? ISDC_KERNEL_TAIL : -2, 0, mg_bytes(p, ISDC_KERNEL_TAIL, l));
+        HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
+        return;
+    }
+    const CCoef<T> k = make_coef5<T>(c, L.h, mg.omega);
+    T* cur = e;
+    T* other = tmp;
+    const Level& C = p->lev[l + 1];
+    int pre = mg.nu_pre;
+    while (pre > 3) {
+        HIPCHK(launch_jacobi5_steps<T>(L.n, k, 3, zero, rhs, cur, other, s));
+        std::swap(cur, other);
+        zero = false;
+        pre -= 3;
+    }
+    if (pre > 0) {
+        ProbeScope probe(p, zero ? -2 : ISDC_KERNEL_SMOOTH_RESTRICT, l, mg_bytes(p, ISDC_KERNEL_SMOOTH_RESTRICT, l));
+        HIPCHK(launch_jres5<T>(L.n, k, pre, zero, rhs, cur, other, (T*)C.r, s));
+        std::swap(cur, other);
+        zero = false;
+    } else {
+        if (zero) {
+            HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
+            zero = false;
+        }
+        const Coef<T> co = make_coef<T>(c, L.h, p->d, mg.omega);
+        HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
+    }
+    jvcycle5_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
+    int post = mg.nu_post;
+    if (post > 0) {
+        const int first = std::min(3, post);
+        {
+            ProbeScope probe(p, ISDC_KERNEL_PROLONG_SMOOTH, l, mg_bytes(p, ISDC_KERNEL_PROLONG_SMOOTH, l));
+            HIPCHK(launch_pjac5<T>(L.n, k, first, rhs, cur, (const T*)C.e, other, s));
+        }
+        std::swap(cur, other);
+        post -= first;
+        while (post > 0) {
+            const int ks = std::min(3, post);
+            HIPCHK(launch_jacobi5_steps<T>(L.n, k, ks, false, rhs, cur, other, s));
+            std::swap(cur, other);
+            post -= ks;
+        }
+    } else {
+        HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
+    }
+    if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
 }
 
 // One V-cycle on level l for (I - c L) e = rhs starting from e (or from zero);
@@ -278,29 +400,37 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
                 const Fuse& fuse = Fuse(), const RhsArgs* fra = nullptr) {
     const Level& L = p->lev[l];
     if (l >= p->tail) {  // (beyond the tail only the coarse MLSDC level, solved the same way)
+        ProbeScope probe(p, l == p->tail ? ISDC_KERNEL_TAIL : -2, 0, mg_bytes(p, ISDC_KERNEL_TAIL, l));
         HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
         return false;
     }
     const bool rbgs = mg.smoother == ISDC_SMOOTH_RBGS;
+    if (!rbgs && p->d == 2) {  // 2D Jacobi: the fused row-tile kernels
+        jvcycle5_rec<T>(p, mg, l, c, zero, rhs, e, tmp, s);
+        return false;
+    }
     Coef<T> co = make_coef<T>(c, L.h, p->d, mg.omega);
     T* cur = e;
     T* other = tmp;
     const Level& C = p->lev[l + 1];
     if (rbgs && mg.nu_pre >= 1 && p->d <= 2) {
         // pre-smoothing steps; the last one fused with residual + restriction
-        smooth_steps<T>(p, mg, mg.nu_pre - 1, L.n, co, zero, rhs, cur, other, s, L.shape);
+        smooth_steps<T>(p, mg, mg.nu_pre - 1, l, co, zero, rhs, cur, other, s, L.shape);
         if (fra && zero && mg.nu_pre == 1 && p->d == 2)  // rhs formed in the first launch (writes rhs)
             HIPCHK(launch_rhs_rbgs_restrict_tile<T>(p->d, L.n, *fra, co, (T*)rhs, other, (T*)C.r, s, L.shape));
-        else
+        else {
+            ProbeScope probe(p, zero ? -2 : ISDC_KERNEL_SMOOTH_RESTRICT, l, mg_bytes(p, ISDC_KERNEL_SMOOTH_RESTRICT, l));
             HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s, L.shape));
+        }
         std::swap(cur, other);
         zero = false;
     } else {
-        smooth_steps<T>(p, mg, mg.nu_pre, L.n, co, zero, rhs, cur, other, s, L.shape);
+        smooth_steps<T>(p, mg, mg.nu_pre, l, co, zero, rhs, cur, other, s, L.shape);
         if (zero) {  // no pre-smoothing and a zero iterate
             HIPCHK(launch_fill<T>(cur, L.N, T(0), s));
             zero = false;
         }
+        ProbeScope probe(p, ISDC_KERNEL_RESTRICT, l, mg_bytes(p, ISDC_KERNEL_RESTRICT, l));
         HIPCHK(launch_restrict_tile<T>(p->d, L.n, co, rhs, cur, (T*)C.r, s));
     }
     vcycle_rec<T>(p, mg, l + 1, c, true, (const T*)C.r, (T*)C.e, (T*)C.e2, s);
@@ -309,14 +439,16 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
         // prolongation + correction fused with the first post-smoothing step
         const bool last = mg.nu_post == 1;
         const int mode = (last && fuse.mode) ? fuse.mode : 0;
+        const int kind = mode == 0 ? ISDC_KERNEL_PROLONG_SMOOTH : (mode == 1 ? ISDC_KERNEL_PROLONG_UPDATE : -2);
+        ProbeScope probe(p, kind, l, mg_bytes(p, kind, l));
         HIPCHK(launch_prolong_rbgs_tile<T>(p->d, L.n, co, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, mode, s,
                                            L.shape));
         if (mode) return true;
         std::swap(cur, other);
-        smooth_steps<T>(p, mg, mg.nu_post - 1, L.n, co, zero, rhs, cur, other, s, L.shape);
+        smooth_steps<T>(p, mg, mg.nu_post - 1, l, co, zero, rhs, cur, other, s, L.shape);
     } else {
         HIPCHK(launch_prolong<T>(p->d, L.n, (const T*)C.e, cur, s));
-        smooth_steps<T>(p, mg, mg.nu_post, L.n, co, zero, rhs, cur, other, s, L.shape);
+        smooth_steps<T>(p, mg, mg.nu_post, l, co, zero, rhs, cur, other, s, L.shape);
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
     return fused;
@@ -350,7 +482,14 @@ void quad_residual(isdc_plan* p, const double* const* nodes, hipStream_t s) {
     qa.n = p->n;
     qa.fe = p->prob.fe_kind;
     int nb = 0;
-    HIPCHK(launch_quad_residual(p->d, qa, p->partial, &nb, s));
+    {
+        // algorithmic bytes: u_0 and every distinct node array read, the S F arrays written
+        int arrays = 1;
+        for (int j = 1; j <= p->M; ++j) arrays += nodes[j] != nodes[0];
+        for (int m = 0; m < p->M; ++m) arrays += p->SF[m] != nullptr;
+        ProbeScope probe(p, ISDC_KERNEL_QUAD, 0, (double)arrays * (double)p->N * 8.0);
+        HIPCHK(launch_quad_residual(p->d, qa, p->partial, &nb, s));
+    }
     HIPCHK(launch_reduce_max(p->partial, nb, p->scalars, s));
 }
 
@@ -619,7 +758,14 @@ void sweep_nodes(isdc_plan* p, hipStream_t s) {
         RhsArgs ra{nw[m], p->cur[m], p->cur[m + 1], p->SF[m], dtm, dtm * p->prob.nu, nu_h2, p->n,
                    p->prob.fe_kind, p->par.guess};
         const bool fuse_rhs = rhs_fusable(p);
-        if (!fuse_rhs) HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
+        if (!fuse_rhs) {
+            // f^E = 0 reads u_m^{k+1}, u_{m+1}^k and S F; f^E != 0 also u_m^k (previous-sweep guess)
+            const double reads = p->prob.fe_kind == ISDC_FE_ZERO ? 3.0 : 4.0;
+            const double w = p->par.precision == ISDC_PREC_MIXED ? 4.0 : 8.0;
+            ProbeScope probe(p, p->par.guess == ISDC_GUESS_PREV_SWEEP ? ISDC_KERNEL_RHS : -2, 0,
+                             (reads * 8.0 + w) * (double)p->N);
+            HIPCHK(launch_euler_rhs<T>(p->d, ra, (T*)p->lev[0].r, s));
+        }
         Fuse upd;
         upd.u_out = (double*)nw[m + 1];
         if (p->par.guess == ISDC_GUESS_ZERO) {
@@ -801,10 +947,18 @@ void check_plan(const isdc_plan* p) {
 // it is not finite, or max_sweeps is reached; returns the step's status.
 int step_loop(isdc_plan* plan, double* d_u, double dt, hipStream_t s, isdc_stats* out) {
     if (!d_u) fail(ISDC_E_INVAL, "d_u is NULL");
+    FILE* trace = trace_stream();
+    const auto t0 = std::chrono::steady_clock::now();
     begin_impl(plan, d_u, dt, s);
     int status = ISDC_E_NOT_CONVERGED;
     for (int k = 0; k < plan->par.max_sweeps; ++k) {
         double res = sweep_any(plan, s);
+        if (trace) {  // host time once the sweep's residual has been read back
+            const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+            std::fprintf(trace, "isdc_trace plan=%p dim=%d n=%d sweep=%d t_us=%.1f residual=%.6e vcycles=%lld\n",
+                         (void*)plan, plan->d, plan->n, k + 1, us, res, (long long)plan->stats.vcycles);
+            std::fflush(trace);
+        }
         if (!std::isfinite(res)) {
             status = ISDC_E_DIVERGED;
             break;
@@ -982,7 +1136,59 @@ int isdc_create(const isdc_problem* prob, const isdc_params* par, void* d_worksp
 void isdc_destroy(isdc_plan* plan) {
     if (!plan) return;
     if (plan->h_pinned) (void)hipHostFree(plan->h_pinned);
+    for (auto& ev : plan->probe.pool) {
+        (void)hipEventDestroy(ev.start);
+        (void)hipEventDestroy(ev.stop);
+    }
     delete plan;
+}
+
+int isdc_probe_arm(isdc_plan* plan, int32_t kernel, int32_t level, int32_t every, int32_t max_samples) {
+    return guarded([&] {
+        check_plan(plan);
+        if (plan->compact) fail(ISDC_E_UNSUPPORTED, "probes follow second-order stencil plans");
+        const bool leveled = kernel == ISDC_KERNEL_SMOOTH_RESTRICT || kernel == ISDC_KERNEL_SMOOTH ||
+                             kernel == ISDC_KERNEL_RESTRICT || kernel == ISDC_KERNEL_PROLONG_SMOOTH;
+        if (!leveled && kernel != ISDC_KERNEL_PROLONG_UPDATE && kernel != ISDC_KERNEL_TAIL &&
+            kernel != ISDC_KERNEL_QUAD && kernel != ISDC_KERNEL_RHS)
+            fail(ISDC_E_INVAL, "kernel cannot be followed by a probe");
+        if (leveled && (level < 0 || level >= plan->tail)) fail(ISDC_E_INVAL, "level must lie above the coarse tail");
+        if (every < 1 || every > 1000000) fail(ISDC_E_INVAL, "every must be in 1..1000000");
+        if (max_samples < 1 || max_samples > 1000000) fail(ISDC_E_INVAL, "max_samples must be in 1..1000000");
+        ProbeState& pr = plan->probe;
+        while (pr.pool.size() < (size_t)max_samples) {
+            LaunchProbe ev{};
+            HIPCHK(hipEventCreate(&ev.start));
+            HIPCHK(hipEventCreate(&ev.stop));
+            pr.pool.push_back(ev);
+        }
+        pr.kind = kernel;
+        pr.level = leveled ? level : 0;
+        pr.every = every;
+        pr.seen = 0;
+        pr.used = 0;
+        pr.bytes = 0.0;
+        pr.limit = (size_t)max_samples;  // samples beyond max_samples are not taken
+    });
+}
+
+int isdc_probe_read(isdc_plan* plan, int64_t* h_samples, double* h_avg_us, double* h_bytes) {
+    return guarded([&] {
+        check_plan(plan);
+        ProbeState& pr = plan->probe;
+        if (pr.kind < 0) fail(ISDC_E_INVAL, "no probe armed");
+        double total_ms = 0.0;
+        for (size_t k = 0; k < pr.used; ++k) {
+            HIPCHK(hipEventSynchronize(pr.pool[k].stop));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.pool[k].start, pr.pool[k].stop));
+            total_ms += ms;
+        }
+        if (h_samples) *h_samples = (int64_t)pr.used;
+        if (h_avg_us) *h_avg_us = pr.used ? 1e3 * total_ms / (double)pr.used : 0.0;
+        if (h_bytes) *h_bytes = pr.used ? pr.bytes / (double)pr.used : 0.0;
+        pr.kind = -1;
+    });
 }
 
 int isdc_begin(isdc_plan* plan, const double* d_u0, double dt, void* stream) {

@@ -88,7 +88,7 @@ static hipError_t launch_quad_d(const QuadArgs& qa, double* partial, int* nblock
     *nblocks = nb;
     switch (qa.M) {
 #define ISDC_QM(MM) \
-    case MM: hipLaunchKernelGGL((k_quad_residual_tile<D, MM>), dim3(nb), dim3(kThreads), 0, s, qa, ntx, nty, partial); break;
+    case MM: ISDC_LAUNCH((k_quad_residual_tile<D, MM>), dim3(nb), dim3(kThreads), 0, s, qa, ntx, nty, partial); break;
         ISDC_QM(1) ISDC_QM(2) ISDC_QM(3) ISDC_QM(4) ISDC_QM(5) ISDC_QM(6) ISDC_QM(7) ISDC_QM(8) ISDC_QM(9)
 #undef ISDC_QM
         default: return hipErrorInvalidValue;
@@ -110,13 +110,13 @@ hipError_t launch_euler_rhs(int d, const RhsArgs& ra, T* r, hipStream_t s) {
     ISDC_DISPATCH_D(d, {
         switch (ra.guess) {
             case ISDC_GUESS_PREV_SWEEP:
-                hipLaunchKernelGGL((k_euler_rhs<T, D, ISDC_GUESS_PREV_SWEEP>), dim3(nb), dim3(kBlock), 0, s, ra, r);
+                ISDC_LAUNCH((k_euler_rhs<T, D, ISDC_GUESS_PREV_SWEEP>), dim3(nb), dim3(kBlock), 0, s, ra, r);
                 break;
             case ISDC_GUESS_ZERO:
-                hipLaunchKernelGGL((k_euler_rhs<T, D, ISDC_GUESS_ZERO>), dim3(nb), dim3(kBlock), 0, s, ra, r);
+                ISDC_LAUNCH((k_euler_rhs<T, D, ISDC_GUESS_ZERO>), dim3(nb), dim3(kBlock), 0, s, ra, r);
                 break;
             default:
-                hipLaunchKernelGGL((k_euler_rhs<T, D, ISDC_GUESS_PREV_NODE>), dim3(nb), dim3(kBlock), 0, s, ra, r);
+                ISDC_LAUNCH((k_euler_rhs<T, D, ISDC_GUESS_PREV_NODE>), dim3(nb), dim3(kBlock), 0, s, ra, r);
                 break;
         }
     });
@@ -129,13 +129,13 @@ hipError_t launch_node_update(size_t N, int guess, const double* up_old, const d
     int nb = grid_for(N, 1 << 16);
     switch (guess) {
         case ISDC_GUESS_PREV_SWEEP:
-            hipLaunchKernelGGL((k_node_update<T, ISDC_GUESS_PREV_SWEEP>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
+            ISDC_LAUNCH((k_node_update<T, ISDC_GUESS_PREV_SWEEP>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
             break;
         case ISDC_GUESS_ZERO:
-            hipLaunchKernelGGL((k_node_update<T, ISDC_GUESS_ZERO>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
+            ISDC_LAUNCH((k_node_update<T, ISDC_GUESS_ZERO>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
             break;
         default:
-            hipLaunchKernelGGL((k_node_update<T, ISDC_GUESS_PREV_NODE>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
+            ISDC_LAUNCH((k_node_update<T, ISDC_GUESS_PREV_NODE>), dim3(nb), dim3(kBlock), 0, s, N, up_old, um_new, e, u_out);
             break;
     }
     return hipGetLastError();

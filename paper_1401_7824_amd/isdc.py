@@ -229,6 +229,17 @@ class Plan:
             tuning.store(key, shapes)
         return shapes
 
+    def probe_arm(self, kernel: int, level: int = 0, every: int = 1, max_samples: int = 100000):
+        """Follow `kernel` on `level` inside the next steps (isdc_probe_arm)."""
+        A.check(self.lib.isdc_probe_arm(self._h, kernel, level, every, max_samples))
+
+    def probe_read(self):
+        """(samples, average microseconds per launch, average algorithmic bytes per launch)
+        of the launches followed since probe_arm (isdc_probe_read)."""
+        n, us, b = C.c_int64(), C.c_double(), C.c_double()
+        A.check(self.lib.isdc_probe_read(self._h, C.byref(n), C.byref(us), C.byref(b)))
+        return n.value, us.value, b.value
+
     def time_kernel(self, kernel: int, level: int, c: float, precision: int, reps: int = 100, stream=None):
         """(average microseconds per launch, algorithmic bytes per launch) of one library kernel."""
         us, b = C.c_double(), C.c_double()

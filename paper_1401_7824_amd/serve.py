@@ -2,13 +2,17 @@
 
 Requests (an initial state, a problem, step size, number of steps and a
 tolerance) arrive over time.  The server keeps one batch per spatial
-dimension; a request is admitted into a free slot as soon as its device memory
-(plan workspace + state) fits under the HBM budget, its state then stays
-resident on the device between sweeps, every ``advance`` moves all admitted
-requests of a batch by one sweep in shared kernel launches, and a request
-leaves (freeing its slot and memory) when its last step has converged or it
-has failed.  Requests therefore join and leave at sweep boundaries while
-others are on the GPU.
+dimension, each advanced on a stream of its own; a request is admitted into a
+free slot as soon as its device memory (plan workspace + state) fits under the
+HBM budget (``choose_admissions``: first come first served, and the oldest
+request that does not fit reserves its memory, so later and smaller requests
+can only fill what is left beside it), its state then stays resident on the
+device between sweeps, every ``advance`` moves all admitted requests of a
+batch by one sweep in shared kernel launches -- the batches of the two
+dimensions at the same time, from two host threads on two streams -- and a
+request leaves (freeing its slot and memory) when its last step has converged
+or it has failed.  Requests therefore join and leave at sweep boundaries
+while others are on the GPU.
 
 All computation is in the HIP library; this module is scheduling and
 bookkeeping only.
@@ -17,6 +21,7 @@ from __future__ import annotations
 
 import math
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -56,8 +61,12 @@ class Request:
                     vcycles=vcycles, max_sweeps=200)
 
     def device_bytes(self, precision: int, vcycles: int) -> int:
-        prob = make_problem(self.dim, self.n, self.nu, self.fe_kind)
-        return workspace_bytes(prob, make_params(**self.params(precision, vcycles))) + self.n ** self.dim * 8
+        key = (precision, vcycles)
+        if getattr(self, "_bytes_key", None) != key:
+            prob = make_problem(self.dim, self.n, self.nu, self.fe_kind)
+            self._bytes = workspace_bytes(prob, make_params(**self.params(precision, vcycles))) + self.n ** self.dim * 8
+            self._bytes_key = key
+        return self._bytes
 
 
 @dataclass
@@ -80,6 +89,31 @@ class ServeStats:
                     peak_concurrency=self.peak_concurrency, batch_sweeps=self.advances)
 
 
+def choose_admissions(waiting, need, used: int, budget: int, free_slots: dict) -> list:
+    """Requests of `waiting` (in arrival order) to admit now: each in turn if a
+    slot of its dimension is free and its memory fits in the budget.  The
+    first request that cannot be admitted reserves its memory: every later one
+    must then fit beside that reservation, so the oldest waiting request gets
+    the memory that frees up and cannot be passed over indefinitely by smaller
+    ones.  `need(r)` gives a request's bytes; `free_slots` maps a dimension to
+    its number of free slots."""
+    slots = dict(free_slots)
+    mem = used
+    reserve = 0
+    blocked = False
+    out = []
+    for r in waiting:
+        b = need(r)
+        if slots.get(r.dim, 0) > 0 and mem + b + reserve <= budget:
+            out.append(r)
+            mem += b
+            slots[r.dim] -= 1
+        elif not blocked:
+            blocked = True
+            reserve = b
+    return out
+
+
 class Server:
     """One batch per dimension, admission by slots and HBM budget (bytes)."""
 
@@ -89,14 +123,27 @@ class Server:
         self.precision = precision
         self.vcycles = vcycles
         self.batches = {d: Batch(slots_per_batch, d, precision=precision, vcycles=vcycles) for d in dims}
+        # one stream per batch (default priority), advanced from a thread each
+        self.streams = {d: torch.cuda.Stream() for d in dims}
+        self.pool = ThreadPoolExecutor(max_workers=len(dims))
         self.free = {d: list(range(slots_per_batch)) for d in dims}
         self.running = {d: {} for d in dims}   # slot -> (request, bytes)
         self.used = 0
 
-    def _admit(self, req: Request, now: float) -> bool:
+    def __del__(self):
+        try:
+            self.pool.shutdown(wait=False)
+        except Exception:
+            pass
+
+    def _need(self, req: Request) -> int:
         need = req.device_bytes(self.precision, self.vcycles)
         if need > self.budget:
             raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
+        return need
+
+    def _admit(self, req: Request, now: float) -> bool:
+        need = self._need(req)
         d = req.dim
         if not self.free[d] or self.used + need > self.budget:
             return False
@@ -142,24 +189,27 @@ class Server:
             while i < len(queue) and queue[i].arrival <= now:
                 waiting.append(queue[i])
                 i += 1
-            # FIFO admission while memory and slots allow (a request that does not
-            # fit blocks the ones behind it of the same dimension)
-            blocked = set()
-            rest = []
-            for r in waiting:
-                if r.dim in blocked or not self._admit(r, now):
-                    blocked.add(r.dim)
-                    rest.append(r)
-            waiting = rest
+            admit = choose_admissions(waiting, self._need, self.used, self.budget,
+                                      {d: len(f) for d, f in self.free.items()})
+            for r in admit:
+                ok = self._admit(r, now)
+                assert ok
+            if admit:
+                chosen = set(id(r) for r in admit)
+                waiting = [r for r in waiting if id(r) not in chosen]
+                # the states were uploaded on the current stream; the batch streams start after them
+                torch.cuda.current_stream().synchronize()
             stats.peak_bytes = max(stats.peak_bytes, self.used)
             stats.peak_concurrency = max(stats.peak_concurrency, sum(len(v) for v in self.running.values()))
-            busy = False
-            for d, b in self.batches.items():
-                if self.running[d]:
-                    b.advance()
-                    stats.advances += 1
-                    busy = True
-                    self._reap(d, clock() - t0, stats)
+            # one sweep of every batch with running slots, the batches side by side
+            live = [d for d in self.batches if self.running[d]]
+            futures = [self.pool.submit(self.batches[d].advance, self.streams[d]) for d in live]
+            for f in futures:
+                f.result()
+            stats.advances += len(live)
+            busy = bool(live)
+            for d in live:
+                self._reap(d, clock() - t0, stats)
             if not busy:
                 # idle until the next arrival
                 if i < len(queue):

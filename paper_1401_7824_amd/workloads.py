@@ -105,8 +105,9 @@ WORKLOADS = {
                    precision=PREC_FP64, sdc_tol=1e-10, modes=[(1.0, (1,)), (0.5, (3,))]),
     "rd2d": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
                  precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2),
+    # all-float64; bench.py runs the float32-V-cycle variant beside it
     "heat3d": dict(dim=3, n=255, nu=1.0, fe_kind=FE_ZERO, node_kind=NODES_RADAU_RIGHT, M=3, dt=1e-3, steps=1,
-                   precision=PREC_MIXED, sdc_tol=1e-10, n_modes=32, seed=3),
+                   precision=PREC_FP64, sdc_tol=1e-10, n_modes=32, seed=3),
     # the rd2d problem with the fourth-order compact stencil and weighting matrix W
     # (weighted-Jacobi V(2,2) cycles for W - dt_m nu A_h)
     "rd2d_compact": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,

@@ -66,7 +66,7 @@ def test_heat3d_full_size_mixed_matches_collocation():
     announce("fullsize heat3d", n)
     modes = W.workload_modes(cfg)
     u0 = W.sine_field(n, d, modes)
-    p = _plan_for(cfg)
+    p = _plan_for(cfg, precision=1)
     u = dev(u0)
     s = p.step(u, cfg["dt"])
     assert s.status == "ok"

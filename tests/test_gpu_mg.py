@@ -257,3 +257,26 @@ def test_autotune_picks_valid_shapes_and_keeps_results(tmp_path, monkeypatch):
         p.tile_shapes = [3] * len(shapes)
     with pytest.raises(ISDCError):
         p.tile_shapes = [0] * (len(shapes) + 1)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nu1,nu2", [(1, 1), (2, 2), (3, 3), (4, 5), (0, 2), (2, 0)])
+def test_jacobi_2d_fused_vcycle_parity(nu1, nu2, dtype):
+    # 2D weighted-Jacobi cycles run fused row-tile launches (up to three steps
+    # with the restriction, the prolongation with up to three steps); every
+    # split of the smoothing steps over the launches gives the oracle's cycle
+    n = 255
+    announce("jacobi fused vcycle", nu1, nu2, dtype)
+    p = _plan(2, n, JAC, nu1, nu2)
+    h = 1.0 / (n + 1)
+    c = 80.0 * h * h
+    nd = _np_dtype(dtype)
+    rhs = random_field((n, n), 17).astype(nd)
+    u0 = random_field((n, n), 18).astype(nd)
+    u = dev(u0, dtype)
+    p.vcycle(c, dev(rhs, dtype), u, ncycles=2)
+    ref = u0
+    for _ in range(2):
+        ref = O.vcycle(ref, rhs, c, h, JAC, nu1, nu2)
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert rel_l2(host(u), ref) < tol
