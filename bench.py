@@ -40,6 +40,11 @@ def parse():
                              "table1b", "kernels", "compare"])
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-solo", type=int, default=2, help="solo lanes of the server (requests on their own plan)")
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.1",
+                    help="arrival rates swept, as fractions of the saturated capacity")
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="saturated capacity (req/s) from an earlier run: skips the saturated run and the sequential baselines")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -216,6 +221,11 @@ def probe_kernel_name(key, cfg, T, shape=0):
         return {"smooth": f"k_march_rbgs<{T},false,0,false>", "restrict": f"k_march_restrict<{T}>",
                 "prolong_smooth": f"k_march_rbgs<{T},true,0,false>",
                 "prolong_update": f"k_march_rbgs<{T},true,1,false>"}[key]
+    if d == 2 and cfg.get("smoother", 0) == 1:  # fused weighted-Jacobi row kernels of the five-point operator
+        kpre, kpost = min(3, cfg.get("nu_pre", 2)), min(3, cfg.get("nu_post", 2))
+        return {"smooth_restrict": f"k_cjres<{T},false,{kpre},false,false>",
+                "prolong_smooth": f"k_cpjac<{T},false,{kpost},false,0>",
+                "prolong_update": f"k_cpjac<{T},false,{kpost},false,1>"}[key]
     if d == 2:
         return {"smooth": f"k_rows_rbgs<{T},false,{shape}>", "smooth_restrict": f"k_rows_rbgs_restrict<{T},false,{shape}>",
                 "prolong_smooth": f"k_rows_prolong_rbgs<{T},0,{shape}>",
@@ -431,6 +441,21 @@ def run_batch(args, torch):
     b = Batch(len(inst), 2, precision=1, vcycles=2)
     ws = [torch.empty(Batch.workspace_bytes_for(x["n"], 2, x["nu"], x["fe_kind"], **par(x)), dtype=torch.uint8,
                       device="cuda") for x in inst]
+    # launch schedule of one batch sweep of all 256 slots: kernel by kernel, as
+    # isdc_batch_advance runs it, against one HIP graph replayed (measurement only)
+    side = torch.cuda.Stream()
+    ub = [torch.from_numpy(u).cuda() for u in u0s]
+    for i, x in enumerate(inst):
+        b.set(i, ub[i], x["dt"], steps, x["nu"], x["fe_kind"], workspace=ws[i], **par(x))
+    torch.cuda.synchronize()
+    b.advance(side)
+    eager_us, launches = b.time_sweeps(10, False, side)
+    graph_us, _ = b.time_sweeps(10, True, side)
+    for i in range(len(inst)):
+        b.release(i)
+    torch.cuda.synchronize()
+    print(f"[batch] sweep of {len(inst)} slots: {launches} launches, eager {eager_us:.1f} us, "
+          f"graph {graph_us:.1f} us", file=sys.stderr, flush=True)
     # warm-up of every kernel shape on a copy
     for rep in range(2):
         ub = [torch.from_numpy(u).cuda() for u in u0s]
@@ -469,6 +494,11 @@ def run_batch(args, torch):
                                   "seconds": round(t_single, 3)},
         "speedup_vs_per_instance": round(t_single / t_batch, 2),
         "bitwise_equal_to_per_instance": bool(same),
+        "sweep_launch_schedule": {"launches_per_sweep": launches, "eager_us_per_sweep": round(eager_us, 1),
+                                  "hip_graph_us_per_sweep": round(graph_us, 1),
+                                  "kept": "eager: the captured graph is within 3 % and would need a new capture "
+                                          "whenever slots join or leave" if graph_us > 0.97 * eager_us
+                                  else "graph is more than 3 % faster here"},
         "batch_seconds": round(t_batch, 3),
     }
     if not args.no_cpu_baseline:
@@ -481,42 +511,39 @@ def serve_accuracy(reqs, torch, rd_sample=8):
     tolerance) against a float64 reference, relative L2: every heat request
     against the exact collocation solution after nsteps steps (each sine mode
     of u_0 multiplied by R(dt nu lambda)^nsteps, R the Pade closed form of the
-    collocation stability function); reaction-diffusion requests (the
-    rd_sample smallest) against an all-float64 plan run to SDC tolerance 1e-12."""
+    collocation stability function; the reference field is built on the
+    device); reaction-diffusion requests (the rd_sample smallest) against an
+    all-float64 plan run to SDC tolerance 1e-12."""
     import numpy as np
     from paper_1401_7824_amd import Plan, workloads as W
     rows = []
     for r in reqs:
-        if r.result is None or r.status != "ok":
+        if r.result is None or r.status != "ok" or r.fe_kind != 0:
             continue
-        got = r.result.detach().cpu().numpy()
-        if r.fe_kind == 0:
-            modes = W.draw_modes(r.dim, 8, seed=10_000 + r.rid, max_wave=4)
-            cfg = dict(dim=r.dim, n=r.n, nu=r.nu, dt=r.dt, node_kind=r.node_kind, M=r.M)
-            ref = collocation_reference(cfg, modes, r.nsteps)
-            kind = "heat vs exact collocation"
-        else:
-            continue
-        rows.append(dict(rid=r.rid, dim=r.dim, n=r.n, tol=r.sdc_tol, steps=r.nsteps, kind=kind,
-                         rel_l2=float(np.linalg.norm(got - ref) / np.linalg.norm(ref))))
+        h = 1.0 / (r.n + 1)
+        lam = np.array([sum(-(4.0 / h ** 2) * np.sin(ai * np.pi * h / 2) ** 2 for ai in a) for _, a in r.modes])
+        R = collocation_stability(r.node_kind, r.M, r.dt * r.nu * lam)
+        ref = W.sine_field_device(r.n, r.dim, [(r.scale * amp * Rk ** r.nsteps, a) for (amp, a), Rk in zip(r.modes, R)])
+        err = (torch.linalg.vector_norm(r.result - ref) / torch.linalg.vector_norm(ref)).item()
+        rows.append(dict(rid=r.rid, dim=r.dim, n=r.n, tol=r.sdc_tol, steps=r.nsteps, kind="heat vs exact collocation",
+                         rel_l2=float(err)))
     rd = sorted((r for r in reqs if r.fe_kind == 1 and r.result is not None and r.status == "ok"),
                 key=lambda r: r.n ** r.dim)[:rd_sample]
     for r in rd:
         p = Plan(r.dim, r.n, r.nu, r.fe_kind, node_kind=r.node_kind, M=r.M, sdc_tol=1e-12, max_sweeps=400,
                  precision=0)
-        u = torch.from_numpy(r.u0).cuda()
+        u = r.u0_device()
         for _ in range(r.nsteps):
             p.step(u, r.dt)
-        ref = u.cpu().numpy()
-        got = r.result.detach().cpu().numpy()
+        err = (torch.linalg.vector_norm(r.result - u) / torch.linalg.vector_norm(u)).item()
         rows.append(dict(rid=r.rid, dim=r.dim, n=r.n, tol=r.sdc_tol, steps=r.nsteps,
-                         kind="reaction-diffusion vs float64 at tol 1e-12",
-                         rel_l2=float(np.linalg.norm(got - ref) / np.linalg.norm(ref))))
+                         kind="reaction-diffusion vs float64 at tol 1e-12", rel_l2=float(err)))
     worst = {}
     for row in rows:
-        key = f"tol {row['tol']:g}"
+        key = f"tol {row['tol']:g}, {row['kind']}"
         worst[key] = max(worst.get(key, 0.0), row["rel_l2"])
-    return {"checked": len(rows), "max_rel_l2_by_tolerance": worst, "per_result": rows}
+    return {"checked": len(rows), "max_rel_l2_by_tolerance": worst,
+            "per_result": rows if len(rows) <= 200 else "omitted (more than 200 results)"}
 
 
 def run_serve(args, torch):
@@ -531,26 +558,49 @@ def run_serve(args, torch):
     count = args.serve_count
 
     def server():
-        return Server(budget, slots_per_batch=64, precision=1, vcycles=2)
+        return Server(budget, slots_per_batch=64, precision=1, vcycles=2, solo_workers=args.serve_solo)
 
+    log = max(1, count // 10)
     warm = make_requests(8, rate=0.0, seed=99)
     server().serve(warm)
-    sat_reqs = make_requests(count, rate=0.0, seed=5)
-    sat = server().serve(sat_reqs)
-    cap = sat.completed / sat.makespan
-    accuracy = serve_accuracy(sat_reqs, torch)
-    print(f"[serve] saturated: {sat.completed} requests in {sat.makespan:.2f} s", file=sys.stderr, flush=True)
+    given = args.serve_capacity > 0
+    if given:
+        cap, sat, accuracy = args.serve_capacity, None, None
+    else:
+        sat_reqs = make_requests(count, rate=0.0, seed=5)
+        sat = server().serve(sat_reqs, log_every=log)
+        cap = sat.completed / sat.makespan
+        accuracy = serve_accuracy(sat_reqs, torch)
+        del sat_reqs
+        print(f"[serve] saturated: {sat.completed} requests in {sat.makespan:.2f} s", file=sys.stderr, flush=True)
     rows = []
-    for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
+    for frac in [float(x) for x in args.serve_rates.split(",") if x]:
         reqs = make_requests(count, rate=frac * cap, seed=5)
-        st = server().serve(reqs).summary()
+        st = server().serve(reqs, log_every=log).summary()
         st["rate_req_s"] = round(frac * cap, 3)
         st["rate_frac_of_capacity"] = frac
         rows.append(st)
         print(f"[serve] rate {frac:.2f} x capacity: p50 {st['p50_ms']} ms, p99 {st['p99_ms']} ms",
               file=sys.stderr, flush=True)
-    seq = serve_sequential(make_requests(count, rate=0.25 * cap, seed=5), precision=1, vcycles=2).summary()
-    seq_sat = serve_sequential(make_requests(count, rate=0.0, seed=5), precision=1, vcycles=2).summary()
+    if given:
+        return {"metric": METRIC, "value": round(cap, 4), "unit": "requests/s", "n_gpus": 1, "steps": 0,
+                "warmup": 8, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64+f32", "data": "synthetic",
+                "config": {"workload": f"serve rate sweep only: {count} requests, capacity {cap} req/s given, HBM "
+                                       f"budget {args.serve_budget_gb} GiB, {args.serve_solo} solo lanes"},
+                "rate_sweep": rows}
+    seq = serve_sequential(make_requests(count, rate=0.25 * cap, seed=5), precision=1, vcycles=2,
+                           log_every=log).summary()
+    print(f"[serve] sequential at 0.25 x capacity: p50 {seq['p50_ms']} ms, p99 {seq['p99_ms']} ms",
+          file=sys.stderr, flush=True)
+    seq_reqs = make_requests(count, rate=0.0, seed=5)
+    seq_sat = serve_sequential(seq_reqs, precision=1, vcycles=2, log_every=log).summary()
+    # where the one-at-a-time time goes: requests the server runs solo (large grids) against the rest
+    from paper_1401_7824_amd.serve import runs_solo
+    big = sum(r.finished - r.admitted for r in seq_reqs if runs_solo(r, 1))
+    small = sum(r.finished - r.admitted for r in seq_reqs if not runs_solo(r, 1))
+    seq_sat["service_s_large_requests"] = round(big, 3)
+    seq_sat["service_s_other_requests"] = round(small, 3)
     print(f"[serve] sequential saturated: {seq_sat['throughput_req_s']} req/s", file=sys.stderr, flush=True)
     steps = sum(r.nsteps for r in make_requests(count, rate=0.0, seed=5))
     return {
@@ -559,7 +609,7 @@ def run_serve(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"serve: {count} requests, half 2D 127..1023, half 3D 31..255, heat / "
                                f"reaction-diffusion, tol 1e-5 / 1e-8, 1..20 steps, HBM budget "
-                               f"{args.serve_budget_gb} GiB, 64 slots per dimension"},
+                               f"{args.serve_budget_gb} GiB, 64 slots per dimension, {args.serve_solo} solo lanes"},
         "saturated": sat.summary(), "accuracy": accuracy, "rate_sweep": rows, "sequential_baseline_at_0.25": seq,
         "sequential_baseline_saturated": seq_sat,
         "capacity_vs_sequential": round(cap / seq_sat["throughput_req_s"], 2) if seq_sat["throughput_req_s"] else None,
@@ -788,8 +838,9 @@ def workload_text(name, cfg):
     return (f"{name}: {cfg['dim']}D n={cfg['n']} {'periodic' if cfg.get('bc', 0) == 1 else 'Dirichlet'} "
             f"nu={cfg['nu']} fe={['zero', 'cubic', 'WENO5 Burgers'][cfg['fe_kind']]} "
             f"{['Lobatto', 'Radau-right', 'Legendre'][cfg['node_kind']]} M={cfg['M']} dt={cfg['dt']} L=2 "
-            + ("compact 4th-order stencil with W, Jacobi "
-               f"V({cfg.get('nu_pre')},{cfg.get('nu_post')})" if cfg.get("stencil", 0) == 1 else "RBGS V(1,1)")
+            + ("compact 4th-order stencil with W, " if cfg.get("stencil", 0) == 1 else "")
+            + ("Jacobi" if cfg.get("smoother", 0) == 1 else "RBGS")
+            + f" V({cfg.get('nu_pre', 1)},{cfg.get('nu_post', 1)})"
             + f" tol={cfg['sdc_tol']}"
             + (" two-level MLSDC (coarse level (n-1)/2, FAS, cubic interpolation)" if cfg.get("levels", 1) == 2 else ""))
 
@@ -802,7 +853,7 @@ def serve_latency(args, torch, count=48):
     budget = int(args.serve_budget_gb * 2 ** 30)
 
     def server():
-        return Server(budget, slots_per_batch=64, precision=1, vcycles=2)
+        return Server(budget, slots_per_batch=64, precision=1, vcycles=2, solo_workers=args.serve_solo)
 
     server().serve(make_requests(8, rate=0.0, seed=99))
     sat = server().serve(make_requests(count, rate=0.0, seed=5))
@@ -910,6 +961,7 @@ COMPARE_VARIANTS = [
     # (name, params): classical SDC solves each implicit system to tol / 50;
     # ISDC runs L = 2 cycles of the given smoother (Sec. 3, Sec. 4.2)
     ("sdc_classical_rbgs11", dict(vcycles=0, smoother=0, nu_pre=1, nu_post=1)),
+    ("sdc_classical_jacobi33", dict(vcycles=0, smoother=1, nu_pre=3, nu_post=3)),
     ("isdc_rbgs11", dict(vcycles=2, smoother=0, nu_pre=1, nu_post=1)),
     ("isdc_rbgs22", dict(vcycles=2, smoother=0, nu_pre=2, nu_post=2)),
     ("isdc_jacobi22", dict(vcycles=2, smoother=1, nu_pre=2, nu_post=2)),

@@ -273,8 +273,10 @@ int isdc_mg_op(isdc_plan* plan, int32_t op, int32_t level, double c, int32_t pre
  * (the V-cycle of Sec. 3 is unchanged); only the launch shape differs.
  * On 3D levels of 127^3 and up, which run z-marching kernels (xy tiles of
  * 60x16 points in float32, 60x8 in float64), the shape picks the depth of a
- * workgroup's column of planes instead: 16, 32 or 8 planes (4, 8 or 2 on
- * 127^3).
+ * workgroup's column of planes instead: shape 0 16 planes (4 on 127^3),
+ * shape 2 8 (2), shape 1 the even depth at which every column of the level
+ * fits in one round of resident workgroups of the kernel (its occupancy per
+ * CU times the device's CUs).
  * isdc_autotune times the red-black kernels of every level with each shape
  * (three rounds of `reps` launches on `stream`, the fastest round of each
  * shape compared) and keeps the fastest; levels where the shape changes
@@ -417,6 +419,17 @@ int isdc_batch_set(isdc_batch* batch, int32_t slot, const isdc_problem* prob, co
  * slots are not affected.  *h_running (may be NULL) receives the number of
  * slots still running. */
 int isdc_batch_advance(isdc_batch* batch, void* stream, int32_t* h_running);
+
+/* Measurement of the batch sweep's launch schedule: `reps` more sweeps of
+ * the running slots (every one of which must have started its step, i.e. the
+ * batch was advanced once), either launched one kernel at a time as
+ * isdc_batch_advance does (graph = 0) or captured once into a HIP graph and
+ * replayed (graph = 1; `stream` must not be the null stream).  Writes the
+ * average microseconds per sweep (HIP events on `stream`) and the kernel
+ * launches per sweep; makes no decisions and leaves the running slots' states
+ * unspecified, so re-set the slots afterwards.  Synchronises `stream`. */
+int isdc_batch_time_sweeps(isdc_batch* batch, int32_t reps, int32_t graph, void* stream, double* h_us_per_sweep,
+                           int32_t* h_launches);
 
 /* State (ISDC_SLOT_*), status of a finished slot, steps completed and the
  * statistics of its last completed step.  Host only; outputs may be NULL. */

@@ -89,6 +89,7 @@ SIGNATURES = [
     ("isdc_batch_set", C.c_int, [_VP, C.c_int32, C.POINTER(Problem), C.POINTER(Params), _VP, C.c_size_t, _VP,
                                  C.c_double, C.c_int32]),
     ("isdc_batch_advance", C.c_int, [_VP, _VP, C.POINTER(C.c_int32)]),
+    ("isdc_batch_time_sweeps", C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _DP, C.POINTER(C.c_int32)]),
     ("isdc_batch_slot_info", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.POINTER(Stats)]),
     ("isdc_batch_release", C.c_int, [_VP, C.c_int32]),

@@ -540,9 +540,17 @@ void launch_quad_m(int M, const Map& m, BArgs a, hipStream_t s) {
     }
 }
 
+// Sweep timing request of isdc_batch_time_sweeps.
+struct SweepTiming {
+    int reps;
+    bool graph;
+    double us;
+    int launches;
+};
+
 // One batch sweep for the running slots (plus the begins and ends around it).
 template <typename T, int D>
-void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
+void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTiming* timing = nullptr) {
     const int cap = b->cap;
     // upload descriptors that changed
     for (int i = 0; i < cap; ++i)
@@ -619,6 +627,7 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
     for (int i : run) b->slots[i].need_begin = false;
     // ---- the sweep
     const int L = b->L;
+    auto sweep = [&]() {
     for (int p = 0; p < maxns; ++p) {
         ISDC_BLAUNCH((kb_rhs<T, D>), kThreads, mrhs[p], 0, A(o_rhs[p], p, 0, 0));
         for (int c = 0; c < L; ++c) {
@@ -646,6 +655,50 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run) {
     for (int M = 1; M <= ISDC_MAX_M; ++M)
         if (mq[M].total) launch_quad_m<D>(M, mq[M], A(o_q[M], 0, 0, 0), s);
     ISDC_BLAUNCH(kb_reduce, kThreads, mred, 0, A(o_red, 0, 0, 0));
+    };
+    if (timing) {
+        // measurement only: `reps` more sweeps of the running slots, eager or
+        // replayed from one captured graph; no decisions, states unspecified
+        hipEvent_t ev[2];
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        if (timing->graph) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            sweep();
+            HIPCHK(hipStreamEndCapture(s, &g));
+            HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            HIPCHK(hipGraphLaunch(ge, s));  // warm-up
+            HIPCHK(hipEventRecord(ev[0], s));
+            for (int r = 0; r < timing->reps; ++r) HIPCHK(hipGraphLaunch(ge, s));
+            HIPCHK(hipEventRecord(ev[1], s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipGraphExecDestroy(ge));
+            HIPCHK(hipGraphDestroy(g));
+        } else {
+            sweep();  // warm-up
+            HIPCHK(hipEventRecord(ev[0], s));
+            for (int r = 0; r < timing->reps; ++r) sweep();
+            HIPCHK(hipEventRecord(ev[1], s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        timing->us = 1e3 * (double)ms / timing->reps;
+        int launches = mred.total > 0;
+        for (int M = 1; M <= ISDC_MAX_M; ++M) launches += mq[M].total > 0;
+        for (int p = 0; p < maxns; ++p) {
+            launches += (mrhs[p].total > 0) + (mupd[p].total > 0);
+            int per_cycle = mtail[p].total > 0;
+            for (int l = 0; l < maxlev; ++l)
+                per_cycle += 2 * (mlev[p][l].total > 0) + (D == 3 && mres[p][l].total > 0);
+            launches += L * per_cycle;
+        }
+        timing->launches = launches;
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        return;
+    }
+    sweep();
     HIPCHK(hipMemcpyAsync(b->h_res, b->d_res, cap * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (FILE* trace = trace_stream()) {  // host time once the batch sweep's residuals are back
@@ -904,6 +957,38 @@ int isdc_batch_advance(isdc_batch* b, void* stream, int32_t* h_running) {
             for (auto& sl : b->slots) c += sl.state == SLOT_RUNNING;
             *h_running = c;
         }
+    });
+}
+
+int isdc_batch_time_sweeps(isdc_batch* b, int32_t reps, int32_t graph, void* stream, double* h_us_per_sweep,
+                           int32_t* h_launches) {
+    return guarded([&] {
+        as_batch(b);
+        if (reps < 1 || reps > 10000) fail(ISDC_E_INVAL, "reps must be in 1..10000");
+        if (graph != 0 && graph != 1) fail(ISDC_E_INVAL, "graph must be 0 or 1");
+        if (!h_us_per_sweep) fail(ISDC_E_INVAL, "h_us_per_sweep is NULL");
+        if (graph && !stream) fail(ISDC_E_INVAL, "graph capture needs a stream other than the null stream");
+        std::vector<int> run;
+        for (int i = 0; i < b->cap; ++i)
+            if (b->slots[i].state == SLOT_RUNNING) {
+                if (b->slots[i].need_begin) fail(ISDC_E_INVAL, "slots must have started their step (advance once first)");
+                run.push_back(i);
+            }
+        if (run.empty()) fail(ISDC_E_INVAL, "no running slot");
+        SweepTiming t{reps, graph != 0, 0.0, 0};
+        hipStream_t s = (hipStream_t)stream;
+        const int d = b->d;
+        if (b->prec == ISDC_PREC_FP64) {
+            if (d == 1) advance_impl<double, 1>(b, s, run, &t);
+            else if (d == 2) advance_impl<double, 2>(b, s, run, &t);
+            else advance_impl<double, 3>(b, s, run, &t);
+        } else {
+            if (d == 1) advance_impl<float, 1>(b, s, run, &t);
+            else if (d == 2) advance_impl<float, 2>(b, s, run, &t);
+            else advance_impl<float, 3>(b, s, run, &t);
+        }
+        *h_us_per_sweep = t.us;
+        if (h_launches) *h_launches = t.launches;
     });
 }
 

@@ -108,7 +108,8 @@ template <int K> struct JTile {
 template <typename T, bool PER, int K, bool ZERO, bool C9 = true>
 __global__ void __launch_bounds__(kThreads)
 k_cjacobi_k(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
-            CCoef<T> k) {
+            CCoef<T> k, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using J = JTile<K>;
     constexpr int L = kJL;
     __shared__ T sa[J::N];
@@ -270,7 +271,8 @@ __device__ __forceinline__ void cj_load(T (&v)[IP], const T* __restrict__ u, int
 template <typename T, bool PER, int K, bool ZERO, bool C9 = true>
 __global__ void __launch_bounds__(kThreads)
 k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc, int n,
-        int ntx, int nty, CCoef<T> k) {
+        int ntx, int nty, CCoef<T> k, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using V = CVT<K>;
     constexpr int L = kJL, H = V::H;
     __shared__ T sa[V::N];
@@ -362,10 +364,14 @@ k_cjres(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_o
     }
 }
 
-template <typename T, bool PER, int K, bool C9 = true>
+// MODE 0 writes the result to e_out; MODE 1 writes the float64 node value
+// g + e to u_out instead (the last launch of an implicit solve).
+template <typename T, bool PER, int K, bool C9 = true, int MODE = 0>
 __global__ void __launch_bounds__(kThreads)
 k_cpjac(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out, int n,
-        int ntx, int nty, CCoef<T> k) {
+        int ntx, int nty, CCoef<T> k, const double* __restrict__ g, double* __restrict__ u_out,
+        const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using V = CVT<K>;
     constexpr int L = kJL;
     constexpr int COLS = V::TX + 2 * K, ROWS = V::TY + 2 * K;
@@ -449,7 +455,11 @@ k_cpjac(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict
     for (int i = 0; i < V::IP; ++i) {
         const int q = j + i * V::RP;
         const int y = by + q;
-        if (q >= K && q < K + V::TY && y < n) e_out[(size_t)y * n + x] = src[threadIdx.x + i * kThreads];
+        if (q >= K && q < K + V::TY && y < n) {
+            const size_t gi = (size_t)y * n + x;
+            if (MODE == 0) e_out[gi] = src[threadIdx.x + i * kThreads];
+            else u_out[gi] = g[gi] + (double)src[threadIdx.x + i * kThreads];
+        }
     }
 }
 
@@ -835,10 +845,10 @@ hipError_t launch_cjacobi_steps(int n, const CCoef<T>& k, int nsteps, bool zero,
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, JTile<KV>::TX, JTile<KV>::TY, 1, ntx, nty, nb);                                     \
-        if (per && zero) hipLaunchKernelGGL((k_cjacobi_k<T, true, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
-        else if (per) hipLaunchKernelGGL((k_cjacobi_k<T, true, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
-        else if (zero) hipLaunchKernelGGL((k_cjacobi_k<T, false, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
-        else hipLaunchKernelGGL((k_cjacobi_k<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        if (per && zero) ISDC_GLAUNCH((k_cjacobi_k<T, true, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else if (per) ISDC_GLAUNCH((k_cjacobi_k<T, true, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else if (zero) ISDC_GLAUNCH((k_cjacobi_k<T, false, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else ISDC_GLAUNCH((k_cjacobi_k<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
     }
     if (nsteps == 2) ISDC_CJK(2)
     else if (nsteps == 3) ISDC_CJK(3)
@@ -854,10 +864,10 @@ hipError_t launch_cjres(int n, const CCoef<T>& k, int nsteps, bool zero, const T
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
-        if (per && zero) hipLaunchKernelGGL((k_cjres<T, true, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
-        else if (per) hipLaunchKernelGGL((k_cjres<T, true, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
-        else if (zero) hipLaunchKernelGGL((k_cjres<T, false, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
-        else hipLaunchKernelGGL((k_cjres<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        if (per && zero) ISDC_GLAUNCH((k_cjres<T, true, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        else if (per) ISDC_GLAUNCH((k_cjres<T, true, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        else if (zero) ISDC_GLAUNCH((k_cjres<T, false, KV, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        else ISDC_GLAUNCH((k_cjres<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
     }
     if (nsteps == 1) ISDC_CJR(1)
     else if (nsteps == 2) ISDC_CJR(2)
@@ -874,8 +884,8 @@ hipError_t launch_cpjac(int n, const CCoef<T>& k, int nsteps, const T* r, const 
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
-        if (per) hipLaunchKernelGGL((k_cpjac<T, true, KV>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k); \
-        else hipLaunchKernelGGL((k_cpjac<T, false, KV>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k); \
+        if (per) ISDC_GLAUNCH((k_cpjac<T, true, KV>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k, nullptr, nullptr); \
+        else ISDC_GLAUNCH((k_cpjac<T, false, KV>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k, nullptr, nullptr); \
     }
     if (nsteps == 1) ISDC_CPJ(1)
     else if (nsteps == 2) ISDC_CPJ(2)
@@ -894,8 +904,8 @@ hipError_t launch_jacobi5_steps(int n, const CCoef<T>& k, int nsteps, bool zero,
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, JTile<KV>::TX, JTile<KV>::TY, 1, ntx, nty, nb);                                     \
-        if (zero) ISDC_LAUNCH((k_cjacobi_k<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
-        else ISDC_LAUNCH((k_cjacobi_k<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        if (zero) ISDC_GLAUNCH((k_cjacobi_k<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
+        else ISDC_GLAUNCH((k_cjacobi_k<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, k); \
     }
     if (nsteps == 1) ISDC_J5K(1)
     else if (nsteps == 2) ISDC_J5K(2)
@@ -912,8 +922,8 @@ hipError_t launch_jres5(int n, const CCoef<T>& k, int nsteps, bool zero, const T
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
-        if (zero) ISDC_LAUNCH((k_cjres<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
-        else ISDC_LAUNCH((k_cjres<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        if (zero) ISDC_GLAUNCH((k_cjres<T, false, KV, true, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
+        else ISDC_GLAUNCH((k_cjres<T, false, KV, false, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, k); \
     }
     if (nsteps == 1) ISDC_J5R(1)
     else if (nsteps == 2) ISDC_J5R(2)
@@ -925,12 +935,13 @@ hipError_t launch_jres5(int n, const CCoef<T>& k, int nsteps, bool zero, const T
 
 template <typename T>
 hipError_t launch_pjac5(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
-                        hipStream_t s) {
+                        const double* g, double* u_out, hipStream_t s) {
 #define ISDC_P5J(KV)                                                                                          \
     {                                                                                                         \
         int ntx, nty, nb;                                                                                     \
         tile_counts<2>(n, CVT<KV>::TX, CVT<KV>::TY, 1, ntx, nty, nb);                                         \
-        ISDC_LAUNCH((k_cpjac<T, false, KV, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k); \
+        if (u_out) ISDC_GLAUNCH((k_cpjac<T, false, KV, false, 1>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k, g, u_out); \
+        else ISDC_GLAUNCH((k_cpjac<T, false, KV, false, 0>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, k, nullptr, nullptr); \
     }
     if (nsteps == 1) ISDC_P5J(1)
     else if (nsteps == 2) ISDC_P5J(2)
@@ -1075,7 +1086,8 @@ hipError_t launch_ctail(const MGConfig& mg, int n, double c, double w, double h,
     template hipError_t launch_cresfw<T>(int, const CCoef<T>&, const T*, const T*, T*, bool, hipStream_t);          \
     template hipError_t launch_jacobi5_steps<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, hipStream_t); \
     template hipError_t launch_jres5<T>(int, const CCoef<T>&, int, bool, const T*, const T*, T*, T*, hipStream_t);  \
-    template hipError_t launch_pjac5<T>(int, const CCoef<T>&, int, const T*, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_pjac5<T>(int, const CCoef<T>&, int, const T*, const T*, const T*, T*, const double*, \
+                                        double*, hipStream_t);                                                     \
     template hipError_t launch_cprolong_p<T>(int, const T*, T*, hipStream_t);                                       \
     template hipError_t launch_cresnorm<T>(int, const CCoef<T>&, const T*, const T*, double*, int*, bool, hipStream_t); \
     template hipError_t launch_crhs<T>(const CRhsArgs&, T*, bool, hipStream_t);                                    \

@@ -42,6 +42,17 @@ LaunchProbe*& armed_probe();
         }                                                                                                 \
     } while (0)
 
+// Device-side gate of a solve's V-cycles (classical SDC / early exit): while
+// the runtime has set a gate on the calling thread, the multigrid launchers
+// pass it to their kernels as the last argument (ISDC_GLAUNCH), and each
+// kernel returns at once when gate[0] != 0 -- set on the device by
+// launch_reduce_gate once the inner residual meets its tolerance -- so a
+// whole run of cycles can be enqueued before the host looks at the result.
+const int*& current_gate();
+
+#define ISDC_GLAUNCH(kernel, grid, block, shmem, stream, ...) \
+    ISDC_LAUNCH(kernel, grid, block, shmem, stream, __VA_ARGS__, ::isdc::current_gate())
+
 // ---------------------------------------------------------------- multigrid launchers
 // Coefficients of A_l = I - c L_{h_l} on one level: a = c / h_l^2,
 // diag = 1 + 2 d a, invdiag = 1 / diag, w = Jacobi weight.
@@ -125,6 +136,16 @@ hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T
 
 // out[0] = NaN-propagating max of partial[0..nblocks).
 hipError_t launch_reduce_max(const double* partial, int nblocks, double* out, hipStream_t s);
+
+// gate[0] = gate[1] = 0 (a kernel, not a memset).
+hipError_t launch_gate_reset(int* gate, hipStream_t s);
+// The inner stopping test on the device: unless gate[0] is set, res = max of
+// partial[0..nblocks) goes to *res_out, and gate[0] = 1 if res <= tol (Sec. 3:
+// the classical solve stops once its residual meets the inner tolerance) or
+// gate[1] >= limit; otherwise, if count_cycle, gate[1] += 1 (the cycle that
+// follows this test runs).
+hipError_t launch_reduce_gate(const double* partial, int nblocks, double tol, int limit, int count_cycle, int* gate,
+                              double* res_out, hipStream_t s);
 
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, T value, hipStream_t s);
@@ -263,9 +284,10 @@ hipError_t launch_jacobi5_steps(int n, const CCoef<T>& k, int nsteps, bool zero,
 template <typename T>
 hipError_t launch_jres5(int n, const CCoef<T>& k, int nsteps, bool zero, const T* r, const T* e_in, T* e_out, T* rc,
                         hipStream_t s);
+// u_out != NULL: the result is not written to e_out; u_out = g + result (float64).
 template <typename T>
 hipError_t launch_pjac5(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
-                        hipStream_t s);
+                        const double* g, double* u_out, hipStream_t s);
 template <typename T>
 hipError_t launch_cpjac(int n, const CCoef<T>& k, int nsteps, const T* r, const T* e_in, const T* ec, T* e_out,
                         bool per, hipStream_t s);

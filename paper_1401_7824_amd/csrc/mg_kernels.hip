@@ -62,7 +62,8 @@ __device__ __forceinline__ T nbsum(const T* __restrict__ u, int n, int x, int y,
 template <typename T, int D, bool ZERO>
 __global__ void __launch_bounds__(kBlock)
 k_jacobi(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ out, int n, T a, T diag,
-         T invdiag, T w) {
+         T invdiag, T w, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     int x, y, z;
     coords<D>(n, x, y, z, blockIdx.x * kBlock + threadIdx.x);
     if (x >= n) return;
@@ -83,7 +84,8 @@ k_jacobi(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ out
 // red points get rhs / diag and black points are cleared.
 template <typename T, int D, bool ZERO>
 __global__ void __launch_bounds__(kBlock)
-k_rbgs_half(const T* __restrict__ rhs, T* __restrict__ u, int n, T a, T invdiag, int colour) {
+k_rbgs_half(const T* __restrict__ rhs, T* __restrict__ u, int n, T a, T invdiag, int colour, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     int j, y, z;
     coords<D>(n, j, y, z, blockIdx.x * kBlock + threadIdx.x);
     int par = (colour + y + z) & 1;
@@ -114,7 +116,8 @@ __device__ __forceinline__ T residual_at(const T* __restrict__ rhs, const T* __r
 // One thread per coarse point (X,Y,Z); the fine centre is (2X+1, 2Y+1, 2Z+1).
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-k_restrict(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ rc, int n, T a, T diag) {
+k_restrict(const T* __restrict__ rhs, const T* __restrict__ u, T* __restrict__ rc, int n, T a, T diag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     const int nc = (n - 1) / 2;
     int X, Y, Z;
     coords<D>(nc, X, Y, Z, blockIdx.x * kBlock + threadIdx.x);
@@ -157,7 +160,8 @@ __device__ __forceinline__ int interp_taps(int i, int nc, int* idx, float* w) {
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-k_prolong(const T* __restrict__ ec, T* __restrict__ u, int n) {
+k_prolong(const T* __restrict__ ec, T* __restrict__ u, int n, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     const int nc = (n - 1) / 2;
     int x, y, z;
     coords<D>(n, x, y, z, blockIdx.x * kBlock + threadIdx.x);
@@ -198,7 +202,8 @@ __device__ double block_max(double v) {
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-k_resnorm(const T* __restrict__ rhs, const T* __restrict__ u, int n, T a, T diag, double* partial) {
+k_resnorm(const T* __restrict__ rhs, const T* __restrict__ u, int n, T a, T diag, double* partial, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     const size_t N = (D == 1) ? (size_t)n : (D == 2 ? (size_t)n * n : (size_t)n * n * n);
     double m = 0.0;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
@@ -221,14 +226,34 @@ k_reduce_max(const double* __restrict__ partial, int nb, double* __restrict__ ou
     if (threadIdx.x == 0) out[0] = m;
 }
 
+__global__ void __launch_bounds__(64) k_gate_reset(int* __restrict__ gate) {
+    if (threadIdx.x < 2) gate[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reduce_gate(const double* __restrict__ partial, int nb, double tol, int limit, int count_cycle, int* __restrict__ gate,
+              double* __restrict__ res_out) {
+    if (gate[0]) return;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) m = nanmax(m, partial[i]);
+    m = block_max(m);
+    if (threadIdx.x == 0) {
+        res_out[0] = m;
+        if (m <= tol || gate[1] >= limit) gate[0] = 1;
+        else if (count_cycle) gate[1] += 1;
+    }
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, size_t count, T v) {
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, size_t count, T v, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
         p[i] = v;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_copy(const T* __restrict__ s, T* __restrict__ d, size_t count) {
+__global__ void __launch_bounds__(kBlock) k_copy(const T* __restrict__ s, T* __restrict__ d, size_t count, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
         d[i] = s[i];
 }
@@ -269,9 +294,9 @@ hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zer
         dim3 g = stencil_grid(d, n, n);
         ISDC_DISPATCH_D(d, {
             if (zero_guess)
-                ISDC_LAUNCH((k_jacobi<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+                ISDC_GLAUNCH((k_jacobi<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
             else
-                ISDC_LAUNCH((k_jacobi<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
+                ISDC_GLAUNCH((k_jacobi<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_in, u_out, n, co.a, co.diag, co.invdiag, co.w);
         });
         return hipGetLastError();
     }
@@ -279,10 +304,10 @@ hipError_t launch_smooth(const MGConfig& cfg, int n, const Coef<T>& co, bool zer
     dim3 g = stencil_grid(d, (n + 1) / 2, n);
     ISDC_DISPATCH_D(d, {
         if (zero_guess)
-            ISDC_LAUNCH((k_rbgs_half<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+            ISDC_GLAUNCH((k_rbgs_half<T, D, true>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
         else
-            ISDC_LAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
-        ISDC_LAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 1);
+            ISDC_GLAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 0);
+        ISDC_GLAUNCH((k_rbgs_half<T, D, false>), g, dim3(kBlock), 0, s, rhs, u_out, n, co.a, co.invdiag, 1);
     });
     return hipGetLastError();
 }
@@ -291,14 +316,14 @@ template <typename T>
 hipError_t launch_restrict(int d, int n, const Coef<T>& co, const T* rhs, const T* u, T* rc, hipStream_t s) {
     int nc = (n - 1) / 2;
     dim3 g = stencil_grid(d, nc, nc);
-    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_restrict<T, D>), g, dim3(kBlock), 0, s, rhs, u, rc, n, co.a, co.diag); });
+    ISDC_DISPATCH_D(d, { ISDC_GLAUNCH((k_restrict<T, D>), g, dim3(kBlock), 0, s, rhs, u, rc, n, co.a, co.diag); });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(int d, int n, const T* ec, T* u, hipStream_t s) {
     dim3 g = stencil_grid(d, n, n);
-    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_prolong<T, D>), g, dim3(kBlock), 0, s, ec, u, n); });
+    ISDC_DISPATCH_D(d, { ISDC_GLAUNCH((k_prolong<T, D>), g, dim3(kBlock), 0, s, ec, u, n); });
     return hipGetLastError();
 }
 
@@ -308,7 +333,7 @@ hipError_t launch_resnorm(int d, int n, const Coef<T>& co, const T* rhs, const T
     size_t N = d == 1 ? (size_t)n : (d == 2 ? (size_t)n * n : (size_t)n * n * n);
     int nb = reduce_blocks(N);
     *nblocks = nb;
-    ISDC_DISPATCH_D(d, { ISDC_LAUNCH((k_resnorm<T, D>), dim3(nb), dim3(kBlock), 0, s, rhs, u, n, co.a, co.diag, partial); });
+    ISDC_DISPATCH_D(d, { ISDC_GLAUNCH((k_resnorm<T, D>), dim3(nb), dim3(kBlock), 0, s, rhs, u, n, co.a, co.diag, partial); });
     return hipGetLastError();
 }
 
@@ -317,17 +342,28 @@ hipError_t launch_reduce_max(const double* partial, int nblocks, double* out, hi
     return hipGetLastError();
 }
 
+hipError_t launch_gate_reset(int* gate, hipStream_t s) {
+    ISDC_LAUNCH(k_gate_reset, dim3(1), dim3(64), 0, s, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_gate(const double* partial, int nblocks, double tol, int limit, int count_cycle, int* gate,
+                              double* res_out, hipStream_t s) {
+    ISDC_LAUNCH(k_reduce_gate, dim3(1), dim3(kBlock), 0, s, partial, nblocks, tol, limit, count_cycle, gate, res_out);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, T value, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    ISDC_LAUNCH((k_fill<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, p, count, value);
+    ISDC_GLAUNCH((k_fill<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, p, count, value);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, size_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    ISDC_LAUNCH((k_copy<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, src, dst, count);
+    ISDC_GLAUNCH((k_copy<T>), dim3(reduce_blocks(count)), dim3(kBlock), 0, s, src, dst, count);
     return hipGetLastError();
 }
 

@@ -65,9 +65,11 @@ using MTile = MTileT<sizeof(T) == 8 ? 8 : 16>;
 // kernels are used instead: a column costs a chain of Z + 4 dependent steps,
 // which only pays where the level is large enough to fill the chip anyway.
 // The tile shape of a marched level picks the depth: shape 0 the default,
-// 1 twice as deep (fewer workgroups, less z overlap), 2 half as deep (more
-// workgroups, shorter chains).  Every depth is even, so a column starts on an
-// even plane, which the coarse-plane bookkeeping of the prolongation assumes.
+// 1 twice as deep (fewer workgroups, less z overlap; the single-instance
+// launchers replace it by the depth that fits all columns in one round of
+// resident workgroups), 2 half as deep (more workgroups, shorter chains).
+// Every depth is even, so a column starts on an even plane, which the
+// coarse-plane bookkeeping of the prolongation assumes.
 __host__ __device__ constexpr int march_depth(int n, int shape = 0) {
     const int base = n >= 255 ? 16 : (n >= 127 ? 4 : 0);
     return shape == 1 ? 2 * base : (shape == 2 ? base / 2 : base);

@@ -26,6 +26,8 @@
 // halo re-reads inside one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 #include "mg_device.h"
 #include "mg_march.h"
@@ -40,7 +42,8 @@ namespace {
 template <typename T, int D, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty,
-            T a, T invdiag) {
+            T a, T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using TL = TileS<D, S>;
     int x0, y0, z0;
     tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
@@ -50,7 +53,8 @@ k_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__
 template <typename T, int D>
 __global__ void __launch_bounds__(kThreads)
 k_restrict_tile(const T* __restrict__ r, const T* __restrict__ e, T* __restrict__ rc, int n, int ntx, int nty,
-                T a, T diag) {
+                T a, T diag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     int X0, Y0, Z0;
     tile_origin(ntx, nty, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, X0, Y0, Z0);
     restrict_tile_body<T, D>(r, e, rc, n, X0, Y0, Z0, a, diag);
@@ -59,7 +63,8 @@ k_restrict_tile(const T* __restrict__ r, const T* __restrict__ e, T* __restrict_
 template <typename T, int D, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rbgs_restrict_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
-                     int n, int ntx, int nty, T a, T diag, T invdiag) {
+                     int n, int ntx, int nty, T a, T diag, T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using TL = TileS<D, S>;
     int x0, y0, z0;
     tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
@@ -69,7 +74,8 @@ k_rbgs_restrict_tile(const T* __restrict__ r, const T* __restrict__ e_in, T* __r
 template <typename T, int D, int MODE, int S>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
-                    int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
+                    int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using TL = TileS<D, S>;
     int x0, y0, z0;
     tile_origin(ntx, nty, TL::X, TL::Y, TL::Z, x0, y0, z0);
@@ -81,7 +87,8 @@ k_prolong_rbgs_tile(const T* __restrict__ r, const T* __restrict__ e_in, const T
 template <typename T, bool PRO, int MODE, bool ZERO>
 __global__ void __launch_bounds__(kThreads)
 k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec, T* __restrict__ e_out,
-             int n, int ntx, int nty, int mz, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out) {
+             int n, int ntx, int nty, int mz, T a, T invdiag, const double* __restrict__ g, double* __restrict__ u_out, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     int x0, y0, z0;
     tile_origin(ntx, nty, MTile<T>::X, MTile<T>::Y, mz, x0, y0, z0);
     march_rbgs_body<T, PRO, MODE, ZERO>(r, e_in, ec, e_out, n, x0, y0, z0, mz, a, invdiag, g, u_out);
@@ -93,7 +100,8 @@ k_march_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __res
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_march_restrict(const T* __restrict__ r, const T* __restrict__ e, T* __restrict__ rc, int n, int ntx, int nty,
-                 int mzc, T a, T diag) {
+                 int mzc, T a, T diag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     int X0, Y0, Z0;
     tile_origin(ntx, nty, MRTile::X, MRTile::Y, mzc, X0, Y0, Z0);
     march_restrict_body<T>(r, e, rc, n, X0, Y0, Z0, mzc, a, diag);
@@ -102,7 +110,8 @@ k_march_restrict(const T* __restrict__ r, const T* __restrict__ e, T* __restrict
 template <typename T, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty, T a,
-            T invdiag) {
+            T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using RT = typename RowShape<S>::RT;
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
@@ -112,7 +121,8 @@ k_rows_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__
 template <typename T, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_rbgs_restrict(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc,
-                     int n, int ntx, int nty, T a, T diag, T invdiag) {
+                     int n, int ntx, int nty, T a, T diag, T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using RT = typename RowShape<S>::RT;
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
@@ -122,7 +132,8 @@ k_rows_rbgs_restrict(const T* __restrict__ r, const T* __restrict__ e_in, T* __r
 template <typename T, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_rhs_rbgs_restrict(RhsArgs ra, T* __restrict__ r, T* __restrict__ e_out, T* __restrict__ rc, int n, int ntx,
-                         int nty, T a, T diag, T invdiag) {
+                         int nty, T a, T diag, T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using RT = typename RowShape<S>::RT;
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
@@ -136,7 +147,8 @@ template <typename T, int MODE, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_prolong_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T* __restrict__ ec,
                     T* __restrict__ e_out, int n, int ntx, int nty, T a, T invdiag, const double* __restrict__ g,
-                    double* __restrict__ u_out) {
+                    double* __restrict__ u_out, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     using RT = typename RowShape<S>::RT;
     int x0, y0, z0;
     tile_origin(ntx, nty, RT::TX, RT::TY, 1, x0, y0, z0);
@@ -146,7 +158,8 @@ k_rows_prolong_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, const T
 template <typename T, int D>
 __global__ void __launch_bounds__(kTail)
 k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, int smoother, int nu1, int nu2,
-       double omega, int zero_guess) {
+       double omega, int zero_guess, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
     tailc_body<T, D>(rhs_g, e_g, n_t, tc, smoother, nu1, nu2, omega, zero_guess);
 }
 
@@ -182,18 +195,54 @@ k_tail(const T* __restrict__ rhs_g, T* __restrict__ e_g, int n_t, TailCoefs tc, 
         default: return hipErrorInvalidValue;                           \
     }
 
+// Workgroups of one z-march kernel that are resident on the device at once
+// (its occupancy per CU from the compiled kernel's registers and LDS, times
+// the CUs), read once per kernel; 0 if the runtime cannot say.
+template <typename T, bool PRO, int MODE, bool ZERO>
+int march_resident() {
+    static const int v = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_march_rbgs<T, PRO, MODE, ZERO>, kThreads, 0) !=
+            hipSuccess)
+            return 0;
+        return per * cus;
+    }();
+    return v;
+}
+
+// Column depth of a marched level for tile shape `shape`: shapes 0 and 2 as
+// march_depth (16 / 8 planes at 255^3); shape 1 the even depth at which all
+// columns of the level fit in one round of resident workgroups, so that no
+// second, partly empty round follows the first.
+inline int march_depth_fitted(int n, int shape, int nxy, int resident) {
+    if (shape != 1 || resident <= 0) return march_depth(n, shape);
+    const int cols = std::max(1, resident / nxy);
+    int dz = (n + cols - 1) / cols;
+    dz += dz & 1;
+    return std::max(2, dz);
+}
+
+template <typename T, bool PRO, int MODE, bool ZERO>
+int march_depth_of(int n, int shape) {
+    int ntx, nty, nb;
+    tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, n, ntx, nty, nb);
+    return march_depth_fitted(n, shape, ntx * nty, shape == 1 ? march_resident<T, PRO, MODE, ZERO>() : 0);
+}
+
 template <typename T>
 hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                             hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
         if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
-        const int mz = march_depth(n, shape);
+        const int mz = zero ? march_depth_of<T, false, 0, true>(n, shape) : march_depth_of<T, false, 0, false>(n, shape);
         int ntx, nty, nb;
         tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (zero)
-            ISDC_LAUNCH((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+            ISDC_GLAUNCH((k_march_rbgs<T, false, 0, true>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         else
-            ISDC_LAUNCH((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
+            ISDC_GLAUNCH((k_march_rbgs<T, false, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, (const T*)nullptr, e_out, n, ntx, nty, mz, co.a, co.invdiag, (const double*)nullptr, (double*)nullptr);
         return hipGetLastError();
     }
     if (d == 2) {
@@ -202,9 +251,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (zero)
-                ISDC_LAUNCH((k_rows_rbgs<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+                ISDC_GLAUNCH((k_rows_rbgs<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
             else
-                ISDC_LAUNCH((k_rows_rbgs<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+                ISDC_GLAUNCH((k_rows_rbgs<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
         });
         return hipGetLastError();
     }
@@ -213,9 +262,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
         int ntx, nty, nb;
         tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (zero)
-            ISDC_LAUNCH((k_rbgs_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            ISDC_GLAUNCH((k_rbgs_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
         else
-            ISDC_LAUNCH((k_rbgs_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
+            ISDC_GLAUNCH((k_rbgs_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, n, ntx, nty, co.a, co.invdiag);
     });
     return hipGetLastError();
 }
@@ -227,14 +276,14 @@ hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, con
         const int mzc = march_restrict_depth();
         int ntx, nty, nb;
         tile_counts<3>(nc, MRTile::X, MRTile::Y, mzc, ntx, nty, nb);
-        ISDC_LAUNCH((k_march_restrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, mzc, co.a,
+        ISDC_GLAUNCH((k_march_restrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, mzc, co.a,
                            co.diag);
         return hipGetLastError();
     }
     ISDC_DISPATCH_D(d, {
         int ntx, nty, nb;
         tile_counts<D>(nc, CTile<D>::X, CTile<D>::Y, CTile<D>::Z, ntx, nty, nb);
-        ISDC_LAUNCH((k_restrict_tile<T, D>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, co.a, co.diag);
+        ISDC_GLAUNCH((k_restrict_tile<T, D>), dim3(nb), dim3(kThreads), 0, s, r, e, rc, n, ntx, nty, co.a, co.diag);
     });
     return hipGetLastError();
 }
@@ -249,9 +298,9 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (zero)
-                ISDC_LAUNCH((k_rows_rbgs_restrict<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_GLAUNCH((k_rows_rbgs_restrict<T, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
             else
-                ISDC_LAUNCH((k_rows_rbgs_restrict<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_GLAUNCH((k_rows_rbgs_restrict<T, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
         });
         return hipGetLastError();
     }
@@ -261,9 +310,9 @@ hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero,
             int ntx, nty, nb;
             tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
             if (zero)
-                ISDC_LAUNCH((k_rbgs_restrict_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_GLAUNCH((k_rbgs_restrict_tile<T, D, true, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
             else
-                ISDC_LAUNCH((k_rbgs_restrict_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+                ISDC_GLAUNCH((k_rbgs_restrict_tile<T, D, false, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
         }
     });
     return hipGetLastError();
@@ -277,7 +326,7 @@ hipError_t launch_rhs_rbgs_restrict_tile(int d, int n, const RhsArgs& ra, const 
         using RT = typename RowShape<S>::RT;
         int ntx, nty, nb;
         tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
-        ISDC_LAUNCH((k_rows_rhs_rbgs_restrict<T, S>), dim3(nb), dim3(kThreads), 0, s, ra, r, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
+        ISDC_GLAUNCH((k_rows_rhs_rbgs_restrict<T, S>), dim3(nb), dim3(kThreads), 0, s, ra, r, e_out, rc, n, ntx, nty, co.a, co.diag, co.invdiag);
     });
     return hipGetLastError();
 }
@@ -287,15 +336,17 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
                                     T* e_out, const double* g, double* u_out, int mode, hipStream_t s, int shape) {
     if (d == 3 && march_depth(n) > 0) {
         if (shape < 0 || shape >= kShapes) return hipErrorInvalidValue;
-        const int mz = march_depth(n, shape);
+        const int mz = mode == 0 ? march_depth_of<T, true, 0, false>(n, shape)
+                                 : (mode == 1 ? march_depth_of<T, true, 1, false>(n, shape)
+                                              : march_depth_of<T, true, 2, false>(n, shape));
         int ntx, nty, nb;
         tile_counts<3>(n, MTile<T>::X, MTile<T>::Y, mz, ntx, nty, nb);
         if (mode == 0)
-            ISDC_LAUNCH((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_march_rbgs<T, true, 0, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else if (mode == 1)
-            ISDC_LAUNCH((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_march_rbgs<T, true, 1, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         else
-            ISDC_LAUNCH((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_march_rbgs<T, true, 2, false>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, mz, co.a, co.invdiag, g, u_out);
         return hipGetLastError();
     }
     if (d == 2) {
@@ -304,11 +355,11 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
             int ntx, nty, nb;
             tile_counts<2>(n, RT::TX, RT::TY, 1, ntx, nty, nb);
             if (mode == 0)
-                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_GLAUNCH((k_rows_prolong_rbgs<T, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
             else if (mode == 1)
-                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_GLAUNCH((k_rows_prolong_rbgs<T, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
             else
-                ISDC_LAUNCH((k_rows_prolong_rbgs<T, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+                ISDC_GLAUNCH((k_rows_prolong_rbgs<T, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         });
         return hipGetLastError();
     }
@@ -317,11 +368,11 @@ hipError_t launch_prolong_rbgs_tile(int d, int n, const Coef<T>& co, const T* r,
         int ntx, nty, nb;
         tile_counts<D>(n, TL::X, TL::Y, TL::Z, ntx, nty, nb);
         if (mode == 0)
-            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_prolong_rbgs_tile<T, D, 0, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else if (mode == 1)
-            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_prolong_rbgs_tile<T, D, 1, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
         else
-            ISDC_LAUNCH((k_prolong_rbgs_tile<T, D, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
+            ISDC_GLAUNCH((k_prolong_rbgs_tile<T, D, 2, S>), dim3(nb), dim3(kThreads), 0, s, r, e_in, ec, e_out, n, ntx, nty, co.a, co.invdiag, g, u_out);
     });
     return hipGetLastError();
 }
@@ -346,7 +397,7 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
         if (m == 1) break;
     }
     ISDC_DISPATCH_D(cfg.d, {
-        ISDC_LAUNCH((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, cfg.smoother, cfg.nu_pre,
+        ISDC_GLAUNCH((k_tail<T, D>), dim3(1), dim3(kTail), 0, s, rhs, e, n, tc, cfg.smoother, cfg.nu_pre,
                            cfg.nu_post, cfg.omega, zero_guess ? 1 : 0);
     });
     return hipGetLastError();

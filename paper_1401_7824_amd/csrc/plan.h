@@ -133,6 +133,12 @@ struct isdc_plan {
     isdc_stats stats;
     double* h_pinned = nullptr;
     isdc::ProbeState probe;
+    // device-side inner stopping test: cycles each substep needed in its last
+    // solve and in the first sweep of the last step (0: none yet), and the
+    // substep being solved
+    int gate_hint[ISDC_MAX_M] = {0};
+    int gate_hint_first[ISDC_MAX_M] = {0};
+    int gate_substep = 0;
 };
 
 namespace isdc {

@@ -33,6 +33,10 @@ FILE* trace_stream() {
     }();
     return stream;
 }
+const int*& current_gate() {
+    thread_local const int* gate = nullptr;
+    return gate;
+}
 LaunchProbe*& armed_probe() {
     thread_local LaunchProbe* probe = nullptr;
     return probe;
@@ -337,13 +341,13 @@ void smooth_steps(isdc_plan* p, const MGConfig& mg, int nsteps, int l, const Coe
 // another; further steps three per launch.  Result in e (tmp: scratch of the
 // level's size).
 template <typename T>
-void jvcycle5_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp,
-                  hipStream_t s) {
+bool jvcycle5_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, const T* rhs, T* e, T* tmp,
+                  hipStream_t s, const Fuse& fuse = Fuse()) {
     const Level& L = p->lev[l];
     if (l >= p->tail) {
         ProbeScope probe(p, l == p->tail ? ISDC_KERNEL_TAIL : -2, 0, mg_bytes(p, ISDC_KERNEL_TAIL, l));
         HIPCHK(launch_tail<T>(mg, L.n, c, L.h, zero, rhs, e, s));
-        return;
+        return false;
     }
     const CCoef<T> k = make_coef5<T>(c, L.h, mg.omega);
     T* cur = e;
@@ -373,9 +377,15 @@ void jvcycle5_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, 
     int post = mg.nu_post;
     if (post > 0) {
         const int first = std::min(3, post);
+        // a single post-smoothing launch can write the node value g + e itself
+        if (post == first && fuse.mode == 1) {
+            ProbeScope probe(p, ISDC_KERNEL_PROLONG_UPDATE, l, mg_bytes(p, ISDC_KERNEL_PROLONG_UPDATE, l));
+            HIPCHK(launch_pjac5<T>(L.n, k, first, rhs, cur, (const T*)C.e, other, fuse.g, fuse.u_out, s));
+            return true;
+        }
         {
             ProbeScope probe(p, ISDC_KERNEL_PROLONG_SMOOTH, l, mg_bytes(p, ISDC_KERNEL_PROLONG_SMOOTH, l));
-            HIPCHK(launch_pjac5<T>(L.n, k, first, rhs, cur, (const T*)C.e, other, s));
+            HIPCHK(launch_pjac5<T>(L.n, k, first, rhs, cur, (const T*)C.e, other, nullptr, nullptr, s));
         }
         std::swap(cur, other);
         post -= first;
@@ -389,6 +399,7 @@ void jvcycle5_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, 
         HIPCHK(launch_prolong<T>(2, L.n, (const T*)C.e, cur, s));
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
+    return false;
 }
 
 // One V-cycle on level l for (I - c L) e = rhs starting from e (or from zero);
@@ -405,10 +416,8 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
         return false;
     }
     const bool rbgs = mg.smoother == ISDC_SMOOTH_RBGS;
-    if (!rbgs && p->d == 2) {  // 2D Jacobi: the fused row-tile kernels
-        jvcycle5_rec<T>(p, mg, l, c, zero, rhs, e, tmp, s);
-        return false;
-    }
+    if (!rbgs && p->d == 2)  // 2D Jacobi: the fused row-tile kernels
+        return jvcycle5_rec<T>(p, mg, l, c, zero, rhs, e, tmp, s, fuse);
     Coef<T> co = make_coef<T>(c, L.h, p->d, mg.omega);
     T* cur = e;
     T* other = tmp;
@@ -452,6 +461,24 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
     }
     if (cur != e) HIPCHK(launch_copy<T>(cur, e, L.N, s));
     return fused;
+}
+
+// The gate of a device-side stopping test is set for the launches of its scope.
+struct GateScope {
+    explicit GateScope(const int* g) { current_gate() = g; }
+    ~GateScope() { current_gate() = nullptr; }
+};
+
+// Residual norm of level l followed by the device-side stopping test
+// (launch_reduce_gate); both skip once the gate is set.
+template <typename T>
+void resnorm_gated(isdc_plan* p, int l, double c, const T* rhs, const T* u, double tol, int limit, int count_cycle,
+                   int* gate, double* res_out, hipStream_t s) {
+    const Level& L = p->lev[l];
+    Coef<T> co = make_coef<T>(c, L.h, p->d, p->mg.omega);
+    int nb = 0;
+    HIPCHK(launch_resnorm<T>(p->d, L.n, co, rhs, u, p->partial, &nb, s));
+    HIPCHK(launch_reduce_gate(p->partial, nb, tol, limit, count_cycle, gate, res_out, s));
 }
 
 template <typename T>
@@ -700,6 +727,42 @@ int inner_solve(isdc_plan* p, double c, const Fuse& upd, hipStream_t s, const Rh
         for (; k < limit; ++k)
             fused = vcycle_rec<T>(p, p->mg, 0, c, k == 0, r0, e0, t0, s, k == limit - 1 ? upd : Fuse(),
                                   k == 0 ? fra : nullptr);
+    } else if (!p->compact) {
+        // The stopping test runs on the device (k_reduce_gate): after the
+        // first test the host enqueues a run of (cycle, test) pairs -- as many
+        // as the same substep needed in its last solve -- and reads the gate
+        // once; each test lets the next cycle run or stops the solve, and the
+        // kernels of cycles after a stop return at once.  Only if the
+        // tolerance is still unmet does another run follow.
+        int* gate = (int*)(p->scalars + 8);
+        double* res_out = p->scalars + 10;
+        HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
+        HIPCHK(launch_gate_reset(gate, s));
+        {
+            GateScope gs(gate);
+            resnorm_gated<T>(p, 0, c, r0, e0, pr.inner_tol, limit, 1, gate, res_out, s);
+        }
+        int* hint = p->stats.sweeps == 0 ? p->gate_hint_first : p->gate_hint;
+        int& h = hint[p->gate_substep];
+        int run = std::max(1, std::min(h > 0 ? h : 3, limit));
+        int enq = 0;  // cycles enqueued
+        while (true) {
+            {
+                GateScope gs(gate);
+                for (int q = 0; q < run && enq < limit; ++q, ++enq) {
+                    vcycle_rec<T>(p, p->mg, 0, c, false, r0, e0, t0, s);
+                    resnorm_gated<T>(p, 0, c, r0, e0, pr.inner_tol, limit, 1, gate, res_out, s);
+                }
+            }
+            int g[2];
+            HIPCHK(hipMemcpyAsync(g, gate, sizeof(g), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            k = g[1];
+            if (g[0] || enq >= limit) break;
+            run = 1;
+        }
+        h = k;
+        p->gate_hint[p->gate_substep] = k;
     } else {
         HIPCHK(launch_fill<T>(e0, L0.N, T(0), s));
         for (; k < limit; ++k) {
@@ -774,6 +837,7 @@ void sweep_nodes(isdc_plan* p, hipStream_t s) {
             upd.mode = 1;
             upd.g = p->par.guess == ISDC_GUESS_PREV_NODE ? nw[m] : p->cur[m + 1];
         }
+        p->gate_substep = m;
         p->stats.vcycles += inner_solve<T>(p, dtm * p->prob.nu, upd, s, fuse_rhs ? &ra : nullptr);
     }
     for (int j = 0; j <= M; ++j) {
@@ -1060,6 +1124,9 @@ void isdc::init_plan(isdc_plan* p, const isdc_problem* prob, const isdc_params* 
     std::memset(p->SF, 0, sizeof(p->SF));
     layout(*prob, *par, (char*)d_workspace, p);
     std::memset(&p->stats, 0, sizeof(p->stats));
+    std::memset(p->gate_hint, 0, sizeof(p->gate_hint));
+    std::memset(p->gate_hint_first, 0, sizeof(p->gate_hint_first));
+    p->gate_substep = 0;
 }
 
 // ================================================================ C ABI

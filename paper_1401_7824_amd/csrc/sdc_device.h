@@ -62,6 +62,25 @@ __device__ __forceinline__ void split(size_t i, int n, int& x, int& y, int& z) {
     z = (D == 3) ? (int)(t / un) : 0;
 }
 
+// The per-point arithmetic of the quadrature + residual kernels, shared by
+// the tiled and the z-marched forms so both give the same bits:
+// f_j = nu L_h u_j + f^E(u_j) from the centre c and the neighbour sum nb
+// (x pair, then y pair, then z pair, as lds_nbsum adds them).
+template <int D>
+__device__ __forceinline__ double quad_f(double c, double nb, const QuadArgs& qa) {
+    return qa.nu_h2 * (nb - 2.0 * D * c) + fexp(c, qa.fe);
+}
+template <int M>
+__device__ __forceinline__ void quad_accumulate(double (&sf)[M], double (&acc)[M], double f, double c, int j,
+                                                const QuadArgs& qa) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        sf[m] += qa.dtS[m * ISDC_MAX_M + j] * f;
+        acc[m] += qa.dtQ[m * ISDC_MAX_M + j] * f;
+    }
+    acc[j] -= c;
+}
+
 // Tiled form of the quadrature + residual kernel: one tile of points per
 // workgroup, each node array staged in LDS (tile plus a halo of 1) in turn,
 // the next two's loads in flight while the current one is used.
@@ -112,13 +131,19 @@ __device__ __forceinline__ double quad_residual_body(const QuadArgs& qa, int x0,
 #pragma unroll
         for (int s = 0; s < P; ++s) {
             const double c = su[li[s]];
-            const double f = qa.nu_h2 * (lds_nbsum<double, D, B1>(su, li[s]) - 2.0 * D * c) + fexp(c, qa.fe);
+            const double f = quad_f<D>(c, lds_nbsum<double, D, B1>(su, li[s]), qa);
+            double sfs[M], accs[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                sf[m][s] += qa.dtS[m * ISDC_MAX_M + j] * f;
-                acc[m][s] += qa.dtQ[m * ISDC_MAX_M + j] * f;
+                sfs[m] = sf[m][s];
+                accs[m] = acc[m][s];
             }
-            acc[j][s] -= c;
+            quad_accumulate<M>(sfs, accs, f, c, j, qa);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                sf[m][s] = sfs[m];
+                acc[m][s] = accs[m];
+            }
         }
     }
     double mx = 0.0;

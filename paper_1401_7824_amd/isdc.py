@@ -305,6 +305,15 @@ class Batch:
         A.check(self.lib.isdc_batch_advance(self._h, _stream_handle(stream), C.byref(running)))
         return running.value
 
+    def time_sweeps(self, reps: int, graph: bool, stream) -> tuple:
+        """(microseconds per sweep, launches per sweep) of `reps` extra sweeps
+        of the running slots, eager or replayed from a captured HIP graph
+        (isdc_batch_time_sweeps); the slots' states are left unspecified."""
+        us, n = C.c_double(), C.c_int32()
+        A.check(self.lib.isdc_batch_time_sweeps(self._h, reps, 1 if graph else 0, _stream_handle(stream),
+                                                C.byref(us), C.byref(n)))
+        return us.value, n.value
+
     def info(self, slot: int):
         state, status, steps = C.c_int32(), C.c_int32(), C.c_int32()
         st = A.Stats()

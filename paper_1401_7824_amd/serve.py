@@ -20,6 +20,7 @@ bookkeeping only.
 from __future__ import annotations
 
 import math
+import sys
 import time
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
@@ -28,7 +29,11 @@ import numpy as np
 import torch
 
 from . import _capi as A
-from .isdc import Batch, Plan, make_params, make_problem, workspace_bytes
+from .isdc import Batch, Plan, make_params, make_problem, workspace_bytes  # noqa: F401
+
+
+# device copies of request initial states, shared by the runs of one process
+_U0_DEVICE: dict = {}
 
 
 @dataclass
@@ -38,13 +43,14 @@ class Request:
     n: int
     nu: float
     fe_kind: int
-    u0: np.ndarray
+    modes: list                 # u_0 = scale * sum of these sine modes
     dt: float
     nsteps: int
     sdc_tol: float
     M: int = 3
     node_kind: int = A.NODES_LOBATTO
     arrival: float = 0.0        # seconds after the start of the run
+    scale: float = 1.0
     # filled by the server
     admitted: float = math.nan
     finished: float = math.nan
@@ -55,6 +61,24 @@ class Request:
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+    @property
+    def u0(self) -> np.ndarray:
+        """Initial state on the host (float64, shape (n,)*dim)."""
+        from . import workloads as W
+        return W.sine_field(self.n, self.dim, self.modes) * self.scale
+
+    def u0_device(self) -> torch.Tensor:
+        """A fresh device copy of the initial state (equal to u0 bit for bit;
+        built on the device once per process and cached)."""
+        from . import workloads as W
+        key = (self.dim, self.n, self.scale, tuple((float(a), tuple(w)) for a, w in self.modes))
+        t = _U0_DEVICE.get(key)
+        if t is None:
+            t = W.sine_field_device(self.n, self.dim, self.modes) * self.scale
+            torch.cuda.current_stream().synchronize()  # other threads' streams read it later
+            _U0_DEVICE[key] = t
+        return t.clone()
 
     def params(self, precision: int, vcycles: int) -> dict:
         return dict(node_kind=self.node_kind, M=self.M, sdc_tol=self.sdc_tol, precision=precision,
@@ -114,18 +138,34 @@ def choose_admissions(waiting, need, used: int, budget: int, free_slots: dict) -
     return out
 
 
+# A request runs on a plan of its own ("solo": isdc_step on its own stream,
+# from a worker thread) when it is large -- 2D grids of 511^2 and up, 3D of
+# 127^3 and up, where the single-instance kernels (row tiles, z-marched
+# planes) beat the batch's generic ones and one instance fills much of the
+# chip -- or when no batch slot of its dimension is running, so that a
+# request arriving at an idle server is not slowed by the batch machinery.
+def runs_solo(req, batch_running: int) -> bool:
+    big = (req.dim == 2 and req.n >= 511) or (req.dim == 3 and req.n >= 127)
+    return big or batch_running == 0
+
+
 class Server:
-    """One batch per dimension, admission by slots and HBM budget (bytes)."""
+    """One batch per dimension plus `solo_workers` solo lanes; admission by
+    slots and HBM budget (bytes)."""
 
     def __init__(self, hbm_budget: int, slots_per_batch: int = 64, precision: int = A.PREC_MIXED,
-                 vcycles: int = 2, dims=(2, 3)):
+                 vcycles: int = 2, dims=(2, 3), solo_workers: int = 2):
         self.budget = int(hbm_budget)
         self.precision = precision
         self.vcycles = vcycles
         self.batches = {d: Batch(slots_per_batch, d, precision=precision, vcycles=vcycles) for d in dims}
-        # one stream per batch (default priority), advanced from a thread each
+        # one stream per batch and per solo lane (default priority), each driven from a thread of its own
         self.streams = {d: torch.cuda.Stream() for d in dims}
         self.pool = ThreadPoolExecutor(max_workers=len(dims))
+        self.solo_pool = ThreadPoolExecutor(max_workers=max(1, solo_workers)) if solo_workers > 0 else None
+        self.solo_streams = [torch.cuda.Stream() for _ in range(solo_workers)]
+        self.solo_free = list(range(solo_workers))
+        self.solo_running = {}  # future -> (request, bytes, lane)
         self.free = {d: list(range(slots_per_batch)) for d in dims}
         self.running = {d: {} for d in dims}   # slot -> (request, bytes)
         self.used = 0
@@ -133,8 +173,51 @@ class Server:
     def __del__(self):
         try:
             self.pool.shutdown(wait=False)
+            if self.solo_pool is not None:
+                self.solo_pool.shutdown(wait=False)
         except Exception:
             pass
+
+    def _solo_job(self, req: Request, stream, t0: float, clock):
+        """All steps of one request on its own plan and stream (a worker thread)."""
+        with torch.cuda.stream(stream):
+            p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(self.precision, self.vcycles))
+            u = req.u0_device()
+            status, sweeps = "ok", 0
+            for _ in range(req.nsteps):
+                st = p.step(u, req.dt, stream=stream)
+                sweeps = st.sweeps
+                if st.status != "ok":
+                    status = st.status
+                    break
+            stream.synchronize()
+        return status, u, sweeps, clock() - t0
+
+    def _admit_solo(self, req: Request, now: float, t0: float, clock) -> None:
+        need = self._need(req)
+        lane = self.solo_free.pop(0)
+        req.admitted = now
+        f = self.solo_pool.submit(self._solo_job, req, self.solo_streams[lane], t0, clock)
+        self.solo_running[f] = (req, need, lane)
+        self.used += need
+
+    def _reap_solo(self, stats: ServeStats) -> bool:
+        done = [f for f in self.solo_running if f.done()]
+        for f in done:
+            req, need, lane = self.solo_running.pop(f)
+            status, u, sweeps, finished = f.result()
+            req.finished = finished
+            req.status = status
+            req.result = u
+            req.sweeps_last_step = sweeps
+            if status == "ok":
+                stats.completed += 1
+                stats.latencies.append(req.latency)
+            else:
+                stats.failed += 1
+            self.solo_free.append(lane)
+            self.used -= need
+        return bool(done)
 
     def _need(self, req: Request) -> int:
         need = req.device_bytes(self.precision, self.vcycles)
@@ -150,7 +233,7 @@ class Server:
         slot = self.free[d].pop(0)
         par = req.params(self.precision, self.vcycles)
         ws = torch.empty(need - req.n ** req.dim * 8, dtype=torch.uint8, device="cuda")
-        u = torch.from_numpy(np.ascontiguousarray(req.u0)).to("cuda")
+        u = req.u0_device()
         self.batches[d].set(slot, u, req.dt, req.nsteps, req.nu, req.fe_kind, workspace=ws, **par)
         req.admitted = now
         req.result = u
@@ -176,31 +259,38 @@ class Server:
                 self.free[d].append(slot)
                 self.used -= need
 
-    def serve(self, requests: list[Request], clock=time.perf_counter) -> ServeStats:
+    def serve(self, requests: list[Request], clock=time.perf_counter, log_every: int = 0) -> ServeStats:
         """Run until every request has finished.  Arrival times are honoured in
-        wall-clock time: a request is admissible once its arrival has passed."""
+        wall-clock time: a request is admissible once its arrival has passed.
+        log_every > 0 prints a progress line to stderr every that many finished requests."""
         queue = sorted(requests, key=lambda r: r.arrival)
         stats = ServeStats()
         t0 = clock()
         i = 0
         waiting: list[Request] = []
-        while i < len(queue) or waiting or any(self.running[d] for d in self.running):
+        while i < len(queue) or waiting or any(self.running[d] for d in self.running) or self.solo_running:
             now = clock() - t0
             while i < len(queue) and queue[i].arrival <= now:
                 waiting.append(queue[i])
                 i += 1
+            before = stats.completed + stats.failed
+            self._reap_solo(stats)
             admit = choose_admissions(waiting, self._need, self.used, self.budget,
                                       {d: len(f) for d, f in self.free.items()})
             for r in admit:
-                ok = self._admit(r, now)
-                assert ok
+                if self.solo_free and runs_solo(r, len(self.running[r.dim])):
+                    self._admit_solo(r, now, t0, clock)
+                else:
+                    ok = self._admit(r, now)
+                    assert ok
             if admit:
                 chosen = set(id(r) for r in admit)
                 waiting = [r for r in waiting if id(r) not in chosen]
                 # the states were uploaded on the current stream; the batch streams start after them
                 torch.cuda.current_stream().synchronize()
             stats.peak_bytes = max(stats.peak_bytes, self.used)
-            stats.peak_concurrency = max(stats.peak_concurrency, sum(len(v) for v in self.running.values()))
+            stats.peak_concurrency = max(stats.peak_concurrency,
+                                         sum(len(v) for v in self.running.values()) + len(self.solo_running))
             # one sweep of every batch with running slots, the batches side by side
             live = [d for d in self.batches if self.running[d]]
             futures = [self.pool.submit(self.batches[d].advance, self.streams[d]) for d in live]
@@ -210,29 +300,39 @@ class Server:
             busy = bool(live)
             for d in live:
                 self._reap(d, clock() - t0, stats)
+            done = stats.completed + stats.failed
+            if log_every and done // log_every > before // log_every:
+                print(f"[serve] {done}/{len(queue)} requests finished at {clock() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
             if not busy:
-                # idle until the next arrival
+                # idle until the next arrival or the next solo request's end
+                delay = 0.05
                 if i < len(queue):
-                    delay = queue[i].arrival - (clock() - t0)
-                    if delay > 0:
-                        time.sleep(min(delay, 0.05))
+                    delay = min(delay, queue[i].arrival - (clock() - t0))
+                if self.solo_running:
+                    delay = min(delay, 0.0005)
+                if delay > 0:
+                    time.sleep(delay)
         stats.makespan = clock() - t0
         return stats
 
 
 def serve_sequential(requests: list[Request], precision: int = A.PREC_MIXED, vcycles: int = 2,
-                     clock=time.perf_counter) -> ServeStats:
+                     clock=time.perf_counter, log_every: int = 0) -> ServeStats:
     """Baseline: requests served one after another (FIFO) with isdc_step."""
     queue = sorted(requests, key=lambda r: r.arrival)
     stats = ServeStats()
     t0 = clock()
-    for req in queue:
+    for k, req in enumerate(queue):
+        if log_every and k and k % log_every == 0:
+            print(f"[serve-seq] {k}/{len(queue)} requests finished at {clock() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
         now = clock() - t0
         if req.arrival > now:
             time.sleep(req.arrival - now)
         req.admitted = clock() - t0
         p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(precision, vcycles))
-        u = torch.from_numpy(np.ascontiguousarray(req.u0)).to("cuda")
+        u = req.u0_device()
         status = "ok"
         for _ in range(req.nsteps):
             st = p.step(u, req.dt)
@@ -274,7 +374,6 @@ def make_requests(count: int, rate: float, seed: int = 5, big: bool = True) -> l
         tol = float(rng.choice([1e-5, 1e-8]))
         steps = int(rng.integers(1, 21)) if big else int(rng.integers(1, 6))
         modes = W.draw_modes(dim, 8, seed=10_000 + rid, max_wave=4)
-        u0 = W.sine_field(n, dim, modes) * (1.0 if heat else 3.0)
-        out.append(Request(rid=rid, dim=dim, n=n, nu=1.0 if heat else 0.1, fe_kind=0 if heat else 1, u0=u0,
-                           dt=1e-3, nsteps=steps, sdc_tol=tol, M=M, arrival=t))
+        out.append(Request(rid=rid, dim=dim, n=n, nu=1.0 if heat else 0.1, fe_kind=0 if heat else 1, modes=modes,
+                           dt=1e-3, nsteps=steps, sdc_tol=tol, M=M, arrival=t, scale=1.0 if heat else 3.0))
     return out

@@ -10,7 +10,7 @@ from __future__ import annotations
 import json
 import os
 
-VERSION = 2  # 2: the shape of a z-marched 3D level selects its column depth
+VERSION = 3  # 2: the shape of a z-marched 3D level selects its column depth; 3: shape 1 there fits one round
 
 
 def path() -> str:

@@ -55,6 +55,24 @@ def sine_field(n: int, d: int, modes) -> np.ndarray:
     return u
 
 
+def sine_field_device(n: int, d: int, modes, device="cuda"):
+    """sine_field built on a torch device: the 1D sine vectors are evaluated
+    on the host in float64 and their products formed on the device in the
+    same order as sine_field, so the result equals sine_field bit for bit."""
+    import torch
+    h = 1.0 / (n + 1)
+    x = (np.arange(n) + 1) * h
+    u = torch.zeros((n,) * d, dtype=torch.float64, device=device)
+    for amp, a in modes:
+        term = torch.tensor(float(amp), dtype=torch.float64, device=device)
+        for ax in range(d):
+            shape = [1] * d
+            shape[ax] = n
+            term = term * torch.from_numpy(np.sin(a[ax] * np.pi * x)).to(device).reshape(shape)
+        u += term
+    return u
+
+
 def sine_field_at(n: int, modes, points: np.ndarray) -> np.ndarray:
     """The same field at integer grid points (rows of `points`, one column per axis)."""
     h = 1.0 / (n + 1)
@@ -103,8 +121,10 @@ def periodic_field(n: int, seed: int, n_modes: int = 8, max_wave: int = 6, d: in
 WORKLOADS = {
     "heat1d": dict(dim=1, n=127, nu=1.0, fe_kind=FE_ZERO, node_kind=NODES_LOBATTO, M=3, dt=0.01, steps=1,
                    precision=PREC_FP64, sdc_tol=1e-10, modes=[(1.0, (1,)), (0.5, (3,))]),
+    # weighted-Jacobi V(3,3): the fewest V-cycles and the least time per step of the
+    # smoothers measured on this problem (bench.py --workload compare)
     "rd2d": dict(dim=2, n=1023, nu=0.1, fe_kind=FE_CUBIC, node_kind=NODES_LOBATTO, M=5, dt=1e-3, steps=10,
-                 precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2),
+                 precision=PREC_FP64, sdc_tol=1e-10, n_modes=16, seed=2, smoother=1, nu_pre=3, nu_post=3),
     # all-float64; bench.py runs the float32-V-cycle variant beside it
     "heat3d": dict(dim=3, n=255, nu=1.0, fe_kind=FE_ZERO, node_kind=NODES_RADAU_RIGHT, M=3, dt=1e-3, steps=1,
                    precision=PREC_FP64, sdc_tol=1e-10, n_modes=32, seed=3),

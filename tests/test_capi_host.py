@@ -239,6 +239,10 @@ def test_fixed_batch_validation_host_only():
     sb = C.c_void_p()
     assert lib.isdc_batch_open(3, 2, 1, 2, fake, base.value, C.byref(sb)) == 0
     assert lib.isdc_batch_step(sb, us, dts, act, None, None) == A.E_INVAL
+    t, nl = C.c_double(), C.c_int32()
+    assert lib.isdc_batch_time_sweeps(sb, 5, 0, None, C.byref(t), C.byref(nl)) == A.E_INVAL  # nothing running
+    assert lib.isdc_batch_time_sweeps(sb, 5, 1, None, C.byref(t), C.byref(nl)) == A.E_INVAL  # graph on null stream
+    assert lib.isdc_batch_time_sweeps(sb, 0, 0, fake, C.byref(t), C.byref(nl)) == A.E_INVAL
     lib.isdc_batch_destroy(sb)
     # instances must share dim, precision and L, and run the batch's solver
     mixed = (A.Params * 2)(make_params(precision=1), make_params(precision=0))

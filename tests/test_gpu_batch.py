@@ -217,3 +217,31 @@ def test_fixed_batch_step_equals_isdc_step(d, prec):
         ref = dev(inst[i]["u0"])
         plans[i].step(ref, inst[i]["dt"])
         assert torch.equal(us[i], ref)
+
+
+def test_sweep_schedule_timing_eager_and_graph_then_slots_still_exact():
+    # isdc_batch_time_sweeps replays the sweep's launches (eager or from one
+    # captured HIP graph) for timing; re-set slots afterwards give isdc_step's bits
+    from paper_1401_7824_amd import Batch
+    announce("batch sweep timing")
+    d, prec = 2, 1
+    inst = _instances(d, prec, 4, seed=55)
+    b = Batch(4, d, precision=prec, vcycles=2)
+    side = torch.cuda.Stream()
+    us = [dev(x["u0"]) for x in inst]
+    for i, x in enumerate(inst):
+        b.set(i, us[i], x["dt"], 1, x["nu"], x["fe"], **x["par"])
+    torch.cuda.synchronize()
+    b.advance(side)
+    t_eager, n_eager = b.time_sweeps(3, False, side)
+    t_graph, n_graph = b.time_sweeps(3, True, side)
+    assert t_eager > 0 and t_graph > 0 and n_eager == n_graph > 10
+    for i in range(4):
+        b.release(i)
+    us = [dev(x["u0"]) for x in inst]
+    for i, x in enumerate(inst):
+        b.set(i, us[i], x["dt"], 1, x["nu"], x["fe"], **x["par"])
+    b.run()
+    for i, x in enumerate(inst):
+        ref, _ = _alone(d, x["n"], x["nu"], x["fe"], x["u0"], x["dt"], 1, **x["par"])
+        assert np.array_equal(host(us[i]), ref)

@@ -1,7 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
 benchmark times: the 2D reaction-diffusion workload (1023^2, Gauss-Lobatto
-M = 5, FP64) against the oracle sweep by sweep, and the 3D heat workload
-(255^3, right Gauss-Radau M = 3, float32 V-cycles) against the direct
+M = 5, FP64, weighted-Jacobi V(3,3) cycles) against the oracle sweep by sweep
+and over its whole first step, and the 3D heat workload (255^3, right
+Gauss-Radau M = 3, all-FP64 and float32 V-cycles) against the direct
 collocation solution, which is known in closed form per sine mode."""
 
 import numpy as np
@@ -23,7 +24,8 @@ def _gpu():
 
 def _plan_for(cfg, **over):
     from paper_1401_7824_amd import Plan
-    kw = dict(node_kind=cfg["node_kind"], M=cfg["M"], precision=cfg["precision"], sdc_tol=cfg["sdc_tol"])
+    kw = dict(node_kind=cfg["node_kind"], M=cfg["M"], precision=cfg["precision"], sdc_tol=cfg["sdc_tol"],
+              smoother=cfg.get("smoother", 0), nu_pre=cfg.get("nu_pre", 1), nu_post=cfg.get("nu_post", 1))
     kw.update(over)
     return Plan(cfg["dim"], cfg["n"], cfg["nu"], cfg["fe_kind"], **kw)
 
@@ -34,7 +36,8 @@ def test_rd2d_full_size_sweeps_match_oracle():
     u0 = W.workload_u0(cfg)
     p = _plan_for(cfg)
     st = sdc_begin(u0, cfg["dt"], 1.0 / (cfg["n"] + 1),
-                   SDCConfig(nu=cfg["nu"], fe_kind=cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"]))
+                   SDCConfig(nu=cfg["nu"], fe_kind=cfg["fe_kind"], node_kind=cfg["node_kind"], M=cfg["M"],
+                             smoother=cfg.get("smoother", 0), nu1=cfg.get("nu_pre", 1), nu2=cfg.get("nu_post", 1)))
     u0d = dev(u0)
     p.begin(u0d, cfg["dt"])
     for k in range(2):

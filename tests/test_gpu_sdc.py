@@ -252,6 +252,32 @@ def test_classical_and_early_exit_match_oracle(vcycles, early):
     assert rel_l2(host(u), ref) < 1e-10
 
 
+@pytest.mark.parametrize("d,n,smoother,nu1", [(2, 255, 0, 1), (2, 255, 1, 3), (3, 31, 0, 1), (1, 1023, 0, 1)])
+def test_classical_device_stopping_test_matches_oracle(d, n, smoother, nu1):
+    # classical SDC on multi-level grids: the inner stopping test runs on the
+    # device, several (test, cycle) pairs are enqueued per host read-back, and
+    # the cycles after the test was met are skipped on the GPU; counts and
+    # iterates equal the oracle's host-side loop (Sec. 3)
+    announce("classical device test", d, n, smoother, nu1)
+    nu, dt = 1.0, 2e-3
+    par = dict(node_kind=LOB, M=3, vcycles=0, inner_tol=1e-10, sdc_tol=1e-9, smoother=smoother,
+               nu_pre=nu1, nu_post=nu1)
+    u0 = W.sine_field(n, d, W.draw_modes(d, 8, seed=61 + d))
+    p = _plan(d, n, nu, O.FE_ZERO, **par)
+    u = dev(u0)
+    st = p.step(u, dt)
+    ref, rst = sdc_step(u0, dt, 1.0 / (n + 1), _cfg(nu, O.FE_ZERO, **par))
+    assert st.status == "ok"
+    assert st.sweeps == rst.sweeps
+    if rst.inner_margin > 1e-6:
+        assert st.vcycles == rst.vcycles, (st.vcycles, rst.vcycles, rst.inner_margin)
+    assert rel_l2(host(u), ref) < 1e-10
+    # a second step reuses the per-substep cycle counts as its run lengths
+    st2 = p.step(u, dt)
+    ref2, rst2 = sdc_step(ref, dt, 1.0 / (n + 1), _cfg(nu, O.FE_ZERO, **par))
+    assert st2.sweeps == rst2.sweeps and rel_l2(host(u), ref2) < 1e-10
+
+
 def test_edge_cases_tiny_grids_and_degenerate_parameters():
     for (d, n, nu, fe, dt, par) in [
         (2, 1, 1.0, O.FE_ZERO, 0.01, dict(node_kind=LOB, M=3)),      # single interior point
