@@ -45,6 +45,8 @@ def parse():
                     help="arrival rates swept, as fractions of the saturated capacity")
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="saturated capacity (req/s) from an earlier run: skips the saturated run and the sequential baselines")
+    ap.add_argument("--serve-seq-sat", action="store_true",
+                    help="with --serve-capacity: also run the one-at-a-time baseline with every request at t = 0")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -583,12 +585,24 @@ def run_serve(args, torch):
         print(f"[serve] rate {frac:.2f} x capacity: p50 {st['p50_ms']} ms, p99 {st['p99_ms']} ms",
               file=sys.stderr, flush=True)
     if given:
-        return {"metric": METRIC, "value": round(cap, 4), "unit": "requests/s", "n_gpus": 1, "steps": 0,
-                "warmup": 8, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "f64+f32", "data": "synthetic",
-                "config": {"workload": f"serve rate sweep only: {count} requests, capacity {cap} req/s given, HBM "
-                                       f"budget {args.serve_budget_gb} GiB, {args.serve_solo} solo lanes"},
-                "rate_sweep": rows}
+        out = {"metric": METRIC, "value": round(cap, 4), "unit": "requests/s", "n_gpus": 1, "steps": 0,
+               "warmup": 8, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64+f32", "data": "synthetic",
+               "config": {"workload": f"serve rate sweep only: {count} requests, capacity {cap} req/s given, HBM "
+                                      f"budget {args.serve_budget_gb} GiB, {args.serve_solo} solo lanes"},
+               "rate_sweep": rows}
+        if args.serve_seq_sat:
+            from paper_1401_7824_amd.serve import runs_solo
+            seq_reqs = make_requests(count, rate=0.0, seed=5)
+            seq_sat = serve_sequential(seq_reqs, precision=1, vcycles=2, log_every=log).summary()
+            seq_sat["service_s_large_requests"] = round(
+                sum(r.finished - r.admitted for r in seq_reqs if runs_solo(r, 1)), 3)
+            seq_sat["service_s_other_requests"] = round(
+                sum(r.finished - r.admitted for r in seq_reqs if not runs_solo(r, 1)), 3)
+            out["sequential_baseline_saturated"] = seq_sat
+            out["capacity_vs_sequential"] = round(cap / seq_sat["throughput_req_s"], 2)
+            print(f"[serve] sequential saturated: {seq_sat['throughput_req_s']} req/s", file=sys.stderr, flush=True)
+        return out
     seq = serve_sequential(make_requests(count, rate=0.25 * cap, seed=5), precision=1, vcycles=2,
                            log_every=log).summary()
     print(f"[serve] sequential at 0.25 x capacity: p50 {seq['p50_ms']} ms, p99 {seq['p99_ms']} ms",

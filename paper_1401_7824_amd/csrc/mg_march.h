@@ -84,7 +84,11 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
     using M = MTile<T>;
     using TO = typename std::conditional<MODE == 0, T, double>::type;
     constexpr int L = M::LPR;
-    constexpr int NE = 5;  // iterate ring (see the hazards below)
+    // iterate ring: 5 planes, or 4 with one more barrier per step (see the
+    // hazards below); the float64 prolongation kernels take 4, which brings
+    // their LDS under 32 KB (five workgroups per CU); the plain step keeps 5
+    // (measured: its extra barrier costs more than the occupancy gains)
+    constexpr int NE = (PRO && sizeof(T) == 8) ? 4 : 5;
     __shared__ T sE[NE * M::PN];
     __shared__ T sC[PRO ? M::CROWS * L : 1];
 
@@ -229,8 +233,9 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
 
     // Step k stores plane k+2 of the iterate, then updates red on k+1 and
     // black on k.  Ring hazard: the store of plane k+2 may overlap black(k-1)
-    // of slower threads, which reads planes k-2 .. k, so the ring has 5 slots.
-    // sk: the slot of plane k.
+    // of slower threads, which reads planes k-2 .. k, so a ring of 5 slots
+    // needs no barrier between steps; a ring of 4 (plane k+2 in the slot of
+    // k-2) ends every step with one.  sk: the slot of plane k.
     int sk = ((z0 - 4) % NE + NE) % NE;
     auto slot = [&](int m) {  // slot of plane k + m, -1 <= m <= 2
         int v = sk + m;
@@ -335,6 +340,7 @@ __device__ __forceinline__ void march_rbgs_body(const T* __restrict__ r, const T
                 }
             }
         }
+        if (NE == 4) __syncthreads();  // black(k) has read plane k-1 before step k+1 stores k+3 there
         sk = sk == NE - 1 ? 0 : sk + 1;
     }
 }
