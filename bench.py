@@ -207,7 +207,7 @@ def accuracy_vs_collocation(cfg, torch):
 
 # kernels followed inside the steps (isdc_probe_arm): (key, ISDC_KERNEL_*, level)
 PROBE_KINDS = [("smooth", 2, 0), ("smooth_restrict", 0, 0), ("restrict", 7, 0), ("prolong_smooth", 1, 0),
-               ("prolong_update", 6, 0), ("quad", 4, 0), ("rhs", 8, 0), ("tail", 3, 0)]
+               ("prolong_update", 6, 0), ("zsmooth_restrict", 9, 0), ("quad", 4, 0), ("rhs", 8, 0), ("tail", 3, 0)]
 
 
 def probe_kernel_name(key, cfg, T, shape=0):
@@ -221,6 +221,7 @@ def probe_kernel_name(key, cfg, T, shape=0):
         return f"k_euler_rhs<{T},{d},0>"
     if d == 3 and cfg["n"] >= 127:
         return {"smooth": f"k_march_rbgs<{T},false,0,false>", "restrict": f"k_march_restrict<{T}>",
+                "zsmooth_restrict": f"k_march_zrestrict<{T}>",
                 "prolong_smooth": f"k_march_rbgs<{T},true,0,false>",
                 "prolong_update": f"k_march_rbgs<{T},true,1,false>"}[key]
     if d == 2 and cfg.get("smoother", 0) == 1:  # fused weighted-Jacobi row kernels of the five-point operator
@@ -230,9 +231,11 @@ def probe_kernel_name(key, cfg, T, shape=0):
                 "prolong_update": f"k_cpjac<{T},false,{kpost},false,1>"}[key]
     if d == 2:
         return {"smooth": f"k_rows_rbgs<{T},false,{shape}>", "smooth_restrict": f"k_rows_rbgs_restrict<{T},false,{shape}>",
+                "zsmooth_restrict": f"k_rows_rbgs_restrict<{T},true,{shape}>",
                 "prolong_smooth": f"k_rows_prolong_rbgs<{T},0,{shape}>",
                 "prolong_update": f"k_rows_prolong_rbgs<{T},1,{shape}>"}[key]
     return {"smooth": f"k_rbgs_tile<{T},{d},false,{shape}>", "smooth_restrict": f"k_rbgs_restrict_tile<{T},{d},false,{shape}>",
+            "zsmooth_restrict": f"k_rbgs_restrict_tile<{T},{d},true,{shape}>",
             "restrict": f"k_restrict_tile<{T},{d}>", "prolong_smooth": f"k_prolong_rbgs_tile<{T},{d},0,{shape}>",
             "prolong_update": f"k_prolong_rbgs_tile<{T},{d},1,{shape}>"}[key]
 

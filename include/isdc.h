@@ -101,7 +101,7 @@ enum { ISDC_OP_SMOOTH = 0, ISDC_OP_RESTRICT = 1, ISDC_OP_PROLONG = 2, ISDC_OP_CO
  * inside steps (see there). */
 enum { ISDC_KERNEL_SMOOTH_RESTRICT = 0, ISDC_KERNEL_PROLONG_SMOOTH = 1, ISDC_KERNEL_SMOOTH = 2,
        ISDC_KERNEL_TAIL = 3, ISDC_KERNEL_QUAD = 4, ISDC_KERNEL_EXPLICIT = 5, ISDC_KERNEL_PROLONG_UPDATE = 6,
-       ISDC_KERNEL_RESTRICT = 7, ISDC_KERNEL_RHS = 8 };
+       ISDC_KERNEL_RESTRICT = 7, ISDC_KERNEL_RHS = 8, ISDC_KERNEL_ZSMOOTH_RESTRICT = 9 };
 
 #define ISDC_MAX_M 9
 #define ISDC_HIST 128
@@ -328,6 +328,11 @@ int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, i
  *   ISDC_KERNEL_SMOOTH_RESTRICT  2D red-black step + residual + restriction
  *                                from a nonzero iterate;
  *   ISDC_KERNEL_SMOOTH           a red-black step from a nonzero iterate;
+ *   ISDC_KERNEL_ZSMOOTH_RESTRICT a red-black step from a zero iterate fused
+ *                                with the residual's restriction (the first
+ *                                launch of a V(1,1) cycle on a level that
+ *                                starts from zero; 2D, and 3D levels of
+ *                                127^3 and up);
  *   ISDC_KERNEL_RESTRICT         residual + full weighting (3D, Jacobi);
  *   ISDC_KERNEL_PROLONG_SMOOTH   prolongation + correction + red-black step;
  *   ISDC_KERNEL_PROLONG_UPDATE   the same fused with the node update

@@ -493,5 +493,215 @@ __device__ __forceinline__ void march_restrict_body(const T* __restrict__ r, con
     }
 }
 
+// Zero-start red-black step fused with the residual and its full weighting,
+// z-marched over the coarse planes of march_restrict_body's tile and column.
+// From e = 0 one red-black step gives e = r / diag at the red points and
+// e = (r + a * sum of the six red neighbours) / diag at the black ones, so the
+// iterate is a function of r alone.  Each fine plane of r (xy halo 2) enters a
+// ring of five LDS planes as r / diag at red points and r at black points;
+// once the planes on either side are in, the black points of a plane (xy
+// halo 1) are updated in place and the points the tile owns go to e_out.
+// The residual of a fine plane (its rhs still in the registers that loaded
+// it) goes to one of two LDS planes, and each coarse point's weighted sum
+// is accumulated in a register over its three fine planes.  One pass over r
+// replaces the zero-start step and the restriction: the iterate is written
+// once and never read back.  The red value, the black neighbour sum and
+// update, the residual and the weighted sums (added in the same order) are
+// the expressions of the two kernels it replaces, term for term.
+template <typename T>
+__device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T* __restrict__ e_out,
+                                                     T* __restrict__ rc, int n, int X0, int Y0, int Z0, int mzc, T a,
+                                                     T diag, T invdiag) {
+    using RB = Box<2, 2 * MRTile::X + 1, 2 * MRTile::Y + 1, 1>;  // residual plane, fine origin (2X0, 2Y0)
+    using ZB = Box<2, 2 * MRTile::X + 5, 2 * MRTile::Y + 5, 1>;  // iterate plane, origin (2X0-2, 2Y0-2)
+    constexpr int IZ = (ZB::N + kThreads - 1) / kThreads;
+    constexpr int NS = 5;  // ring of fine planes f .. f+4 of a step
+    constexpr int NC = MRTile::X * MRTile::Y;
+    static_assert(NC <= kThreads, "one coarse point per thread");
+    __shared__ T sZ[NS][ZB::N];
+    __shared__ T sRes[2][RB::N];
+    const size_t nn = (size_t)n * n;
+    const int nc = (n - 1) / 2;
+    const int Z1 = min(Z0 + mzc, nc);
+    const int fx = 2 * X0, fy = 2 * Y0;
+    auto slot = [](int p) { return (p % NS + NS) % NS; };
+
+    // This thread's points of the plane box (the same in every pass): the
+    // row offset in the level, the residual-box index, and flags: inside the
+    // grid, in the black pass's box (halo 1), in the residual box, owned
+    // (the tile writes fine columns [fx, fx + 2 X) and rows [fy, fy + 2 Y),
+    // and column / row n - 1 where its coarse range reaches nc), and the
+    // parity of x + y.
+    enum { F_IN = 1, F_EB = 2, F_RB = 4, F_OWN = 8, F_ODD = 16 };
+    unsigned goff[IZ];
+    int rbi[IZ], fl[IZ];
+#pragma unroll
+    for (int it = 0; it < IZ; ++it) {
+        const int k = threadIdx.x + it * kThreads;
+        int lx, ly, lz;
+        ZB::split(k, lx, ly, lz);
+        const int x = fx - 2 + lx, y = fy - 2 + ly;
+        int f = 0;
+        if (k < ZB::N) {
+            if (inside<2>(x, y, 0, n)) f |= F_IN;
+            if (lx >= 1 && lx <= ZB::X - 2 && ly >= 1 && ly <= ZB::Y - 2) f |= F_EB;
+            if (lx >= 2 && lx <= ZB::X - 3 && ly >= 2 && ly <= ZB::Y - 3) f |= F_RB;
+            const bool ox = x >= fx && x < n && (x < fx + 2 * MRTile::X || x == n - 1);
+            const bool oy = y >= fy && y < n && (y < fy + 2 * MRTile::Y || y == n - 1);
+            if (ox && oy) f |= F_OWN;
+            if ((lx + ly) & 1) f |= F_ODD;  // fx, fy even: the parity of x + y
+        }
+        fl[it] = f;
+        goff[it] = (f & F_IN) ? (unsigned)y * (unsigned)n + (unsigned)x : 0u;
+        rbi[it] = (ly - 2) * RB::X + (lx - 2);
+    }
+
+    auto load_z = [&](T (&dst)[IZ], int p) {
+        const bool pok = (unsigned)p < (unsigned)n;
+        const T* b = pok ? r + (size_t)p * nn : r;
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) dst[it] = (pok && (fl[it] & F_IN)) ? b[goff[it]] : T(0);
+    };
+    // plane p enters the ring: red points (even x + y + p) hold their final
+    // value r / diag, black points r until their update
+    auto store_z = [&](const T (&src)[IZ], int p) {
+        T* d = sZ[slot(p)];
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            const bool red = (((fl[it] & F_ODD) ? 1 : 0) + p) % 2 == 0;
+            if (k < ZB::N) d[k] = red ? src[it] * invdiag : src[it];
+        }
+    };
+    // black points of plane p (tile plus an xy halo of 1) from the red
+    // values around them; the points the tile owns go to e_out
+    auto black = [&](int p) {
+        if ((unsigned)p >= (unsigned)n) return;  // ghost planes stay zero
+        T* e0 = sZ[slot(p)];
+        const T* em = sZ[slot(p - 1)];
+        const T* ep = sZ[slot(p + 1)];
+        const bool pown = p >= 2 * Z0 && (p < 2 * Z1 || p == n - 1);
+        T* ob = e_out + (size_t)p * nn;
+        const int pb = p & 1;
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            if ((fl[it] & (F_EB | F_IN)) != (F_EB | F_IN)) continue;
+            T v = e0[k];
+            if (((fl[it] & F_ODD) ? 1 : 0) != pb) {  // odd x + y + p
+                const T nb = e0[k - 1] + e0[k + 1] + e0[k - ZB::X] + e0[k + ZB::X] + em[k] + ep[k];
+                v = (v + a * nb) * invdiag;
+                e0[k] = v;
+            }
+            if (pown && (fl[it] & F_OWN)) ob[goff[it]] = v;
+        }
+    };
+    // residual of fine plane f (iterate planes f-1..f+1 in the ring) from
+    // the rhs values rr this thread loaded for plane f; points outside the
+    // grid keep 0
+    auto residual = [&](const T (&rr)[IZ], int f) {
+        const T* em = sZ[slot(f - 1)];
+        const T* e0 = sZ[slot(f)];
+        const T* ep = sZ[slot(f + 1)];
+        T* out = sRes[f & 1];
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            if (!(fl[it] & F_RB)) continue;
+            const int i = threadIdx.x + it * kThreads;
+            T v = T(0);
+            if (fl[it] & F_IN) {
+                const T nb = e0[i - 1] + e0[i + 1] + e0[i - ZB::X] + e0[i + ZB::X] + em[i] + ep[i];
+                v = rr[it] - (diag * e0[i] - a * nb);
+            }
+            out[rbi[it]] = v;
+        }
+    };
+    // this thread's coarse point (threads below NC) and the weights
+    const int cx = threadIdx.x % MRTile::X, cy = threadIdx.x / MRTile::X;
+    const bool cown = threadIdx.x < NC && X0 + cx < nc && Y0 + cy < nc;
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    // weighted rows of residual plane f with the z weight w[oz], added to acc
+    auto weigh = [&](T& acc, int f, int oz) {
+        const T* s = sRes[f & 1];
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const int base = (2 * cy + oy) * RB::X + 2 * cx;
+            T row = w[0] * s[base] + w[1] * s[base + 1] + w[2] * s[base + 2];
+            T wyz = w[oy] * w[oz];
+            acc += wyz * row;
+        }
+    };
+
+    T za[IZ], zb[IZ], r1[IZ], r2[IZ];
+    T acc = T(0);
+    const int f0 = 2 * Z0;
+    // prologue: r planes f0-2 .. f0+2, iterate planes f0-1 .. f0+1, residual
+    // plane f0 and its part of coarse plane Z0
+    {
+        T zc[IZ];
+        load_z(za, f0 - 2);
+        load_z(zb, f0 - 1);
+        load_z(zc, f0);
+        load_z(r1, f0 + 1);
+        load_z(r2, f0 + 2);
+        store_z(za, f0 - 2);
+        store_z(zb, f0 - 1);
+        store_z(zc, f0);
+        store_z(r1, f0 + 1);
+        store_z(r2, f0 + 2);
+        __syncthreads();
+        // black(p) reads only red points of planes p-1 .. p+1, which no
+        // black update writes: the three planes share one pass
+        black(f0 - 1);
+        black(f0);
+        black(f0 + 1);
+        __syncthreads();
+        residual(zc, f0);
+        __syncthreads();
+        if (cown) weigh(acc, f0, 0);
+    }
+    // loads of the first step: r planes f0+3, f0+4
+    load_z(za, f0 + 3);
+    load_z(zb, f0 + 4);
+    for (int Z = Z0; Z < Z1; ++Z) {
+        const int f = 2 * Z;
+        // planes f+3, f+4 go into the slots of f-2 and f-1, whose last
+        // readers (the residuals of f-1 and f) passed the step's last barrier
+        store_z(za, f + 3);
+        store_z(zb, f + 4);
+        T n1[IZ], n2[IZ];
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            n1[it] = za[it];
+            n2[it] = zb[it];
+        }
+        if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
+            load_z(za, f + 5);
+            load_z(zb, f + 6);
+        }
+        __syncthreads();
+        black(f + 2);
+        black(f + 3);
+        __syncthreads();
+        residual(r1, f + 1);
+        residual(r2, f + 2);
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            r1[it] = n1[it];
+            r2[it] = n2[it];
+        }
+        __syncthreads();
+        // coarse plane Z from residual planes f (already in acc), f+1, f+2;
+        // plane f+2 starts coarse plane Z+1
+        if (cown) {
+            weigh(acc, f + 1, 1);
+            weigh(acc, f + 2, 2);
+            rc[((size_t)Z * nc + (Y0 + cy)) * nc + (X0 + cx)] = acc;
+            acc = T(0);
+            weigh(acc, f + 2, 0);
+        }
+    }
+}
+
 }  // namespace
 }  // namespace isdc

@@ -293,6 +293,7 @@ double mg_bytes(const isdc_plan* p, int kind, int l) {
     const double Nc = l + 1 < (int)p->lev.size() ? (double)p->lev[l + 1].N : 0.0;
     switch (kind) {
         case ISDC_KERNEL_SMOOTH_RESTRICT: return (3.0 * N + Nc) * w;  // rhs, e in; e, coarse rhs out
+        case ISDC_KERNEL_ZSMOOTH_RESTRICT: return (2.0 * N + Nc) * w; // rhs in; e, coarse rhs out
         case ISDC_KERNEL_SMOOTH: return 3.0 * N * w;                  // rhs, e in; e out
         case ISDC_KERNEL_RESTRICT: return (2.0 * N + Nc) * w;         // rhs, e in; coarse rhs out
         case ISDC_KERNEL_PROLONG_SMOOTH: return (3.0 * N + Nc) * w;   // rhs, e, coarse e in; e out
@@ -422,13 +423,14 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
     T* cur = e;
     T* other = tmp;
     const Level& C = p->lev[l + 1];
-    if (rbgs && mg.nu_pre >= 1 && p->d <= 2) {
+    if (rbgs && mg.nu_pre >= 1 && rbgs_restrict_fused(p->d, L.n, zero && mg.nu_pre == 1)) {
         // pre-smoothing steps; the last one fused with residual + restriction
         smooth_steps<T>(p, mg, mg.nu_pre - 1, l, co, zero, rhs, cur, other, s, L.shape);
         if (fra && zero && mg.nu_pre == 1 && p->d == 2)  // rhs formed in the first launch (writes rhs)
             HIPCHK(launch_rhs_rbgs_restrict_tile<T>(p->d, L.n, *fra, co, (T*)rhs, other, (T*)C.r, s, L.shape));
         else {
-            ProbeScope probe(p, zero ? -2 : ISDC_KERNEL_SMOOTH_RESTRICT, l, mg_bytes(p, ISDC_KERNEL_SMOOTH_RESTRICT, l));
+            const int kind = zero ? ISDC_KERNEL_ZSMOOTH_RESTRICT : ISDC_KERNEL_SMOOTH_RESTRICT;
+            ProbeScope probe(p, kind, l, mg_bytes(p, kind, l));
             HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, zero, rhs, cur, other, (T*)C.r, s, L.shape));
         }
         std::swap(cur, other);
@@ -1215,7 +1217,8 @@ int isdc_probe_arm(isdc_plan* plan, int32_t kernel, int32_t level, int32_t every
         check_plan(plan);
         if (plan->compact) fail(ISDC_E_UNSUPPORTED, "probes follow second-order stencil plans");
         const bool leveled = kernel == ISDC_KERNEL_SMOOTH_RESTRICT || kernel == ISDC_KERNEL_SMOOTH ||
-                             kernel == ISDC_KERNEL_RESTRICT || kernel == ISDC_KERNEL_PROLONG_SMOOTH;
+                             kernel == ISDC_KERNEL_RESTRICT || kernel == ISDC_KERNEL_PROLONG_SMOOTH ||
+                             kernel == ISDC_KERNEL_ZSMOOTH_RESTRICT;
         if (!leveled && kernel != ISDC_KERNEL_PROLONG_UPDATE && kernel != ISDC_KERNEL_TAIL &&
             kernel != ISDC_KERNEL_QUAD && kernel != ISDC_KERNEL_RHS)
             fail(ISDC_E_INVAL, "kernel cannot be followed by a probe");

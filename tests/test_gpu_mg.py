@@ -235,6 +235,27 @@ def test_vcycle_parity_every_march_depth(dtype):
         assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5), shape
 
 
+def test_vcycle_v11_zero_start_marched_level_parity():
+    # V(1,1) on 255^3: the 127^3 level starts every cycle from zero, so its
+    # first red-black step runs fused with the residual's restriction
+    # (k_march_zrestrict); 255^3 and 127^3 are both z-marched
+    n, d = 255, 3
+    h = 1.0 / (n + 1)
+    c = 64.0 * h * h
+    rhs = random_field((n,) * d, 37)
+    u0 = random_field((n,) * d, 38)
+    for dtype in (torch.float64, torch.float32):
+        nd = _np_dtype(dtype)
+        ref = u0.astype(nd)
+        for _ in range(2):
+            ref = O.vcycle(ref, rhs.astype(nd), c, h, RBGS, 1, 1)
+        announce("vcycle V(1,1) 255^3", dtype)
+        p = _plan(d, n, RBGS, nu_pre=1, nu_post=1)
+        u = dev(u0, dtype)
+        p.vcycle(c, dev(rhs, dtype), u, ncycles=2)
+        assert rel_l2(host(u), ref) < (1e-12 if dtype == torch.float64 else 2e-5), dtype
+
+
 def test_autotune_picks_valid_shapes_and_keeps_results(tmp_path, monkeypatch):
     from paper_1401_7824_amd import ISDCError
     announce("autotune")
