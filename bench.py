@@ -221,7 +221,7 @@ def probe_kernel_name(key, cfg, T, shape=0):
         return f"k_euler_rhs<{T},{d},0>"
     if d == 3 and cfg["n"] >= 127:
         return {"smooth": f"k_march_rbgs<{T},false,0,false>", "restrict": f"k_march_restrict<{T}>",
-                "zsmooth_restrict": f"k_march_zrestrict<{T}>",
+                "zsmooth_restrict": f"k_march_zrestrict<{T}>", "smooth_restrict": f"k_march_srestrict<{T}>",
                 "prolong_smooth": f"k_march_rbgs<{T},true,0,false>",
                 "prolong_update": f"k_march_rbgs<{T},true,1,false>"}[key]
     if d == 2 and cfg.get("smoother", 0) == 1:  # fused weighted-Jacobi row kernels of the five-point operator

@@ -306,7 +306,8 @@ int isdc_get_tile_shapes(const isdc_plan* plan, int32_t* h_shapes, int32_t max_l
  * ISDC_KERNEL_TAIL (the compact tail) and ISDC_KERNEL_EXPLICIT only.
  *   ISDC_KERNEL_SMOOTH_RESTRICT  one red-black step fused with the residual's
  *                                full-weighting restriction (levels above the
- *                                coarse tail, d = 1 or 2)
+ *                                coarse tail, d = 1 or 2; 3D levels of 127^3
+ *                                and up)
  *   ISDC_KERNEL_PROLONG_SMOOTH   prolongation + correction + one red-black step
  *   ISDC_KERNEL_SMOOTH           one red-black step
  *   ISDC_KERNEL_TAIL             the single-workgroup coarse tail (level ignored)
@@ -325,8 +326,9 @@ int isdc_time_kernel(isdc_plan* plan, int32_t kernel, int32_t level, double c, i
  * event pair (hipExtLaunchKernelGGL, so no extra packet is placed between
  * launches), up to max_samples (1..1000000) launches.  The launches that are
  * followed (second-order stencil plans; other launches are not followed):
- *   ISDC_KERNEL_SMOOTH_RESTRICT  2D red-black step + residual + restriction
- *                                from a nonzero iterate;
+ *   ISDC_KERNEL_SMOOTH_RESTRICT  red-black step + residual + restriction
+ *                                from a nonzero iterate (2D; 3D levels of
+ *                                127^3 and up);
  *   ISDC_KERNEL_SMOOTH           a red-black step from a nonzero iterate;
  *   ISDC_KERNEL_ZSMOOTH_RESTRICT a red-black step from a zero iterate fused
  *                                with the residual's restriction (the first

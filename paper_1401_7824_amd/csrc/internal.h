@@ -116,9 +116,9 @@ hipError_t launch_rbgs_tile(int d, int n, const Coef<T>& co, bool zero, const T*
 template <typename T>
 hipError_t launch_restrict_tile(int d, int n, const Coef<T>& co, const T* r, const T* e, T* rc, hipStream_t s);
 // One red-black step from e_in to e_out fused with rc = full weighting of
-// (r - A e_out).  d = 1, 2; in 3D only the zero-start step (zero = true) of a
-// z-marched level (rbgs_restrict_fused says which).
-bool rbgs_restrict_fused(int d, int n, bool zero);
+// (r - A e_out).  d = 1, 2, and 3D z-marched levels (rbgs_restrict_fused
+// says which).
+bool rbgs_restrict_fused(int d, int n);
 template <typename T>
 hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                                      T* rc, hipStream_t s, int shape = 0);

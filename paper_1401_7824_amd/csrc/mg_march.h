@@ -703,5 +703,244 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
     }
 }
 
+// One red-black step from a nonzero iterate fused with the residual and its
+// full weighting, z-marched over the coarse planes of march_restrict_body's
+// tile and column.  Planes of the old iterate (xy halo 3) enter a ring of six
+// LDS planes; per coarse step the red points of the two newest complete
+// planes are updated on the tile plus an xy halo of 2 (they read only old
+// black values: the black points of those planes are updated after them),
+// then the black points of the two planes below on the tile plus a halo of
+// 1 (reading only new red values), whose owned points go to e_out; the
+// residual of the two planes below those goes to one of two LDS planes and
+// each coarse point's weighted sum accumulates in a register.  The rhs of a
+// plane stays in the registers that loaded it for its red, black and
+// residual passes.  One pass replaces the red-black step and the
+// restriction (the iterate is written once and never read back); the red
+// and black updates, the residual and the weighted sums (added in the same
+// order) are the expressions of the two kernels it replaces, term for term.
+template <typename T>
+__device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, const T* __restrict__ e_in,
+                                                     T* __restrict__ e_out, T* __restrict__ rc, int n, int X0, int Y0,
+                                                     int Z0, int mzc, T a, T diag, T invdiag) {
+    using RB = Box<2, 2 * MRTile::X + 1, 2 * MRTile::Y + 1, 1>;  // residual plane, fine origin (2X0, 2Y0)
+    using OB = Box<2, 2 * MRTile::X + 7, 2 * MRTile::Y + 7, 1>;  // iterate plane, origin (2X0-3, 2Y0-3)
+    constexpr int IZ = (OB::N + kThreads - 1) / kThreads;
+    constexpr int NS = 6;  // ring of fine planes f .. f+5 of a step
+    constexpr int NC = MRTile::X * MRTile::Y;
+    static_assert(NC <= kThreads, "one coarse point per thread");
+    __shared__ T sE[NS][OB::N];
+    __shared__ T sRes[2][RB::N];
+    const size_t nn = (size_t)n * n;
+    const int nc = (n - 1) / 2;
+    const int Z1 = min(Z0 + mzc, nc);
+    const int fx = 2 * X0, fy = 2 * Y0;
+    auto slot = [](int p) { return (p % NS + NS) % NS; };
+
+    // This thread's points of the plane box (the same in every pass), as in
+    // march_zrestrict_body: row offset, residual-box index and flags (inside
+    // the grid; in the red box (halo 2), the black box (halo 1) or the
+    // residual box; owned; parity of x + y).
+    enum { F_IN = 1, F_ZB = 2, F_EB = 4, F_RB = 8, F_OWN = 16, F_ODD = 32 };
+    unsigned goff[IZ];
+    int rbi[IZ], fl[IZ];
+#pragma unroll
+    for (int it = 0; it < IZ; ++it) {
+        const int k = threadIdx.x + it * kThreads;
+        int lx, ly, lz;
+        OB::split(k, lx, ly, lz);
+        const int x = fx - 3 + lx, y = fy - 3 + ly;
+        int f = 0;
+        if (k < OB::N) {
+            if (inside<2>(x, y, 0, n)) f |= F_IN;
+            if (lx >= 1 && lx <= OB::X - 2 && ly >= 1 && ly <= OB::Y - 2) f |= F_ZB;
+            if (lx >= 2 && lx <= OB::X - 3 && ly >= 2 && ly <= OB::Y - 3) f |= F_EB;
+            if (lx >= 3 && lx <= OB::X - 4 && ly >= 3 && ly <= OB::Y - 4) f |= F_RB;
+            const bool ox = x >= fx && x < n && (x < fx + 2 * MRTile::X || x == n - 1);
+            const bool oy = y >= fy && y < n && (y < fy + 2 * MRTile::Y || y == n - 1);
+            if (ox && oy) f |= F_OWN;
+            if ((lx + ly) & 1) f |= F_ODD;  // x + y = fx + fy - 6 + lx + ly: the parity of lx + ly
+        }
+        fl[it] = f;
+        goff[it] = (f & F_IN) ? (unsigned)y * (unsigned)n + (unsigned)x : 0u;
+        rbi[it] = (ly - 3) * RB::X + (lx - 3);
+    }
+
+    auto load_e = [&](T (&dst)[IZ], int p) {
+        const bool pok = (unsigned)p < (unsigned)n;
+        const T* b = pok ? e_in + (size_t)p * nn : e_in;
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) dst[it] = (pok && (fl[it] & F_IN)) ? b[goff[it]] : T(0);
+    };
+    auto load_r = [&](T (&dst)[IZ], int p) {
+        const bool pok = (unsigned)p < (unsigned)n;
+        const T* b = pok ? r + (size_t)p * nn : r;
+#pragma unroll
+        for (int it = 0; it < IZ; ++it)
+            dst[it] = (pok && (fl[it] & (F_IN | F_ZB)) == (F_IN | F_ZB)) ? b[goff[it]] : T(0);
+    };
+    auto store_e = [&](const T (&src)[IZ], int p) {
+        T* d = sE[slot(p)];
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            if (k < OB::N) d[k] = src[it];
+        }
+    };
+    // one colour of plane p in place: red (even x + y + p) on the red box or
+    // black on the black box; the black pass writes the owned points of p
+    auto colour = [&](int p, const T (&rr)[IZ], bool blk) {
+        if ((unsigned)p >= (unsigned)n) return;  // ghost planes stay zero
+        T* e0 = sE[slot(p)];
+        const T* em = sE[slot(p - 1)];
+        const T* ep = sE[slot(p + 1)];
+        const bool pown = blk && p >= 2 * Z0 && (p < 2 * Z1 || p == n - 1);
+        T* ob = e_out + (size_t)p * nn;
+        const int want = blk ? 1 - (p & 1) : (p & 1);  // parity of x + y of the colour's points
+        const int box = blk ? F_EB : F_ZB;
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            const int k = threadIdx.x + it * kThreads;
+            if ((fl[it] & (box | F_IN)) != (box | F_IN)) continue;
+            if (((fl[it] & F_ODD) ? 1 : 0) == want) {
+                const T nb = e0[k - 1] + e0[k + 1] + e0[k - OB::X] + e0[k + OB::X] + em[k] + ep[k];
+                const T v = (rr[it] + a * nb) * invdiag;
+                e0[k] = v;
+                if (pown && (fl[it] & F_OWN)) ob[goff[it]] = v;
+            } else if (pown && (fl[it] & F_OWN)) {
+                ob[goff[it]] = e0[k];  // the red point, final since the red pass
+            }
+        }
+    };
+    auto residual = [&](const T (&rr)[IZ], int f) {
+        const T* em = sE[slot(f - 1)];
+        const T* e0 = sE[slot(f)];
+        const T* ep = sE[slot(f + 1)];
+        T* out = sRes[f & 1];
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            if (!(fl[it] & F_RB)) continue;
+            const int i = threadIdx.x + it * kThreads;
+            T v = T(0);
+            if (fl[it] & F_IN) {
+                const T nb = e0[i - 1] + e0[i + 1] + e0[i - OB::X] + e0[i + OB::X] + em[i] + ep[i];
+                v = rr[it] - (diag * e0[i] - a * nb);
+            }
+            out[rbi[it]] = v;
+        }
+    };
+    const int cx = threadIdx.x % MRTile::X, cy = threadIdx.x / MRTile::X;
+    const bool cown = threadIdx.x < NC && X0 + cx < nc && Y0 + cy < nc;
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    auto weigh = [&](T& acc, int f, int oz) {
+        const T* s = sRes[f & 1];
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const int base = (2 * cy + oy) * RB::X + 2 * cx;
+            T row = w[0] * s[base] + w[1] * s[base + 1] + w[2] * s[base + 2];
+            T wyz = w[oy] * w[oz];
+            acc += wyz * row;
+        }
+    };
+
+    T ea[IZ], eb[IZ], rA[IZ], rB[IZ], rC[IZ], rD[IZ];
+    T acc = T(0);
+    const int f0 = 2 * Z0;
+    // prologue: red on planes f0-2 .. f0+2, black on f0-1 .. f0+1, residual
+    // plane f0 and its part of coarse plane Z0
+    {
+        T e2[IZ], e3[IZ], e4[IZ], e5[IZ], rr[IZ];
+        load_e(ea, f0 - 3);
+        load_e(eb, f0 - 2);
+        load_e(e2, f0 - 1);
+        load_e(e3, f0);
+        load_e(e4, f0 + 1);
+        load_e(e5, f0 + 2);
+        load_r(rr, f0 - 2);
+        load_r(rA, f0 - 1);
+        load_r(rB, f0);
+        load_r(rC, f0 + 1);
+        store_e(ea, f0 - 3);
+        store_e(eb, f0 - 2);
+        store_e(e2, f0 - 1);
+        store_e(e3, f0);
+        store_e(e4, f0 + 1);
+        store_e(e5, f0 + 2);
+        load_e(ea, f0 + 3);
+        __syncthreads();
+        // a red pass reads only black points, which no red update writes:
+        // the planes share one pass
+        colour(f0 - 2, rr, false);
+        colour(f0 - 1, rA, false);
+        colour(f0, rB, false);
+        colour(f0 + 1, rC, false);
+        load_r(rD, f0 + 2);
+        __syncthreads();  // red(f0 - 2), the last reader of plane f0 - 3, is done
+        store_e(ea, f0 + 3);
+        __syncthreads();
+        colour(f0 + 2, rD, false);
+        __syncthreads();
+        colour(f0 - 1, rA, true);
+        colour(f0, rB, true);
+        colour(f0 + 1, rC, true);
+        __syncthreads();
+        residual(rB, f0);
+        __syncthreads();
+        if (cown) weigh(acc, f0, 0);
+    }
+    // registers of the first step: rhs of planes f0+1 .. f0+4 in rA .. rD,
+    // iterate planes f0+4, f0+5 in ea, eb
+#pragma unroll
+    for (int it = 0; it < IZ; ++it) {
+        rA[it] = rC[it];
+        rB[it] = rD[it];
+    }
+    load_r(rC, f0 + 3);
+    load_r(rD, f0 + 4);
+    load_e(ea, f0 + 4);
+    load_e(eb, f0 + 5);
+    for (int Z = Z0; Z < Z1; ++Z) {
+        const int f = 2 * Z;
+        // planes f+4, f+5 go into the slots of f-2 and f-1, whose last
+        // readers (the residuals of f-1 and f) passed the step's last barrier
+        store_e(ea, f + 4);
+        store_e(eb, f + 5);
+        T rE[IZ], rF[IZ];
+        if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
+            load_e(ea, f + 6);
+            load_e(eb, f + 7);
+            load_r(rE, f + 5);
+            load_r(rF, f + 6);
+        } else {
+#pragma unroll
+            for (int it = 0; it < IZ; ++it) rE[it] = rF[it] = T(0);
+        }
+        __syncthreads();
+        // red on f+3 and f+4 reads old black values of f+2 .. f+5
+        colour(f + 3, rC, false);
+        colour(f + 4, rD, false);
+        __syncthreads();
+        colour(f + 2, rB, true);
+        colour(f + 3, rC, true);
+        __syncthreads();
+        residual(rA, f + 1);
+        residual(rB, f + 2);
+        __syncthreads();
+        if (cown) {
+            weigh(acc, f + 1, 1);
+            weigh(acc, f + 2, 2);
+            rc[((size_t)Z * nc + (Y0 + cy)) * nc + (X0 + cx)] = acc;
+            acc = T(0);
+            weigh(acc, f + 2, 0);
+        }
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            rA[it] = rC[it];
+            rB[it] = rD[it];
+            rC[it] = rE[it];
+            rD[it] = rF[it];
+        }
+    }
+}
+
 }  // namespace
 }  // namespace isdc

@@ -120,6 +120,19 @@ k_march_zrestrict(const T* __restrict__ r, T* __restrict__ e_out, T* __restrict_
     march_zrestrict_body<T>(r, e_out, rc, n, X0, Y0, Z0, mzc, a, diag, invdiag);
 }
 
+// 3D red-black step from a nonzero iterate fused with the residual and full
+// weighting, z-marched over coarse planes (levels of 127^3 and up): writes
+// the iterate and the coarse rhs.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_march_srestrict(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, T* __restrict__ rc, int n,
+                  int ntx, int nty, int mzc, T a, T diag, T invdiag, const int* __restrict__ gate) {
+    if (gate && *gate) return;  // the solve met its tolerance on the device
+    int X0, Y0, Z0;
+    tile_origin(ntx, nty, MRTile::X, MRTile::Y, mzc, X0, Y0, Z0);
+    march_srestrict_body<T>(r, e_in, e_out, rc, n, X0, Y0, Z0, mzc, a, diag, invdiag);
+}
+
 template <typename T, bool ZERO, int S>
 __global__ void __launch_bounds__(kThreads)
 k_rows_rbgs(const T* __restrict__ r, const T* __restrict__ e_in, T* __restrict__ e_out, int n, int ntx, int nty, T a,
@@ -244,16 +257,21 @@ int march_depth_of(int n, int shape) {
     return march_depth_fitted(n, shape, ntx * nty, shape == 1 ? march_resident<T, PRO, MODE, ZERO>() : 0);
 }
 
-// Coarse planes per column of the fused zero-start restriction: the depth at
-// which all columns fit in one round of resident workgroups, at least 4.
-template <typename T>
-int zrestrict_depth(int nc, int nxy) {
+// Coarse planes per column of the fused red-black step + restriction (ZERO:
+// from a zero iterate): the depth at which all columns fit in one round of
+// resident workgroups, at least 4.
+template <typename T, bool ZERO>
+int frestrict_depth(int nc, int nxy) {
     static const int resident = [] {
         int dev = 0, cus = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess) return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_march_zrestrict<T>, kThreads, 0) != hipSuccess)
-            return 0;
+        hipError_t e;
+        if constexpr (ZERO)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_march_zrestrict<T>, kThreads, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_march_srestrict<T>, kThreads, 0);
+        if (e != hipSuccess) return 0;
         return per * cus;
     }();
     if (resident <= 0) return march_restrict_depth();
@@ -322,16 +340,19 @@ template <typename T>
 hipError_t launch_rbgs_restrict_tile(int d, int n, const Coef<T>& co, bool zero, const T* r, const T* e_in, T* e_out,
                                      T* rc, hipStream_t s, int shape) {
     if (d == 3) {
-        // 3D: only the zero-start step of a marched level is fused (a step
-        // from a nonzero iterate uses the separate kernels: LDS budget)
-        if (!zero || march_depth(n) <= 0) return hipErrorInvalidValue;
+        // 3D: z-marched levels only (the 3D tiles would need a halo of 3)
+        if (march_depth(n) <= 0) return hipErrorInvalidValue;
         const int nc = (n - 1) / 2;
         int ntx, nty, nb;
         tile_counts<3>(nc, MRTile::X, MRTile::Y, nc, ntx, nty, nb);
-        const int mzc = zrestrict_depth<T>(nc, ntx * nty);
+        const int mzc = zero ? frestrict_depth<T, true>(nc, ntx * nty) : frestrict_depth<T, false>(nc, ntx * nty);
         tile_counts<3>(nc, MRTile::X, MRTile::Y, mzc, ntx, nty, nb);
-        ISDC_GLAUNCH((k_march_zrestrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e_out, rc, n, ntx, nty, mzc, co.a,
-                     co.diag, co.invdiag);
+        if (zero)
+            ISDC_GLAUNCH((k_march_zrestrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e_out, rc, n, ntx, nty, mzc, co.a,
+                         co.diag, co.invdiag);
+        else
+            ISDC_GLAUNCH((k_march_srestrict<T>), dim3(nb), dim3(kThreads), 0, s, r, e_in, e_out, rc, n, ntx, nty, mzc,
+                         co.a, co.diag, co.invdiag);
         return hipGetLastError();
     }
     if (d == 2) {
@@ -445,7 +466,7 @@ hipError_t launch_tail(const MGConfig& cfg, int n, double c, double h, bool zero
     return hipGetLastError();
 }
 
-bool rbgs_restrict_fused(int d, int n, bool zero) { return d <= 2 || (d == 3 && zero && march_depth(n) > 0); }
+bool rbgs_restrict_fused(int d, int n) { return d <= 2 || (d == 3 && march_depth(n) > 0); }
 
 #define ISDC_INST_T(T)                                                                                          \
     template hipError_t launch_rbgs_tile<T>(int, int, const Coef<T>&, bool, const T*, const T*, T*, hipStream_t, int); \

@@ -423,7 +423,7 @@ bool vcycle_rec(isdc_plan* p, const MGConfig& mg, int l, double c, bool zero, co
     T* cur = e;
     T* other = tmp;
     const Level& C = p->lev[l + 1];
-    if (rbgs && mg.nu_pre >= 1 && rbgs_restrict_fused(p->d, L.n, zero && mg.nu_pre == 1)) {
+    if (rbgs && mg.nu_pre >= 1 && rbgs_restrict_fused(p->d, L.n)) {
         // pre-smoothing steps; the last one fused with residual + restriction
         smooth_steps<T>(p, mg, mg.nu_pre - 1, l, co, zero, rhs, cur, other, s, L.shape);
         if (fra && zero && mg.nu_pre == 1 && p->d == 2)  // rhs formed in the first launch (writes rhs)
@@ -1534,7 +1534,8 @@ void time_kernel_impl(isdc_plan* p, int kernel, int level, double c, int reps, h
         const Coef<T> co = make_coef<T>(c, L.h, d, p->mg.omega);
         const double N = (double)L.N, Nc = (double)C.N;
         if (kernel == ISDC_KERNEL_SMOOTH_RESTRICT) {
-            if (d == 3) fail(ISDC_E_UNSUPPORTED, "the fused smoothing + restriction kernel is 1D/2D only");
+            if (!rbgs_restrict_fused(d, L.n))
+                fail(ISDC_E_UNSUPPORTED, "3D fused smoothing + restriction runs on levels of 127^3 and up");
             launch = [=]() { HIPCHK(launch_rbgs_restrict_tile<T>(d, L.n, co, false, (const T*)L.r, (const T*)L.e, (T*)L.e2, (T*)C.r, s, L.shape)); };
             b = (3.0 * N + Nc) * w;
         } else if (kernel == ISDC_KERNEL_PROLONG_SMOOTH) {
@@ -1599,7 +1600,7 @@ void level_tile_kernels(isdc_plan* p, int l, hipStream_t s) {
     T* a = (T*)L.e;
     T* b = (T*)L.e2;
     int plain = mg.nu_pre + (mg.nu_post > 0 ? mg.nu_post - 1 : 0);
-    if (p->d <= 2 && mg.nu_pre >= 1) {
+    if (rbgs_restrict_fused(p->d, L.n) && mg.nu_pre >= 1) {
         HIPCHK(launch_rbgs_restrict_tile<T>(p->d, L.n, co, false, r, a, b, (T*)C.r, s, L.shape));
         --plain;
     }
