@@ -649,9 +649,9 @@ def run_kernels(args, torch):
         p = Plan(d, n, 1.0, 0, node_kind=0, M=3, precision=prec)
         c = 1e-3 * 0.5
         row = {"dim": d, "n": n, "dtype": "f64" if prec == 0 else "f32"}
-        kinds = [("smooth", P.KERNEL_SMOOTH), ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH)]
-        if d < 3:
-            kinds.insert(0, ("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT))
+        # the fused smoothing + restriction runs on 2D levels and on z-marched 3D levels
+        kinds = [("smooth_restrict", P.KERNEL_SMOOTH_RESTRICT), ("smooth", P.KERNEL_SMOOTH),
+                 ("prolong_smooth", P.KERNEL_PROLONG_SMOOTH)]
         nl = len(p.tile_shapes)
         shapes = range(3)  # tile shapes (3D levels of 127^3 and up: column depths of the z-march)
         for name, k in kinds:
@@ -906,6 +906,9 @@ def run_followed(args, cfg, torch):
     elapsed, wall, stats = time_steps(plan, u, cfg["dt"], args.steps, 0, torch)
     nl, avg_us, alg_b = plan.probe_read()
     print(f"[bench] {name}: {args.steps} timed steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # as many further steps with no kernel followed: what the per-launch event
+    # pairs cost, which shows only where the followed launches are short
+    elapsed_free, _, stats_free = time_steps(plan, u, cfg["dt"], args.steps, 0, torch)
     sweeps = sum(s.sweeps for s in stats) / len(stats)
     vcyc = sum(s.vcycles for s in stats) / len(stats)
     kname = probe_kernel_name(dom_key, cfg, T, (shapes or [0])[0])
@@ -931,9 +934,15 @@ def run_followed(args, cfg, torch):
                    "survey_steps": nsurvey},
         "roofline": roof,
         "kernels_followed_us_per_step": kernels,
+        # later steps of the same integration may take other sweep counts, so the
+        # time per sweep is the comparable figure
+        "unobserved": {"steps_per_s": round(args.steps / elapsed_free, 4),
+                       "sweeps_per_step": sum(s.sweeps for s in stats_free) / len(stats_free),
+                       "ms_per_sweep": round(elapsed_free * 1e3 / sum(s.sweeps for s in stats_free), 4),
+                       "ms_per_sweep_followed": round(elapsed * 1e3 / sum(s.sweeps for s in stats), 4)},
         "kernel_share_of_step": round(total / (elapsed / args.steps * 1e6), 3),
     }
-    nstep = nsurvey + args.warmup + args.steps
+    nstep = nsurvey + args.warmup + 2 * args.steps  # survey, warm-up, followed and unobserved steps
     if cfg["fe_kind"] == W.FE_ZERO and modes is not None:
         ref = collocation_reference(cfg, modes, nstep)
         got = u.cpu().numpy()
