@@ -49,6 +49,8 @@ def parse():
                     help="with --serve-capacity: also run the one-at-a-time baseline with every request at t = 0")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-cycles", default="jacobi33", choices=["rbgs11", "jacobi33"],
+                    help="V-cycles of the batched instances: red-black V(1,1) or weighted-Jacobi V(3,3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve-latency", action="store_true",
                     help="skip the short serving run that gives the headline line its p50/p99 latency")
@@ -442,7 +444,9 @@ def run_batch(args, torch):
     inst = W.batch_instances(args.batch_count)
     u0s = [W.sine_field(x["n"], 2, W.draw_modes(2, x["n_modes"], x["seed"])) for x in inst]
     steps = args.batch_steps
-    par = lambda x: dict(node_kind=x["node_kind"], M=x["M"], precision=x["precision"], sdc_tol=x["sdc_tol"])  # noqa: E731
+    cyc = dict(smoother=1, nu_pre=3, nu_post=3) if args.batch_cycles == "jacobi33" else {}
+    par = lambda x: dict(node_kind=x["node_kind"], M=x["M"], precision=x["precision"], sdc_tol=x["sdc_tol"],  # noqa: E731
+                         **cyc)
     b = Batch(len(inst), 2, precision=1, vcycles=2)
     ws = [torch.empty(Batch.workspace_bytes_for(x["n"], 2, x["nu"], x["fe_kind"], **par(x)), dtype=torch.uint8,
                       device="cuda") for x in inst]
@@ -493,7 +497,8 @@ def run_batch(args, torch):
         "steps": total, "warmup": 1, "ms_per_step": round(t_batch / total * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"batch: {len(inst)} 2D reaction-diffusion instances, side 63..511, "
-                               f"{steps} steps each, float32 V-cycles, tol 1e-8",
+                               f"{steps} steps each, float32 "
+                               f"{'weighted-Jacobi V(3,3)' if cyc else 'red-black V(1,1)'} V-cycles, tol 1e-8",
                    "batch_sweeps": sweeps, "sizes": {str(k): sum(1 for x in inst if x['n'] == k) for k in (63, 127, 255, 511)}},
         "per_instance_baseline": {"value": round(total / t_single, 3), "unit": "instance-steps/s",
                                   "seconds": round(t_single, 3)},

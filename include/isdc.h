@@ -356,11 +356,13 @@ int isdc_probe_read(isdc_plan* plan, int64_t* h_samples, double* h_avg_us, doubl
  * A batch advances many independent ISDC instances ("slots") together: every
  * phase of a sweep is one kernel launch covering all running slots, so small
  * and uneven instances fill the GPU together.  Slots may differ in grid size,
- * nu, f^E, dt, node family, M, tolerance, max_sweeps and number of steps; all
- * slots of a batch share the dimension, the V-cycle precision and L, and run
- * red-black Gauss-Seidel V(1,1) cycles warm-started from the previous sweep
- * (Sec. 3, Sec. 4.3) -- other parameters return ISDC_E_UNSUPPORTED.  A
- * slot's results are bitwise those of isdc_step on the same instance. */
+ * nu, f^E, dt, node family, M, tolerance, max_sweeps, number of steps and
+ * (2D) cycles; all slots of a batch share the dimension, the V-cycle
+ * precision and L, and run red-black Gauss-Seidel V(1,1) cycles or, in 2D,
+ * weighted-Jacobi V(nu1, nu2) cycles with 1 <= nu1, nu2 <= 3, warm-started
+ * from the previous sweep (Sec. 3, Sec. 4.3) -- other parameters return
+ * ISDC_E_UNSUPPORTED.  A slot's results are bitwise those of isdc_step on the
+ * same instance. */
 typedef struct isdc_batch isdc_batch;
 
 /* Slot states reported by isdc_batch_slot_info. */

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "jrows.h"
 #include "mg_device.h"
 #include "mg_march.h"
 #include "plan.h"
@@ -50,6 +51,11 @@ struct SlotDesc {
     void* le2[kMaxLev];
     double la[ISDC_MAX_M][kMaxLev], ldiag[ISDC_MAX_M][kMaxLev], linv[ISDC_MAX_M][kMaxLev];
     TailCoefs tail[ISDC_MAX_M];
+    // weighted-Jacobi V(jpre, jpost) cycles (jac = 1; 2D): the five-point
+    // operator's coefficients (make_coef5) per phase and level, and omega
+    int jac, jpre, jpost;
+    double jomega;
+    double jb0[ISDC_MAX_M][kMaxLev], jbf[ISDC_MAX_M][kMaxLev], jinv[ISDC_MAX_M][kMaxLev];
     double* ustate;                // u_0 of the current step; receives u_M at its end
     double* U[2][ISDC_MAX_M + 1];  // node j of buffer b (j = 0, and j = 1 for Gauss-Lobatto: ustate)
     double* SF[ISDC_MAX_M];
@@ -187,7 +193,44 @@ __global__ void __launch_bounds__(kTail) kb_tail(BArgs a) {
     const int l = s.nlev;
     // the tail starts from zero below the finest level and in the first cycle
     const int zero = (a.flag == 0 || l > 0) ? 1 : 0;
-    tailc_body<T, D>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_RBGS, 1, 1, 0.0, zero);
+    if (s.jac)
+        tailc_body<T, D>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_JACOBI, s.jpre, s.jpost,
+                         s.jomega, zero);
+    else
+        tailc_body<T, D>((const T*)s.lr[l], (T*)s.le[l], s.ln[l], s.tail[a.p], ISDC_SMOOTH_RBGS, 1, 1, 0.0, zero);
+}
+
+// 2D weighted-Jacobi cycles, as the single-instance fused row kernels: K
+// steps + residual + full weighting (e: le -> le2, coarse rhs: lr[l+1]) ...
+template <typename T, int K, bool ZERO>
+__global__ void __launch_bounds__(kThreads) kb_jres(BArgs a) {
+    int i, t;
+    map_lookup(a.map, i, t);
+    const SlotDesc& s = a.desc[i];
+    const int l = a.level, p = a.p;
+    int x0, y0, z0;
+    tile_xyz<2>(t, s.ln[l], CVT<K>::TX, CVT<K>::TY, 1, x0, y0, z0);
+    const CCoef<T> k{T(s.jb0[p][l]), T(s.jbf[p][l]), T(0), T(s.jinv[p][l]), T(s.jomega)};
+    cjres_tile<T, false, K, ZERO, false>((const T*)s.lr[l], (const T*)s.le[l], (T*)s.le2[l], (T*)s.lr[l + 1], s.ln[l],
+                                        x0, y0, k);
+}
+
+// ... and prolongation + correction + K steps (le2 + P le[l+1] -> le; MODE 1:
+// the node value g + e to the sweep's node array instead)
+template <typename T, int K, int MODE>
+__global__ void __launch_bounds__(kThreads) kb_pjac(BArgs a) {
+    int i, t;
+    map_lookup(a.map, i, t);
+    const SlotDesc& s = a.desc[i];
+    const int l = a.level, p = a.p;
+    int x0, y0, z0;
+    tile_xyz<2>(t, s.ln[l], CVT<K>::TX, CVT<K>::TY, 1, x0, y0, z0);
+    const int par = a.st[i].parity, m = s.sub[p];
+    const double* g = MODE == 1 ? s.U[par ^ 1][m + 1] : nullptr;
+    double* u_out = MODE == 1 ? s.U[par][m + 1] : nullptr;
+    const CCoef<T> k{T(s.jb0[p][l]), T(s.jbf[p][l]), T(0), T(s.jinv[p][l]), T(s.jomega)};
+    cpjac_tile<T, false, K, false, MODE>((const T*)s.lr[l], (const T*)s.le2[l], (const T*)s.le[l + 1], (T*)s.le[l],
+                                         s.ln[l], x0, y0, k, g, u_out);
 }
 
 template <typename T, int D, int MODE>
@@ -384,6 +427,15 @@ int tiles_smooth(int d, int n, bool fp64) {
     return tiles_fine(d, n);
 }
 
+// Workgroups of the 2D weighted-Jacobi kernels with K steps on an n^2 level.
+int tiles_jac(int K, int n) {
+    switch (K) {
+        case 1: return ntiles_of<2>(n, CVT<1>::TX, CVT<1>::TY, 1);
+        case 2: return ntiles_of<2>(n, CVT<2>::TX, CVT<2>::TY, 1);
+        default: return ntiles_of<2>(n, CVT<3>::TX, CVT<3>::TY, 1);
+    }
+}
+
 int tiles_coarse(int d, int nc) {
     if (d == 3 && march_depth(2 * nc + 1) > 0)  // the fine level is marched: so is its restriction
         return ntiles_of<3>(nc, MRTile::X, MRTile::Y, march_restrict_depth());
@@ -400,8 +452,13 @@ void check_batch_params(const isdc_batch* b, const isdc_problem* pb, const isdc_
         fail(ISDC_E_UNSUPPORTED, "batches run node families that end on tau_M = 1 only");
     if (pr->precision != b->prec) fail(ISDC_E_INVAL, "slot precision differs from the batch's");
     if (pr->vcycles != b->L) fail(ISDC_E_INVAL, "slot vcycles differs from the batch's");
-    if (pr->smoother != ISDC_SMOOTH_RBGS || pr->nu_pre != 1 || pr->nu_post != 1)
-        fail(ISDC_E_UNSUPPORTED, "batches run red-black Gauss-Seidel V(1,1) cycles only");
+    const bool rb11 = pr->smoother == ISDC_SMOOTH_RBGS && pr->nu_pre == 1 && pr->nu_post == 1;
+    const bool jac = b->d == 2 && pr->smoother == ISDC_SMOOTH_JACOBI && pr->nu_pre >= 1 && pr->nu_pre <= 3 &&
+                     pr->nu_post >= 1 && pr->nu_post <= 3;
+    if (!rb11 && !jac)
+        fail(ISDC_E_UNSUPPORTED,
+             "batches run red-black Gauss-Seidel V(1,1) cycles, or in 2D weighted-Jacobi V(nu1, nu2) cycles with "
+             "1 <= nu1, nu2 <= 3");
     if (pr->guess != ISDC_GUESS_PREV_SWEEP) fail(ISDC_E_UNSUPPORTED, "batches warm-start from the previous sweep only");
     if (pr->early_exit) fail(ISDC_E_UNSUPPORTED, "batches run exactly L cycles per solve");
     if (pr->levels != 1) fail(ISDC_E_UNSUPPORTED, "batches run single-level ISDC only");
@@ -465,6 +522,13 @@ void build_desc(isdc_batch* b, int slot) {
             s.ldiag[q][l] = co.diag;
             s.linv[q][l] = co.invdiag;
         }
+        if (p->mg.smoother == ISDC_SMOOTH_JACOBI)
+            for (int l = 0; l < p->tail; ++l) {  // as the single-instance 2D Jacobi cycle forms them
+                const CCoef<double> k5 = make_coef5<double>(c, p->lev[l].h, p->mg.omega);
+                s.jb0[q][l] = k5.b0;
+                s.jbf[q][l] = k5.bf;
+                s.jinv[q][l] = k5.inv_b0;
+            }
         // the tail's level coefficients, exactly as the single-instance launcher forms them
         double hl = p->lev[p->tail].h;
         for (int l = 0, m = p->lev[p->tail].n; l < 16; ++l, m = (m - 1) / 2, hl *= 2.0) {
@@ -475,6 +539,10 @@ void build_desc(isdc_batch* b, int slot) {
             if (m == 1) break;
         }
     }
+    s.jac = p->mg.smoother == ISDC_SMOOTH_JACOBI ? 1 : 0;
+    s.jpre = p->mg.nu_pre;
+    s.jpost = p->mg.nu_post;
+    s.jomega = p->mg.omega;
     s.ustate = sl.u;
     for (int bf = 0; bf < 2; ++bf) {
         s.U[bf][0] = sl.u;
@@ -576,6 +644,9 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
     }
     std::vector<Map> mrhs(maxns), mtail(maxns), mupd(maxns);
     std::vector<std::vector<Map>> mlev(maxns, std::vector<Map>(maxlev)), mres(maxns, std::vector<Map>(maxlev));
+    // 2D weighted-Jacobi slots by number of steps K (1..3): pre- and post-smoothing launches
+    std::vector<std::vector<std::vector<Map>>> mjres(4, std::vector<std::vector<Map>>(maxns, std::vector<Map>(maxlev)));
+    std::vector<std::vector<std::vector<Map>>> mpjac(4, std::vector<std::vector<Map>>(maxns, std::vector<Map>(maxlev)));
     std::vector<Map> mq(ISDC_MAX_M + 1);
     Map mred;
     for (int i : run) {
@@ -585,6 +656,11 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
             mtail[p].add(i, 1);
             if (sd.nlev == 0) mupd[p].add(i, ceil_div(sd.N, kChunkPts));
             for (int l = 0; l < sd.nlev; ++l) {
+                if (D == 2 && sd.jac) {
+                    mjres[sd.jpre][p][l].add(i, tiles_jac(sd.jpre, sd.ln[l]));
+                    mpjac[sd.jpost][p][l].add(i, tiles_jac(sd.jpost, sd.ln[l]));
+                    continue;
+                }
                 mlev[p][l].add(i, tiles_smooth(D, sd.ln[l], b->prec == ISDC_PREC_FP64));
                 mres[p][l].add(i, tiles_coarse(D, (sd.ln[l] - 1) / 2));
             }
@@ -600,6 +676,8 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
     }
     std::vector<size_t> o_rhs(maxns), o_tail(maxns), o_upd(maxns);
     std::vector<std::vector<size_t>> o_lev(maxns, std::vector<size_t>(maxlev)), o_res(maxns, std::vector<size_t>(maxlev));
+    std::vector<std::vector<std::vector<size_t>>> o_jres(4, std::vector<std::vector<size_t>>(maxns, std::vector<size_t>(maxlev)));
+    std::vector<std::vector<std::vector<size_t>>> o_pjac(4, std::vector<std::vector<size_t>>(maxns, std::vector<size_t>(maxlev)));
     for (int p = 0; p < maxns; ++p) {
         o_rhs[p] = mb.put(mrhs[p]);
         o_tail[p] = mb.put(mtail[p]);
@@ -607,6 +685,10 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
         for (int l = 0; l < maxlev; ++l) {
             o_lev[p][l] = mb.put(mlev[p][l]);
             o_res[p][l] = mb.put(mres[p][l]);
+            for (int K = 1; K <= 3; ++K) {
+                if (mjres[K][p][l].total) o_jres[K][p][l] = mb.put(mjres[K][p][l]);
+                if (mpjac[K][p][l].total) o_pjac[K][p][l] = mb.put(mpjac[K][p][l]);
+            }
         }
     }
     const size_t o_red = mb.put(mred);
@@ -636,6 +718,18 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
                 if (D <= 2) {
                     if (zero) ISDC_BLAUNCH((kb_rbgs_restrict<T, D, true>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
                     else ISDC_BLAUNCH((kb_rbgs_restrict<T, D, false>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
+                    if constexpr (D == 2)
+                        for (int K = 1; K <= 3; ++K) {
+                            const Map& m = mjres[K][p][l];
+                            if (!m.total) continue;
+                            const BArgs ba = A(o_jres[K][p][l], p, l, 0);
+                            if (K == 1 && zero) ISDC_BLAUNCH((kb_jres<T, 1, true>), kThreads, m, 0, ba);
+                            else if (K == 1) ISDC_BLAUNCH((kb_jres<T, 1, false>), kThreads, m, 0, ba);
+                            else if (K == 2 && zero) ISDC_BLAUNCH((kb_jres<T, 2, true>), kThreads, m, 0, ba);
+                            else if (K == 2) ISDC_BLAUNCH((kb_jres<T, 2, false>), kThreads, m, 0, ba);
+                            else if (zero) ISDC_BLAUNCH((kb_jres<T, 3, true>), kThreads, m, 0, ba);
+                            else ISDC_BLAUNCH((kb_jres<T, 3, false>), kThreads, m, 0, ba);
+                        }
                 } else {
                     if (zero) ISDC_BLAUNCH((kb_rbgs<T, D, true>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
                     else ISDC_BLAUNCH((kb_rbgs<T, D, false>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
@@ -644,10 +738,23 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
             }
             ISDC_BLAUNCH((kb_tail<T, D>), kTail, mtail[p], 0, A(o_tail[p], p, 0, c));
             for (int l = maxlev - 1; l >= 0; --l) {
-                if (l == 0 && c == L - 1)
+                const bool upd = l == 0 && c == L - 1;  // the node update u = g + e in the last launch
+                if (upd)
                     ISDC_BLAUNCH((kb_prolong_rbgs<T, D, 1>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
                 else
                     ISDC_BLAUNCH((kb_prolong_rbgs<T, D, 0>), kThreads, mlev[p][l], 0, A(o_lev[p][l], p, l, 0));
+                if constexpr (D == 2)
+                    for (int K = 1; K <= 3; ++K) {
+                        const Map& m = mpjac[K][p][l];
+                        if (!m.total) continue;
+                        const BArgs ba = A(o_pjac[K][p][l], p, l, 0);
+                        if (K == 1 && upd) ISDC_BLAUNCH((kb_pjac<T, 1, 1>), kThreads, m, 0, ba);
+                        else if (K == 1) ISDC_BLAUNCH((kb_pjac<T, 1, 0>), kThreads, m, 0, ba);
+                        else if (K == 2 && upd) ISDC_BLAUNCH((kb_pjac<T, 2, 1>), kThreads, m, 0, ba);
+                        else if (K == 2) ISDC_BLAUNCH((kb_pjac<T, 2, 0>), kThreads, m, 0, ba);
+                        else if (upd) ISDC_BLAUNCH((kb_pjac<T, 3, 1>), kThreads, m, 0, ba);
+                        else ISDC_BLAUNCH((kb_pjac<T, 3, 0>), kThreads, m, 0, ba);
+                    }
             }
         }
         ISDC_BLAUNCH((kb_update<T>), kThreads, mupd[p], 0, A(o_upd[p], p, 0, 0));
@@ -690,8 +797,10 @@ void advance_impl(isdc_batch* b, hipStream_t s, std::vector<int>& run, SweepTimi
         for (int p = 0; p < maxns; ++p) {
             launches += (mrhs[p].total > 0) + (mupd[p].total > 0);
             int per_cycle = mtail[p].total > 0;
-            for (int l = 0; l < maxlev; ++l)
+            for (int l = 0; l < maxlev; ++l) {
                 per_cycle += 2 * (mlev[p][l].total > 0) + (D == 3 && mres[p][l].total > 0);
+                for (int K = 1; K <= 3; ++K) per_cycle += (mjres[K][p][l].total > 0) + (mpjac[K][p][l].total > 0);
+            }
             launches += L * per_cycle;
         }
         timing->launches = launches;

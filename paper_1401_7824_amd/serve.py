@@ -81,23 +81,22 @@ class Request:
             _U0_DEVICE[key] = t
         return t.clone()
 
-    def params(self, precision: int, vcycles: int, solo: bool = True) -> dict:
-        """Plan parameters.  solo: the request runs on a plan of its own, where a
-        large 2D grid takes weighted-Jacobi V(3,3) cycles on the fused row
-        kernels (fewer sweeps than red-black V(1,1) at these sizes); in a batch
-        slot (the batches run red-black cycles only) it keeps red-black V(1,1).
-        The workspace is the same either way."""
+    def params(self, precision: int, vcycles: int) -> dict:
+        """Plan parameters, the same on a solo lane and in a batch slot: 2D
+        requests take weighted-Jacobi V(3,3) cycles on the fused row kernels
+        (fewer sweeps than red-black V(1,1), most of all for the reaction-
+        diffusion requests), 3D requests red-black V(1,1)."""
         p = dict(node_kind=self.node_kind, M=self.M, sdc_tol=self.sdc_tol, precision=precision,
                  vcycles=vcycles, max_sweeps=200)
-        if solo and large_2d(self):
+        if self.dim == 2:
             p.update(smoother=A.SMOOTH_JACOBI, nu_pre=3, nu_post=3)
         return p
 
-    def device_bytes(self, precision: int, vcycles: int, solo: bool = True) -> int:
-        key = (precision, vcycles, solo)
+    def device_bytes(self, precision: int, vcycles: int) -> int:
+        key = (precision, vcycles)
         if getattr(self, "_bytes_key", None) != key:
             prob = make_problem(self.dim, self.n, self.nu, self.fe_kind)
-            par = make_params(**self.params(precision, vcycles, solo))
+            par = make_params(**self.params(precision, vcycles))
             self._bytes = workspace_bytes(prob, par) + self.n ** self.dim * 8
             self._bytes_key = key
         return self._bytes
@@ -155,13 +154,8 @@ def choose_admissions(waiting, need, used: int, budget: int, free_slots: dict) -
 # chip -- or when no batch slot of its dimension is running, so that a
 # request arriving at an idle server is not slowed by the batch machinery.
 def runs_solo(req, batch_running: int) -> bool:
-    big = large_2d(req) or (req.dim == 3 and req.n >= 127)
+    big = (req.dim == 2 and req.n >= 511) or (req.dim == 3 and req.n >= 127)
     return big or batch_running == 0
-
-
-def large_2d(req) -> bool:
-    """2D grids of 511^2 and up: always solo, on weighted-Jacobi V(3,3) cycles."""
-    return req.dim == 2 and req.n >= 511
 
 
 class Server:
@@ -196,7 +190,7 @@ class Server:
     def _solo_job(self, req: Request, stream, t0: float, clock):
         """All steps of one request on its own plan and stream (a worker thread)."""
         with torch.cuda.stream(stream):
-            p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(self.precision, self.vcycles, solo=True))
+            p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(self.precision, self.vcycles))
             u = req.u0_device()
             status, sweeps = "ok", 0
             for _ in range(req.nsteps):
@@ -247,7 +241,7 @@ class Server:
         if not self.free[d] or self.used + need > self.budget:
             return False
         slot = self.free[d].pop(0)
-        par = req.params(self.precision, self.vcycles, solo=False)
+        par = req.params(self.precision, self.vcycles)
         ws = torch.empty(need - req.n ** req.dim * 8, dtype=torch.uint8, device="cuda")
         u = req.u0_device()
         self.batches[d].set(slot, u, req.dt, req.nsteps, req.nu, req.fe_kind, workspace=ws, **par)

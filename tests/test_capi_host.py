@@ -248,8 +248,14 @@ def test_fixed_batch_validation_host_only():
     mixed = (A.Params * 2)(make_params(precision=1), make_params(precision=0))
     two = (A.Problem * 2)(A.problem(2, 63, 1.0), A.problem(2, 63, 1.0))
     assert lib.isdc_batch_bytes(2, two, mixed, C.byref(out)) == A.E_INVAL
-    jac = (A.Params * 2)(make_params(), make_params(smoother=A.SMOOTH_JACOBI, nu_pre=2, nu_post=2))
-    assert lib.isdc_batch_bytes(2, two, jac, C.byref(out)) == A.E_UNSUPPORTED
+    # 2D weighted-Jacobi V(nu1, nu2) with nu1, nu2 <= 3 runs in a batch (beside red-black slots);
+    # more steps, or Jacobi in 3D, do not
+    jac = (A.Params * 2)(make_params(), make_params(smoother=A.SMOOTH_JACOBI, nu_pre=2, nu_post=3))
+    assert lib.isdc_batch_bytes(2, two, jac, C.byref(out)) == 0
+    jac4 = (A.Params * 2)(make_params(), make_params(smoother=A.SMOOTH_JACOBI, nu_pre=4, nu_post=4))
+    assert lib.isdc_batch_bytes(2, two, jac4, C.byref(out)) == A.E_UNSUPPORTED
+    cubes = (A.Problem * 2)(A.problem(3, 15, 1.0), A.problem(3, 15, 1.0))
+    assert lib.isdc_batch_bytes(2, cubes, jac, C.byref(out)) == A.E_UNSUPPORTED
     dims = (A.Problem * 2)(A.problem(2, 63, 1.0), A.problem(3, 15, 1.0))
     assert lib.isdc_batch_bytes(2, dims, (A.Params * 2)(make_params(), make_params()), C.byref(out)) == A.E_INVAL
     assert lib.isdc_batch_bytes(0, two, mixed, C.byref(out)) == A.E_INVAL

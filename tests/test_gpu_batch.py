@@ -174,13 +174,38 @@ def test_batch_matches_oracle_collocation():
     assert np.linalg.norm(got - coll) / np.linalg.norm(coll) < 1e-8
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_jacobi_2d_slots_equal_single_instance_runs(prec):
+    # 2D weighted-Jacobi slots (V(3,3) and V(2,1): the fused row kernels with
+    # 3, 2 and 1 steps) beside red-black V(1,1) slots in one batch; every slot
+    # equals its run alone bit for bit
+    from paper_1401_7824_amd import Batch
+    announce("batch jacobi 2d", prec)
+    inst = _instances(2, prec, 9, seed=70 + prec)
+    cycles = [dict(smoother=1, nu_pre=3, nu_post=3), dict(smoother=1, nu_pre=2, nu_post=1), dict()]
+    b = Batch(9, 2, precision=prec, vcycles=2)
+    us = []
+    for i, x in enumerate(inst):
+        x["par"].update(cycles[i % 3])
+        u = dev(x["u0"])
+        b.set(i, u, x["dt"], 2, x["nu"], x["fe"], **x["par"])
+        us.append(u)
+    b.run()
+    for i, x in enumerate(inst):
+        state, status, steps, st = b.info(i)
+        ref, rstats = _alone(2, x["n"], x["nu"], x["fe"], x["u0"], x["dt"], 2, **x["par"])
+        assert status == "ok" and steps == 2, (i, status)
+        assert np.array_equal(host(us[i]), ref), f"slot {i} ({cycles[i % 3]}) differs from the single-instance run"
+        assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
+
+
 def test_batch_rejects_unsupported_parameters():
     from paper_1401_7824_amd import Batch, ISDCError
     announce("batch unsupported")
     b = Batch(2, 2, precision=0, vcycles=2)
     u = dev(np.zeros((31, 31)))
     with pytest.raises(ISDCError):
-        b.set(0, u, 1e-3, 1, 1.0, smoother=1, nu_pre=2, nu_post=2)
+        b.set(0, u, 1e-3, 1, 1.0, smoother=1, nu_pre=4, nu_post=4)
     with pytest.raises(ISDCError):
         b.set(0, u, 1e-3, 1, 1.0, guess=1)
     with pytest.raises(ISDCError):

@@ -18,7 +18,7 @@ def _gpu():
 
 def _alone(req, precision, vcycles):
     from paper_1401_7824_amd import Plan
-    p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(precision, vcycles, solo=req.solo))
+    p = Plan(req.dim, req.n, req.nu, req.fe_kind, **req.params(precision, vcycles))
     u = torch.from_numpy(np.ascontiguousarray(req.u0)).cuda()
     for _ in range(req.nsteps):
         assert p.step(u, req.dt).status == "ok"
@@ -67,9 +67,9 @@ def test_request_larger_than_budget_is_rejected():
 
 @pytest.mark.parametrize("solo_lanes", [0, 1])
 def test_large_2d_request_equals_alone_in_a_batch_slot_or_solo(solo_lanes):
-    # a 511^2 reaction-diffusion request runs weighted-Jacobi cycles on a solo
-    # lane and red-black cycles in a batch slot; either way its result is the
-    # same request run alone with the same cycles
+    # a 511^2 reaction-diffusion request (weighted-Jacobi V(3,3) cycles) on a
+    # solo lane or in a batch slot beside a smaller one: either way its result
+    # is the request run alone
     from paper_1401_7824_amd.serve import Request, Server
     from paper_1401_7824_amd import workloads as W
     announce("serve large 2d", solo_lanes)
@@ -78,5 +78,7 @@ def test_large_2d_request_equals_alone_in_a_batch_slot_or_solo(solo_lanes):
     small = Request(rid=1, dim=2, n=127, nu=0.1, fe_kind=1, modes=W.draw_modes(2, 8, seed=41, max_wave=4),
                     dt=1e-3, nsteps=2, sdc_tol=1e-8, scale=3.0, arrival=0.001)
     Server(1 << 34, slots_per_batch=4, precision=1, vcycles=2, solo_workers=solo_lanes).serve([big, small])
-    assert big.status == "ok" and big.solo == (solo_lanes > 0)
-    assert np.array_equal(host(big.result), _alone(big, 1, 2))
+    for r in (big, small):
+        assert r.status == "ok"
+        assert np.array_equal(host(r.result), _alone(r, 1, 2)), f"request {r.rid}"
+    assert big.solo == (solo_lanes > 0)

@@ -70,15 +70,14 @@ def test_large_request_is_not_starved_by_steady_small_arrivals():
     assert admitted_at[-1] <= 5 + 3  # the running small requests finish within 3 ticks
 
 
-def test_large_2d_requests_run_weighted_jacobi_on_a_plan_of_their_own():
+def test_2d_requests_run_weighted_jacobi_cycles_3d_red_black():
     from paper_1401_7824_amd import _capi as A
-    from paper_1401_7824_amd.serve import Request, large_2d, runs_solo
+    from paper_1401_7824_amd.serve import Request, runs_solo
     big = Request(rid=0, dim=2, n=511, nu=0.1, fe_kind=1, modes=[], dt=1e-3, nsteps=1, sdc_tol=1e-8)
-    small = Request(rid=1, dim=2, n=255, nu=0.1, fe_kind=1, modes=[], dt=1e-3, nsteps=1, sdc_tol=1e-8)
+    small = Request(rid=1, dim=2, n=127, nu=1.0, fe_kind=0, modes=[], dt=1e-3, nsteps=1, sdc_tol=1e-8)
     cube = Request(rid=2, dim=3, n=127, nu=1.0, fe_kind=0, modes=[], dt=1e-3, nsteps=1, sdc_tol=1e-8)
-    assert large_2d(big) and not large_2d(small) and not large_2d(cube)
-    assert runs_solo(big, 5) and runs_solo(cube, 5) and not runs_solo(small, 5)
-    p = big.params(1, 2)
-    assert (p["smoother"], p["nu_pre"], p["nu_post"]) == (A.SMOOTH_JACOBI, 3, 3)
-    assert "smoother" not in big.params(1, 2, solo=False)  # in a batch: its red-black cycles
-    assert "smoother" not in small.params(1, 2) and "smoother" not in cube.params(1, 2)
+    assert runs_solo(big, 5) and runs_solo(cube, 5) and not runs_solo(small, 5) and runs_solo(small, 0)
+    for r in (big, small):
+        p = r.params(1, 2)
+        assert (p["smoother"], p["nu_pre"], p["nu_post"]) == (A.SMOOTH_JACOBI, 3, 3)
+    assert "smoother" not in cube.params(1, 2)
