@@ -218,10 +218,25 @@ k_resnorm(const T* __restrict__ rhs, const T* __restrict__ u, int n, T a, T diag
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
+// Max over nb per-workgroup partial maxima, one thread's share: eight independent loads in flight per
+// pass (the partials come from tens of thousands of workgroups, and one load at a time would leave the
+// single reducing workgroup waiting on L2 latency once per 256 values).
+__device__ __forceinline__ double partials_share_max(const double* __restrict__ partial, int nb) {
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = threadIdx.x;
+    for (; i + 7 * kBlock < nb; i += 8 * kBlock) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = nanmax(m[k], partial[i + k * kBlock]);
+    }
+    for (; i < nb; i += kBlock) m[0] = nanmax(m[0], partial[i]);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) m[0] = nanmax(m[0], m[k]);
+    return m[0];
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_reduce_max(const double* __restrict__ partial, int nb, double* __restrict__ out) {
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) m = nanmax(m, partial[i]);
+    double m = partials_share_max(partial, nb);
     m = block_max(m);
     if (threadIdx.x == 0) out[0] = m;
 }
@@ -234,8 +249,7 @@ __global__ void __launch_bounds__(kBlock)
 k_reduce_gate(const double* __restrict__ partial, int nb, double tol, int limit, int count_cycle, int* __restrict__ gate,
               double* __restrict__ res_out) {
     if (gate[0]) return;
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) m = nanmax(m, partial[i]);
+    double m = partials_share_max(partial, nb);
     m = block_max(m);
     if (threadIdx.x == 0) {
         res_out[0] = m;

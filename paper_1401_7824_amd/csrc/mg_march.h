@@ -786,13 +786,16 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             if (k < OB::N) d[k] = src[it];
         }
     };
-    // one colour of plane p in place: red (even x + y + p) on the red box or
-    // black on the black box; the black pass writes the owned points of p
-    auto colour = [&](int p, const T (&rr)[IZ], bool blk) {
+    // A thread holds the same points k of every plane, and only it writes
+    // them, so its registers keep a copy of its own points of each ring plane
+    // (c for plane p, cm and cp for p - 1 and p + 1) equal to the LDS plane at
+    // every pass: the z neighbours and the centre come from those registers,
+    // only the four xy neighbours from LDS.
+    // One colour of plane p in place: red (even x + y + p) on the red box or
+    // black on the black box; the black pass writes the owned points of p.
+    auto colour = [&](int p, const T (&rr)[IZ], bool blk, T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ]) {
         if ((unsigned)p >= (unsigned)n) return;  // ghost planes stay zero
         T* e0 = sE[slot(p)];
-        const T* em = sE[slot(p - 1)];
-        const T* ep = sE[slot(p + 1)];
         const bool pown = blk && p >= 2 * Z0 && (p < 2 * Z1 || p == n - 1);
         T* ob = e_out + (size_t)p * nn;
         const int want = blk ? 1 - (p & 1) : (p & 1);  // parity of x + y of the colour's points
@@ -802,19 +805,18 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             const int k = threadIdx.x + it * kThreads;
             if ((fl[it] & (box | F_IN)) != (box | F_IN)) continue;
             if (((fl[it] & F_ODD) ? 1 : 0) == want) {
-                const T nb = e0[k - 1] + e0[k + 1] + e0[k - OB::X] + e0[k + OB::X] + em[k] + ep[k];
+                const T nb = e0[k - 1] + e0[k + 1] + e0[k - OB::X] + e0[k + OB::X] + cm[it] + cp[it];
                 const T v = (rr[it] + a * nb) * invdiag;
                 e0[k] = v;
+                c[it] = v;
                 if (pown && (fl[it] & F_OWN)) ob[goff[it]] = v;
             } else if (pown && (fl[it] & F_OWN)) {
-                ob[goff[it]] = e0[k];  // the red point, final since the red pass
+                ob[goff[it]] = c[it];  // the red point, final since the red pass
             }
         }
     };
-    auto residual = [&](const T (&rr)[IZ], int f) {
-        const T* em = sE[slot(f - 1)];
+    auto residual = [&](const T (&rr)[IZ], int f, const T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ]) {
         const T* e0 = sE[slot(f)];
-        const T* ep = sE[slot(f + 1)];
         T* out = sRes[f & 1];
 #pragma unroll
         for (int it = 0; it < IZ; ++it) {
@@ -822,8 +824,8 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             const int i = threadIdx.x + it * kThreads;
             T v = T(0);
             if (fl[it] & F_IN) {
-                const T nb = e0[i - 1] + e0[i + 1] + e0[i - OB::X] + e0[i + OB::X] + em[i] + ep[i];
-                v = rr[it] - (diag * e0[i] - a * nb);
+                const T nb = e0[i - 1] + e0[i + 1] + e0[i - OB::X] + e0[i + OB::X] + cm[it] + cp[it];
+                v = rr[it] - (diag * c[it] - a * nb);
             }
             out[rbi[it]] = v;
         }
@@ -841,59 +843,60 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             acc += wyz * row;
         }
     };
+    auto copy = [](T (&d)[IZ], const T (&s)[IZ]) {
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) d[it] = s[it];
+    };
 
+    // own points of planes f .. f+5 of a step in q0 .. q5
+    T q0[IZ], q1[IZ], q2[IZ], q3[IZ], q4[IZ], q5[IZ];
     T ea[IZ], eb[IZ], rA[IZ], rB[IZ], rC[IZ], rD[IZ];
     T acc = T(0);
     const int f0 = 2 * Z0;
     // prologue: red on planes f0-2 .. f0+2, black on f0-1 .. f0+1, residual
     // plane f0 and its part of coarse plane Z0
     {
-        T e2[IZ], e3[IZ], e4[IZ], e5[IZ], rr[IZ];
-        load_e(ea, f0 - 3);
-        load_e(eb, f0 - 2);
-        load_e(e2, f0 - 1);
-        load_e(e3, f0);
-        load_e(e4, f0 + 1);
-        load_e(e5, f0 + 2);
+        T m3[IZ], m2[IZ], m1[IZ], rr[IZ];
+        // plane f0-3 is only a z neighbour (of red on f0-2): registers only
+        load_e(m3, f0 - 3);
+        load_e(m2, f0 - 2);
+        load_e(m1, f0 - 1);
+        load_e(q0, f0);
+        load_e(q1, f0 + 1);
+        load_e(q2, f0 + 2);
+        load_e(q3, f0 + 3);
         load_r(rr, f0 - 2);
         load_r(rA, f0 - 1);
         load_r(rB, f0);
         load_r(rC, f0 + 1);
-        store_e(ea, f0 - 3);
-        store_e(eb, f0 - 2);
-        store_e(e2, f0 - 1);
-        store_e(e3, f0);
-        store_e(e4, f0 + 1);
-        store_e(e5, f0 + 2);
-        load_e(ea, f0 + 3);
+        load_r(rD, f0 + 2);
+        store_e(m2, f0 - 2);
+        store_e(m1, f0 - 1);
+        store_e(q0, f0);
+        store_e(q1, f0 + 1);
+        store_e(q2, f0 + 2);
+        store_e(q3, f0 + 3);
         __syncthreads();
         // a red pass reads only black points, which no red update writes:
         // the planes share one pass
-        colour(f0 - 2, rr, false);
-        colour(f0 - 1, rA, false);
-        colour(f0, rB, false);
-        colour(f0 + 1, rC, false);
-        load_r(rD, f0 + 2);
-        __syncthreads();  // red(f0 - 2), the last reader of plane f0 - 3, is done
-        store_e(ea, f0 + 3);
+        colour(f0 - 2, rr, false, m2, m3, m1);
+        colour(f0 - 1, rA, false, m1, m2, q0);
+        colour(f0, rB, false, q0, m1, q1);
+        colour(f0 + 1, rC, false, q1, q0, q2);
+        colour(f0 + 2, rD, false, q2, q1, q3);
         __syncthreads();
-        colour(f0 + 2, rD, false);
+        colour(f0 - 1, rA, true, m1, m2, q0);
+        colour(f0, rB, true, q0, m1, q1);
+        colour(f0 + 1, rC, true, q1, q0, q2);
         __syncthreads();
-        colour(f0 - 1, rA, true);
-        colour(f0, rB, true);
-        colour(f0 + 1, rC, true);
-        __syncthreads();
-        residual(rB, f0);
+        residual(rB, f0, q0, m1, q1);
         __syncthreads();
         if (cown) weigh(acc, f0, 0);
     }
     // registers of the first step: rhs of planes f0+1 .. f0+4 in rA .. rD,
     // iterate planes f0+4, f0+5 in ea, eb
-#pragma unroll
-    for (int it = 0; it < IZ; ++it) {
-        rA[it] = rC[it];
-        rB[it] = rD[it];
-    }
+    copy(rA, rC);
+    copy(rB, rD);
     load_r(rC, f0 + 3);
     load_r(rD, f0 + 4);
     load_e(ea, f0 + 4);
@@ -904,6 +907,8 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
         // readers (the residuals of f-1 and f) passed the step's last barrier
         store_e(ea, f + 4);
         store_e(eb, f + 5);
+        copy(q4, ea);
+        copy(q5, eb);
         T rE[IZ], rF[IZ];
         if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
             load_e(ea, f + 6);
@@ -916,14 +921,14 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
         }
         __syncthreads();
         // red on f+3 and f+4 reads old black values of f+2 .. f+5
-        colour(f + 3, rC, false);
-        colour(f + 4, rD, false);
+        colour(f + 3, rC, false, q3, q2, q4);
+        colour(f + 4, rD, false, q4, q3, q5);
         __syncthreads();
-        colour(f + 2, rB, true);
-        colour(f + 3, rC, true);
+        colour(f + 2, rB, true, q2, q1, q3);
+        colour(f + 3, rC, true, q3, q2, q4);
         __syncthreads();
-        residual(rA, f + 1);
-        residual(rB, f + 2);
+        residual(rA, f + 1, q1, q0, q2);
+        residual(rB, f + 2, q2, q1, q3);
         __syncthreads();
         if (cown) {
             weigh(acc, f + 1, 1);
@@ -932,13 +937,14 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             acc = T(0);
             weigh(acc, f + 2, 0);
         }
-#pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            rA[it] = rC[it];
-            rB[it] = rD[it];
-            rC[it] = rE[it];
-            rD[it] = rF[it];
-        }
+        copy(rA, rC);
+        copy(rB, rD);
+        copy(rC, rE);
+        copy(rD, rF);
+        copy(q0, q2);
+        copy(q1, q3);
+        copy(q2, q4);
+        copy(q3, q5);
     }
 }
 
