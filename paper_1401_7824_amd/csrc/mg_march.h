@@ -562,24 +562,35 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
 #pragma unroll
         for (int it = 0; it < IZ; ++it) dst[it] = (pok && (fl[it] & F_IN)) ? b[goff[it]] : T(0);
     };
-    // plane p enters the ring: red points (even x + y + p) hold their final
-    // value r / diag, black points r until their update
-    auto store_z = [&](const T (&src)[IZ], int p) {
+    // the value plane p holds at this thread's points when it enters the
+    // ring: r / diag at red points (even x + y + p, final), r at black points
+    // until their update
+    auto entry = [&](const T (&src)[IZ], int p, T (&dst)[IZ]) {
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) {
+            const bool red = (((fl[it] & F_ODD) ? 1 : 0) + p) % 2 == 0;
+            dst[it] = red ? src[it] * invdiag : src[it];
+        }
+    };
+    auto store_z = [&](const T (&own)[IZ], int p) {
         T* d = sZ[slot(p)];
 #pragma unroll
         for (int it = 0; it < IZ; ++it) {
             const int k = threadIdx.x + it * kThreads;
-            const bool red = (((fl[it] & F_ODD) ? 1 : 0) + p) % 2 == 0;
-            if (k < ZB::N) d[k] = red ? src[it] * invdiag : src[it];
+            if (k < ZB::N) d[k] = own[it];
         }
     };
-    // black points of plane p (tile plus an xy halo of 1) from the red
-    // values around them; the points the tile owns go to e_out
-    auto black = [&](int p) {
+    // A thread holds the same points k of every plane, and only it writes
+    // them, so registers keep a copy of its own points of the middle ring
+    // planes equal to the LDS plane at every pass: the centre and z
+    // neighbours come from those registers (c for plane p, cm and cp for
+    // p - 1 and p + 1; a null lm / lp takes that neighbour from the register,
+    // else from that LDS plane), the four xy neighbours from LDS.
+    // Black points of plane p (tile plus an xy halo of 1) from the red
+    // values around them; the points the tile owns go to e_out.
+    auto black = [&](int p, T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ], const T* lp) {
         if ((unsigned)p >= (unsigned)n) return;  // ghost planes stay zero
         T* e0 = sZ[slot(p)];
-        const T* em = sZ[slot(p - 1)];
-        const T* ep = sZ[slot(p + 1)];
         const bool pown = p >= 2 * Z0 && (p < 2 * Z1 || p == n - 1);
         T* ob = e_out + (size_t)p * nn;
         const int pb = p & 1;
@@ -587,11 +598,13 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
         for (int it = 0; it < IZ; ++it) {
             const int k = threadIdx.x + it * kThreads;
             if ((fl[it] & (F_EB | F_IN)) != (F_EB | F_IN)) continue;
-            T v = e0[k];
+            T v = c[it];
             if (((fl[it] & F_ODD) ? 1 : 0) != pb) {  // odd x + y + p
-                const T nb = e0[k - 1] + e0[k + 1] + e0[k - ZB::X] + e0[k + ZB::X] + em[k] + ep[k];
+                const T up = lp ? lp[k] : cp[it];
+                const T nb = e0[k - 1] + e0[k + 1] + e0[k - ZB::X] + e0[k + ZB::X] + cm[it] + up;
                 v = (v + a * nb) * invdiag;
                 e0[k] = v;
+                c[it] = v;
             }
             if (pown && (fl[it] & F_OWN)) ob[goff[it]] = v;
         }
@@ -599,10 +612,9 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
     // residual of fine plane f (iterate planes f-1..f+1 in the ring) from
     // the rhs values rr this thread loaded for plane f; points outside the
     // grid keep 0
-    auto residual = [&](const T (&rr)[IZ], int f) {
-        const T* em = sZ[slot(f - 1)];
+    auto residual = [&](const T (&rr)[IZ], int f, const T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ],
+                        const T* lm) {
         const T* e0 = sZ[slot(f)];
-        const T* ep = sZ[slot(f + 1)];
         T* out = sRes[f & 1];
 #pragma unroll
         for (int it = 0; it < IZ; ++it) {
@@ -610,8 +622,9 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
             const int i = threadIdx.x + it * kThreads;
             T v = T(0);
             if (fl[it] & F_IN) {
-                const T nb = e0[i - 1] + e0[i + 1] + e0[i - ZB::X] + e0[i + ZB::X] + em[i] + ep[i];
-                v = rr[it] - (diag * e0[i] - a * nb);
+                const T dn = lm ? lm[i] : cm[it];
+                const T nb = e0[i - 1] + e0[i + 1] + e0[i - ZB::X] + e0[i + ZB::X] + dn + cp[it];
+                v = rr[it] - (diag * c[it] - a * nb);
             }
             out[rbi[it]] = v;
         }
@@ -631,32 +644,43 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
             acc += wyz * row;
         }
     };
+    auto copy = [](T (&d)[IZ], const T (&s)[IZ]) {
+#pragma unroll
+        for (int it = 0; it < IZ; ++it) d[it] = s[it];
+    };
 
+    // own iterate points of planes f+1 .. f+3 of a step in q1 .. q3
+    T q1[IZ], q2[IZ], q3[IZ];
     T za[IZ], zb[IZ], r1[IZ], r2[IZ];
     T acc = T(0);
     const int f0 = 2 * Z0;
     // prologue: r planes f0-2 .. f0+2, iterate planes f0-1 .. f0+1, residual
     // plane f0 and its part of coarse plane Z0
     {
-        T zc[IZ];
+        T zc[IZ], m2[IZ], m1[IZ], q0[IZ];
         load_z(za, f0 - 2);
         load_z(zb, f0 - 1);
         load_z(zc, f0);
         load_z(r1, f0 + 1);
         load_z(r2, f0 + 2);
-        store_z(za, f0 - 2);
-        store_z(zb, f0 - 1);
-        store_z(zc, f0);
-        store_z(r1, f0 + 1);
-        store_z(r2, f0 + 2);
+        entry(za, f0 - 2, m2);
+        entry(zb, f0 - 1, m1);
+        entry(zc, f0, q0);
+        entry(r1, f0 + 1, q1);
+        entry(r2, f0 + 2, q2);
+        store_z(m2, f0 - 2);
+        store_z(m1, f0 - 1);
+        store_z(q0, f0);
+        store_z(q1, f0 + 1);
+        store_z(q2, f0 + 2);
         __syncthreads();
         // black(p) reads only red points of planes p-1 .. p+1, which no
         // black update writes: the three planes share one pass
-        black(f0 - 1);
-        black(f0);
-        black(f0 + 1);
+        black(f0 - 1, m1, m2, q0, nullptr);
+        black(f0, q0, m1, q1, nullptr);
+        black(f0 + 1, q1, q0, q2, nullptr);
         __syncthreads();
-        residual(zc, f0);
+        residual(zc, f0, q0, m1, q1, nullptr);
         __syncthreads();
         if (cown) weigh(acc, f0, 0);
     }
@@ -667,29 +691,28 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
         const int f = 2 * Z;
         // planes f+3, f+4 go into the slots of f-2 and f-1, whose last
         // readers (the residuals of f-1 and f) passed the step's last barrier
-        store_z(za, f + 3);
-        store_z(zb, f + 4);
         T n1[IZ], n2[IZ];
-#pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            n1[it] = za[it];
-            n2[it] = zb[it];
+        copy(n1, za);
+        copy(n2, zb);
+        entry(n1, f + 3, q3);
+        store_z(q3, f + 3);
+        {
+            T q4[IZ];
+            entry(n2, f + 4, q4);
+            store_z(q4, f + 4);
         }
         if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
             load_z(za, f + 5);
             load_z(zb, f + 6);
         }
         __syncthreads();
-        black(f + 2);
-        black(f + 3);
+        black(f + 2, q2, q1, q3, nullptr);
+        black(f + 3, q3, q2, q3, sZ[slot(f + 4)]);
         __syncthreads();
-        residual(r1, f + 1);
-        residual(r2, f + 2);
-#pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            r1[it] = n1[it];
-            r2[it] = n2[it];
-        }
+        residual(r1, f + 1, q1, q1, q2, sZ[slot(f)]);
+        residual(r2, f + 2, q2, q1, q3, nullptr);
+        copy(r1, n1);
+        copy(r2, n2);
         __syncthreads();
         // coarse plane Z from residual planes f (already in acc), f+1, f+2;
         // plane f+2 starts coarse plane Z+1
@@ -700,6 +723,9 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
             acc = T(0);
             weigh(acc, f + 2, 0);
         }
+        // plane f+3 (its black points updated) and plane f+4 as it entered
+        copy(q1, q3);
+        entry(r2, f + 4, q2);
     }
 }
 

@@ -111,7 +111,7 @@ k_march_restrict(const T* __restrict__ r, const T* __restrict__ e, T* __restrict
 // z-marched over coarse planes (levels of 127^3 and up): writes the iterate
 // and the coarse rhs.
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_march_zrestrict(const T* __restrict__ r, T* __restrict__ e_out, T* __restrict__ rc, int n, int ntx, int nty, int mzc,
                   T a, T diag, T invdiag, const int* __restrict__ gate) {
     if (gate && *gate) return;  // the solve met its tolerance on the device
