@@ -744,17 +744,30 @@ __device__ __forceinline__ void march_zrestrict_body(const T* __restrict__ r, T*
 // restriction (the iterate is written once and never read back); the red
 // and black updates, the residual and the weighted sums (added in the same
 // order) are the expressions of the two kernels it replaces, term for term.
+//
+// A thread works on pairs of x-neighbours (even x, odd x): every pair has
+// one point of each colour, so every lane has a point in each colour pass.
+// An LDS plane holds its even columns, then its odd columns, each row-major
+// with one value per pair, so a pass reads its neighbours at unit stride.  A
+// thread holds the same pairs in every plane and only it writes them, so
+// its registers keep a copy of its own points of the six ring planes equal
+// to what LDS holds: the centre, the pair partner and the z neighbours come
+// from registers, only the other x neighbour and the two y neighbours from
+// LDS.
 template <typename T>
 __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, const T* __restrict__ e_in,
                                                      T* __restrict__ e_out, T* __restrict__ rc, int n, int X0, int Y0,
                                                      int Z0, int mzc, T a, T diag, T invdiag) {
     using RB = Box<2, 2 * MRTile::X + 1, 2 * MRTile::Y + 1, 1>;  // residual plane, fine origin (2X0, 2Y0)
-    using OB = Box<2, 2 * MRTile::X + 7, 2 * MRTile::Y + 7, 1>;  // iterate plane, origin (2X0-3, 2Y0-3)
-    constexpr int IZ = (OB::N + kThreads - 1) / kThreads;
+    constexpr int PX = MRTile::X + 4;      // pairs per row: fine columns 2X0-4 .. 2X0+2X+3
+    constexpr int PR = 2 * MRTile::Y + 7;  // rows 2Y0-3 .. 2Y0+2Y+3
+    constexpr int NP = PX * PR;            // pairs per plane
+    constexpr int IP = (NP + kThreads - 1) / kThreads;
     constexpr int NS = 6;  // ring of fine planes f .. f+5 of a step
     constexpr int NC = MRTile::X * MRTile::Y;
+    constexpr int OX = 2 * MRTile::X + 7;  // columns 2X0-3 .. 2X0+2X+3 hold the iterate (halo 3)
     static_assert(NC <= kThreads, "one coarse point per thread");
-    __shared__ T sE[NS][OB::N];
+    __shared__ T sE[NS][2 * NP];  // [0, NP): even columns, [NP, 2 NP): odd columns
     __shared__ T sRes[2][RB::N];
     const size_t nn = (size_t)n * n;
     const int nc = (n - 1) / 2;
@@ -762,98 +775,133 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
     const int fx = 2 * X0, fy = 2 * Y0;
     auto slot = [](int p) { return (p % NS + NS) % NS; };
 
-    // This thread's points of the plane box (the same in every pass), as in
-    // march_zrestrict_body: row offset, residual-box index and flags (inside
-    // the grid; in the red box (halo 2), the black box (halo 1) or the
-    // residual box; owned; parity of x + y).
-    enum { F_IN = 1, F_ZB = 2, F_EB = 4, F_RB = 8, F_OWN = 16, F_ODD = 32 };
-    unsigned goff[IZ];
-    int rbi[IZ], fl[IZ];
+    // This thread's pairs (the same in every pass): the even point's offset
+    // in a plane, the pair's row and index in an LDS half, the residual-box
+    // index of its even point, and per point (even in bits 0-7, odd in bits
+    // 8-15) flags: inside the grid; in the iterate box (halo 3), the red box
+    // (halo 2), the black box (halo 1) or the residual box; owned.
+    // Pairs are dealt out even rows first, then odd rows, so that most waves
+    // hold rows of one parity, whose colour passes then take one branch.
+    enum { F_IN = 1, F_OB = 2, F_ZB = 4, F_EB = 8, F_RB = 16, F_OWN = 32 };
+    constexpr int NEVEN = (PR + 1) / 2 * PX;  // pairs in even rows
+    unsigned goff[IP];
+    int li[IP], rbi[IP], fl[IP], rowp[IP];
 #pragma unroll
-    for (int it = 0; it < IZ; ++it) {
+    for (int it = 0; it < IP; ++it) {
         const int k = threadIdx.x + it * kThreads;
-        int lx, ly, lz;
-        OB::split(k, lx, ly, lz);
-        const int x = fx - 3 + lx, y = fy - 3 + ly;
+        const int kk = k < NEVEN ? k : k - NEVEN;
+        const int row = 2 * (kk / PX) + (k < NEVEN ? 0 : 1), j = kk % PX;
+        const int x0 = fx - 4 + 2 * j, y = fy - 3 + row;
         int f = 0;
-        if (k < OB::N) {
-            if (inside<2>(x, y, 0, n)) f |= F_IN;
-            if (lx >= 1 && lx <= OB::X - 2 && ly >= 1 && ly <= OB::Y - 2) f |= F_ZB;
-            if (lx >= 2 && lx <= OB::X - 3 && ly >= 2 && ly <= OB::Y - 3) f |= F_EB;
-            if (lx >= 3 && lx <= OB::X - 4 && ly >= 3 && ly <= OB::Y - 4) f |= F_RB;
-            const bool ox = x >= fx && x < n && (x < fx + 2 * MRTile::X || x == n - 1);
-            const bool oy = y >= fy && y < n && (y < fy + 2 * MRTile::Y || y == n - 1);
-            if (ox && oy) f |= F_OWN;
-            if ((lx + ly) & 1) f |= F_ODD;  // x + y = fx + fy - 6 + lx + ly: the parity of lx + ly
+        if (k < NP) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int x = x0 + b, lx = 2 * j + b - 1;  // lx: column in the iterate box (origin 2X0-3)
+                int g = 0;
+                if (inside<2>(x, y, 0, n)) g |= F_IN;
+                if (lx >= 0 && lx <= OX - 1) g |= F_OB;
+                if (lx >= 1 && lx <= OX - 2 && row >= 1 && row <= PR - 2) g |= F_ZB;
+                if (lx >= 2 && lx <= OX - 3 && row >= 2 && row <= PR - 3) g |= F_EB;
+                if (lx >= 3 && lx <= OX - 4 && row >= 3 && row <= PR - 4) g |= F_RB;
+                const bool ox = x >= fx && x < n && (x < fx + 2 * MRTile::X || x == n - 1);
+                const bool oy = y >= fy && y < n && (y < fy + 2 * MRTile::Y || y == n - 1);
+                if (ox && oy) g |= F_OWN;
+                f |= g << (8 * b);
+            }
         }
         fl[it] = f;
-        goff[it] = (f & F_IN) ? (unsigned)y * (unsigned)n + (unsigned)x : 0u;
-        rbi[it] = (ly - 3) * RB::X + (lx - 3);
+        // the odd point is inside only if the even one is (x0 is even)
+        goff[it] = (f & F_IN) ? (unsigned)y * (unsigned)n + (unsigned)x0 : 0u;
+        li[it] = k < NP ? row * PX + j : 0;
+        rbi[it] = (row - 3) * RB::X + (x0 - fx);
+        rowp[it] = row & 1;
     }
+    auto has = [](int f, int b, int m) { return ((f >> (8 * b)) & m) == m; };
 
-    auto load_e = [&](T (&dst)[IZ], int p) {
+    // iterate plane p at this thread's points (zero outside the grid and the box)
+    auto load_e = [&](T (&dst)[2 * IP], int p) {
         const bool pok = (unsigned)p < (unsigned)n;
-        const T* b = pok ? e_in + (size_t)p * nn : e_in;
+        const T* bp = pok ? e_in + (size_t)p * nn : e_in;
 #pragma unroll
-        for (int it = 0; it < IZ; ++it) dst[it] = (pok && (fl[it] & F_IN)) ? b[goff[it]] : T(0);
+        for (int it = 0; it < IP; ++it)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                dst[2 * it + b] = (pok && has(fl[it], b, F_IN | F_OB)) ? bp[goff[it] + b] : T(0);
     };
-    auto load_r = [&](T (&dst)[IZ], int p) {
+    // rhs of plane p at this thread's points of the red box
+    auto load_r = [&](T (&dst)[2 * IP], int p) {
         const bool pok = (unsigned)p < (unsigned)n;
-        const T* b = pok ? r + (size_t)p * nn : r;
+        const T* bp = pok ? r + (size_t)p * nn : r;
 #pragma unroll
-        for (int it = 0; it < IZ; ++it)
-            dst[it] = (pok && (fl[it] & (F_IN | F_ZB)) == (F_IN | F_ZB)) ? b[goff[it]] : T(0);
+        for (int it = 0; it < IP; ++it)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                dst[2 * it + b] = (pok && has(fl[it], b, F_IN | F_ZB)) ? bp[goff[it] + b] : T(0);
     };
-    auto store_e = [&](const T (&src)[IZ], int p) {
+    auto store_e = [&](const T (&src)[2 * IP], int p) {
         T* d = sE[slot(p)];
 #pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            if (k < OB::N) d[k] = src[it];
+        for (int it = 0; it < IP; ++it) {
+            if (threadIdx.x + it * kThreads >= NP) continue;
+            d[li[it]] = src[2 * it];
+            d[NP + li[it]] = src[2 * it + 1];
         }
     };
-    // A thread holds the same points k of every plane, and only it writes
-    // them, so its registers keep a copy of its own points of each ring plane
-    // (c for plane p, cm and cp for p - 1 and p + 1) equal to the LDS plane at
-    // every pass: the z neighbours and the centre come from those registers,
-    // only the four xy neighbours from LDS.
     // One colour of plane p in place: red (even x + y + p) on the red box or
     // black on the black box; the black pass writes the owned points of p.
-    auto colour = [&](int p, const T (&rr)[IZ], bool blk, T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ]) {
+    // c: this thread's points of plane p, cm and cp: of p - 1 and p + 1.
+    auto colour = [&](int p, const T (&rr)[2 * IP], bool blk, T (&c)[2 * IP], const T (&cm)[2 * IP],
+                      const T (&cp)[2 * IP]) {
         if ((unsigned)p >= (unsigned)n) return;  // ghost planes stay zero
         T* e0 = sE[slot(p)];
         const bool pown = blk && p >= 2 * Z0 && (p < 2 * Z1 || p == n - 1);
         T* ob = e_out + (size_t)p * nn;
-        const int want = blk ? 1 - (p & 1) : (p & 1);  // parity of x + y of the colour's points
-        const int box = blk ? F_EB : F_ZB;
+        const int box = (blk ? F_EB : F_ZB) | F_IN;
 #pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            const int k = threadIdx.x + it * kThreads;
-            if ((fl[it] & (box | F_IN)) != (box | F_IN)) continue;
-            if (((fl[it] & F_ODD) ? 1 : 0) == want) {
-                const T nb = e0[k - 1] + e0[k + 1] + e0[k - OB::X] + e0[k + OB::X] + cm[it] + cp[it];
-                const T v = (rr[it] + a * nb) * invdiag;
-                e0[k] = v;
-                c[it] = v;
-                if (pown && (fl[it] & F_OWN)) ob[goff[it]] = v;
-            } else if (pown && (fl[it] & F_OWN)) {
-                ob[goff[it]] = c[it];  // the red point, final since the red pass
+        for (int it = 0; it < IP; ++it) {
+            const int l = li[it];
+            // the even point is red when y + p is even (y = 2Y0 - 3 + row)
+            const bool even_red = ((rowp[it] + 1 + p) & 1) == 0;
+            if (blk != even_red) {  // the colour's point is the even one
+                if (has(fl[it], 0, box)) {
+                    const T nb = e0[NP + l - 1] + c[2 * it + 1] + e0[l - PX] + e0[l + PX] + cm[2 * it] + cp[2 * it];
+                    const T v = (rr[2 * it] + a * nb) * invdiag;
+                    e0[l] = v;
+                    c[2 * it] = v;
+                }
+            } else if (has(fl[it], 1, box)) {  // ... the odd one
+                const T nb = c[2 * it] + e0[l + 1] + e0[NP + l - PX] + e0[NP + l + PX] + cm[2 * it + 1] + cp[2 * it + 1];
+                const T v = (rr[2 * it + 1] + a * nb) * invdiag;
+                e0[NP + l] = v;
+                c[2 * it + 1] = v;
+            }
+            if (pown) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (has(fl[it], b, F_OWN)) ob[goff[it] + b] = c[2 * it + b];
             }
         }
     };
-    auto residual = [&](const T (&rr)[IZ], int f, const T (&c)[IZ], const T (&cm)[IZ], const T (&cp)[IZ]) {
+    auto residual = [&](const T (&rr)[2 * IP], int f, const T (&c)[2 * IP], const T (&cm)[2 * IP],
+                        const T (&cp)[2 * IP]) {
         const T* e0 = sE[slot(f)];
         T* out = sRes[f & 1];
 #pragma unroll
-        for (int it = 0; it < IZ; ++it) {
-            if (!(fl[it] & F_RB)) continue;
-            const int i = threadIdx.x + it * kThreads;
-            T v = T(0);
-            if (fl[it] & F_IN) {
-                const T nb = e0[i - 1] + e0[i + 1] + e0[i - OB::X] + e0[i + OB::X] + cm[it] + cp[it];
-                v = rr[it] - (diag * c[it] - a * nb);
+        for (int it = 0; it < IP; ++it) {
+            const int l = li[it];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (!has(fl[it], b, F_RB)) continue;
+                T v = T(0);
+                if (has(fl[it], b, F_IN)) {
+                    const T xm = b == 0 ? e0[NP + l - 1] : c[2 * it];
+                    const T xp = b == 0 ? c[2 * it + 1] : e0[l + 1];
+                    const int yb = b == 0 ? l : NP + l;
+                    const T nb = xm + xp + e0[yb - PX] + e0[yb + PX] + cm[2 * it + b] + cp[2 * it + b];
+                    v = rr[2 * it + b] - (diag * c[2 * it + b] - a * nb);
+                }
+                out[rbi[it] + b] = v;
             }
-            out[rbi[it]] = v;
         }
     };
     const int cx = threadIdx.x % MRTile::X, cy = threadIdx.x / MRTile::X;
@@ -869,20 +917,20 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             acc += wyz * row;
         }
     };
-    auto copy = [](T (&d)[IZ], const T (&s)[IZ]) {
+    auto copy = [](T (&d)[2 * IP], const T (&s)[2 * IP]) {
 #pragma unroll
-        for (int it = 0; it < IZ; ++it) d[it] = s[it];
+        for (int i = 0; i < 2 * IP; ++i) d[i] = s[i];
     };
 
     // own points of planes f .. f+5 of a step in q0 .. q5
-    T q0[IZ], q1[IZ], q2[IZ], q3[IZ], q4[IZ], q5[IZ];
-    T ea[IZ], eb[IZ], rA[IZ], rB[IZ], rC[IZ], rD[IZ];
+    T q0[2 * IP], q1[2 * IP], q2[2 * IP], q3[2 * IP], q4[2 * IP], q5[2 * IP];
+    T ea[2 * IP], eb[2 * IP], rA[2 * IP], rB[2 * IP], rC[2 * IP], rD[2 * IP];
     T acc = T(0);
     const int f0 = 2 * Z0;
     // prologue: red on planes f0-2 .. f0+2, black on f0-1 .. f0+1, residual
     // plane f0 and its part of coarse plane Z0
     {
-        T m3[IZ], m2[IZ], m1[IZ], rr[IZ];
+        T m3[2 * IP], m2[2 * IP], m1[2 * IP], rr[2 * IP];
         // plane f0-3 is only a z neighbour (of red on f0-2): registers only
         load_e(m3, f0 - 3);
         load_e(m2, f0 - 2);
@@ -935,7 +983,7 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
         store_e(eb, f + 5);
         copy(q4, ea);
         copy(q5, eb);
-        T rE[IZ], rF[IZ];
+        T rE[2 * IP], rF[2 * IP];
         if (Z + 1 < Z1) {  // the next step's planes, in flight during this one
             load_e(ea, f + 6);
             load_e(eb, f + 7);
@@ -943,7 +991,7 @@ __device__ __forceinline__ void march_srestrict_body(const T* __restrict__ r, co
             load_r(rF, f + 6);
         } else {
 #pragma unroll
-            for (int it = 0; it < IZ; ++it) rE[it] = rF[it] = T(0);
+            for (int i = 0; i < 2 * IP; ++i) rE[i] = rF[i] = T(0);
         }
         __syncthreads();
         // red on f+3 and f+4 reads old black values of f+2 .. f+5
