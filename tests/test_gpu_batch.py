@@ -93,6 +93,28 @@ def test_batch_marched_3d_slots_equal_single_instance_runs(prec):
         assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_255_cube_slot_equals_single_instance_run(prec):
+    # the benchmark's grid: 255^3 and its 127^3 level run the z-marched
+    # kernels, the fused smoothing + restriction with its fitted column depth
+    # (six columns a tile on 255^3) in the plan, the separate kernels in the
+    # batch; Radau-right M = 3 heat, the benchmark's node set
+    from paper_1401_7824_amd import Batch
+    announce("batch 255^3", prec)
+    d, n, nu, dt = 3, 255, 1.0, 1e-3
+    u0 = W.sine_field(n, d, W.draw_modes(d, 8, seed=4242, max_wave=4))
+    par = dict(node_kind=RAD, M=3, precision=prec, sdc_tol=1e-10 if prec == 0 else 1e-9)
+    b = Batch(1, d, precision=prec, vcycles=2)
+    u = dev(u0)
+    b.set(0, u, dt, 1, nu, O.FE_ZERO, **par)
+    b.run()
+    state, status, steps, st = b.info(0)
+    ref, rstats = _alone(d, n, nu, O.FE_ZERO, u0, dt, 1, **par)
+    assert status == "ok" and steps == 1, status
+    assert np.array_equal(host(u), ref), "the 255^3 slot differs from the single-instance run"
+    assert st.sweeps == rstats[-1].sweeps and st.vcycles == rstats[-1].vcycles
+
+
 def test_continuous_batching_join_and_leave():
     # slots join while others are mid-step and a finished slot is reused;
     # every result equals its run alone
