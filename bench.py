@@ -1052,7 +1052,7 @@ def run_compare(args, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); runs on several GPUs are not supported",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -59,7 +59,7 @@ typedef enum {
     ISDC_E_HIP = -3,            /* a HIP runtime call failed                            */
     ISDC_E_NOT_CONVERGED = -4,  /* max_sweeps reached; the last iterate was written     */
     ISDC_E_DIVERGED = -5,       /* non-finite SDC residual; the last iterate was written */
-    ISDC_E_UNSUPPORTED = -6     /* valid request this build does not implement          */
+    ISDC_E_UNSUPPORTED = -6     /* valid request the library does not implement         */
 } isdc_status;
 
 /* Collocation node families (Sec. 1; Sec. 2 after eq. (2)).  Gauss-Lobatto

@@ -115,7 +115,7 @@ def test_validation_rejects(bad):
 
 
 def test_axis_counts():
-    # n[a] = 1 beyond dim; unequal counts on the used axes are a valid grid this build does not run
+    # n[a] = 1 beyond dim; unequal counts on the used axes are a valid grid the library does not run
     lib = A.load()
     out = C.c_size_t()
     par = _params()
